@@ -1,0 +1,316 @@
+"""Pins for the CPU oracle, against facts fixed outside the oracle itself.
+
+* cell ids (Eq. 1): exact rational floor with fractions.Fraction, and Python's
+  float floor division;
+* ring sizes: Eq. 2 (cells on layer l) and Eq. 3 (cells on layers 1..l);
+* the k = 3 walk-through of Fig. 2c (Section III-B) and a stop-rule miss;
+* brute force: exact integer arithmetic on lattice inputs and exact rationals on
+  random float32 inputs;
+* the grid walk under the EXACT rule equals brute force; under the PAPER rule
+  it equals an independent set-based re-statement of the rule;
+* vote and mean closed forms.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_02290_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return json.load(fh)
+
+
+# ----------------------------------------------------------------------------- Eq. 1
+def _exact_cell(x, a, o=0.0):
+    v = float(np.float64(np.float32(x)) - np.float64(np.float32(o)))
+    return math.floor(Fraction(v) / Fraction(float(np.float32(a))))
+
+
+def test_cell_floor_adversarial():
+    # 1 // 0.1 is 9 in exact arithmetic although 1 / 0.1 rounds to 10.
+    xs = np.array([1.0, -1.0, 0.3, 0.7, 3.0, -3.0, 0.0, -0.0, 1e-30, -1e-30, 2.5, 1e6, -1e6, 0.1, 0.2],
+                  dtype=np.float32)
+    for a in (0.1, 0.3, 0.7, 1.0, 0.021281155, 1.0 / 3.0, 2.5e-3):
+        got = oracle.cells(xs.reshape(-1, 1), a)[:, 0]
+        want = [_exact_cell(x, a) for x in xs]
+        assert list(got) == want, a
+        af = float(np.float32(a))
+        assert list(got) == [int(float(np.float32(x)) // af) for x in xs]
+    assert oracle.cells(np.array([[1.0]], np.float32), 0.1)[0, 0] == 9
+
+
+def test_cell_floor_random_and_multiples():
+    rng = np.random.default_rng(11)
+    x = (rng.standard_normal(4000) * rng.choice([1e-3, 1.0, 50.0], 4000)).astype(np.float32)
+    a = rng.choice([0.1, 0.05, 0.021281155, 0.75, 3.0], 4000).astype(np.float32)
+    # exact multiples t*a (and their float neighbours) are the hard cases
+    t = rng.integers(-1000, 1000, 2000)
+    xm = (t * a[:2000].astype(np.float64)).astype(np.float32)
+    x[:2000] = xm
+    x[2000:2500] = np.nextafter(xm[:500], np.float32(np.inf))
+    x[2500:3000] = np.nextafter(xm[500:1000], np.float32(-np.inf))
+    for i in range(0, 4000, 7):
+        got = oracle.cells(x[i:i + 1].reshape(1, 1), a[i])[0, 0]
+        assert got == _exact_cell(x[i], a[i]), (x[i], a[i])
+
+
+def test_cell_floor_with_origin_and_per_dim_widths():
+    rng = np.random.default_rng(12)
+    pts = rng.normal(0, 2, (300, 3)).astype(np.float32)
+    widths = np.array([0.3, 0.05, 1.7], np.float32)
+    origin = np.array([-0.25, 0.1, 3.0], np.float32)
+    got = oracle.cells(pts, widths, origin)
+    for i in range(300):
+        for j in range(3):
+            assert got[i, j] == _exact_cell(pts[i, j], widths[j], origin[j])
+
+
+def test_cells_partition_points():
+    # Each point lands in exactly one cell and inside it; #cells <= n (Section III-C).
+    prob = W.make("blobs2d", n=3000, m=10)
+    g = oracle.Grid(prob.points, prob.targets, prob.task, prob.cell_width)
+    ids, counts = g.cells()
+    assert counts.sum() == prob.n
+    assert g.num_cells <= prob.n
+    assert len({tuple(r) for r in ids}) == g.num_cells
+    c = oracle.cells(prob.points, prob.cell_width)
+    a = Fraction(float(np.float32(prob.cell_width)))
+    for i in range(0, prob.n, 37):
+        for j in range(prob.f):
+            x = Fraction(float(prob.points[i, j]))
+            assert c[i, j] * a <= x < (c[i, j] + 1) * a
+
+
+# ----------------------------------------------------------------------------- Eq. 2 / Eq. 3
+@pytest.mark.parametrize("f,L", [(1, 6), (2, 4), (3, 3), (4, 3), (5, 2), (8, 1)])
+def test_ring_sizes_match_eq2_eq3(f, L):
+    # One point at the centre of every cell of the (2L+1)^f box around cell 0;
+    # k = n forces the walk through every layer.
+    side = np.arange(-L, L + 1, dtype=np.float64)
+    grid = np.stack(np.meshgrid(*([side] * f), indexing="ij"), -1).reshape(-1, f)
+    pts = (grid + 0.5).astype(np.float32)
+    n = pts.shape[0]
+    g = oracle.Grid(pts, np.zeros(n, np.int32), oracle.CLASSIFY, 1.0)
+    stop, lc, _ = g.trace(np.full(f, 0.5, np.float32), k=n, stop=oracle.STOP_PAPER, max_layers=L + 2)
+    assert stop == L
+    assert lc[0] == 1
+    for l in range(1, L + 1):
+        assert lc[l] == (2 * l + 1) ** f - (2 * l - 1) ** f          # Eq. 2
+        assert lc[1:l + 1].sum() == (2 * l + 1) ** f - 1             # Eq. 3 (layers 1..l)
+
+
+# ----------------------------------------------------------------------------- Fig. 2c walk
+def test_fig2c_walkthrough():
+    gd = _load("fig2c_walk.json")
+    pts = np.array(gd["points"], np.float32)
+    lab = np.array(gd["labels"], np.int32)
+    q = np.array([gd["query"]], np.float32)
+    ex = gd["expect"]
+    g = oracle.Grid(pts, lab, oracle.CLASSIFY, gd["cell_width"])
+    stop, lc, lu = g.trace(q[0], gd["k"], oracle.STOP_PAPER, max_layers=8)
+    assert stop == ex["paper_stop_layer"]
+    assert list(lc[:3]) == ex["paper_layer_cells"]
+    assert list(lu[:3]) == ex["paper_layer_updated"]
+    assert lc[1:3].sum() == (2 * 2 + 1) ** 2 - 1                     # Eq. 3 at l = 2
+    r = g.predict(q, gd["k"], oracle.STOP_PAPER)
+    assert list(r["idx"][0]) == ex["neighbours"]
+    assert r["pred"][0] == ex["label"]
+    assert r["cells"][0] == 1 + 8 + 16
+    r2 = g.predict(q, gd["k"], oracle.STOP_EXACT)
+    assert r2["stop_layer"][0] == ex["exact_stop_layer"]
+    assert list(r2["idx"][0]) == ex["neighbours"]
+
+
+def test_paper_rule_can_miss():
+    gd = _load("paper_rule_miss.json")
+    pts = np.array(gd["points"], np.float32)
+    lab = np.array(gd["labels"], np.int32)
+    q = np.array([gd["query"]], np.float32)
+    ex = gd["expect"]
+    g = oracle.Grid(pts, lab, oracle.CLASSIFY, gd["cell_width"])
+    rp = g.predict(q, gd["k"], oracle.STOP_PAPER)
+    re = g.predict(q, gd["k"], oracle.STOP_EXACT)
+    bi, _, _ = oracle.bruteforce(pts, lab, oracle.CLASSIFY, q, gd["k"])
+    assert list(rp["idx"][0]) == ex["paper_neighbours"]
+    assert rp["stop_layer"][0] == ex["paper_stop_layer"]
+    assert list(bi[0]) == ex["true_neighbours"]
+    assert list(re["idx"][0]) == ex["true_neighbours"]
+    assert re["stop_layer"][0] == ex["exact_stop_layer"]
+
+
+# ----------------------------------------------------------------------------- brute force
+def test_bruteforce_exact_on_lattice():
+    # Coordinates are multiples of 1/4 in [-2, 2]: every FP64 step is exact, so the
+    # (distance, index) order must equal exact integer arithmetic, ties included.
+    prob = W.lattice_problem(n=400, m=60, f=3, k=9, seed=3)
+    idx, d2, pred = oracle.bruteforce(prob.points, prob.targets, prob.task, prob.queries, prob.k)
+    P = np.rint(prob.points * 4).astype(np.int64)
+    Q = np.rint(prob.queries * 4).astype(np.int64)
+    for qi in range(prob.m):
+        d = ((P - Q[qi]) ** 2).sum(axis=1)
+        order = sorted(range(prob.n), key=lambda i: (int(d[i]), i))[:prob.k]
+        assert list(idx[qi]) == order
+        assert list(d2[qi]) == [d[i] / 16.0 for i in order]
+        labs = prob.targets[order]
+        counts = np.bincount(labs, minlength=3)
+        assert pred[qi] == int(np.flatnonzero(counts == counts.max())[0])
+
+
+def test_bruteforce_exact_rationals_random_f32():
+    rng = np.random.default_rng(5)
+    n, m, f, k = 70, 15, 3, 6
+    pts = rng.normal(0, 1, (n, f)).astype(np.float32)
+    qs = rng.normal(0, 1, (m, f)).astype(np.float32)
+    tgt = rng.normal(0, 1, n).astype(np.float32)
+    idx, d2, pred = oracle.bruteforce(pts, tgt, oracle.REGRESS, qs, k)
+    for qi in range(m):
+        ex = [sum((Fraction(float(qs[qi, j])) - Fraction(float(pts[i, j]))) ** 2 for j in range(f))
+              for i in range(n)]
+        order = sorted(range(n), key=lambda i: (ex[i], i))
+        kth, nxt = ex[order[k - 1]], ex[order[k]]
+        assert (nxt - kth) / kth > 1e-12  # no rounding-level near tie at the boundary
+        assert list(idx[qi]) == order[:k]
+        for t in range(k):
+            assert abs(Fraction(d2[qi, t]) - ex[order[t]]) <= ex[order[t]] * Fraction(1, 2 ** 48)
+        s = 0.0
+        for t in range(k):
+            s += float(tgt[order[t]])
+        assert pred[qi] == np.float32(s / k)
+
+
+def test_bruteforce_rejects_k_out_of_range():
+    pts = np.zeros((5, 2), np.float32)
+    with pytest.raises(ValueError):
+        oracle.bruteforce(pts, np.zeros(5, np.int32), 0, pts, 6)
+    with pytest.raises(ValueError):
+        oracle.bruteforce(pts, np.zeros(5, np.int32), 0, pts, 0)
+
+
+# ----------------------------------------------------------------------------- vote / mean
+def test_vote_ties_and_mean_closed_form():
+    # 5 neighbours on a line, labels 2,1,1,2,3: labels 1 and 2 tie -> smallest label (1).
+    pts = np.array([[0.0], [1.0], [2.0], [3.0], [4.0], [9.0]], np.float32)
+    lab = np.array([2, 1, 1, 2, 3, 0], np.int32)
+    q = np.array([[0.0]], np.float32)
+    _, _, pred = oracle.bruteforce(pts, lab, oracle.CLASSIFY, q, 5)
+    assert pred[0] == 1
+    g = oracle.Grid(pts, lab, oracle.CLASSIFY, 1.0)
+    assert g.predict(q, 5)["pred"][0] == 1
+    y = np.array([0.1, 1e8, -1e8, 0.3, 7.0, 5.0], np.float32)
+    _, _, mean = oracle.bruteforce(pts, y, oracle.REGRESS, q, 4)
+    want = np.float32((float(y[0]) + float(y[1]) + float(y[2]) + float(y[3])) / 4.0)
+    assert mean[0] == want
+
+
+# ----------------------------------------------------------------------------- grid walk
+def _random_case(rng, case):
+    f = int(rng.choice([1, 2, 3, 4, 5, 8]))
+    n = int(rng.integers(1, 160))
+    m = int(rng.integers(1, 12))
+    k = int(rng.integers(1, n + 1))
+    kind = case % 4
+    if kind == 0:   # uniform, queries may fall far outside
+        pts = rng.uniform(-1, 1, (n, f))
+        qs = rng.uniform(-3, 3, (m, f))
+    elif kind == 1:  # coarse lattice with duplicates and exact ties
+        pts = rng.integers(-3, 4, (n, f)) * 0.5
+        qs = rng.integers(-5, 6, (m, f)) * 0.25
+    elif kind == 2:  # clustered, negative coordinates
+        c = rng.normal(-2, 1, (3, f))
+        pts = c[rng.integers(0, 3, n)] + rng.normal(0, 0.1, (n, f))
+        qs = c[rng.integers(0, 3, m)] + rng.normal(0, 0.3, (m, f))
+    else:           # queries exactly on data points
+        pts = rng.normal(0, 1, (n, f))
+        qs = pts[rng.integers(0, n, m)]
+    widths = rng.uniform(0.05, 1.0, f if rng.random() < 0.5 else 1)
+    origin = rng.normal(0, 0.5, f) if rng.random() < 0.3 else None
+    task = int(rng.integers(0, 2))
+    tgt = rng.integers(0, 4, n).astype(np.int32) if task == 0 else rng.normal(0, 1, n).astype(np.float32)
+    return (pts.astype(np.float32), tgt, task, qs.astype(np.float32), k,
+            widths.astype(np.float32), None if origin is None else origin.astype(np.float32))
+
+
+def test_grid_exact_equals_bruteforce():
+    rng = np.random.default_rng(2024)
+    for case in range(300):
+        pts, tgt, task, qs, k, widths, origin = _random_case(rng, case)
+        g = oracle.Grid(pts, tgt, task, widths, origin)
+        r = g.predict(qs, k, oracle.STOP_EXACT)
+        bi, bd, bp = oracle.bruteforce(pts, tgt, task, qs, k)
+        assert np.array_equal(r["idx"], bi), case
+        assert np.array_equal(r["d2"], bd), case
+        assert np.array_equal(r["pred"], bp), case
+
+
+def _seq_d2(q, X):
+    s = np.zeros(X.shape[0])
+    for j in range(X.shape[1]):
+        d = np.float64(q[j]) - X[:, j].astype(np.float64)
+        s = s + d * d
+    return s
+
+
+def _paper_rule_by_sets(pts, q, k, cell_ids, center):
+    """Set-based statement of the PAPER rule: S_l = the k best points of layers 0..l;
+    stop at the first l with |S_l| = k and S_l = S_{l-1}, or once all cells are in."""
+    layer = np.abs(cell_ids - center).max(axis=1)
+    d = _seq_d2(q, pts)
+    prev = None
+    for l in range(int(layer.min()), int(layer.max()) + 1):
+        sel = np.flatnonzero(layer <= l)
+        best = sorted(sel, key=lambda i: (d[i], i))[:k]
+        full = len(best) == k
+        if l == layer.max() or (full and prev is not None and best == prev):
+            return l, best
+        prev = best if full else None
+    raise AssertionError("unreachable")
+
+
+def test_grid_paper_rule_matches_set_statement():
+    rng = np.random.default_rng(77)
+    for case in range(200):
+        pts, tgt, task, qs, k, widths, origin = _random_case(rng, case)
+        g = oracle.Grid(pts, tgt, task, widths, origin)
+        r = g.predict(qs, k, oracle.STOP_PAPER)
+        cid = oracle.cells(pts, widths, origin)
+        qid = oracle.cells(qs, widths, origin)
+        for qi in range(qs.shape[0]):
+            l, best = _paper_rule_by_sets(pts, qs[qi], k, cid, qid[qi])
+            assert r["stop_layer"][qi] == l, case
+            assert list(r["idx"][qi]) == best, case
+
+
+def test_kth_distance_monotone_and_exact_stop_sound():
+    # Along the walk the k-th distance never grows; at an EXACT stop it is below the
+    # squared distance to the outside of the visited box.
+    prob = W.make("clusters4d", n=4000, m=40)
+    g = oracle.Grid(prob.points, prob.targets, prob.task, prob.cell_width)
+    cid = oracle.cells(prob.points, prob.cell_width)
+    qid = oracle.cells(prob.queries, prob.cell_width)
+    r = g.predict(prob.queries, prob.k, oracle.STOP_EXACT)
+    a = float(np.float32(prob.cell_width))
+    for qi in range(prob.m):
+        q = prob.queries[qi]
+        d = _seq_d2(q, prob.points)
+        layer = np.abs(cid - qid[qi]).max(axis=1)
+        prev = math.inf
+        for l in range(int(layer.min()), int(r["stop_layer"][qi]) + 1):
+            sel = np.flatnonzero(layer <= l)
+            if len(sel) >= prob.k:
+                kth = np.sort(d[sel])[prob.k - 1]
+                assert kth <= prev
+                prev = kth
+        l = int(r["stop_layer"][qi])
+        if l < layer.max():
+            lo = q.astype(np.float64) - (qid[qi] - l) * a
+            hi = (qid[qi] + l + 1) * a - q.astype(np.float64)
+            assert r["d2"][qi, -1] < np.minimum(lo, hi).min() ** 2
