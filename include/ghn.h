@@ -1,0 +1,166 @@
+/*
+ * ghn.h - C ABI of libghn, a gfx950 (MI355X) implementation of Grid Hashing
+ * Neighborhood KNN (Tchaye-Kondi, Zhai, Zhu, arXiv 2004.02290).
+ *
+ * The method (Section III):
+ *   build   - "cell sampling": every training point is hashed to the cell of a
+ *             virtual grid given by Eq. 1 (cell id = point // cell measurement,
+ *             per dimension) and the points are grouped by cell (Algorithm 1);
+ *             only non-empty cells are kept.
+ *   predict - "exploration": each query is hashed to its central cell; cells are
+ *             then visited layer by layer outward (layer l = the cells whose
+ *             index differs from the central cell's by at most l in every
+ *             dimension and by exactly l in one), keeping the k nearest points
+ *             seen so far, until a stop rule fires; the k neighbours then give a
+ *             majority vote or a mean (Section I, Section III-D).
+ *
+ * Conventions shared by every entry point:
+ *   - All array arguments are DEVICE pointers owned by the caller unless marked
+ *     HOST.  Arrays are dense and row-major: points are n x f, queries m x f,
+ *     neighbour outputs m x k.  Pointers must be aligned to their element size.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  The library
+ *     never synchronises a stream except where stated (ghn_build).
+ *   - Every function returns a ghn_status; no exception crosses the ABI.  On
+ *     failure ghn_last_error() returns a message for the calling thread.
+ *   - Argument errors are detected on the host before anything is launched.
+ *     An asynchronous HIP error from earlier work on the device is reported
+ *     as GHN_E_HIP by the next call that checks.
+ *   - Distances are squared Euclidean.  Neighbours are ordered by
+ *     (d, original row index), d being the FP64 value
+ *       d = (...((q0-x0)^2 + (q1-x1)^2) + ...) + (q_{f-1}-x_{f-1})^2
+ *     with every difference, square and sum rounded to FP64 in that order (no
+ *     fused multiply-add).  Ties in d go to the smaller row index.
+ *   - Cell ids are the exact floor of (x_j - o_j) / a_j, where x_j - o_j is
+ *     rounded to FP64 first (exact whenever o = 0, the grid of Eq. 1).
+ */
+#ifndef GHN_H
+#define GHN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GHN_K_MAX 64 /* largest k a predict call accepts */
+#define GHN_F_MAX 32 /* largest number of features */
+
+typedef enum {
+    GHN_OK = 0,
+    GHN_E_INVALID_ARG = -1,  /* bad size, null pointer, bad enum, width <= 0 or not finite */
+    GHN_E_UNSUPPORTED = -2,  /* valid request this build cannot serve */
+    GHN_E_K_GT_N = -3,       /* k larger than the number of training points */
+    GHN_E_NONFINITE = -4,    /* a training point has a NaN or infinite coordinate */
+    GHN_E_KEY_OVERFLOW = -5, /* cell ids span more than the key can hold */
+    GHN_E_WORKSPACE = -6,    /* workspace missing or smaller than required */
+    GHN_E_HIP = -7,          /* a HIP runtime call failed */
+    GHN_E_NOMEM = -8         /* device allocation failed */
+} ghn_status;
+
+typedef enum { GHN_F32 = 0, GHN_BF16 = 1 } ghn_dtype;        /* storage of training points */
+typedef enum { GHN_CLASSIFY = 0, GHN_REGRESS = 1 } ghn_task; /* int32 labels | float32 targets */
+
+/* Stop rule of the exploration (Section III-B).
+ * GHN_STOP_PAPER: stop after a layer that changed none of the k buffered
+ *   neighbours while the buffer is full (the rule as the paper states it; it
+ *   can miss a true neighbour, which the paper acknowledges).
+ * GHN_STOP_EXACT: stop after layer l once the buffer is full and its k-th
+ *   distance is below the squared distance from the query to the outside of
+ *   the box of layers 0..l; the result then equals brute-force KNN.
+ * Both rules also stop once every occupied cell has been visited. */
+typedef enum { GHN_STOP_EXACT = 0, GHN_STOP_PAPER = 1 } ghn_stop;
+
+/* Distance arithmetic of the candidate screen.  The selected neighbours are
+ * the same in both: candidates near the k-th distance are re-scored in FP64.
+ * GHN_PREC_FP32: per-query FP32 distances on the vector ALUs.
+ * GHN_PREC_BF16_MFMA: queries grouped by central cell; |q|^2 + |x|^2 - 2 q.x
+ *   on bf16 matrix cores with FP32 accumulation. */
+typedef enum { GHN_PREC_FP32 = 0, GHN_PREC_BF16_MFMA = 1 } ghn_prec;
+
+/* predict flags */
+#define GHN_FLAG_NO_PRUNE 1u /* visit every cell of a layer, even those that provably
+                                cannot hold a closer point (same result, slower) */
+#define GHN_FLAG_NO_SORT 2u  /* do not reorder queries by central cell before the walk */
+
+typedef struct ghn_index ghn_index; /* opaque HOST handle; owns its device memory */
+
+typedef struct {
+    int64_t n;               /* training points */
+    int32_t f;               /* features */
+    int32_t dtype;           /* ghn_dtype */
+    int32_t task;            /* ghn_task */
+    int32_t lookup;          /* 0 = dense table over the occupied box of cells, 1 = hash table */
+    int64_t num_cells;       /* non-empty cells (never more than n, Section III-C) */
+    int64_t box_cells;       /* cells in the bounding box of the occupied cells */
+    int64_t max_occupancy;   /* points in the fullest cell */
+    int32_t cell_min[GHN_F_MAX]; /* per-dimension range of occupied cell ids */
+    int32_t cell_max[GHN_F_MAX];
+    float cell_width[GHN_F_MAX];
+    float origin[GHN_F_MAX];
+    size_t device_bytes;     /* device memory held by the index */
+} ghn_index_info;
+
+/* Cell sampling (Eq. 1, Algorithm 1).
+ *   points      n x f, float32 (dtype GHN_F32) or bfloat16 bits (GHN_BF16)
+ *   targets     n int32 class labels (GHN_CLASSIFY) or n float32 values (GHN_REGRESS)
+ *   cell_width  HOST, n_width floats: one width for every dimension (n_width = 1)
+ *               or one per dimension (n_width = f); each finite and > 0
+ *   origin      HOST, f floats or NULL (NULL = 0, the grid of Eq. 1)
+ *   out         receives the handle
+ * The index copies what it needs (points in cell order, targets), so the
+ * caller's arrays may be freed afterwards.  Allocates device memory and
+ * synchronises `stream` once (to learn the cell range and check the data).
+ * Errors: GHN_E_INVALID_ARG, GHN_E_NONFINITE, GHN_E_KEY_OVERFLOW (cell ids of
+ * one dimension span 2^28 or more, or the packed key needs more than 64 bits),
+ * GHN_E_NOMEM, GHN_E_HIP.  On error *out is NULL and nothing is leaked. */
+ghn_status ghn_build(const void* points, int64_t n, int32_t f, int32_t dtype, const void* targets,
+                     int32_t task, const float* cell_width, int32_t n_width, const float* origin,
+                     void* stream, ghn_index** out);
+
+/* Describe a built index.  `out` is HOST memory. */
+ghn_status ghn_index_get_info(const ghn_index* index, ghn_index_info* out);
+
+/* Release the index and its device memory.  NULL is ignored. */
+void ghn_destroy(ghn_index* index);
+
+typedef struct {
+    int32_t stop;            /* ghn_stop */
+    int32_t prec;            /* ghn_prec */
+    uint32_t flags;          /* GHN_FLAG_* */
+    int32_t* out_stop_layer; /* optional, m int32: layer at which each walk stopped */
+    int64_t* out_cands;      /* optional, m int64: candidate points scored per query */
+    int64_t* out_probes;     /* optional, m int64: cell-table entries read per query */
+} ghn_predict_opts;
+
+/* Bytes of device workspace ghn_predict needs for these arguments. */
+size_t ghn_predict_workspace_bytes(const ghn_index* index, int64_t m, int32_t k, const ghn_predict_opts* opts);
+
+/* Exploration + prediction for m queries (Section III-B, III-D).
+ *   queries   m x f float32
+ *   k         1 <= k <= min(n, GHN_K_MAX)
+ *   opts      HOST, may be NULL (= EXACT stop, FP32 screen, no flags)
+ *   out_idx   m x k int64: original row ids of the neighbours, ascending (d, id)
+ *   out_d2    m x k double, may be NULL: the FP64 distances d defined above
+ *   out_pred  m int32 majority label (ties -> smallest label), or m float32
+ *             mean (FP64 sum over the neighbours in order, / k, rounded to FP32)
+ *   ws        device workspace of ghn_predict_workspace_bytes() bytes (may be
+ *             NULL when that is 0)
+ * Asynchronous on `stream`; allocates nothing.  m = 0 is a no-op.  A query
+ * with a non-finite coordinate gets ids -1, distances NaN and prediction -1
+ * (classification) or NaN (regression).
+ * Errors: GHN_E_INVALID_ARG, GHN_E_K_GT_N, GHN_E_WORKSPACE, GHN_E_UNSUPPORTED,
+ * GHN_E_HIP. */
+ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, int32_t k,
+                       const ghn_predict_opts* opts, int64_t* out_idx, double* out_d2, void* out_pred,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* Last error message of the calling thread ("" if none).  Valid until the
+ * thread's next failing call. */
+const char* ghn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GHN_H */

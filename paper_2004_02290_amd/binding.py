@@ -1,0 +1,209 @@
+"""Python binding of libghn, the gfx950 Grid Hashing Neighborhood KNN library.
+
+Argument marshalling only: every step of build and predict runs in the HIP
+kernels of libghn.so.  The module-level functions carry the names of the C
+entry points (see include/ghn.h); `Index` is a small owner object around a
+handle.  Tensors must be on the GPU; the current torch stream is used unless
+a stream is passed.  Importing this module fails loudly if libghn.so has not
+been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Union
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libghn.so")
+
+GHN_OK = 0
+STATUS = {0: "GHN_OK", -1: "GHN_E_INVALID_ARG", -2: "GHN_E_UNSUPPORTED", -3: "GHN_E_K_GT_N",
+          -4: "GHN_E_NONFINITE", -5: "GHN_E_KEY_OVERFLOW", -6: "GHN_E_WORKSPACE", -7: "GHN_E_HIP",
+          -8: "GHN_E_NOMEM"}
+GHN_F32, GHN_BF16 = 0, 1
+GHN_CLASSIFY, GHN_REGRESS = 0, 1
+GHN_STOP_EXACT, GHN_STOP_PAPER = 0, 1
+GHN_PREC_FP32, GHN_PREC_BF16_MFMA = 0, 1
+GHN_FLAG_NO_PRUNE, GHN_FLAG_NO_SORT = 1, 2
+GHN_K_MAX, GHN_F_MAX = 64, 32
+
+EXPORTED = ["ghn_build", "ghn_index_get_info", "ghn_destroy", "ghn_predict_workspace_bytes", "ghn_predict",
+            "ghn_last_error"]
+
+
+class GHNError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, message))
+        self.code = code
+        self.message = message
+
+
+class ghn_index_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("f", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("task", ctypes.c_int32), ("lookup", ctypes.c_int32), ("num_cells", ctypes.c_int64),
+                ("box_cells", ctypes.c_int64), ("max_occupancy", ctypes.c_int64),
+                ("cell_min", ctypes.c_int32 * GHN_F_MAX), ("cell_max", ctypes.c_int32 * GHN_F_MAX),
+                ("cell_width", ctypes.c_float * GHN_F_MAX), ("origin", ctypes.c_float * GHN_F_MAX),
+                ("device_bytes", ctypes.c_size_t)]
+
+
+class ghn_predict_opts(ctypes.Structure):
+    _fields_ = [("stop", ctypes.c_int32), ("prec", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("out_stop_layer", ctypes.c_void_p), ("out_cands", ctypes.c_void_p),
+                ("out_probes", ctypes.c_void_p)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libghn.so is not built (%s); run __graft_entry__.build() or "
+                          "python -m paper_2004_02290_amd._build" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    L.ghn_build.argtypes = [P, I64, I32, I32, P, I32, P, I32, P, P, ctypes.POINTER(P)]
+    L.ghn_build.restype = ctypes.c_int
+    L.ghn_index_get_info.argtypes = [P, ctypes.POINTER(ghn_index_info)]
+    L.ghn_index_get_info.restype = ctypes.c_int
+    L.ghn_destroy.argtypes = [P]
+    L.ghn_destroy.restype = None
+    L.ghn_predict_workspace_bytes.argtypes = [P, I64, I32, ctypes.POINTER(ghn_predict_opts)]
+    L.ghn_predict_workspace_bytes.restype = SZ
+    L.ghn_predict.argtypes = [P, P, I64, I32, ctypes.POINTER(ghn_predict_opts), P, P, P, P, SZ, P]
+    L.ghn_predict.restype = ctypes.c_int
+    L.ghn_last_error.argtypes = []
+    L.ghn_last_error.restype = ctypes.c_char_p
+    return L
+
+
+_lib = _load()
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+def ghn_last_error() -> str:
+    return _lib.ghn_last_error().decode()
+
+
+def _check(code: int):
+    if code != GHN_OK:
+        raise GHNError(code, ghn_last_error())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def ghn_build(points: torch.Tensor, targets: torch.Tensor, task: int,
+              cell_width: Union[float, Sequence[float]], origin: Optional[Sequence[float]] = None,
+              stream=None) -> ctypes.c_void_p:
+    """ghn_build: points n x f (float32, or bfloat16 -> stored as bf16), targets n (int32 | float32)."""
+    if points.dim() != 2:
+        raise ValueError("points must be n x f")
+    n, f = points.shape
+    dtype = GHN_BF16 if points.dtype == torch.bfloat16 else GHN_F32
+    if dtype == GHN_F32 and points.dtype != torch.float32:
+        raise ValueError("points must be float32 or bfloat16")
+    want = torch.int32 if task == GHN_CLASSIFY else torch.float32
+    if targets.dtype != want or targets.numel() != n:
+        raise ValueError("targets must be %s with n entries" % want)
+    w = (ctypes.c_float * GHN_F_MAX)()
+    ws = [float(cell_width)] if isinstance(cell_width, (int, float)) else [float(x) for x in cell_width]
+    for i, x in enumerate(ws):
+        w[i] = x
+    o = None
+    if origin is not None:
+        o = (ctypes.c_float * GHN_F_MAX)()
+        for i, x in enumerate(origin):
+            o[i] = float(x)
+    h = ctypes.c_void_p()
+    _check(_lib.ghn_build(_ptr(points), n, f, dtype, _ptr(targets), task, w, len(ws), o, _stream(stream),
+                          ctypes.byref(h)))
+    return h
+
+
+def ghn_index_get_info(handle) -> ghn_index_info:
+    info = ghn_index_info()
+    _check(_lib.ghn_index_get_info(handle, ctypes.byref(info)))
+    return info
+
+
+def ghn_destroy(handle) -> None:
+    _lib.ghn_destroy(handle)
+
+
+def _opts(stop, prec, flags, out_stop_layer=None, out_cands=None, out_probes=None) -> ghn_predict_opts:
+    return ghn_predict_opts(int(stop), int(prec), int(flags), _ptr(out_stop_layer), _ptr(out_cands),
+                            _ptr(out_probes))
+
+
+def ghn_predict_workspace_bytes(handle, m: int, k: int, stop=GHN_STOP_EXACT, prec=GHN_PREC_FP32, flags=0) -> int:
+    o = _opts(stop, prec, flags)
+    return int(_lib.ghn_predict_workspace_bytes(handle, m, k, ctypes.byref(o)))
+
+
+def ghn_predict(handle, queries: torch.Tensor, k: int, out_idx: torch.Tensor, out_pred: torch.Tensor,
+                out_d2: Optional[torch.Tensor] = None, stop=GHN_STOP_EXACT, prec=GHN_PREC_FP32, flags=0,
+                out_stop_layer: Optional[torch.Tensor] = None, out_cands: Optional[torch.Tensor] = None,
+                out_probes: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+                stream=None) -> None:
+    """ghn_predict into caller-provided outputs (int64 idx m x k, pred m, optional float64 d2 m x k)."""
+    m = queries.shape[0]
+    o = _opts(stop, prec, flags, out_stop_layer, out_cands, out_probes)
+    ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
+    _check(_lib.ghn_predict(handle, _ptr(queries), m, k, ctypes.byref(o), _ptr(out_idx), _ptr(out_d2),
+                            _ptr(out_pred), _ptr(ws), ws_bytes, _stream(stream)))
+
+
+class Index:
+    """Owner of a built index (build on construction, free on close / garbage collection)."""
+
+    def __init__(self, points: torch.Tensor, targets: torch.Tensor, task: int,
+                 cell_width: Union[float, Sequence[float]], origin=None, stream=None):
+        self.task = task
+        self.handle = ghn_build(points, targets, task, cell_width, origin, stream)
+        self.info = ghn_index_get_info(self.handle)
+
+    def predict(self, queries: torch.Tensor, k: int, stop=GHN_STOP_EXACT, prec=GHN_PREC_FP32, flags=0,
+                with_d2: bool = True, with_stats: bool = False, stream=None):
+        """Returns dict(idx, pred[, d2][, stop_layer, cands]) as GPU tensors."""
+        dev = queries.device
+        m = queries.shape[0]
+        out = dict(idx=torch.empty((m, k), dtype=torch.int64, device=dev),
+                   pred=torch.empty(m, dtype=torch.int32 if self.task == GHN_CLASSIFY else torch.float32,
+                                    device=dev))
+        if with_d2:
+            out["d2"] = torch.empty((m, k), dtype=torch.float64, device=dev)
+        if with_stats:
+            out["stop_layer"] = torch.empty(m, dtype=torch.int32, device=dev)
+            out["cands"] = torch.empty(m, dtype=torch.int64, device=dev)
+            out["probes"] = torch.empty(m, dtype=torch.int64, device=dev)
+        nbytes = ghn_predict_workspace_bytes(self.handle, m, k, stop, prec, flags)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev) if nbytes else None
+        ghn_predict(self.handle, queries, k, out["idx"], out["pred"], out.get("d2"), stop, prec, flags,
+                    out.get("stop_layer"), out.get("cands"), out.get("probes"), ws, stream)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ghn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,277 @@
+// Cell sampling on the GPU (Eq. 1, Algorithm 1): every training point gets its
+// cell id; points are then grouped by cell with a stable LSD radix sort on the
+// cell key, copied in cell order, and an offset table maps each cell of the
+// occupied box to its run of points.  Empty cells own empty runs and store no
+// points (Section III-A keeps no information about empty cells).
+#include "ghn_internal.h"
+
+namespace ghn {
+namespace {
+
+constexpr int BT = 256;  // threads per block for the simple build kernels
+
+__device__ __forceinline__ float load_coord(const void* pts, int64_t idx, int32_t dtype) {
+    if (dtype == GHN_BF16) {
+        uint32_t b = ((const uint16_t*)pts)[idx];
+        return __uint_as_float(b << 16);
+    }
+    return ((const float*)pts)[idx];
+}
+
+// Per-dimension range of cell ids plus data checks.
+// minmax[j] = min cell id of dimension j, minmax[F_MAX + j] = max.
+// flags[0] = a coordinate is NaN/Inf, flags[1] = a cell id is outside (-COORD_LIMIT, COORD_LIMIT).
+__global__ __launch_bounds__(BT) void k_cells_minmax(const void* pts, int64_t n, int32_t f, int32_t dtype,
+                                                     const float* __restrict__ a, const float* __restrict__ o,
+                                                     int32_t* minmax, int32_t* flags) {
+    __shared__ int32_t smin[F_MAX], smax[F_MAX];
+    __shared__ int32_t sflag[2];
+    if (threadIdx.x < F_MAX) { smin[threadIdx.x] = INT32_MAX; smax[threadIdx.x] = INT32_MIN; }
+    if (threadIdx.x < 2) sflag[threadIdx.x] = 0;
+    __syncthreads();
+    for (int j = 0; j < f; ++j) {
+        const double aj = a[j], oj = o[j];
+        int32_t lmin = INT32_MAX, lmax = INT32_MIN;
+        int32_t nonfinite = 0, overflow = 0;
+        for (int64_t i = blockIdx.x * (int64_t)BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) {
+            float x = load_coord(pts, i * f + j, dtype);
+            if (!isfinite(x)) { nonfinite = 1; continue; }
+            int64_t c = exact_floor_div(__dadd_rn((double)x, -oj), aj);
+            if (c <= -COORD_LIMIT || c >= COORD_LIMIT) { overflow = 1; continue; }
+            lmin = min(lmin, (int32_t)c);
+            lmax = max(lmax, (int32_t)c);
+        }
+        if (lmin != INT32_MAX) atomicMin(&smin[j], lmin);
+        if (lmax != INT32_MIN) atomicMax(&smax[j], lmax);
+        if (nonfinite) sflag[0] = 1;
+        if (overflow) sflag[1] = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)f) {
+        atomicMin(&minmax[threadIdx.x], smin[threadIdx.x]);
+        atomicMax(&minmax[F_MAX + threadIdx.x], smax[threadIdx.x]);
+    }
+    if (threadIdx.x < 2 && sflag[threadIdx.x]) atomicOr(&flags[threadIdx.x], 1);
+}
+
+// Dense-box key of every point: linear index of its cell inside the occupied box.
+__global__ __launch_bounds__(BT) void k_dense_keys(const void* pts, int64_t n, int32_t dtype, IndexView iv,
+                                                   uint64_t* keys, uint32_t* vals) {
+    const int32_t f = iv.f;
+    for (int64_t i = blockIdx.x * (int64_t)BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) {
+        uint64_t key = 0;
+        for (int j = 0; j < f; ++j) {
+            float x = load_coord(pts, i * f + j, dtype);
+            int64_t c = exact_floor_div(__dadd_rn((double)x, -(double)iv.o[j]), (double)iv.a[j]);
+            key += (uint64_t)(c - iv.cmin[j]) * (uint64_t)iv.stride[j];
+        }
+        keys[i] = key;
+        vals[i] = (uint32_t)i;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Stable LSD radix sort of (u64 key, u32 value) pairs, 8-bit digits, reduce-then-scan
+// (per pass: block digit histograms, one exclusive scan over digit-major counts, then a
+// stable scatter in which each block ranks its keys with wave ballots).
+constexpr int RS_T = 256;
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = RS_T * RS_ITEMS;
+
+__global__ __launch_bounds__(RS_T) void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+                                                     uint32_t* __restrict__ counts, int nblocks) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        int64_t i = base + it * RS_T + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+constexpr int SCAN_T = 1024;
+
+// Exclusive scan of `total` counts in place, one block.
+__global__ __launch_bounds__(SCAN_T) void k_exclusive_scan_u32(uint32_t* data, int64_t total) {
+    __shared__ uint32_t part[SCAN_T];
+    const int64_t chunk = (total + SCAN_T - 1) / SCAN_T;
+    const int64_t b = threadIdx.x * chunk;
+    const int64_t e = min(b + chunk, total);
+    uint32_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += data[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int d = 1; d < SCAN_T; d <<= 1) {
+        uint32_t t = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += t;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - s;
+    for (int64_t i = b; i < e; ++i) {
+        uint32_t v = data[i];
+        data[i] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(RS_T) void k_radix_scatter(const uint64_t* __restrict__ kin,
+                                                        const uint32_t* __restrict__ vin,
+                                                        uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                        int64_t n, int shift, const uint32_t* __restrict__ offs,
+                                                        int nblocks) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wc[RS_T / WAVE][256];
+    const int t = threadIdx.x, w = t / WAVE;
+    run[t] = offs[(int64_t)t * nblocks + blockIdx.x];
+    for (int i = 0; i < RS_T / WAVE; ++i) wc[i][t] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const uint64_t lt = __lanemask_lt();
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const int64_t i = base + r * RS_T + t;
+        const bool valid = i < n;
+        uint64_t key = 0;
+        uint32_t val = 0;
+        uint32_t d = 0;
+        if (valid) {
+            key = kin[i];
+            val = vin[i];
+            d = (uint32_t)(key >> shift) & 255u;
+        }
+        uint64_t peers = ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = ballot(valid && bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = __popcll(peers & lt);
+        if (valid && rank == 0) wc[w][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pre = 0;
+            for (int ww = 0; ww < w; ++ww) pre += wc[ww][d];
+            const uint32_t pos = run[d] + pre + rank;
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        uint32_t tot = 0;
+        for (int ww = 0; ww < RS_T / WAVE; ++ww) { tot += wc[ww][t]; wc[ww][t] = 0; }
+        run[t] += tot;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(BT) void k_gather_points(const void* pts, int64_t n, int32_t f, int32_t dtype,
+                                                      const uint32_t* __restrict__ perm, float* __restrict__ spts,
+                                                      int32_t* __restrict__ sid) {
+    for (int64_t r = blockIdx.x * (int64_t)BT + threadIdx.x; r < n; r += (int64_t)gridDim.x * BT) {
+        const uint32_t src = perm[r];
+        for (int j = 0; j < f; ++j) spts[r * f + j] = load_coord(pts, (int64_t)src * f + j, dtype);
+        sid[r] = (int32_t)src;
+    }
+}
+
+// cell_start[L] = first position whose key is >= L, for L in [0, box_cells].
+__global__ __launch_bounds__(BT) void k_dense_cell_start(const uint64_t* __restrict__ keys, int64_t n,
+                                                         int64_t box_cells, uint32_t* __restrict__ cs) {
+    for (int64_t L = blockIdx.x * (int64_t)BT + threadIdx.x; L <= box_cells; L += (int64_t)gridDim.x * BT) {
+        int64_t lo = 0, hi = n;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (keys[mid] < (uint64_t)L) lo = mid + 1;
+            else hi = mid;
+        }
+        cs[L] = (uint32_t)lo;
+    }
+}
+
+// stats[0] += non-empty cells, stats[1] = max(points in one cell).
+__global__ __launch_bounds__(BT) void k_dense_cell_stats(const uint32_t* __restrict__ cs, int64_t box_cells,
+                                                         int64_t* stats) {
+    int64_t cnt = 0, mx = 0;
+    for (int64_t L = blockIdx.x * (int64_t)BT + threadIdx.x; L < box_cells; L += (int64_t)gridDim.x * BT) {
+        const int64_t occ = (int64_t)cs[L + 1] - (int64_t)cs[L];
+        if (occ > 0) { cnt += 1; mx = max(mx, occ); }
+    }
+    for (int d = 1; d < WAVE; d <<= 1) {
+        cnt += __shfl_xor(cnt, d, WAVE);
+        mx = max(mx, (int64_t)__shfl_xor(mx, d, WAVE));
+    }
+    if (lane_id() == 0) {
+        atomicAdd((unsigned long long*)&stats[0], (unsigned long long)cnt);
+        atomicMax((unsigned long long*)&stats[1], (unsigned long long)mx);
+    }
+}
+
+int grid_for(int64_t work, int threads, int cap = 65536) {
+    int64_t g = (work + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_cells_minmax(const void* pts, int64_t n, int32_t f, int32_t dtype, const float* a,
+                               const float* o, int32_t* d_minmax, int32_t* d_flags, hipStream_t s) {
+    hipLaunchKernelGGL(k_cells_minmax, dim3(grid_for(n, BT, 4096)), dim3(BT), 0, s, pts, n, f, dtype, a, o,
+                       d_minmax, d_flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_keys(const void* pts, int64_t n, int32_t f, int32_t dtype, const IndexView& iv,
+                             uint64_t* keys, uint32_t* vals, hipStream_t s) {
+    (void)f;
+    hipLaunchKernelGGL(k_dense_keys, dim3(grid_for(n, BT)), dim3(BT), 0, s, pts, n, dtype, iv, keys, vals);
+    return hipGetLastError();
+}
+
+size_t radix_sort_temp_bytes(int64_t n) {
+    const int64_t nblocks = (n + RS_TILE - 1) / RS_TILE;
+    return (size_t)(256 * nblocks) * sizeof(uint32_t);
+}
+
+hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                            int nbits, void* temp, bool* result_in_alt, hipStream_t s) {
+    const int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
+    uint32_t* counts = (uint32_t*)temp;
+    uint64_t *ki = keys, *ko = keys_alt;
+    uint32_t *vi = vals, *vo = vals_alt;
+    bool alt = false;
+    for (int shift = 0; shift < nbits; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(RS_T), 0, s, ki, n, shift, counts, nblocks);
+        hipLaunchKernelGGL(k_exclusive_scan_u32, dim3(1), dim3(SCAN_T), 0, s, counts, (int64_t)256 * nblocks);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(RS_T), 0, s, ki, vi, ko, vo, n, shift, counts,
+                           nblocks);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        uint64_t* tk = ki; ki = ko; ko = tk;
+        uint32_t* tv = vi; vi = vo; vo = tv;
+        alt = !alt;
+    }
+    *result_in_alt = alt;
+    return hipSuccess;
+}
+
+hipError_t launch_gather_points(const void* pts, int64_t n, int32_t f, int32_t dtype, const uint32_t* perm,
+                                float* spts, int32_t* sid, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_points, dim3(grid_for(n, BT)), dim3(BT), 0, s, pts, n, f, dtype, perm, spts, sid);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_cell_start(const uint64_t* sorted_keys, int64_t n, int64_t box_cells, uint32_t* cell_start,
+                                   int64_t* d_stats, hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_cell_start, dim3(grid_for(box_cells + 1, BT)), dim3(BT), 0, s, sorted_keys, n,
+                       box_cells, cell_start);
+    hipLaunchKernelGGL(k_dense_cell_stats, dim3(grid_for(box_cells, BT, 4096)), dim3(BT), 0, s, cell_start,
+                       box_cells, d_stats);
+    return hipGetLastError();
+}
+
+}  // namespace ghn

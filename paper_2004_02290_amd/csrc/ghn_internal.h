@@ -1,0 +1,133 @@
+// Internal declarations shared by the libghn translation units: the device view
+// of an index, launch entry points, and small wave64 helpers for gfx950.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ghn.h"
+
+namespace ghn {
+
+constexpr int WAVE = 64;
+constexpr int F_MAX = GHN_F_MAX;
+constexpr int K_MAX = GHN_K_MAX;
+// Training-point cell ids must lie in (-COORD_LIMIT, COORD_LIMIT).
+constexpr int64_t COORD_LIMIT = int64_t(1) << 27;
+// A query cell id further than CLAMP cells outside the occupied range of its
+// dimension is moved to distance CLAMP.  Cell ids within that range stay below
+// 2^29 in magnitude, where the exact floor below is verified.
+constexpr int64_t CLAMP = int64_t(1) << 28;
+
+enum Lookup : int32_t { LOOKUP_DENSE = 0, LOOKUP_HASH = 1 };
+
+// Device-side view of an index, passed by value to kernels.
+struct IndexView {
+    int64_t n;
+    int32_t f;
+    int32_t dtype;
+    int32_t task;
+    int32_t lookup;
+    const float* spts;          // n x f points in cell order (FP32 copy; exact for bf16 input)
+    const int32_t* sid;         // n original row ids, cell order
+    const uint32_t* cell_start; // dense: box_cells + 1 offsets into spts
+    const void* targets;        // n targets, original order
+    int64_t box_cells;
+    float a[F_MAX];             // cell width per dimension
+    float o[F_MAX];             // origin per dimension
+    int32_t cmin[F_MAX];
+    int32_t cmax[F_MAX];
+    int64_t stride[F_MAX];      // dense-box linear index stride per dimension (last = 1)
+};
+
+// ---------------------------------------------------------------------------------------
+// Exact floor of v / a (a > 0 finite, v finite): the largest integer t with t * a <= v.
+// The FP64 quotient is rounded, so the candidate is checked against exact products; for
+// |t| < 2^29 and an FP32 width, t * a is exact in FP64.
+__device__ __forceinline__ int64_t exact_floor_div(double v, double a) {
+    double t = floor(v / a);
+    if (!(fabs(t) < 4.0e18)) return t > 0 ? int64_t(4000000000000000000LL) : -int64_t(4000000000000000000LL);
+    if (fabs(t) < 536870912.0) {
+        if (__dmul_rn(t, a) > v) t -= 1.0;
+        else if (__dmul_rn(t + 1.0, a) <= v) t += 1.0;
+    }
+    return int64_t(t);
+}
+
+// ---------------------------------------------------------------------------------------
+// wave64 helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int readlane_i32(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+__device__ __forceinline__ float readlane_f32(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    int64_t b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_readlane(int(uint32_t(b)), l);
+    int hi = __builtin_amdgcn_readlane(int(uint32_t(uint64_t(b) >> 32)), l);
+    return __longlong_as_double(int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo)));
+}
+
+// Value of `v` held by lane (lane - 1); lane 0 gets its own value.
+__device__ __forceinline__ int shfl_up1_i32(int v) { return __shfl_up(v, 1, WAVE); }
+__device__ __forceinline__ double shfl_up1_f64(double v) {
+    int64_t b = __double_as_longlong(v);
+    int lo = __shfl_up(int(uint32_t(b)), 1, WAVE);
+    int hi = __shfl_up(int(uint32_t(uint64_t(b) >> 32)), 1, WAVE);
+    return __longlong_as_double(int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo)));
+}
+
+// Inclusive prefix sum over the wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, WAVE);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) v += __shfl_xor(v, d, WAVE);
+    return v;
+}
+
+// ---------------------------------------------------------------------------------------
+// Host-side launchers (defined in the .hip files).
+hipError_t launch_cells_minmax(const void* pts, int64_t n, int32_t f, int32_t dtype, const float* a,
+                               const float* o, int32_t* d_minmax, int32_t* d_flags, hipStream_t s);
+hipError_t launch_dense_keys(const void* pts, int64_t n, int32_t f, int32_t dtype, const IndexView& iv,
+                             uint64_t* keys, uint32_t* vals, hipStream_t s);
+size_t radix_sort_temp_bytes(int64_t n);
+hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                            int64_t n, int nbits, void* temp, bool* result_in_alt, hipStream_t s);
+hipError_t launch_gather_points(const void* pts, int64_t n, int32_t f, int32_t dtype, const uint32_t* perm,
+                                float* spts, int32_t* sid, hipStream_t s);
+hipError_t launch_dense_cell_start(const uint64_t* sorted_keys, int64_t n, int64_t box_cells,
+                                   uint32_t* cell_start, int64_t* d_stats, hipStream_t s);
+
+struct PredictArgs {
+    IndexView ix;
+    const float* queries;
+    int64_t m;
+    int32_t k;
+    int32_t stop;
+    uint32_t flags;
+    int64_t* out_idx;
+    double* out_d2;
+    void* out_pred;
+    int32_t* out_stop_layer;
+    int64_t* out_cands;
+    int64_t* out_probes;
+    const uint32_t* order;  // optional processing order of the queries (NULL = 0..m-1)
+};
+hipError_t launch_predict_dense(const PredictArgs& a, hipStream_t s);
+
+}  // namespace ghn

@@ -1,0 +1,253 @@
+"""GPU (HIP, gfx950) results against the CPU oracle, element by element.
+
+Neighbour ids, FP64 distances, labels and regression means must be bit-identical:
+  * EXACT stop rule  -> brute-force KNN (the plain definition);
+  * PAPER stop rule  -> the oracle's grid walk, including the layer it stopped at.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_02290_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ghn():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2004_02290_amd import binding
+    return binding
+
+
+def _dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _index(ghn, prob, widths=None, origin=None):
+    import torch
+    if prob.dtype == "bf16":
+        pts = _dev(prob.points.view(np.int16)).view(torch.bfloat16)
+    else:
+        pts = _dev(prob.points)
+    return ghn.Index(pts, _dev(prob.targets), prob.task, prob.cell_width if widths is None else widths, origin)
+
+
+def _run(ghn, ix, queries, k, stop, **kw):
+    import torch
+    out = ix.predict(_dev(queries), k, stop=stop, with_stats=True, **kw)
+    torch.cuda.synchronize()
+    return {key: v.cpu().numpy() for key, v in out.items()}
+
+
+def _assert_same(got, want, what, check_layers=False):
+    for key in ("idx", "d2", "pred"):
+        g, w = got[key], want[key]
+        if not np.array_equal(g, w):
+            bad = np.flatnonzero((g != w).reshape(g.shape[0], -1).any(axis=1))
+            raise AssertionError("%s: %s differs on %d rows, first %d: got %s want %s" % (
+                what, key, bad.size, bad[0], g[bad[0]], w[bad[0]]))
+    if check_layers:
+        assert np.array_equal(got["stop_layer"], want["stop_layer"]), what
+
+
+def _check_exact(ghn, prob, sample=None, seed=0, **kw):
+    ix = _index(ghn, prob, **{k: v for k, v in kw.items() if k in ("widths", "origin")})
+    flags = kw.get("flags", 0)
+    got = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_EXACT, flags=flags)
+    rows = np.arange(prob.m)
+    if sample is not None and sample < prob.m:
+        rows = np.sort(np.random.default_rng(seed).choice(prob.m, sample, replace=False))
+    bi, bd, bp = oracle.bruteforce(prob.points_f32(), prob.targets, prob.task, prob.queries[rows], prob.k)
+    _assert_same({k: v[rows] for k, v in got.items()}, dict(idx=bi, d2=bd, pred=bp), prob.name + " EXACT")
+    return ix, got
+
+
+def _check_paper(ghn, prob, sample=None, seed=1, widths=None, origin=None, flags=0):
+    ix = _index(ghn, prob, widths, origin)
+    got = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_PAPER, flags=flags)
+    rows = np.arange(prob.m)
+    if sample is not None and sample < prob.m:
+        rows = np.sort(np.random.default_rng(seed).choice(prob.m, sample, replace=False))
+    g = oracle.Grid(prob.points_f32(), prob.targets, prob.task, prob.cell_width if widths is None else widths,
+                    origin)
+    want = g.predict(prob.queries[rows], prob.k, oracle.STOP_PAPER)
+    _assert_same({k: v[rows] for k, v in got.items()}, want, prob.name + " PAPER", check_layers=True)
+    return got
+
+
+# ---------------------------------------------------------------------------------- workloads
+def test_blobs2d_full_exact_and_paper(ghn):
+    prob = W.make("blobs2d")
+    _check_exact(ghn, prob)
+    _check_paper(ghn, prob)
+
+
+def test_clusters4d_small_exact_and_paper(ghn):
+    prob = W.make("clusters4d", n=60_000, m=3_001)
+    _check_exact(ghn, prob)
+    _check_paper(ghn, prob)
+
+
+def test_clusters4d_full_size_sampled(ghn):
+    prob = W.make("clusters4d")
+    _check_exact(ghn, prob, sample=1500)
+    _check_paper(ghn, prob, sample=3000)
+
+
+def test_exact_stop_layer_matches_oracle(ghn):
+    prob = W.make("clusters4d", n=40_000, m=997)
+    ix = _index(ghn, prob)
+    got = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_EXACT)
+    want = oracle.Grid(prob.points, prob.targets, prob.task, prob.cell_width).predict(
+        prob.queries, prob.k, oracle.STOP_EXACT)
+    _assert_same(got, want, "EXACT vs grid oracle", check_layers=True)
+
+
+def test_no_prune_same_result(ghn):
+    prob = W.make("clusters4d", n=20_000, m=500)
+    ix = _index(ghn, prob)
+    for stop in (ghn.GHN_STOP_EXACT, ghn.GHN_STOP_PAPER):
+        a = _run(ghn, ix, prob.queries, prob.k, stop)
+        b = _run(ghn, ix, prob.queries, prob.k, stop, flags=ghn.GHN_FLAG_NO_PRUNE)
+        _assert_same(a, b, "prune vs no-prune", check_layers=True)
+        assert (b["cands"] >= a["cands"]).all()
+
+
+def test_deterministic(ghn):
+    prob = W.make("clusters4d", n=30_000, m=800)
+    ix = _index(ghn, prob)
+    a = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_PAPER)
+    b = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_PAPER)
+    for key in a:
+        assert np.array_equal(a[key], b[key])
+
+
+# ---------------------------------------------------------------------------------- shapes, dims
+@pytest.mark.parametrize("f", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_dims_uniform(ghn, f):
+    n = {1: 3000, 2: 3000, 3: 5000, 4: 6000, 5: 6000, 6: 8000, 7: 8000, 8: 8000}[f]
+    width = {1: 0.003, 2: 0.05, 3: 0.1, 4: 0.2, 5: 0.3, 6: 0.34, 7: 0.5, 8: 0.5}[f]
+    prob = W.uniform_problem(n=n, m=333, f=f, k=7, seed=f, width=width, q_lo=-0.3, q_hi=1.3)
+    _check_exact(ghn, prob)
+    _check_paper(ghn, prob)
+
+
+@pytest.mark.parametrize("k", [1, 2, 13, 33, 64])
+def test_k_values(ghn, k):
+    prob = W.uniform_problem(n=4000, m=257, f=3, k=k, seed=100 + k, width=0.08)
+    _check_exact(ghn, prob)
+    _check_paper(ghn, prob)
+
+
+def test_k_equals_n(ghn):
+    prob = W.uniform_problem(n=40, m=65, f=2, k=40, seed=9, width=0.3, q_lo=-2.0, q_hi=3.0)
+    _check_exact(ghn, prob)
+    _check_paper(ghn, prob)
+
+
+def test_lattice_ties_and_duplicates(ghn):
+    for f in (2, 3):
+        prob = W.lattice_problem(n=3000, m=300, f=f, k=12, seed=f)
+        _check_exact(ghn, prob)
+        _check_paper(ghn, prob)
+        reg = W.lattice_problem(n=3000, m=300, f=f, k=12, seed=f, task=W.REGRESS)
+        _check_exact(ghn, reg)
+
+
+def test_regression_mean(ghn):
+    prob = W.uniform_problem(n=20000, m=1000, f=3, k=16, seed=4, task=W.REGRESS, width=0.05)
+    _check_exact(ghn, prob)
+    _check_paper(ghn, prob)
+
+
+def test_per_dim_widths_and_origin(ghn):
+    prob = W.uniform_problem(n=8000, m=400, f=3, k=9, seed=21, lo=-2.0, hi=2.0, q_lo=-3.0, q_hi=3.0)
+    widths = np.array([0.31, 0.07, 0.19], np.float32)
+    origin = np.array([-0.123, 0.05, 1.7], np.float32)
+    _check_exact(ghn, prob, widths=widths, origin=origin)
+    _check_paper(ghn, prob, widths=widths, origin=origin)
+
+
+def test_far_queries(ghn):
+    prob = W.uniform_problem(n=5000, m=200, f=3, k=5, seed=5, width=0.1)
+    prob.queries[:50] *= 1e3
+    prob.queries[50:100] -= 37.0
+    prob.queries[100:110, 0] = 1e7
+    _check_exact(ghn, prob)
+    _check_paper(ghn, prob)
+
+
+def test_queries_on_points(ghn):
+    prob = W.make("clusters4d", n=20000, m=10)
+    prob.queries = prob.points[::37].copy()
+    _check_exact(ghn, prob)
+    _check_paper(ghn, prob)
+
+
+def test_single_point_and_single_cell(ghn):
+    p = W.uniform_problem(n=1, m=70, f=2, k=1, seed=3, width=0.5, q_lo=-5, q_hi=5)
+    _check_exact(ghn, p)
+    _check_paper(ghn, p)
+    p = W.uniform_problem(n=500, m=70, f=3, k=20, seed=3, width=100.0)
+    _check_exact(ghn, p)
+    _check_paper(ghn, p)
+
+
+# ---------------------------------------------------------------------------------- errors
+def test_nonfinite_query_gets_sentinels(ghn):
+    prob = W.uniform_problem(n=1000, m=8, f=2, k=3, seed=1, width=0.1)
+    prob.queries[3, 1] = np.nan
+    prob.queries[5, 0] = np.inf
+    ix = _index(ghn, prob)
+    got = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_EXACT)
+    for r in (3, 5):
+        assert (got["idx"][r] == -1).all() and np.isnan(got["d2"][r]).all() and got["pred"][r] == -1
+    ok = [0, 1, 2, 4, 6, 7]
+    bi, bd, bp = oracle.bruteforce(prob.points, prob.targets, prob.task, prob.queries[ok], prob.k)
+    assert np.array_equal(got["idx"][ok], bi) and np.array_equal(got["d2"][ok], bd)
+
+
+def test_build_errors(ghn):
+    pts = np.random.default_rng(0).random((100, 2)).astype(np.float32)
+    lab = np.zeros(100, np.int32)
+    bad = pts.copy()
+    bad[7, 1] = np.nan
+    with pytest.raises(ghn.GHNError) as e:
+        ghn.Index(_dev(bad), _dev(lab), 0, 0.1)
+    assert e.value.code == -4
+    big = pts.copy()
+    big[3, 0] = 1e30
+    with pytest.raises(ghn.GHNError) as e:
+        ghn.Index(_dev(big), _dev(lab), 0, 0.1)
+    assert e.value.code == -5
+    spread = pts.copy()
+    spread[:, 0] *= 1e5
+    spread[:, 1] *= 1e5
+    with pytest.raises(ghn.GHNError) as e:
+        ghn.Index(_dev(spread), _dev(lab), 0, 0.01)
+    assert e.value.code == -2
+
+
+def test_predict_errors_and_empty(ghn):
+    import torch
+    prob = W.uniform_problem(n=50, m=4, f=2, k=3, seed=1, width=0.1)
+    ix = _index(ghn, prob)
+    q = _dev(prob.queries)
+    with pytest.raises(ghn.GHNError) as e:
+        ix.predict(q, 51)
+    assert e.value.code == -3  # k > n
+    empty = torch.empty((0, 2), dtype=torch.float32, device="cuda")
+    out = ix.predict(empty, 3)
+    assert out["idx"].shape == (0, 3)
+    with pytest.raises(ghn.GHNError) as e:
+        ix.predict(q, 65)
+    assert e.value.code == -1
+    with pytest.raises(ghn.GHNError) as e:
+        ix.predict(q, 0)
+    assert e.value.code == -1
