@@ -79,6 +79,7 @@ def main():
     ap.add_argument("--workload", default="clusters4d")
     ap.add_argument("--stop", default="exact", choices=["exact", "paper"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sort", action="store_true", help="walk queries in input order")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -118,33 +119,52 @@ def main():
     out_pred = torch.empty(m, dtype=torch.int32 if prob.task == 0 else torch.float32, device=dev)
 
     # Work counts for the algorithmic byte figure (untimed pass with statistics).
-    st = ix.predict(qs, k, stop=stop, with_d2=False, with_stats=True)
+    flags = ghn.GHN_FLAG_NO_SORT if args.no_sort else 0
+    nws = ghn.ghn_predict_workspace_bytes(ix.handle, m, k, stop, ghn.GHN_PREC_FP32, flags)
+    ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dev)
+    st = ix.predict(qs, k, stop=stop, flags=flags, with_d2=False, with_stats=True)
     torch.cuda.synchronize()
     cands = int(st["cands"].sum().item())
     probes = int(st["probes"].sum().item())
     layers = st["stop_layer"].double()
     del st
 
-    def step():
-        ghn.ghn_predict(ix.handle, qs, k, out_idx, out_pred, None, stop)
+    # A step = spatial order of the batch (Morton sort) + the walk kernel.  Events
+    # between the two calls time the walk kernel alone, on the stream both run on.
+    order = torch.empty(m, dtype=torch.int32, device=dev)
+    ows = torch.empty(max(ghn.ghn_query_order_workspace_bytes(m), 1), dtype=torch.uint8, device=dev)
+
+    def step(ev_mid=None):
+        if args.no_sort:
+            if ev_mid is not None:
+                ev_mid.record()
+            ghn.ghn_predict(ix.handle, qs, k, out_idx, out_pred, None, stop, ghn.GHN_PREC_FP32, flags, ws=ws)
+        else:
+            ghn.ghn_query_order(ix.handle, qs, order, ows)
+            if ev_mid is not None:
+                ev_mid.record()
+            ghn.ghn_predict(ix.handle, qs, k, out_idx, out_pred, None, stop, ghn.GHN_PREC_FP32, flags, order=order)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    evm = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
-    evs[0].record()
     for i in range(args.steps):
-        step()
-        evs[i + 1].record()
+        ev0[i].record()
+        step(evm[i])
+        ev1[i].record()
     torch.cuda.synchronize()
-    per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
-    total_ms = evs[0].elapsed_time(evs[-1])
-    ms = total_ms / args.steps
+    per = np.array([ev0[i].elapsed_time(ev1[i]) for i in range(args.steps)])
+    walk = np.array([evm[i].elapsed_time(ev1[i]) for i in range(args.steps)])
+    ms = float(ev0[0].elapsed_time(ev1[-1])) / args.steps
+    walk_ms = float(walk.mean())
 
     f = prob.f
     alg_bytes = (m * 4 * f + cands * (4 * f + 4) + probes * 4 + m * k * 4 + m * k * 8 + m * 4)
-    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    achieved = alg_bytes / (walk_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload)
     line = {
         "metric": METRIC,
@@ -160,10 +180,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": describe(prob, args.stop.upper()), "n": prob.n, "f": f, "m": m, "k": k,
-                   "cell_width": prob.cell_width, "stop": args.stop, "form": "fp32_plain"},
+                   "cell_width": prob.cell_width, "stop": args.stop, "form": "fp32_plain",
+                   "query_order": "input" if args.no_sort else "morton"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "forms": {"fp32_plain_qps": m / (ms * 1e-3), "bf16_batched_qps": None},
+        "walk_kernel_ms": walk_ms,
         "step_ms_p10_p50_p90": [float(np.percentile(per, 10)), float(np.median(per)), float(np.percentile(per, 90))],
         "work": {"candidates_per_query": cands / m, "table_reads_per_query": probes / m,
                  "mean_stop_layer": float(layers.mean().item()), "algorithmic_bytes_per_step": alg_bytes},

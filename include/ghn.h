@@ -131,6 +131,9 @@ typedef struct {
     int32_t* out_stop_layer; /* optional, m int32: layer at which each walk stopped */
     int64_t* out_cands;      /* optional, m int64: candidate points scored per query */
     int64_t* out_probes;     /* optional, m int64: cell-table entries read per query */
+    const uint32_t* order;   /* optional, m uint32: order in which to walk the queries (a
+                                permutation of 0..m-1, e.g. from ghn_query_order); when set,
+                                no sort is done and no workspace is needed */
 } ghn_predict_opts;
 
 /* Bytes of device workspace ghn_predict needs for these arguments. */
@@ -144,8 +147,11 @@ size_t ghn_predict_workspace_bytes(const ghn_index* index, int64_t m, int32_t k,
  *   out_d2    m x k double, may be NULL: the FP64 distances d defined above
  *   out_pred  m int32 majority label (ties -> smallest label), or m float32
  *             mean (FP64 sum over the neighbours in order, / k, rounded to FP32)
- *   ws        device workspace of ghn_predict_workspace_bytes() bytes (may be
- *             NULL when that is 0)
+ *   ws        device workspace of at least ghn_predict_workspace_bytes() bytes,
+ *             256-byte aligned (may be NULL when that is 0).  Batches of 4096
+ *             queries or more are walked in a spatial order (a sort by the
+ *             Morton code of the central cell) unless GHN_FLAG_NO_SORT is set;
+ *             the sort needs the workspace.
  * Asynchronous on `stream`; allocates nothing.  m = 0 is a no-op.  A query
  * with a non-finite coordinate gets ids -1, distances NaN and prediction -1
  * (classification) or NaN (regression).
@@ -154,6 +160,19 @@ size_t ghn_predict_workspace_bytes(const ghn_index* index, int64_t m, int32_t k,
 ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, int32_t k,
                        const ghn_predict_opts* opts, int64_t* out_idx, double* out_d2, void* out_pred,
                        void* ws, size_t ws_bytes, void* stream);
+
+/* Spatial walk order of a query batch: the permutation of 0..m-1 that sorts
+ * the queries by the Morton code of their central cell (Eq. 1) clamped to the
+ * occupied box.  Neighbouring queries then share cells, which keeps the
+ * gathered cells in cache.  Only the order of work depends on it.
+ *   queries   m x f float32;  out_order  m uint32 (device)
+ *   ws        device workspace of ghn_query_order_workspace_bytes(m) bytes,
+ *             256-byte aligned
+ * Asynchronous on `stream`; allocates nothing.
+ * Errors: GHN_E_INVALID_ARG, GHN_E_WORKSPACE, GHN_E_HIP. */
+size_t ghn_query_order_workspace_bytes(int64_t m);
+ghn_status ghn_query_order(const ghn_index* index, const float* queries, int64_t m, uint32_t* out_order, void* ws,
+                           size_t ws_bytes, void* stream);
 
 /* Last error message of the calling thread ("" if none).  Valid until the
  * thread's next failing call. */

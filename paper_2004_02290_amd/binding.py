@@ -30,7 +30,7 @@ GHN_FLAG_NO_PRUNE, GHN_FLAG_NO_SORT = 1, 2
 GHN_K_MAX, GHN_F_MAX = 64, 32
 
 EXPORTED = ["ghn_build", "ghn_index_get_info", "ghn_destroy", "ghn_predict_workspace_bytes", "ghn_predict",
-            "ghn_last_error"]
+            "ghn_query_order_workspace_bytes", "ghn_query_order", "ghn_last_error"]
 
 
 class GHNError(RuntimeError):
@@ -52,7 +52,7 @@ class ghn_index_info(ctypes.Structure):
 class ghn_predict_opts(ctypes.Structure):
     _fields_ = [("stop", ctypes.c_int32), ("prec", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("out_stop_layer", ctypes.c_void_p), ("out_cands", ctypes.c_void_p),
-                ("out_probes", ctypes.c_void_p)]
+                ("out_probes", ctypes.c_void_p), ("order", ctypes.c_void_p)]
 
 
 def _load() -> ctypes.CDLL:
@@ -71,6 +71,10 @@ def _load() -> ctypes.CDLL:
     L.ghn_predict_workspace_bytes.restype = SZ
     L.ghn_predict.argtypes = [P, P, I64, I32, ctypes.POINTER(ghn_predict_opts), P, P, P, P, SZ, P]
     L.ghn_predict.restype = ctypes.c_int
+    L.ghn_query_order_workspace_bytes.argtypes = [I64]
+    L.ghn_query_order_workspace_bytes.restype = SZ
+    L.ghn_query_order.argtypes = [P, P, I64, P, P, SZ, P]
+    L.ghn_query_order.restype = ctypes.c_int
     L.ghn_last_error.argtypes = []
     L.ghn_last_error.restype = ctypes.c_char_p
     return L
@@ -145,9 +149,9 @@ def ghn_destroy(handle) -> None:
     _lib.ghn_destroy(handle)
 
 
-def _opts(stop, prec, flags, out_stop_layer=None, out_cands=None, out_probes=None) -> ghn_predict_opts:
+def _opts(stop, prec, flags, out_stop_layer=None, out_cands=None, out_probes=None, order=None) -> ghn_predict_opts:
     return ghn_predict_opts(int(stop), int(prec), int(flags), _ptr(out_stop_layer), _ptr(out_cands),
-                            _ptr(out_probes))
+                            _ptr(out_probes), _ptr(order))
 
 
 def ghn_predict_workspace_bytes(handle, m: int, k: int, stop=GHN_STOP_EXACT, prec=GHN_PREC_FP32, flags=0) -> int:
@@ -159,13 +163,24 @@ def ghn_predict(handle, queries: torch.Tensor, k: int, out_idx: torch.Tensor, ou
                 out_d2: Optional[torch.Tensor] = None, stop=GHN_STOP_EXACT, prec=GHN_PREC_FP32, flags=0,
                 out_stop_layer: Optional[torch.Tensor] = None, out_cands: Optional[torch.Tensor] = None,
                 out_probes: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
-                stream=None) -> None:
+                order: Optional[torch.Tensor] = None, stream=None) -> None:
     """ghn_predict into caller-provided outputs (int64 idx m x k, pred m, optional float64 d2 m x k)."""
     m = queries.shape[0]
-    o = _opts(stop, prec, flags, out_stop_layer, out_cands, out_probes)
+    o = _opts(stop, prec, flags, out_stop_layer, out_cands, out_probes, order)
     ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
     _check(_lib.ghn_predict(handle, _ptr(queries), m, k, ctypes.byref(o), _ptr(out_idx), _ptr(out_d2),
                             _ptr(out_pred), _ptr(ws), ws_bytes, _stream(stream)))
+
+
+def ghn_query_order_workspace_bytes(m: int) -> int:
+    return int(_lib.ghn_query_order_workspace_bytes(m))
+
+
+def ghn_query_order(handle, queries: torch.Tensor, out_order: torch.Tensor, ws: torch.Tensor, stream=None) -> None:
+    """ghn_query_order: spatial walk order (m uint32, passed as an int32 tensor) of a query batch."""
+    m = queries.shape[0]
+    ws_bytes = ws.numel() * ws.element_size()
+    _check(_lib.ghn_query_order(handle, _ptr(queries), m, _ptr(out_order), _ptr(ws), ws_bytes, _stream(stream)))
 
 
 class Index:

@@ -190,9 +190,61 @@ void ghn_destroy(ghn_index* index) {
     delete index;
 }
 
+namespace {
+// Workspace of the query sort: keys, values, their alternates, radix counts.
+size_t sort_ws_bytes(int64_t m) {
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    return 2 * up(m * 8) + 2 * up(m * 4) + up(ghn::radix_sort_temp_bytes(m));
+}
+bool wants_sort(int64_t m, uint32_t flags) { return m >= ghn::SORT_MIN_QUERIES && !(flags & GHN_FLAG_NO_SORT); }
+
+// Keys + radix sort in `ws` (sort_ws_bytes(m) bytes); *order points into ws.
+hipError_t sort_queries(const ghn_index* index, const float* queries, int64_t m, void* ws, uint32_t** order,
+                        hipStream_t s) {
+    using namespace ghn;
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    char* p = (char*)ws;
+    uint64_t* k0 = (uint64_t*)p; p += up(m * 8);
+    uint64_t* k1 = (uint64_t*)p; p += up(m * 8);
+    uint32_t* v0 = (uint32_t*)p; p += up(m * 4);
+    uint32_t* v1 = (uint32_t*)p; p += up(m * 4);
+    hipError_t e = launch_query_keys(queries, m, index->view, QUERY_KEY_BITS, k0, v0, s);
+    if (e != hipSuccess) return e;
+    bool alt = false;
+    e = radix_sort_pairs(k0, v0, k1, v1, m, QUERY_KEY_BITS, p, &alt, s);
+    *order = alt ? v1 : v0;
+    return e;
+}
+}  // namespace
+
 size_t ghn_predict_workspace_bytes(const ghn_index* index, int64_t m, int32_t k, const ghn_predict_opts* opts) {
-    (void)index; (void)m; (void)k; (void)opts;
-    return 0;
+    (void)index; (void)k;
+    const uint32_t flags = opts ? opts->flags : 0u;
+    if (opts && opts->order) return 0;
+    return wants_sort(m, flags) ? sort_ws_bytes(m) : 0;
+}
+
+size_t ghn_query_order_workspace_bytes(int64_t m) { return m > 0 ? sort_ws_bytes(m) : 0; }
+
+ghn_status ghn_query_order(const ghn_index* index, const float* queries, int64_t m, uint32_t* out_order, void* ws,
+                           size_t ws_bytes, void* stream) {
+    if (!index) return fail(GHN_E_INVALID_ARG, "ghn_query_order: index is NULL");
+    if (m < 0 || m >= (int64_t(1) << 32)) return fail(GHN_E_INVALID_ARG, "ghn_query_order: m=%lld outside [0, 2^32)", (long long)m);
+    if (m == 0) return GHN_OK;
+    if (!queries || !out_order) return fail(GHN_E_INVALID_ARG, "ghn_query_order: queries and out_order must not be NULL");
+    const size_t need = sort_ws_bytes(m);
+    if (!ws || ws_bytes < need)
+        return fail(GHN_E_WORKSPACE, "ghn_query_order: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
+    if ((uintptr_t)ws % 256 || (uintptr_t)queries % 4 || (uintptr_t)out_order % 4)
+        return fail(GHN_E_INVALID_ARG, "ghn_query_order: misaligned pointer");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "ghn_query_order: pending HIP error");
+    uint32_t* order = nullptr;
+    if ((e = sort_queries(index, queries, m, ws, &order, s)) != hipSuccess) return hip_fail(e, "ghn_query_order: sort");
+    if ((e = hipMemcpyAsync(out_order, order, (size_t)m * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+        return hip_fail(e, "ghn_query_order: copy");
+    return GHN_OK;
 }
 
 ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, int32_t k,
@@ -204,7 +256,7 @@ ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, 
     if (m < 0) return fail(GHN_E_INVALID_ARG, "ghn_predict: m=%lld < 0", (long long)m);
     if (k < 1 || k > K_MAX) return fail(GHN_E_INVALID_ARG, "ghn_predict: k=%d outside [1, %d]", k, K_MAX);
     if (k > index->info.n) return fail(GHN_E_K_GT_N, "ghn_predict: k=%d exceeds n=%lld", k, (long long)index->info.n);
-    ghn_predict_opts o = {GHN_STOP_EXACT, GHN_PREC_FP32, 0u, nullptr, nullptr, nullptr};
+    ghn_predict_opts o = {GHN_STOP_EXACT, GHN_PREC_FP32, 0u, nullptr, nullptr, nullptr, nullptr};
     if (opts) o = *opts;
     if (o.stop != GHN_STOP_EXACT && o.stop != GHN_STOP_PAPER) return fail(GHN_E_INVALID_ARG, "ghn_predict: bad stop rule %d", o.stop);
     if (o.prec != GHN_PREC_FP32 && o.prec != GHN_PREC_BF16_MFMA) return fail(GHN_E_INVALID_ARG, "ghn_predict: bad precision %d", o.prec);
@@ -229,8 +281,18 @@ ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, 
     pa.out_stop_layer = o.out_stop_layer;
     pa.out_cands = o.out_cands;
     pa.out_probes = o.out_probes;
-    pa.order = nullptr;
-    if ((e = launch_predict_dense(pa, (hipStream_t)stream)) != hipSuccess) return hip_fail(e, "ghn_predict: launch");
+    pa.order = o.order;
+    hipStream_t s = (hipStream_t)stream;
+    if (!o.order && wants_sort(m, o.flags)) {
+        const size_t need = sort_ws_bytes(m);
+        if (!ws || ws_bytes < need)
+            return fail(GHN_E_WORKSPACE, "ghn_predict: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
+        if ((uintptr_t)ws % 256) return fail(GHN_E_INVALID_ARG, "ghn_predict: workspace must be 256-byte aligned");
+        uint32_t* order = nullptr;
+        if ((e = sort_queries(index, queries, m, ws, &order, s)) != hipSuccess) return hip_fail(e, "ghn_predict: query sort");
+        pa.order = order;
+    }
+    if ((e = launch_predict_dense(pa, s)) != hipSuccess) return hip_fail(e, "ghn_predict: launch");
     return GHN_OK;
 }
 

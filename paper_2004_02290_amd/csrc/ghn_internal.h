@@ -73,12 +73,16 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
     return __longlong_as_double(int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo)));
 }
 
-// Value of `v` held by lane (lane - 1); lane 0 gets its own value.
-__device__ __forceinline__ int shfl_up1_i32(int v) { return __shfl_up(v, 1, WAVE); }
+// Value of `v` held by lane (lane - 1); lane 0 gets its own value.  DPP wave_shr:1
+// (a VALU lane shift across the whole wave64, no LDS round trip).
+constexpr int DPP_WAVE_SHR1 = 0x138;
+__device__ __forceinline__ int shfl_up1_i32(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, DPP_WAVE_SHR1, 0xf, 0xf, false);
+}
 __device__ __forceinline__ double shfl_up1_f64(double v) {
     int64_t b = __double_as_longlong(v);
-    int lo = __shfl_up(int(uint32_t(b)), 1, WAVE);
-    int hi = __shfl_up(int(uint32_t(uint64_t(b) >> 32)), 1, WAVE);
+    int lo = shfl_up1_i32(int(uint32_t(b)));
+    int hi = shfl_up1_i32(int(uint32_t(uint64_t(b) >> 32)));
     return __longlong_as_double(int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo)));
 }
 
@@ -129,5 +133,10 @@ struct PredictArgs {
     const uint32_t* order;  // optional processing order of the queries (NULL = 0..m-1)
 };
 hipError_t launch_predict_dense(const PredictArgs& a, hipStream_t s);
+// Spatial sort key of every query (Morton code of its box-clamped central cell).
+hipError_t launch_query_keys(const float* qs, int64_t m, const IndexView& ix, int keep_bits, uint64_t* keys,
+                             uint32_t* vals, hipStream_t s);
+constexpr int QUERY_KEY_BITS = 16;   // two 8-bit radix passes
+constexpr int64_t SORT_MIN_QUERIES = 4096;  // smaller batches run in input order
 
 }  // namespace ghn

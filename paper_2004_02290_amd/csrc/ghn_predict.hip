@@ -28,6 +28,7 @@ namespace {
 constexpr int PT = 256;                 // threads per block = 4 waves = 4 queries
 constexpr int WPB = PT / WAVE;
 constexpr int SEG_CAP = 2 * WAVE;       // runs per 64-row batch (interior rows give 2)
+constexpr int NUM_XCD = 8;
 constexpr double LB_SHRINK = 1.0 - 0x1p-40;   // lower bounds are shrunk by this before pruning
 constexpr double EXACT_SHRINK = 1.0 - 0x1p-44; // squared ring distance is shrunk by this (EXACT rule)
 
@@ -118,44 +119,65 @@ struct WaveState {
     int64_t probes; // cell-table entries read
 };
 
+// One 64-wide chunk of candidates, gathered ahead of its scoring.
 template <int FT>
-__device__ __forceinline__ void score_chunk(const IndexView& ix, const float* q, int f, int k, bool valid,
-                                            uint32_t pidx, WaveState& st) {
-    const int lane = lane_id();
+struct Chunk {
     float x[FT > 0 ? FT : F_MAX];
-    float d32 = __int_as_float(0x7f800000);
-    int id = 0;
+    int id;
+    bool valid;
+};
+
+template <int FT>
+__device__ __forceinline__ void fetch_chunk(const IndexView& ix, int f, bool valid, uint32_t pidx, Chunk<FT>& c) {
+    c.valid = valid;
+    c.id = 0;
     if (valid) {
-        load_point<FT>(ix.spts + (size_t)pidx * (FT > 0 ? FT : f), x, f);
-        id = ix.sid[pidx];
-        d32 = dist32<FT>(q, x, f);
+        load_point<FT>(ix.spts + (size_t)pidx * (FT > 0 ? FT : f), c.x, f);
+        c.id = ix.sid[pidx];
     }
-    uint64_t mask = ballot(valid && d32 <= st.t32);
+}
+
+// Screen a chunk in FP32; candidates that may enter the buffer get their FP64
+// distance and are inserted one at a time (exact (distance, id) comparison).
+template <int FT>
+__device__ __forceinline__ void score_chunk(const float* q, int f, int k, const Chunk<FT>& c, WaveState& st) {
+    const int lane = lane_id();
+    float d32 = __int_as_float(0x7f800000);
+    if (c.valid) d32 = dist32<FT>(q, c.x, f);
+    const bool adm = c.valid && d32 <= st.t32;
+    uint64_t mask = ballot(adm);
     if (mask == 0) return;
     double d64 = 0.0;
-    if (valid && d32 <= st.t32) d64 = dist64<FT>(q, x, f);
+    if (adm) d64 = dist64<FT>(q, c.x, f);
     while (mask) {
         const int src = __ffsll((unsigned long long)mask) - 1;
         mask &= mask - 1;
         const double cd = readlane_f64(d64, src);
-        const int ci = readlane_i32(id, src);
+        const int ci = readlane_i32(c.id, src);
         if (!(cd < st.tau || (cd == st.tau && ci < st.tau_i))) continue;
+        // The new k-th entry is the old (k-1)-th unless the candidate lands last.
+        double kd = cd;
+        int ki = ci;
+        if (k > 1) { kd = readlane_f64(st.bd, k - 2); ki = readlane_i32(st.bi, k - 2); }
         // Insert (cd, ci): slots holding a larger entry shift up by one lane.
-        const bool gt = lane < k && (st.bd > cd || (st.bd == cd && st.bi > ci));
+        const uint64_t cb = (uint64_t)__double_as_longlong(cd);
+        const uint64_t bb = (uint64_t)__double_as_longlong(st.bd);
+        const bool gt = lane < k && (bb > cb || (bb == cb && st.bi > ci));
         const int pos = k - __popcll(ballot(gt));
         const double ud = shfl_up1_f64(st.bd);
         const int ui = shfl_up1_i32(st.bi);
-        if (lane < k) {
-            if (lane == pos) { st.bd = cd; st.bi = ci; }
-            else if (lane > pos) { st.bd = ud; st.bi = ui; }
+        if (gt) {
+            st.bd = lane == pos ? cd : ud;
+            st.bi = lane == pos ? ci : ui;
         }
-        st.count = st.count < k ? st.count + 1 : k;
         st.updated = true;
+        if (st.count < k) st.count += 1;
         if (st.count == k) {
-            st.tau = readlane_f64(st.bd, k - 1);
-            st.tau_i = readlane_i32(st.bi, k - 1);
+            const bool last = pos == k - 1;
+            st.tau = last ? cd : kd;
+            st.tau_i = last ? ci : ki;
             st.t32 = admit_threshold(st.tau);
-            mask &= ballot(valid && d32 <= st.t32);
+            mask &= ballot(c.valid && d32 <= st.t32);
         }
     }
 }
@@ -167,7 +189,14 @@ __global__ __launch_bounds__(PT) void k_predict_dense(PredictArgs A) {
     const IndexView& ix = A.ix;
     const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    const int64_t slot = (int64_t)blockIdx.x * WPB + wv;
+    // With a spatial query order, give each XCD (blocks are dealt round-robin over the
+    // 8 XCDs) one contiguous range of blocks, so each XCD's L2 serves one region.
+    int64_t blk = blockIdx.x;
+    if (A.order) {
+        const int64_t nb = gridDim.x, x = blk % NUM_XCD, t = blk / NUM_XCD;
+        blk = x * (nb / NUM_XCD) + min(x, nb % NUM_XCD) + t;
+    }
+    const int64_t slot = blk * WPB + wv;
     if (slot >= A.m) return;
     const int64_t qi = A.order ? (int64_t)A.order[slot] : slot;
     const int f = FT > 0 ? FT : ix.f;
@@ -242,11 +271,24 @@ __global__ __launch_bounds__(PT) void k_predict_dense(PredictArgs A) {
                 uint32_t b0 = 0, n0 = 0, b1 = 0, n1 = 0, probes_l = 0;
                 if (r < rows) {
                     // decode row r: offsets of dimensions 0..L-1, last of them fastest
-                    int64_t rem = r, maxoff = 0, lin = 0;
+                    int64_t maxoff = 0, lin = 0;
                     double lb = 0.0;
-                    for (int j = L - 1; j >= 0; --j) {
-                        const int64_t oj = lo[j] + rem % w[j];
-                        rem /= w[j];
+                    uint64_t rem64 = (uint64_t)r;
+                    uint32_t rem32 = (uint32_t)r;
+                    const bool small = rows < (int64_t(1) << 32);
+#pragma unroll
+                    for (int j = (FT > 0 ? FT - 2 : F_MAX - 2); j >= 0; --j) {
+                        if (FT == 0 && j > L - 1) continue;
+                        int64_t digit;
+                        if (small) {
+                            const uint32_t wj = (uint32_t)w[j];
+                            digit = rem32 % wj;
+                            rem32 /= wj;
+                        } else {
+                            digit = (int64_t)(rem64 % (uint64_t)w[j]);
+                            rem64 /= (uint64_t)w[j];
+                        }
+                        const int64_t oj = lo[j] + digit;
                         maxoff = max(maxoff, oj > c[j] ? oj - c[j] : c[j] - oj);
                         lin += (oj - ix.cmin[j]) * ix.stride[j];
                         const double g = gap_to_cell(v[j], oj, (double)ix.a[j]);
@@ -307,22 +349,22 @@ __global__ __launch_bounds__(PT) void k_predict_dense(PredictArgs A) {
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // Position p of the batch -> point index (last run whose prefix is <= p).
+                auto locate = [&](uint32_t p) -> uint32_t {
+                    uint32_t a0 = 0, a1 = nseg;
+                    while (a1 - a0 > 1) {
+                        const uint32_t mid = (a0 + a1) >> 1;
+                        if (s_pre[wv][mid] <= p) a0 = mid;
+                        else a1 = mid;
+                    }
+                    return s_begin[wv][a0] + (p - s_pre[wv][a0]);
+                };
                 for (uint32_t base = 0; base < npts; base += WAVE) {
                     const uint32_t p = base + lane;
-                    const bool valid = p < npts;
-                    uint32_t pidx = 0;
-                    if (valid) {
-                        // last run whose prefix is <= p
-                        uint32_t a0 = 0, a1 = nseg;
-                        while (a1 - a0 > 1) {
-                            const uint32_t mid = (a0 + a1) >> 1;
-                            if (s_pre[wv][mid] <= p) a0 = mid;
-                            else a1 = mid;
-                        }
-                        pidx = s_begin[wv][a0] + (p - s_pre[wv][a0]);
-                    }
-                    st.cands += __popcll(ballot(valid));
-                    score_chunk<FT>(ix, q, f, k, valid, pidx, st);
+                    Chunk<FT> cur;
+                    fetch_chunk<FT>(ix, f, p < npts, p < npts ? locate(p) : 0u, cur);
+                    st.cands += __popcll(ballot(cur.valid));
+                    score_chunk<FT>(q, f, k, cur, st);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -384,6 +426,39 @@ __global__ __launch_bounds__(PT) void k_predict_dense(PredictArgs A) {
     }
 }
 
+// Sort key of a query: Morton interleave of its central cell id clamped to the
+// occupied box, keeping the `keep_bits` most significant bits.  Only the order of
+// processing depends on it; every query's result is independent of the order.
+__global__ __launch_bounds__(256) void k_query_keys(const float* __restrict__ qs, int64_t m, IndexView ix,
+                                                    int keep_bits, uint64_t* __restrict__ keys,
+                                                    uint32_t* __restrict__ vals) {
+    const int f = ix.f;
+    int bits[F_MAX];
+    int total = 0, maxb = 0;
+    for (int j = 0; j < f; ++j) {
+        const uint32_t span = (uint32_t)(ix.cmax[j] - ix.cmin[j]);
+        bits[j] = span ? 32 - __clz(span) : 0;
+        total += bits[j];
+        maxb = max(maxb, bits[j]);
+    }
+    const int drop = total > keep_bits ? total - keep_bits : 0;
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
+        uint64_t code = 0;
+        uint32_t u[F_MAX];
+        for (int j = 0; j < f; ++j) {
+            const float x = qs[i * f + j];
+            int64_t c = isfinite(x) ? exact_floor_div(__dadd_rn((double)x, -(double)ix.o[j]), (double)ix.a[j]) : 0;
+            c = min(max(c, (int64_t)ix.cmin[j]), (int64_t)ix.cmax[j]);
+            u[j] = (uint32_t)(c - ix.cmin[j]);
+        }
+        for (int b = maxb - 1; b >= 0; --b)
+            for (int j = 0; j < f; ++j)
+                if (b < bits[j]) code = (code << 1) | ((u[j] >> b) & 1u);
+        keys[i] = code >> drop;
+        vals[i] = (uint32_t)i;
+    }
+}
+
 template <int FT>
 hipError_t launch_ft(const PredictArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)((a.m + WPB - 1) / WPB)), block(PT);
@@ -395,6 +470,14 @@ hipError_t launch_ft(const PredictArgs& a, hipStream_t s) {
 }
 
 }  // namespace
+
+hipError_t launch_query_keys(const float* qs, int64_t m, const IndexView& ix, int keep_bits, uint64_t* keys,
+                             uint32_t* vals, hipStream_t s) {
+    int64_t g = (m + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_query_keys, dim3((unsigned)g), dim3(256), 0, s, qs, m, ix, keep_bits, keys, vals);
+    return hipGetLastError();
+}
 
 hipError_t launch_predict_dense(const PredictArgs& a, hipStream_t s) {
     switch (a.ix.f) {

@@ -72,10 +72,10 @@ WORKLOADS: Dict[str, dict] = {
                        centers=10, sigma=0.05, width=0.023601368),
     # 5 tight clusters + 10% uniform background in 8-D, regression target.
     "skew8d": dict(f=8, n=10_000_000, m=1_000_000, k=16, task=REGRESS, seed=3,
-                   centers=5, sigma=0.02, width=0.03125),
+                   centers=5, sigma=0.02, width=0.031533688),
     # 32 clusters in 16-D, points stored as bf16, 32 classes.
     "bf16_16d": dict(f=16, n=4_000_000, m=500_000, k=32, task=CLASSIFY, seed=4,
-                     centers=32, sigma=0.03, width=0.125),
+                     centers=32, sigma=0.03, width=0.11001434),
 }
 
 # Many independent uniform 3-D problems of log-uniform size.

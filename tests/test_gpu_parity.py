@@ -119,6 +119,40 @@ def test_no_prune_same_result(ghn):
         assert (b["cands"] >= a["cands"]).all()
 
 
+def test_query_sort_same_result_and_workspace(ghn):
+    import torch
+    prob = W.make("clusters4d", n=50_000, m=9_000)
+    ix = _index(ghn, prob)
+    for stop in (ghn.GHN_STOP_EXACT, ghn.GHN_STOP_PAPER):
+        a = _run(ghn, ix, prob.queries, prob.k, stop)
+        b = _run(ghn, ix, prob.queries, prob.k, stop, flags=ghn.GHN_FLAG_NO_SORT)
+        _assert_same(a, b, "sorted vs input order", check_layers=True)
+        assert np.array_equal(a["cands"], b["cands"])
+    assert ghn.ghn_predict_workspace_bytes(ix.handle, prob.m, prob.k) > 0
+    assert ghn.ghn_predict_workspace_bytes(ix.handle, prob.m, prob.k, flags=ghn.GHN_FLAG_NO_SORT) == 0
+    q = _dev(prob.queries)
+    idx = torch.empty((prob.m, prob.k), dtype=torch.int64, device="cuda")
+    pred = torch.empty(prob.m, dtype=torch.int32, device="cuda")
+    with pytest.raises(ghn.GHNError) as e:
+        ghn.ghn_predict(ix.handle, q, prob.k, idx, pred)
+    assert e.value.code == -6
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ghn.GHNError) as e:
+        ghn.ghn_predict(ix.handle, q, prob.k, idx, pred, ws=small)
+    assert e.value.code == -6
+    # an explicit order from ghn_query_order: a permutation, same results, no workspace
+    order = torch.empty(prob.m, dtype=torch.int32, device="cuda")
+    ows = torch.empty(ghn.ghn_query_order_workspace_bytes(prob.m), dtype=torch.uint8, device="cuda")
+    ghn.ghn_query_order(ix.handle, q, order, ows)
+    torch.cuda.synchronize()
+    assert np.array_equal(np.sort(order.cpu().numpy()), np.arange(prob.m))
+    d2 = torch.empty((prob.m, prob.k), dtype=torch.float64, device="cuda")
+    ghn.ghn_predict(ix.handle, q, prob.k, idx, pred, d2, order=order)
+    torch.cuda.synchronize()
+    want = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_EXACT)
+    assert np.array_equal(idx.cpu().numpy(), want["idx"]) and np.array_equal(d2.cpu().numpy(), want["d2"])
+
+
 def test_deterministic(ghn):
     prob = W.make("clusters4d", n=30_000, m=800)
     ix = _index(ghn, prob)
