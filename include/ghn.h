@@ -90,7 +90,7 @@ typedef struct {
     int32_t f;               /* features */
     int32_t dtype;           /* ghn_dtype */
     int32_t task;            /* ghn_task */
-    int32_t lookup;          /* 0 = dense table over the occupied box of cells, 1 = hash table */
+    int32_t lookup;          /* GHN_LOOKUP_DENSE or GHN_LOOKUP_TREE */
     int64_t num_cells;       /* non-empty cells (never more than n, Section III-C) */
     int64_t box_cells;       /* cells in the bounding box of the occupied cells */
     int64_t max_occupancy;   /* points in the fullest cell */
@@ -117,6 +117,31 @@ typedef struct {
 ghn_status ghn_build(const void* points, int64_t n, int32_t f, int32_t dtype, const void* targets,
                      int32_t task, const float* cell_width, int32_t n_width, const float* origin,
                      void* stream, ghn_index** out);
+
+/* Cell lookup structures (ghn_build_opts.lookup, ghn_index_info.lookup).
+ * GHN_LOOKUP_DENSE: an offset table over every cell of the bounding box of the
+ *   occupied cells, points in row-major cell order; a run of cells along the
+ *   last dimension is one run of points.  For low dimensions.
+ * GHN_LOOKUP_TREE: only the occupied cells, in Morton order, under a 64-ary
+ *   tree of bounding boxes; for many dimensions, where the box (and the number
+ *   of cells per layer, Eq. 2) grows exponentially.
+ * GHN_LOOKUP_AUTO: dense when the box holds at most max(16 n, 2^24) cells,
+ *   otherwise the tree. */
+#define GHN_LOOKUP_AUTO (-1)
+#define GHN_LOOKUP_DENSE 0
+#define GHN_LOOKUP_TREE 1
+
+typedef struct {
+    int32_t lookup; /* GHN_LOOKUP_* */
+} ghn_build_opts;
+
+/* ghn_build with options (HOST, may be NULL = GHN_LOOKUP_AUTO).  A dense table
+ * larger than the limit above is refused with GHN_E_UNSUPPORTED; the tree needs
+ * the Morton code of the cell ids (sum over dimensions of the bits of each
+ * dimension's id range) to fit 64 bits, else GHN_E_KEY_OVERFLOW. */
+ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype, const void* targets,
+                        int32_t task, const float* cell_width, int32_t n_width, const float* origin,
+                        const ghn_build_opts* opts, void* stream, ghn_index** out);
 
 /* Describe a built index.  `out` is HOST memory. */
 ghn_status ghn_index_get_info(const ghn_index* index, ghn_index_info* out);

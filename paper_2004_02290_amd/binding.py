@@ -29,7 +29,9 @@ GHN_PREC_FP32, GHN_PREC_BF16_MFMA = 0, 1
 GHN_FLAG_NO_PRUNE, GHN_FLAG_NO_SORT = 1, 2
 GHN_K_MAX, GHN_F_MAX = 64, 32
 
-EXPORTED = ["ghn_build", "ghn_index_get_info", "ghn_destroy", "ghn_predict_workspace_bytes", "ghn_predict",
+GHN_LOOKUP_AUTO, GHN_LOOKUP_DENSE, GHN_LOOKUP_TREE = -1, 0, 1
+
+EXPORTED = ["ghn_build", "ghn_build_ex", "ghn_index_get_info", "ghn_destroy", "ghn_predict_workspace_bytes", "ghn_predict",
             "ghn_query_order_workspace_bytes", "ghn_query_order", "ghn_last_error"]
 
 
@@ -63,6 +65,8 @@ def _load() -> ctypes.CDLL:
     P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     L.ghn_build.argtypes = [P, I64, I32, I32, P, I32, P, I32, P, P, ctypes.POINTER(P)]
     L.ghn_build.restype = ctypes.c_int
+    L.ghn_build_ex.argtypes = [P, I64, I32, I32, P, I32, P, I32, P, P, P, ctypes.POINTER(P)]
+    L.ghn_build_ex.restype = ctypes.c_int
     L.ghn_index_get_info.argtypes = [P, ctypes.POINTER(ghn_index_info)]
     L.ghn_index_get_info.restype = ctypes.c_int
     L.ghn_destroy.argtypes = [P]
@@ -111,10 +115,21 @@ def _stream(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(s.cuda_stream)
 
 
+class ghn_build_opts(ctypes.Structure):
+    _fields_ = [("lookup", ctypes.c_int32)]
+
+
 def ghn_build(points: torch.Tensor, targets: torch.Tensor, task: int,
               cell_width: Union[float, Sequence[float]], origin: Optional[Sequence[float]] = None,
               stream=None) -> ctypes.c_void_p:
     """ghn_build: points n x f (float32, or bfloat16 -> stored as bf16), targets n (int32 | float32)."""
+    return ghn_build_ex(points, targets, task, cell_width, origin, None, stream)
+
+
+def ghn_build_ex(points: torch.Tensor, targets: torch.Tensor, task: int,
+                 cell_width: Union[float, Sequence[float]], origin: Optional[Sequence[float]] = None,
+                 lookup: Optional[int] = None, stream=None) -> ctypes.c_void_p:
+    """ghn_build_ex: as ghn_build, with the cell lookup structure chosen (GHN_LOOKUP_*)."""
     if points.dim() != 2:
         raise ValueError("points must be n x f")
     n, f = points.shape
@@ -134,8 +149,9 @@ def ghn_build(points: torch.Tensor, targets: torch.Tensor, task: int,
         for i, x in enumerate(origin):
             o[i] = float(x)
     h = ctypes.c_void_p()
-    _check(_lib.ghn_build(_ptr(points), n, f, dtype, _ptr(targets), task, w, len(ws), o, _stream(stream),
-                          ctypes.byref(h)))
+    opts = None if lookup is None else ctypes.byref(ghn_build_opts(int(lookup)))
+    _check(_lib.ghn_build_ex(_ptr(points), n, f, dtype, _ptr(targets), task, w, len(ws), o, opts, _stream(stream),
+                             ctypes.byref(h)))
     return h
 
 
@@ -187,9 +203,9 @@ class Index:
     """Owner of a built index (build on construction, free on close / garbage collection)."""
 
     def __init__(self, points: torch.Tensor, targets: torch.Tensor, task: int,
-                 cell_width: Union[float, Sequence[float]], origin=None, stream=None):
+                 cell_width: Union[float, Sequence[float]], origin=None, lookup: Optional[int] = None, stream=None):
         self.task = task
-        self.handle = ghn_build(points, targets, task, cell_width, origin, stream)
+        self.handle = ghn_build_ex(points, targets, task, cell_width, origin, lookup, stream)
         self.info = ghn_index_get_info(self.handle)
 
     def predict(self, queries: torch.Tensor, k: int, stop=GHN_STOP_EXACT, prec=GHN_PREC_FP32, flags=0,

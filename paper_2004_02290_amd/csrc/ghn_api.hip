@@ -67,6 +67,12 @@ const char* ghn_last_error(void) { return g_err.c_str(); }
 ghn_status ghn_build(const void* points, int64_t n, int32_t f, int32_t dtype, const void* targets, int32_t task,
                      const float* cell_width, int32_t n_width, const float* origin, void* stream,
                      ghn_index** out) {
+    return ghn_build_ex(points, n, f, dtype, targets, task, cell_width, n_width, origin, nullptr, stream, out);
+}
+
+ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype, const void* targets, int32_t task,
+                        const float* cell_width, int32_t n_width, const float* origin, const ghn_build_opts* bopts,
+                        void* stream, ghn_index** out) {
     using namespace ghn;
     if (!out) return fail(GHN_E_INVALID_ARG, "ghn_build: out is NULL");
     *out = nullptr;
@@ -79,6 +85,9 @@ ghn_status ghn_build(const void* points, int64_t n, int32_t f, int32_t dtype, co
         return fail(GHN_E_INVALID_ARG, "ghn_build: cell_width must hold 1 or f values (n_width=%d)", n_width);
     if (((uintptr_t)points % (dtype == GHN_BF16 ? 2 : 4)) || ((uintptr_t)targets % 4))
         return fail(GHN_E_INVALID_ARG, "ghn_build: misaligned points or targets");
+    const int32_t want_lookup = bopts ? bopts->lookup : GHN_LOOKUP_AUTO;
+    if (want_lookup != GHN_LOOKUP_AUTO && want_lookup != GHN_LOOKUP_DENSE && want_lookup != GHN_LOOKUP_TREE)
+        return fail(GHN_E_INVALID_ARG, "ghn_build: bad lookup %d", want_lookup);
     float a[F_MAX], o[F_MAX];
     for (int j = 0; j < f; ++j) {
         a[j] = cell_width[n_width == 1 ? 0 : j];
@@ -125,14 +134,28 @@ ghn_status ghn_build(const void* points, int64_t n, int32_t f, int32_t dtype, co
         if (box > (int64_t(1) << 40) / wj) too_big = true;
         else box *= wj;
     }
-    if (too_big || box > dense_limit(n))
-        return fail(GHN_E_UNSUPPORTED, "ghn_build: the occupied box holds more than %lld cells; this build only has the "
-                    "dense cell table (use a larger cell width or fewer dimensions)", (long long)dense_limit(n));
-    iv.box_cells = box;
+    const bool dense_ok = !too_big && box <= dense_limit(n);
+    const int32_t lookup = want_lookup == GHN_LOOKUP_AUTO ? (dense_ok ? GHN_LOOKUP_DENSE : GHN_LOOKUP_TREE) : want_lookup;
+    if (lookup == GHN_LOOKUP_DENSE && !dense_ok)
+        return fail(GHN_E_UNSUPPORTED, "ghn_build: the occupied box holds more than %lld cells, too many for the dense "
+                    "table (use the tree lookup or a larger cell width)", (long long)dense_limit(n));
+    iv.lookup = lookup;
     int nbits = 0;
-    while (nbits < 64 && (uint64_t(1) << nbits) < (uint64_t)box) ++nbits;
+    if (lookup == GHN_LOOKUP_DENSE) {
+        iv.box_cells = box;
+        while (nbits < 64 && (uint64_t(1) << nbits) < (uint64_t)box) ++nbits;
+    } else {
+        iv.box_cells = too_big ? -1 : box;
+        for (int j = 0; j < f; ++j) {
+            const uint32_t span = (uint32_t)(iv.cmax[j] - iv.cmin[j]);
+            nbits += span ? 32 - __builtin_clz(span) : 0;
+        }
+        if (nbits > 64)
+            return fail(GHN_E_KEY_OVERFLOW, "ghn_build: the Morton code of the cell ids needs %d bits (> 64); use a "
+                        "larger cell width", nbits);
+    }
 
-    // 3. keys, sort, gather, table
+    // 3. keys, sort, gather
     uint64_t *keys, *keys2;
     uint32_t *vals, *vals2;
     void* rtemp;
@@ -141,30 +164,94 @@ ghn_status ghn_build(const void* points, int64_t n, int32_t f, int32_t dtype, co
         return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the sort");
     float* spts;
     int32_t* sid;
-    uint32_t* cs;
     void* tg;
     if (keep.alloc((void**)&spts, (size_t)n * f * 4) || keep.alloc((void**)&sid, (size_t)n * 4) ||
-        keep.alloc((void**)&cs, (size_t)(box + 1) * 4) || keep.alloc(&tg, (size_t)n * 4))
+        keep.alloc(&tg, (size_t)n * 4))
         return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the index");
-    if ((e = launch_dense_keys(points, n, f, dtype, iv, keys, vals, s)) != hipSuccess) return hip_fail(e, "ghn_build: keys");
+    e = lookup == GHN_LOOKUP_DENSE ? launch_dense_keys(points, n, f, dtype, iv, keys, vals, s)
+                                   : launch_morton_keys(points, n, dtype, iv, keys, vals, s);
+    if (e != hipSuccess) return hip_fail(e, "ghn_build: keys");
     bool in_alt = false;
     if ((e = radix_sort_pairs(keys, vals, keys2, vals2, n, nbits, rtemp, &in_alt, s)) != hipSuccess)
         return hip_fail(e, "ghn_build: radix sort");
     const uint64_t* skeys = in_alt ? keys2 : keys;
     const uint32_t* perm = in_alt ? vals2 : vals;
     if ((e = launch_gather_points(points, n, f, dtype, perm, spts, sid, s)) != hipSuccess) return hip_fail(e, "ghn_build: gather");
-    if ((e = launch_dense_cell_start(skeys, n, box, cs, d_small->stats, s)) != hipSuccess) return hip_fail(e, "ghn_build: table");
     if ((e = hipMemcpyAsync(tg, targets, (size_t)n * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(e, "ghn_build: targets");
+    iv.spts = spts; iv.sid = sid; iv.targets = tg;
+    size_t table_bytes = 0;
+
+    // 4. cell table
+    if (lookup == GHN_LOOKUP_DENSE) {
+        uint32_t* cs;
+        if (keep.alloc((void**)&cs, (size_t)(box + 1) * 4)) return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the table");
+        if ((e = launch_dense_cell_start(skeys, n, box, cs, d_small->stats, s)) != hipSuccess) return hip_fail(e, "ghn_build: table");
+        iv.cell_start = cs;
+        table_bytes = (size_t)(box + 1) * 4;
+    } else {
+        // occupied cells: heads of equal-key runs, their ranks, first points and ids
+        uint32_t *heads, *rank;
+        void* stemp;
+        if (tmp.alloc((void**)&heads, n * 4) || tmp.alloc((void**)&rank, n * 4) ||
+            tmp.alloc(&stemp, exclusive_scan_temp_bytes(n)))
+            return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the cell list");
+        if ((e = launch_cell_heads(skeys, n, heads, s)) != hipSuccess) return hip_fail(e, "ghn_build: heads");
+        if ((e = exclusive_scan_u32(heads, rank, n, stemp, s)) != hipSuccess) return hip_fail(e, "ghn_build: scan");
+        uint32_t last[2] = {0, 0};
+        if ((e = hipMemcpyAsync(&last[0], rank + n - 1, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(&last[1], heads + n - 1, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return hip_fail(e, "ghn_build: cell count");
+        const int64_t ncell = (int64_t)last[0] + last[1];
+        uint32_t* cs;
+        int32_t* coord;
+        if (keep.alloc((void**)&cs, (size_t)(ncell + 1) * 4) || keep.alloc((void**)&coord, (size_t)ncell * f * 4))
+            return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the cell list");
+        if ((e = launch_cell_list(heads, rank, n, iv, cs, coord, s)) != hipSuccess) return hip_fail(e, "ghn_build: cell list");
+        const uint32_t n32 = (uint32_t)n;
+        if ((e = hipMemcpyAsync(cs + ncell, &n32, 4, hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e, "ghn_build: cell end");
+        // bounding-box levels above the cells
+        int64_t count[TREE_LEVELS_MAX] = {0};
+        int64_t off[TREE_LEVELS_MAX] = {0};
+        count[0] = ncell;
+        int top = 0;
+        int64_t total = 0;
+        while (count[top] > WAVE) {
+            if (top + 1 >= TREE_LEVELS_MAX) return fail(GHN_E_UNSUPPORTED, "ghn_build: too many cells for the tree");
+            count[top + 1] = (count[top] + WAVE - 1) / WAVE;
+            off[top + 1] = total;
+            total += count[top + 1];
+            ++top;
+        }
+        int32_t *nlo = nullptr, *nhi = nullptr;
+        if (total > 0 && (keep.alloc((void**)&nlo, (size_t)total * f * 4) || keep.alloc((void**)&nhi, (size_t)total * f * 4)))
+            return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the tree");
+        for (int L = 1; L <= top; ++L) {
+            const int32_t* clo = L == 1 ? coord : nlo + off[L - 1] * f;
+            const int32_t* chi = L == 1 ? coord : nhi + off[L - 1] * f;
+            if ((e = launch_tree_level(clo, chi, count[L - 1], f, nlo + off[L] * f, nhi + off[L] * f, count[L], s)) != hipSuccess)
+                return hip_fail(e, "ghn_build: tree level");
+        }
+        if ((e = launch_cell_stats(cs, ncell, d_small->stats, s)) != hipSuccess) return hip_fail(e, "ghn_build: stats");
+        iv.cell_start = cs;
+        iv.num_cells = ncell;
+        iv.cell_coord = coord;
+        iv.tree_levels = top;
+        for (int L = 0; L < TREE_LEVELS_MAX; ++L) { iv.tree_count[L] = count[L]; iv.tree_off[L] = off[L]; }
+        iv.node_lo = nlo;
+        iv.node_hi = nhi;
+        table_bytes = (size_t)(ncell + 1) * 4 + (size_t)ncell * f * 4 + (size_t)total * f * 8;
+    }
     if ((e = hipMemcpyAsync(&h, d_small, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess) return hip_fail(e, "ghn_build: readback");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "ghn_build: sync");
+    if (lookup == GHN_LOOKUP_DENSE) iv.num_cells = h.stats[0];
 
-    iv.spts = spts; iv.sid = sid; iv.cell_start = cs; iv.targets = tg;
     ghn_index* ix = new ghn_index();
     ix->view = iv;
     std::memset(&ix->info, 0, sizeof ix->info);
-    ix->info.n = n; ix->info.f = f; ix->info.dtype = dtype; ix->info.task = task; ix->info.lookup = LOOKUP_DENSE;
-    ix->info.num_cells = h.stats[0];
-    ix->info.box_cells = box;
+    ix->info.n = n; ix->info.f = f; ix->info.dtype = dtype; ix->info.task = task; ix->info.lookup = lookup;
+    ix->info.num_cells = iv.num_cells;
+    ix->info.box_cells = iv.box_cells;
     ix->info.max_occupancy = h.stats[1];
     for (int j = 0; j < f; ++j) {
         ix->info.cell_min[j] = iv.cmin[j];
@@ -172,7 +259,7 @@ ghn_status ghn_build(const void* points, int64_t n, int32_t f, int32_t dtype, co
         ix->info.cell_width[j] = a[j];
         ix->info.origin[j] = o[j];
     }
-    ix->info.device_bytes = (size_t)n * f * 4 + (size_t)n * 4 + (size_t)(box + 1) * 4 + (size_t)n * 4;
+    ix->info.device_bytes = (size_t)n * f * 4 + (size_t)n * 4 + (size_t)n * 4 + table_bytes;
     keep.release(ix->allocs);
     *out = ix;
     return GHN_OK;
@@ -292,7 +379,8 @@ ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, 
         if ((e = sort_queries(index, queries, m, ws, &order, s)) != hipSuccess) return hip_fail(e, "ghn_predict: query sort");
         pa.order = order;
     }
-    if ((e = launch_predict_dense(pa, s)) != hipSuccess) return hip_fail(e, "ghn_predict: launch");
+    e = index->view.lookup == LOOKUP_DENSE ? launch_predict_dense(pa, s) : launch_predict_tree(pa, s);
+    if (e != hipSuccess) return hip_fail(e, "ghn_predict: launch");
     return GHN_OK;
 }
 

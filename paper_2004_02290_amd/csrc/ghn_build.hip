@@ -167,6 +167,55 @@ __global__ __launch_bounds__(RS_T) void k_radix_scatter(const uint64_t* __restri
     }
 }
 
+// Multi-block exclusive scan: per-tile sums, one scan of the sums, per-tile scan.
+constexpr int SC_ITEMS = 16;
+constexpr int SC_TILE = BT * SC_ITEMS;
+
+__global__ __launch_bounds__(BT) void k_tile_sums(const uint32_t* __restrict__ in, int64_t n, uint32_t* sums) {
+    __shared__ uint32_t red[BT / WAVE];
+    const int64_t base = (int64_t)blockIdx.x * SC_TILE;
+    uint32_t s = 0;
+    for (int it = 0; it < SC_ITEMS; ++it) {
+        const int64_t i = base + it * BT + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    s = wave_sum_u32(s);
+    if (lane_id() == 0) red[threadIdx.x / WAVE] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < BT / WAVE; ++w) t += red[w];
+        sums[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(BT) void k_tile_scan(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                  int64_t n, const uint32_t* __restrict__ offs) {
+    __shared__ uint32_t part[BT];
+    const int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
+    uint32_t v[SC_ITEMS];
+    uint32_t s = 0;
+    for (int it = 0; it < SC_ITEMS; ++it) {
+        const int64_t i = base + it;
+        v[it] = i < n ? in[i] : 0u;
+        s += v[it];
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int d = 1; d < BT; d <<= 1) {
+        const uint32_t t = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += t;
+        __syncthreads();
+    }
+    uint32_t run = offs[blockIdx.x] + part[threadIdx.x] - s;
+    for (int it = 0; it < SC_ITEMS; ++it) {
+        const int64_t i = base + it;
+        if (i < n) out[i] = run;
+        run += v[it];
+    }
+}
+
 __global__ __launch_bounds__(BT) void k_gather_points(const void* pts, int64_t n, int32_t f, int32_t dtype,
                                                       const uint32_t* __restrict__ perm, float* __restrict__ spts,
                                                       int32_t* __restrict__ sid) {
@@ -259,6 +308,19 @@ hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, 
     return hipSuccess;
 }
 
+size_t exclusive_scan_temp_bytes(int64_t n) {
+    return (size_t)((n + SC_TILE - 1) / SC_TILE + 1) * sizeof(uint32_t);
+}
+
+hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* temp, hipStream_t s) {
+    const int nb = (int)((n + SC_TILE - 1) / SC_TILE);
+    uint32_t* sums = (uint32_t*)temp;
+    hipLaunchKernelGGL(k_tile_sums, dim3(nb), dim3(BT), 0, s, in, n, sums);
+    hipLaunchKernelGGL(k_exclusive_scan_u32, dim3(1), dim3(SCAN_T), 0, s, sums, (int64_t)nb);
+    hipLaunchKernelGGL(k_tile_scan, dim3(nb), dim3(BT), 0, s, in, out, n, sums);
+    return hipGetLastError();
+}
+
 hipError_t launch_gather_points(const void* pts, int64_t n, int32_t f, int32_t dtype, const uint32_t* perm,
                                 float* spts, int32_t* sid, hipStream_t s) {
     hipLaunchKernelGGL(k_gather_points, dim3(grid_for(n, BT)), dim3(BT), 0, s, pts, n, f, dtype, perm, spts, sid);
@@ -271,6 +333,11 @@ hipError_t launch_dense_cell_start(const uint64_t* sorted_keys, int64_t n, int64
                        box_cells, cell_start);
     hipLaunchKernelGGL(k_dense_cell_stats, dim3(grid_for(box_cells, BT, 4096)), dim3(BT), 0, s, cell_start,
                        box_cells, d_stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_stats(const uint32_t* cell_start, int64_t ncells, int64_t* d_stats, hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_cell_stats, dim3(grid_for(ncells, BT, 4096)), dim3(BT), 0, s, cell_start, ncells, d_stats);
     return hipGetLastError();
 }
 

@@ -19,7 +19,8 @@ constexpr int64_t COORD_LIMIT = int64_t(1) << 27;
 // 2^29 in magnitude, where the exact floor below is verified.
 constexpr int64_t CLAMP = int64_t(1) << 28;
 
-enum Lookup : int32_t { LOOKUP_DENSE = 0, LOOKUP_HASH = 1 };
+enum Lookup : int32_t { LOOKUP_DENSE = 0, LOOKUP_TREE = 1 };
+constexpr int TREE_LEVELS_MAX = 6;  // levels of the bounding-box tree, cells included
 
 // Device-side view of an index, passed by value to kernels.
 struct IndexView {
@@ -30,9 +31,17 @@ struct IndexView {
     int32_t lookup;
     const float* spts;          // n x f points in cell order (FP32 copy; exact for bf16 input)
     const int32_t* sid;         // n original row ids, cell order
-    const uint32_t* cell_start; // dense: box_cells + 1 offsets into spts
+    const uint32_t* cell_start; // dense: box_cells + 1 offsets into spts; tree: num_cells + 1
     const void* targets;        // n targets, original order
     int64_t box_cells;
+    // tree lookup: occupied cells in Morton order and the bounding boxes above them
+    int64_t num_cells;
+    const int32_t* cell_coord;  // num_cells x f cell ids
+    int32_t tree_levels;        // levels above the cells (the root entry's level)
+    int64_t tree_count[TREE_LEVELS_MAX];  // nodes per level; level 0 = cells
+    int64_t tree_off[TREE_LEVELS_MAX];    // first node of level L (>= 1) in node_lo / node_hi
+    const int32_t* node_lo;     // per node, f lowest cell ids of its subtree
+    const int32_t* node_hi;     // per node, f highest cell ids
     float a[F_MAX];             // cell width per dimension
     float o[F_MAX];             // origin per dimension
     int32_t cmin[F_MAX];
@@ -117,6 +126,18 @@ hipError_t launch_gather_points(const void* pts, int64_t n, int32_t f, int32_t d
 hipError_t launch_dense_cell_start(const uint64_t* sorted_keys, int64_t n, int64_t box_cells,
                                    uint32_t* cell_start, int64_t* d_stats, hipStream_t s);
 
+// stats[0] += non-empty cells, stats[1] = max points in one cell, over `ncells` offsets.
+hipError_t launch_cell_stats(const uint32_t* cell_start, int64_t ncells, int64_t* d_stats, hipStream_t s);
+hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* temp, hipStream_t s);
+size_t exclusive_scan_temp_bytes(int64_t n);
+hipError_t launch_morton_keys(const void* pts, int64_t n, int32_t dtype, const IndexView& iv, uint64_t* keys,
+                              uint32_t* vals, hipStream_t s);
+hipError_t launch_cell_heads(const uint64_t* sorted_keys, int64_t n, uint32_t* heads, hipStream_t s);
+hipError_t launch_cell_list(const uint32_t* heads, const uint32_t* rank, int64_t n, const IndexView& iv,
+                            uint32_t* cell_start, int32_t* cell_coord, hipStream_t s);
+hipError_t launch_tree_level(const int32_t* child_lo, const int32_t* child_hi, int64_t nchild, int32_t f,
+                             int32_t* node_lo, int32_t* node_hi, int64_t nnode, hipStream_t s);
+
 struct PredictArgs {
     IndexView ix;
     const float* queries;
@@ -133,6 +154,7 @@ struct PredictArgs {
     const uint32_t* order;  // optional processing order of the queries (NULL = 0..m-1)
 };
 hipError_t launch_predict_dense(const PredictArgs& a, hipStream_t s);
+hipError_t launch_predict_tree(const PredictArgs& a, hipStream_t s);
 // Spatial sort key of every query (Morton code of its box-clamped central cell).
 hipError_t launch_query_keys(const float* qs, int64_t m, const IndexView& ix, int keep_bits, uint64_t* keys,
                              uint32_t* vals, hipStream_t s);

@@ -1,0 +1,344 @@
+// Device pieces shared by the exploration kernels (Section III-B): query set-up,
+// the FP32 screen + FP64 size-k buffer, the load-balanced gather of a list of
+// point runs, the stop rules, and the prediction from the buffer.
+//
+// One wave64 walks one query.  The size-k buffer (the paper's heap) lives in
+// lanes 0..k-1 sorted by (FP64 distance, row id).  Candidates are screened with
+// an FP32 distance; only those that may still enter the buffer get their FP64
+// distance and an exact (distance, id) comparison, so the buffer always holds
+// exactly the k best of everything scored so far.
+#pragma once
+
+#include "ghn_internal.h"
+
+namespace ghn {
+
+constexpr int NUM_XCD = 8;
+constexpr double LB_SHRINK = 1.0 - 0x1p-40;    // cell lower bounds are shrunk by this before pruning
+constexpr double EXACT_SHRINK = 1.0 - 0x1p-44; // squared ring distance is shrunk by this (EXACT rule)
+constexpr int RUN_CAP = 2 * WAVE;              // point runs listed per batch
+
+// Smallest float >= x (x >= 0, finite or inf).
+__device__ __forceinline__ float f32_round_up(double x) {
+    float r = (float)x;
+    if ((double)r < x) r = __int_as_float(__float_as_int(r) + 1);
+    return r;
+}
+
+// FP32 admission threshold for a k-th FP64 distance tau: any point with FP64
+// distance <= tau has an FP32 screen distance <= the returned value.  The FP32
+// screen (f rounded differences, squares and fused adds) and the FP64 value
+// both lie within a relative (f + 2) * 2^-24 of the exact distance; 2^-16 covers
+// that for f <= 32, and 2^-125 covers FP32 underflow.
+__device__ __forceinline__ float admit_threshold(double tau) {
+    if (!(tau < 1.0e300)) return __int_as_float(0x7f800000);
+    return f32_round_up(tau * (1.0 + 0x1p-16)) + 0x1p-125f;
+}
+
+template <int FT>
+__device__ __forceinline__ void load_point(const float* __restrict__ p, float* x, int f) {
+    if constexpr (FT == 2) {
+        float2 v = *(const float2*)p;
+        x[0] = v.x; x[1] = v.y;
+    } else if constexpr (FT > 0 && FT % 4 == 0) {
+#pragma unroll
+        for (int j = 0; j < FT; j += 4) {
+            float4 v = *(const float4*)(p + j);
+            x[j] = v.x; x[j + 1] = v.y; x[j + 2] = v.z; x[j + 3] = v.w;
+        }
+    } else if constexpr (FT > 0) {
+#pragma unroll
+        for (int j = 0; j < FT; ++j) x[j] = p[j];
+    } else {
+        for (int j = 0; j < f; ++j) x[j] = p[j];
+    }
+}
+
+// FP64 squared distance in the defined order: ((q0-x0)^2 + (q1-x1)^2) + ..., no FMA.
+template <int FT>
+__device__ __forceinline__ double dist64(const float* q, const float* x, int f) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < (FT > 0 ? FT : F_MAX); ++j) {
+        if (FT == 0 && j >= f) break;
+        double d = __dadd_rn((double)q[j], -(double)x[j]);
+        s = __dadd_rn(s, __dmul_rn(d, d));
+    }
+    return s;
+}
+
+template <int FT>
+__device__ __forceinline__ float dist32(const float* q, const float* x, int f) {
+    float s = 0.0f;
+#pragma unroll
+    for (int j = 0; j < (FT > 0 ? FT : F_MAX); ++j) {
+        if (FT == 0 && j >= f) break;
+        float d = q[j] - x[j];
+        s = __builtin_fmaf(d, d, s);
+    }
+    return s;
+}
+
+// Distance from v to the id interval [lo*a, (hi+1)*a) in FP64 (0 inside).
+__device__ __forceinline__ double gap_to_cells(double v, int64_t lo, int64_t hi, double a) {
+    double below = __dadd_rn(__dmul_rn((double)lo, a), -v);
+    double above = __dadd_rn(v, -__dmul_rn((double)(hi + 1), a));
+    double g = below > above ? below : above;
+    return g > 0.0 ? g : 0.0;
+}
+
+struct WaveState {
+    double bd;      // this lane's buffer slot: distance (lanes < k)
+    int bi;         // this lane's buffer slot: row id
+    double tau;     // k-th distance (+inf while the buffer is not full)
+    int tau_i;      // k-th row id
+    float t32;      // FP32 admission threshold derived from tau
+    int count;      // entries in the buffer (<= k)
+    bool updated;   // an insertion happened in the current layer
+    int64_t cands;  // candidates scored
+    int64_t probes; // index entries read to find cells
+};
+
+__device__ __forceinline__ void init_state(WaveState& st) {
+    st.bd = __longlong_as_double(0x7ff0000000000000LL);
+    st.bi = INT32_MAX;
+    st.tau = st.bd;
+    st.tau_i = INT32_MAX;
+    st.t32 = __int_as_float(0x7f800000);
+    st.count = 0;
+    st.updated = false;
+    st.cands = 0;
+    st.probes = 0;
+}
+
+// Query set-up: coordinates, central cell (Eq. 1, clamped to CLAMP cells outside
+// the occupied box), first layer that reaches the box, layer that covers it.
+template <int FT>
+struct Query {
+    float q[FT > 0 ? FT : F_MAX];
+    double v[FT > 0 ? FT : F_MAX];   // q - origin, FP64
+    int64_t c[FT > 0 ? FT : F_MAX];  // central cell id
+    int64_t l0, lcover;
+    bool finite;
+};
+
+template <int FT>
+__device__ __forceinline__ void setup_query(const IndexView& ix, const float* queries, int64_t qi, int f, Query<FT>& Q) {
+    Q.finite = true;
+    Q.l0 = 0;
+    Q.lcover = 0;
+#pragma unroll
+    for (int j = 0; j < (FT > 0 ? FT : F_MAX); ++j) {
+        if (FT == 0 && j >= f) break;
+        Q.q[j] = queries[qi * f + j];
+        Q.finite = Q.finite && isfinite(Q.q[j]);
+        Q.v[j] = __dadd_rn((double)Q.q[j], -(double)ix.o[j]);
+        int64_t cj = Q.finite ? exact_floor_div(Q.v[j], (double)ix.a[j]) : 0;
+        cj = max(cj, (int64_t)ix.cmin[j] - CLAMP);
+        cj = min(cj, (int64_t)ix.cmax[j] + CLAMP);
+        Q.c[j] = cj;
+        Q.l0 = max(Q.l0, max((int64_t)ix.cmin[j] - cj, cj - (int64_t)ix.cmax[j]));
+        Q.lcover = max(Q.lcover, max(cj - (int64_t)ix.cmin[j], (int64_t)ix.cmax[j] - cj));
+    }
+}
+
+// Outputs of a query with a non-finite coordinate.
+__device__ __forceinline__ void write_invalid(const PredictArgs& A, int64_t qi) {
+    const int lane = lane_id();
+    const int k = A.k;
+    if (lane < k) {
+        A.out_idx[qi * k + lane] = -1;
+        if (A.out_d2) A.out_d2[qi * k + lane] = __longlong_as_double(0x7ff8000000000000LL);
+    }
+    if (lane == 0) {
+        if (A.ix.task == GHN_CLASSIFY) ((int32_t*)A.out_pred)[qi] = -1;
+        else ((float*)A.out_pred)[qi] = __int_as_float(0x7fc00000);
+        if (A.out_stop_layer) A.out_stop_layer[qi] = -1;
+        if (A.out_cands) A.out_cands[qi] = 0;
+        if (A.out_probes) A.out_probes[qi] = 0;
+    }
+}
+
+// Which query this wave walks.  With a spatial query order each XCD (blocks are
+// dealt round-robin over the 8 XCDs) gets one contiguous range of blocks, so
+// each XCD's L2 serves one region of space.
+__device__ __forceinline__ int64_t wave_slot(const PredictArgs& A, int waves_per_block) {
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    int64_t blk = blockIdx.x;
+    if (A.order) {
+        const int64_t nb = gridDim.x, x = blk % NUM_XCD, t = blk / NUM_XCD;
+        blk = x * (nb / NUM_XCD) + min(x, nb % NUM_XCD) + t;
+    }
+    return blk * waves_per_block + wv;
+}
+
+// One 64-wide chunk of candidates.
+template <int FT>
+struct Chunk {
+    float x[FT > 0 ? FT : F_MAX];
+    int id;
+    bool valid;
+};
+
+template <int FT>
+__device__ __forceinline__ void fetch_chunk(const IndexView& ix, int f, bool valid, uint32_t pidx, Chunk<FT>& c) {
+    c.valid = valid;
+    c.id = 0;
+    if (valid) {
+        load_point<FT>(ix.spts + (size_t)pidx * (FT > 0 ? FT : f), c.x, f);
+        c.id = ix.sid[pidx];
+    }
+}
+
+// Screen a chunk in FP32; candidates that may enter the buffer get their FP64
+// distance and are inserted one at a time (exact (distance, id) comparison).
+template <int FT>
+__device__ __forceinline__ void score_chunk(const float* q, int f, int k, const Chunk<FT>& c, WaveState& st) {
+    const int lane = lane_id();
+    float d32 = __int_as_float(0x7f800000);
+    if (c.valid) d32 = dist32<FT>(q, c.x, f);
+    const bool adm = c.valid && d32 <= st.t32;
+    uint64_t mask = ballot(adm);
+    if (mask == 0) return;
+    double d64 = 0.0;
+    if (adm) d64 = dist64<FT>(q, c.x, f);
+    while (mask) {
+        const int src = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const double cd = readlane_f64(d64, src);
+        const int ci = readlane_i32(c.id, src);
+        if (!(cd < st.tau || (cd == st.tau && ci < st.tau_i))) continue;
+        // The new k-th entry is the old (k-1)-th unless the candidate lands last.
+        double kd = cd;
+        int ki = ci;
+        if (k > 1) { kd = readlane_f64(st.bd, k - 2); ki = readlane_i32(st.bi, k - 2); }
+        // Insert (cd, ci): slots holding a larger entry shift up by one lane.  The
+        // distances are >= 0, so their IEEE bit patterns order like the values.
+        const uint64_t cb = (uint64_t)__double_as_longlong(cd);
+        const uint64_t bb = (uint64_t)__double_as_longlong(st.bd);
+        const bool gt = lane < k && (bb > cb || (bb == cb && st.bi > ci));
+        const int pos = k - __popcll(ballot(gt));
+        const double ud = shfl_up1_f64(st.bd);
+        const int ui = shfl_up1_i32(st.bi);
+        if (gt) {
+            st.bd = lane == pos ? cd : ud;
+            st.bi = lane == pos ? ci : ui;
+        }
+        st.updated = true;
+        if (st.count < k) st.count += 1;
+        if (st.count == k) {
+            const bool last = pos == k - 1;
+            st.tau = last ? cd : kd;
+            st.tau_i = last ? ci : ki;
+            st.t32 = admit_threshold(st.tau);
+            mask &= ballot(c.valid && d32 <= st.t32);
+        }
+    }
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lane-held runs of points (begin b0/b1, length n0/n1; 0 = none) are listed in
+// the wave's LDS arrays and scored in 64-wide chunks, each lane finding its
+// point by a binary search over the run prefixes.
+template <int FT>
+__device__ __forceinline__ void score_runs(const IndexView& ix, const float* q, int f, int k, uint32_t b0, uint32_t n0,
+                                           uint32_t b1, uint32_t n1, uint32_t* s_begin, uint32_t* s_pre,
+                                           WaveState& st) {
+    const int lane = lane_id();
+    const uint32_t nseg_l = (n0 > 0) + (n1 > 0);
+    const uint32_t npts_l = n0 + n1;
+    const uint32_t seg_incl = wave_incl_scan(nseg_l);
+    const uint32_t pts_incl = wave_incl_scan(npts_l);
+    const uint32_t nseg = readlane_i32((int)seg_incl, WAVE - 1);
+    const uint32_t npts = readlane_i32((int)pts_incl, WAVE - 1);
+    if (npts == 0) return;
+    uint32_t sidx = seg_incl - nseg_l, pofs = pts_incl - npts_l;
+    if (n0 > 0) { s_begin[sidx] = b0; s_pre[sidx] = pofs; ++sidx; pofs += n0; }
+    if (n1 > 0) { s_begin[sidx] = b1; s_pre[sidx] = pofs; }
+    wave_lds_sync();
+    for (uint32_t base = 0; base < npts; base += WAVE) {
+        const uint32_t p = base + lane;
+        uint32_t pidx = 0;
+        if (p < npts) {
+            uint32_t a0 = 0, a1 = nseg;  // last run whose prefix is <= p
+            while (a1 - a0 > 1) {
+                const uint32_t mid = (a0 + a1) >> 1;
+                if (s_pre[mid] <= p) a0 = mid;
+                else a1 = mid;
+            }
+            pidx = s_begin[a0] + (p - s_pre[a0]);
+        }
+        Chunk<FT> cur;
+        fetch_chunk<FT>(ix, f, p < npts, pidx, cur);
+        st.cands += __popcll(ballot(cur.valid));
+        score_chunk<FT>(q, f, k, cur, st);
+    }
+    wave_lds_sync();
+}
+
+// Stop rules, checked after every complete layer l.
+template <int FT, int STOP>
+__device__ __forceinline__ bool stop_after_layer(const IndexView& ix, const Query<FT>& Q, int f, int k, int64_t l,
+                                                 const WaveState& st) {
+    if (l >= Q.lcover) return true;  // every occupied cell has been visited
+    if (st.count != k) return false;
+    if (STOP == GHN_STOP_PAPER) return !st.updated;
+    double r2 = __longlong_as_double(0x7ff0000000000000LL);
+#pragma unroll
+    for (int j = 0; j < (FT > 0 ? FT : F_MAX); ++j) {
+        if (FT == 0 && j >= f) break;
+        const double a = ix.a[j];
+        const double glo = __dadd_rn(Q.v[j], -__dmul_rn((double)(Q.c[j] - l), a));
+        const double ghi = __dadd_rn(__dmul_rn((double)(Q.c[j] + l + 1), a), -Q.v[j]);
+        double g = glo < ghi ? glo : ghi;
+        if (g < 0.0) g = 0.0;
+        const double g2 = __dmul_rn(g, g);
+        if (g2 < r2) r2 = g2;
+    }
+    return st.tau < __dmul_rn(r2, EXACT_SHRINK);
+}
+
+// Neighbours in (distance, id) order, then the majority vote (ties -> smallest
+// label) or the mean (FP64 sum in neighbour order, / k, rounded to FP32).
+__device__ __forceinline__ void finish_query(const PredictArgs& A, int64_t qi, int64_t l, const WaveState& st) {
+    const int lane = lane_id();
+    const int k = A.k;
+    const IndexView& ix = A.ix;
+    if (lane < k) {
+        A.out_idx[qi * k + lane] = st.bi;
+        if (A.out_d2) A.out_d2[qi * k + lane] = st.bd;
+    }
+    if (ix.task == GHN_CLASSIFY) {
+        const int32_t* lab = (const int32_t*)ix.targets;
+        const int my = lane < k ? lab[st.bi] : INT32_MAX;
+        uint64_t todo = ballot(lane < k);
+        int best = INT32_MAX, best_n = -1;
+        while (todo) {
+            const int src = __ffsll((unsigned long long)todo) - 1;
+            const int label = readlane_i32(my, src);
+            const uint64_t same = ballot(lane < k && my == label);
+            const int cnt = __popcll(same);
+            if (cnt > best_n || (cnt == best_n && label < best)) { best = label; best_n = cnt; }
+            todo &= ~same;
+        }
+        if (lane == 0) ((int32_t*)A.out_pred)[qi] = best;
+    } else {
+        const float* y = (const float*)ix.targets;
+        const float my = lane < k ? y[st.bi] : 0.0f;
+        double s = 0.0;
+        for (int t = 0; t < k; ++t) s = __dadd_rn(s, (double)readlane_f32(my, t));
+        if (lane == 0) ((float*)A.out_pred)[qi] = (float)(s / (double)k);
+    }
+    if (lane == 0) {
+        if (A.out_stop_layer) A.out_stop_layer[qi] = (int32_t)l;
+        if (A.out_cands) A.out_cands[qi] = st.cands;
+        if (A.out_probes) A.out_probes[qi] = st.probes;
+    }
+}
+
+}  // namespace ghn

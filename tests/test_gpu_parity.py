@@ -29,13 +29,14 @@ def _dev(a, dtype=None):
     return t.cuda()
 
 
-def _index(ghn, prob, widths=None, origin=None):
+def _index(ghn, prob, widths=None, origin=None, lookup=None):
     import torch
     if prob.dtype == "bf16":
         pts = _dev(prob.points.view(np.int16)).view(torch.bfloat16)
     else:
         pts = _dev(prob.points)
-    return ghn.Index(pts, _dev(prob.targets), prob.task, prob.cell_width if widths is None else widths, origin)
+    return ghn.Index(pts, _dev(prob.targets), prob.task, prob.cell_width if widths is None else widths, origin,
+                     lookup=lookup)
 
 
 def _run(ghn, ix, queries, k, stop, **kw):
@@ -57,7 +58,7 @@ def _assert_same(got, want, what, check_layers=False):
 
 
 def _check_exact(ghn, prob, sample=None, seed=0, **kw):
-    ix = _index(ghn, prob, **{k: v for k, v in kw.items() if k in ("widths", "origin")})
+    ix = _index(ghn, prob, **{k: v for k, v in kw.items() if k in ("widths", "origin", "lookup")})
     flags = kw.get("flags", 0)
     got = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_EXACT, flags=flags)
     rows = np.arange(prob.m)
@@ -68,8 +69,8 @@ def _check_exact(ghn, prob, sample=None, seed=0, **kw):
     return ix, got
 
 
-def _check_paper(ghn, prob, sample=None, seed=1, widths=None, origin=None, flags=0):
-    ix = _index(ghn, prob, widths, origin)
+def _check_paper(ghn, prob, sample=None, seed=1, widths=None, origin=None, flags=0, lookup=None):
+    ix = _index(ghn, prob, widths, origin, lookup)
     got = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_PAPER, flags=flags)
     rows = np.arange(prob.m)
     if sample is not None and sample < prob.m:
@@ -264,8 +265,17 @@ def test_build_errors(ghn):
     spread[:, 0] *= 1e5
     spread[:, 1] *= 1e5
     with pytest.raises(ghn.GHNError) as e:
-        ghn.Index(_dev(spread), _dev(lab), 0, 0.01)
+        ghn.Index(_dev(spread), _dev(lab), 0, 0.01, lookup=0)
     assert e.value.code == -2
+    ix = ghn.Index(_dev(spread), _dev(lab), 0, 0.01)  # automatic choice falls back to the tree
+    assert ix.info.lookup == 1
+    wide = np.random.default_rng(1).random((200, 32)).astype(np.float32)  # 32 dims x 4 bits > 64
+    with pytest.raises(ghn.GHNError) as e:
+        ghn.Index(_dev(wide), _dev(np.zeros(200, np.int32)), 0, 0.1)
+    assert e.value.code == -5
+    with pytest.raises(ghn.GHNError) as e:
+        ghn.Index(_dev(pts), _dev(lab), 0, 0.1, lookup=7)
+    assert e.value.code == -1
 
 
 def test_predict_errors_and_empty(ghn):
@@ -285,3 +295,58 @@ def test_predict_errors_and_empty(ghn):
     with pytest.raises(ghn.GHNError) as e:
         ix.predict(q, 0)
     assert e.value.code == -1
+
+
+# ---------------------------------------------------------------------------------- tree lookup
+TREE = 1
+
+
+@pytest.mark.parametrize("f", [1, 2, 3, 4, 5, 8])
+def test_tree_lookup_uniform(ghn, f):
+    width = {1: 0.003, 2: 0.05, 3: 0.1, 4: 0.2, 5: 0.3, 8: 0.5}[f]
+    prob = W.uniform_problem(n=6000, m=301, f=f, k=9, seed=40 + f, width=width, q_lo=-0.3, q_hi=1.3)
+    _check_exact(ghn, prob, lookup=TREE)
+    _check_paper(ghn, prob, lookup=TREE)
+
+
+def test_tree_lookup_edge_cases(ghn):
+    lat = W.lattice_problem(n=3000, m=300, f=3, k=12, seed=7)
+    _check_exact(ghn, lat, lookup=TREE)
+    _check_paper(ghn, lat, lookup=TREE)
+    far = W.uniform_problem(n=5000, m=120, f=3, k=5, seed=5, width=0.1)
+    far.queries[:40] *= 1e3
+    far.queries[40:80] -= 37.0
+    _check_exact(ghn, far, lookup=TREE)
+    _check_paper(ghn, far, lookup=TREE)
+    one = W.uniform_problem(n=1, m=20, f=2, k=1, seed=3, width=0.5, q_lo=-5, q_hi=5)
+    _check_exact(ghn, one, lookup=TREE)
+    _check_paper(ghn, one, lookup=TREE)
+    reg = W.uniform_problem(n=8000, m=200, f=3, k=16, seed=4, task=W.REGRESS, width=0.05)
+    _check_exact(ghn, reg, lookup=TREE)
+    widths = np.array([0.31, 0.07, 0.19], np.float32)
+    origin = np.array([-0.123, 0.05, 1.7], np.float32)
+    wo = W.uniform_problem(n=8000, m=200, f=3, k=9, seed=21, lo=-2.0, hi=2.0, q_lo=-3.0, q_hi=3.0)
+    _check_exact(ghn, wo, widths=widths, origin=origin, lookup=TREE)
+    _check_paper(ghn, wo, widths=widths, origin=origin, lookup=TREE)
+
+
+def test_tree_equals_dense(ghn):
+    prob = W.make("clusters4d", n=40_000, m=2_000)
+    for stop in (ghn.GHN_STOP_EXACT, ghn.GHN_STOP_PAPER):
+        a = _run(ghn, _index(ghn, prob, lookup=0), prob.queries, prob.k, stop)
+        b = _run(ghn, _index(ghn, prob, lookup=TREE), prob.queries, prob.k, stop)
+        _assert_same(a, b, "dense vs tree", check_layers=True)
+
+
+def test_skew8d_regression_small(ghn):
+    prob = W.make("skew8d", n=100_000, m=1_000)
+    ix, _ = _check_exact(ghn, prob)
+    assert ix.info.lookup == TREE
+    _check_paper(ghn, prob, sample=300)
+
+
+def test_bf16_16d_small(ghn):
+    prob = W.make("bf16_16d", n=60_000, m=600)
+    ix, _ = _check_exact(ghn, prob)
+    assert ix.info.lookup == TREE
+    _check_paper(ghn, prob, sample=200)
