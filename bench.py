@@ -104,7 +104,10 @@ def main():
     prob = W.make(args.workload)
     stop = ghn.GHN_STOP_EXACT if args.stop == "exact" else ghn.GHN_STOP_PAPER
     dev = torch.device("cuda:0")
-    pts = torch.from_numpy(prob.points).to(dev)
+    if prob.dtype == "bf16":
+        pts = torch.from_numpy(prob.points.view(np.int16)).to(dev).view(torch.bfloat16)
+    else:
+        pts = torch.from_numpy(prob.points).to(dev)
     tgt = torch.from_numpy(prob.targets).to(dev)
     qs = torch.from_numpy(prob.queries).to(dev)
     torch.cuda.synchronize()

@@ -158,10 +158,16 @@ typedef struct {
     int64_t* out_probes;     /* optional, m int64: cell-table entries read per query */
     const uint32_t* order;   /* optional, m uint32: order in which to walk the queries (a
                                 permutation of 0..m-1, e.g. from ghn_query_order); when set,
-                                no sort is done and no workspace is needed */
+                                no sort is done and no workspace is needed (FP32 screen) */
+    int32_t group_levels;    /* bf16 screen, EXACT rule: queries whose central cells agree
+                                after dropping the lowest group_levels bits of every cell id
+                                (blocks of 2^group_levels cells per dimension) are walked
+                                together, up to 16 per group; -1 = automatic (1).  The PAPER
+                                rule always groups by identical central cell. */
 } ghn_predict_opts;
 
-/* Bytes of device workspace ghn_predict needs for these arguments. */
+/* Bytes of device workspace ghn_predict needs for these arguments (the bf16
+ * screen always needs one: it sorts and groups the queries). */
 size_t ghn_predict_workspace_bytes(const ghn_index* index, int64_t m, int32_t k, const ghn_predict_opts* opts);
 
 /* Exploration + prediction for m queries (Section III-B, III-D).

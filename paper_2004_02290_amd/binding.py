@@ -54,7 +54,8 @@ class ghn_index_info(ctypes.Structure):
 class ghn_predict_opts(ctypes.Structure):
     _fields_ = [("stop", ctypes.c_int32), ("prec", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("out_stop_layer", ctypes.c_void_p), ("out_cands", ctypes.c_void_p),
-                ("out_probes", ctypes.c_void_p), ("order", ctypes.c_void_p)]
+                ("out_probes", ctypes.c_void_p), ("order", ctypes.c_void_p),
+                ("group_levels", ctypes.c_int32)]
 
 
 def _load() -> ctypes.CDLL:
@@ -165,13 +166,15 @@ def ghn_destroy(handle) -> None:
     _lib.ghn_destroy(handle)
 
 
-def _opts(stop, prec, flags, out_stop_layer=None, out_cands=None, out_probes=None, order=None) -> ghn_predict_opts:
+def _opts(stop, prec, flags, out_stop_layer=None, out_cands=None, out_probes=None, order=None,
+          group_levels=-1) -> ghn_predict_opts:
     return ghn_predict_opts(int(stop), int(prec), int(flags), _ptr(out_stop_layer), _ptr(out_cands),
-                            _ptr(out_probes), _ptr(order))
+                            _ptr(out_probes), _ptr(order), int(group_levels))
 
 
-def ghn_predict_workspace_bytes(handle, m: int, k: int, stop=GHN_STOP_EXACT, prec=GHN_PREC_FP32, flags=0) -> int:
-    o = _opts(stop, prec, flags)
+def ghn_predict_workspace_bytes(handle, m: int, k: int, stop=GHN_STOP_EXACT, prec=GHN_PREC_FP32, flags=0,
+                                group_levels=-1) -> int:
+    o = _opts(stop, prec, flags, group_levels=group_levels)
     return int(_lib.ghn_predict_workspace_bytes(handle, m, k, ctypes.byref(o)))
 
 
@@ -179,10 +182,10 @@ def ghn_predict(handle, queries: torch.Tensor, k: int, out_idx: torch.Tensor, ou
                 out_d2: Optional[torch.Tensor] = None, stop=GHN_STOP_EXACT, prec=GHN_PREC_FP32, flags=0,
                 out_stop_layer: Optional[torch.Tensor] = None, out_cands: Optional[torch.Tensor] = None,
                 out_probes: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
-                order: Optional[torch.Tensor] = None, stream=None) -> None:
+                order: Optional[torch.Tensor] = None, group_levels: int = -1, stream=None) -> None:
     """ghn_predict into caller-provided outputs (int64 idx m x k, pred m, optional float64 d2 m x k)."""
     m = queries.shape[0]
-    o = _opts(stop, prec, flags, out_stop_layer, out_cands, out_probes, order)
+    o = _opts(stop, prec, flags, out_stop_layer, out_cands, out_probes, order, group_levels)
     ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
     _check(_lib.ghn_predict(handle, _ptr(queries), m, k, ctypes.byref(o), _ptr(out_idx), _ptr(out_d2),
                             _ptr(out_pred), _ptr(ws), ws_bytes, _stream(stream)))
@@ -209,7 +212,7 @@ class Index:
         self.info = ghn_index_get_info(self.handle)
 
     def predict(self, queries: torch.Tensor, k: int, stop=GHN_STOP_EXACT, prec=GHN_PREC_FP32, flags=0,
-                with_d2: bool = True, with_stats: bool = False, stream=None):
+                with_d2: bool = True, with_stats: bool = False, group_levels: int = -1, stream=None):
         """Returns dict(idx, pred[, d2][, stop_layer, cands]) as GPU tensors."""
         dev = queries.device
         m = queries.shape[0]
@@ -222,10 +225,10 @@ class Index:
             out["stop_layer"] = torch.empty(m, dtype=torch.int32, device=dev)
             out["cands"] = torch.empty(m, dtype=torch.int64, device=dev)
             out["probes"] = torch.empty(m, dtype=torch.int64, device=dev)
-        nbytes = ghn_predict_workspace_bytes(self.handle, m, k, stop, prec, flags)
+        nbytes = ghn_predict_workspace_bytes(self.handle, m, k, stop, prec, flags, group_levels)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev) if nbytes else None
         ghn_predict(self.handle, queries, k, out["idx"], out["pred"], out.get("d2"), stop, prec, flags,
-                    out.get("stop_layer"), out.get("cands"), out.get("probes"), ws, stream)
+                    out.get("stop_layer"), out.get("cands"), out.get("probes"), ws, None, group_levels, stream)
         return out
 
     def close(self):

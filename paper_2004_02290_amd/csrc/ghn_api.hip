@@ -179,72 +179,70 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
     if ((e = launch_gather_points(points, n, f, dtype, perm, spts, sid, s)) != hipSuccess) return hip_fail(e, "ghn_build: gather");
     if ((e = hipMemcpyAsync(tg, targets, (size_t)n * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(e, "ghn_build: targets");
     iv.spts = spts; iv.sid = sid; iv.targets = tg;
-    size_t table_bytes = 0;
 
-    // 4. cell table
+    // 4. occupied cells (both lookups): heads of equal-key runs, their ranks, first
+    //    points and ids, then the bounding-box levels above them
+    uint32_t *heads, *rank;
+    void* stemp;
+    if (tmp.alloc((void**)&heads, n * 4) || tmp.alloc((void**)&rank, n * 4) ||
+        tmp.alloc(&stemp, exclusive_scan_temp_bytes(n)))
+        return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the cell list");
+    if ((e = launch_cell_heads(skeys, n, heads, s)) != hipSuccess) return hip_fail(e, "ghn_build: heads");
+    if ((e = exclusive_scan_u32(heads, rank, n, stemp, s)) != hipSuccess) return hip_fail(e, "ghn_build: scan");
+    uint32_t last[2] = {0, 0};
+    if ((e = hipMemcpyAsync(&last[0], rank + n - 1, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&last[1], heads + n - 1, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "ghn_build: cell count");
+    const int64_t ncell = (int64_t)last[0] + last[1];
+    uint32_t* cf;
+    int32_t* coord;
+    if (keep.alloc((void**)&cf, (size_t)(ncell + 1) * 4) || keep.alloc((void**)&coord, (size_t)ncell * f * 4))
+        return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the cell list");
+    if ((e = launch_cell_list(heads, rank, n, iv, cf, coord, s)) != hipSuccess) return hip_fail(e, "ghn_build: cell list");
+    const uint32_t n32 = (uint32_t)n;
+    if ((e = hipMemcpyAsync(cf + ncell, &n32, 4, hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e, "ghn_build: cell end");
+    int64_t count[TREE_LEVELS_MAX] = {0};
+    int64_t off[TREE_LEVELS_MAX] = {0};
+    count[0] = ncell;
+    int top = 0;
+    int64_t total = 0;
+    while (count[top] > WAVE) {
+        if (top + 1 >= TREE_LEVELS_MAX) return fail(GHN_E_UNSUPPORTED, "ghn_build: too many cells for the tree");
+        count[top + 1] = (count[top] + WAVE - 1) / WAVE;
+        off[top + 1] = total;
+        total += count[top + 1];
+        ++top;
+    }
+    int32_t *nlo = nullptr, *nhi = nullptr;
+    if (total > 0 && (keep.alloc((void**)&nlo, (size_t)total * f * 4) || keep.alloc((void**)&nhi, (size_t)total * f * 4)))
+        return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the tree");
+    for (int L = 1; L <= top; ++L) {
+        const int32_t* clo = L == 1 ? coord : nlo + off[L - 1] * f;
+        const int32_t* chi = L == 1 ? coord : nhi + off[L - 1] * f;
+        if ((e = launch_tree_level(clo, chi, count[L - 1], f, nlo + off[L] * f, nhi + off[L] * f, count[L], s)) != hipSuccess)
+            return hip_fail(e, "ghn_build: tree level");
+    }
+    if ((e = launch_cell_stats(cf, ncell, d_small->stats, s)) != hipSuccess) return hip_fail(e, "ghn_build: stats");
+    iv.cell_first = cf;
+    iv.num_cells = ncell;
+    iv.cell_coord = coord;
+    iv.tree_levels = top;
+    for (int L = 0; L < TREE_LEVELS_MAX; ++L) { iv.tree_count[L] = count[L]; iv.tree_off[L] = off[L]; }
+    iv.node_lo = nlo;
+    iv.node_hi = nhi;
+    size_t table_bytes = (size_t)(ncell + 1) * 4 + (size_t)ncell * f * 4 + (size_t)total * f * 8;
+    // 5. dense table over the whole box
+    iv.cell_start = cf;
     if (lookup == GHN_LOOKUP_DENSE) {
         uint32_t* cs;
         if (keep.alloc((void**)&cs, (size_t)(box + 1) * 4)) return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the table");
-        if ((e = launch_dense_cell_start(skeys, n, box, cs, d_small->stats, s)) != hipSuccess) return hip_fail(e, "ghn_build: table");
+        if ((e = launch_dense_cell_start(skeys, n, box, cs, s)) != hipSuccess) return hip_fail(e, "ghn_build: table");
         iv.cell_start = cs;
-        table_bytes = (size_t)(box + 1) * 4;
-    } else {
-        // occupied cells: heads of equal-key runs, their ranks, first points and ids
-        uint32_t *heads, *rank;
-        void* stemp;
-        if (tmp.alloc((void**)&heads, n * 4) || tmp.alloc((void**)&rank, n * 4) ||
-            tmp.alloc(&stemp, exclusive_scan_temp_bytes(n)))
-            return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the cell list");
-        if ((e = launch_cell_heads(skeys, n, heads, s)) != hipSuccess) return hip_fail(e, "ghn_build: heads");
-        if ((e = exclusive_scan_u32(heads, rank, n, stemp, s)) != hipSuccess) return hip_fail(e, "ghn_build: scan");
-        uint32_t last[2] = {0, 0};
-        if ((e = hipMemcpyAsync(&last[0], rank + n - 1, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            (e = hipMemcpyAsync(&last[1], heads + n - 1, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            (e = hipStreamSynchronize(s)) != hipSuccess)
-            return hip_fail(e, "ghn_build: cell count");
-        const int64_t ncell = (int64_t)last[0] + last[1];
-        uint32_t* cs;
-        int32_t* coord;
-        if (keep.alloc((void**)&cs, (size_t)(ncell + 1) * 4) || keep.alloc((void**)&coord, (size_t)ncell * f * 4))
-            return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the cell list");
-        if ((e = launch_cell_list(heads, rank, n, iv, cs, coord, s)) != hipSuccess) return hip_fail(e, "ghn_build: cell list");
-        const uint32_t n32 = (uint32_t)n;
-        if ((e = hipMemcpyAsync(cs + ncell, &n32, 4, hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e, "ghn_build: cell end");
-        // bounding-box levels above the cells
-        int64_t count[TREE_LEVELS_MAX] = {0};
-        int64_t off[TREE_LEVELS_MAX] = {0};
-        count[0] = ncell;
-        int top = 0;
-        int64_t total = 0;
-        while (count[top] > WAVE) {
-            if (top + 1 >= TREE_LEVELS_MAX) return fail(GHN_E_UNSUPPORTED, "ghn_build: too many cells for the tree");
-            count[top + 1] = (count[top] + WAVE - 1) / WAVE;
-            off[top + 1] = total;
-            total += count[top + 1];
-            ++top;
-        }
-        int32_t *nlo = nullptr, *nhi = nullptr;
-        if (total > 0 && (keep.alloc((void**)&nlo, (size_t)total * f * 4) || keep.alloc((void**)&nhi, (size_t)total * f * 4)))
-            return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the tree");
-        for (int L = 1; L <= top; ++L) {
-            const int32_t* clo = L == 1 ? coord : nlo + off[L - 1] * f;
-            const int32_t* chi = L == 1 ? coord : nhi + off[L - 1] * f;
-            if ((e = launch_tree_level(clo, chi, count[L - 1], f, nlo + off[L] * f, nhi + off[L] * f, count[L], s)) != hipSuccess)
-                return hip_fail(e, "ghn_build: tree level");
-        }
-        if ((e = launch_cell_stats(cs, ncell, d_small->stats, s)) != hipSuccess) return hip_fail(e, "ghn_build: stats");
-        iv.cell_start = cs;
-        iv.num_cells = ncell;
-        iv.cell_coord = coord;
-        iv.tree_levels = top;
-        for (int L = 0; L < TREE_LEVELS_MAX; ++L) { iv.tree_count[L] = count[L]; iv.tree_off[L] = off[L]; }
-        iv.node_lo = nlo;
-        iv.node_hi = nhi;
-        table_bytes = (size_t)(ncell + 1) * 4 + (size_t)ncell * f * 4 + (size_t)total * f * 8;
+        table_bytes += (size_t)(box + 1) * 4;
     }
     if ((e = hipMemcpyAsync(&h, d_small, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess) return hip_fail(e, "ghn_build: readback");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "ghn_build: sync");
-    if (lookup == GHN_LOOKUP_DENSE) iv.num_cells = h.stats[0];
 
     ghn_index* ix = new ghn_index();
     ix->view = iv;
@@ -307,6 +305,8 @@ hipError_t sort_queries(const ghn_index* index, const float* queries, int64_t m,
 size_t ghn_predict_workspace_bytes(const ghn_index* index, int64_t m, int32_t k, const ghn_predict_opts* opts) {
     (void)index; (void)k;
     const uint32_t flags = opts ? opts->flags : 0u;
+    if (m <= 0) return 0;
+    if (opts && opts->prec == GHN_PREC_BF16_MFMA) return ghn::group_ws_bytes(m);
     if (opts && opts->order) return 0;
     return wants_sort(m, flags) ? sort_ws_bytes(m) : 0;
 }
@@ -343,7 +343,7 @@ ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, 
     if (m < 0) return fail(GHN_E_INVALID_ARG, "ghn_predict: m=%lld < 0", (long long)m);
     if (k < 1 || k > K_MAX) return fail(GHN_E_INVALID_ARG, "ghn_predict: k=%d outside [1, %d]", k, K_MAX);
     if (k > index->info.n) return fail(GHN_E_K_GT_N, "ghn_predict: k=%d exceeds n=%lld", k, (long long)index->info.n);
-    ghn_predict_opts o = {GHN_STOP_EXACT, GHN_PREC_FP32, 0u, nullptr, nullptr, nullptr, nullptr};
+    ghn_predict_opts o = {GHN_STOP_EXACT, GHN_PREC_FP32, 0u, nullptr, nullptr, nullptr, nullptr, -1};
     if (opts) o = *opts;
     if (o.stop != GHN_STOP_EXACT && o.stop != GHN_STOP_PAPER) return fail(GHN_E_INVALID_ARG, "ghn_predict: bad stop rule %d", o.stop);
     if (o.prec != GHN_PREC_FP32 && o.prec != GHN_PREC_BF16_MFMA) return fail(GHN_E_INVALID_ARG, "ghn_predict: bad precision %d", o.prec);
@@ -352,7 +352,7 @@ ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, 
     if (!queries || !out_idx || !out_pred) return fail(GHN_E_INVALID_ARG, "ghn_predict: queries, out_idx and out_pred must not be NULL");
     if (((uintptr_t)queries % 4) || ((uintptr_t)out_idx % 8) || ((uintptr_t)out_pred % 4) || ((uintptr_t)out_d2 % 8))
         return fail(GHN_E_INVALID_ARG, "ghn_predict: misaligned array");
-    if (o.prec == GHN_PREC_BF16_MFMA) return fail(GHN_E_UNSUPPORTED, "ghn_predict: the bf16 matrix-core screen is not built yet");
+    if (o.group_levels < -1 || o.group_levels > 16) return fail(GHN_E_INVALID_ARG, "ghn_predict: group_levels=%d outside [-1, 16]", o.group_levels);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "ghn_predict: pending HIP error");
     PredictArgs pa;
@@ -370,6 +370,19 @@ ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, 
     pa.out_probes = o.out_probes;
     pa.order = o.order;
     hipStream_t s = (hipStream_t)stream;
+    if (o.prec == GHN_PREC_BF16_MFMA) {
+        const size_t need = group_ws_bytes(m);
+        if (!ws || ws_bytes < need)
+            return fail(GHN_E_WORKSPACE, "ghn_predict: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
+        if ((uintptr_t)ws % 256) return fail(GHN_E_INVALID_ARG, "ghn_predict: workspace must be 256-byte aligned");
+        if (m >= (int64_t(1) << 32)) return fail(GHN_E_INVALID_ARG, "ghn_predict: m=%lld too large for one call", (long long)m);
+        const int levels = o.stop == GHN_STOP_PAPER ? 0 : (o.group_levels < 0 ? 1 : o.group_levels);
+        int bits = 0;
+        e = run_grouped(pa, levels, ws, s, &bits);
+        if (bits > 64) return fail(GHN_E_UNSUPPORTED, "ghn_predict: the Morton code of the cell ids needs %d bits (> 64)", bits);
+        if (e != hipSuccess) return hip_fail(e, "ghn_predict: grouped walk");
+        return GHN_OK;
+    }
     if (!o.order && wants_sort(m, o.flags)) {
         const size_t need = sort_ws_bytes(m);
         if (!ws || ws_bytes < need)

@@ -328,11 +328,9 @@ hipError_t launch_gather_points(const void* pts, int64_t n, int32_t f, int32_t d
 }
 
 hipError_t launch_dense_cell_start(const uint64_t* sorted_keys, int64_t n, int64_t box_cells, uint32_t* cell_start,
-                                   int64_t* d_stats, hipStream_t s) {
+                                   hipStream_t s) {
     hipLaunchKernelGGL(k_dense_cell_start, dim3(grid_for(box_cells + 1, BT)), dim3(BT), 0, s, sorted_keys, n,
                        box_cells, cell_start);
-    hipLaunchKernelGGL(k_dense_cell_stats, dim3(grid_for(box_cells, BT, 4096)), dim3(BT), 0, s, cell_start,
-                       box_cells, d_stats);
     return hipGetLastError();
 }
 

@@ -1,0 +1,652 @@
+// Grouped exploration with bf16 matrix-core screening (Section III-B with the
+// distance step batched over queries).
+//
+// Queries are sorted by the Morton code of their central cell and cut into
+// groups of at most 16 that share a cell (or, under the EXACT rule, a block of
+// 2^s cells per dimension).  One wave walks one group: layer l of the group is
+// the set of occupied cells at Chebyshev distance l from the group's box of
+// central cells, found with the cell tree.  Every query's own layers 0..l lie
+// inside the group's layers 0..l, so each query's stop rule is applied exactly
+// as in the per-query walk.  Under the PAPER rule the group is a single cell,
+// so group layers are the queries' layers.
+//
+// Candidates are staged 64 at a time in LDS, centred on the group box and split
+// into bf16 hi + lo parts.  v_mfma_f32_16x16x32_bf16 forms the 16 x 64 tile of
+// q'.x' with K = [qh, qh, ql] . [xh, xl, xh] (the lo x lo term is dropped), and
+// the screen value is s = |q'|^2 + |x'|^2 - 2 q'.x' in FP32.  With round-to-
+// nearest splits |s - d| <= 2^-16 (|q'|^2 + |x'|^2) (Jacobian of the split and of
+// the FP32 accumulation over 3f terms; see the design notes); a candidate is
+// re-scored in FP64 only if s - 2^-12 (|q'|^2 + |x'|^2) is within the query's
+// k-th distance, so the selected set is the exact FP64 one.
+//
+// In the result tile, lane l holds column l % 16 and rows 4 (l / 16) + i: the
+// 16-lane DPP row g holds queries 4g .. 4g+3.  Each query's size-k buffer lives
+// in registers of its row (entry e = 16 j + t in register j of lane t), so the
+// four rows insert in parallel with row-local DPP shifts.
+#include "ghn_walk.h"
+
+namespace ghn {
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+
+constexpr int GT = 256;          // threads per block
+constexpr int GWPB = GT / WAVE;  // groups (waves) per block
+constexpr int GQ = 16;           // queries per group
+constexpr int STACK_CAP = TREE_LEVELS_MAX * WAVE;
+constexpr float SCREEN_REL = 0x1p-12f;   // admission margin, relative to |q'|^2 + |x'|^2
+constexpr float SCREEN_ABS = 0x1p-100f;  // absolute margin (FP32 underflow)
+
+template <int FT>
+struct KPad {
+    static constexpr int value = FT > 0 ? ((3 * FT + 31) / 32) * 32 : ((3 * F_MAX + 31) / 32) * 32;
+};
+
+// ---- row (16-lane) DPP helpers -------------------------------------------------------------
+__device__ __forceinline__ int row_ror1(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x121, 0xf, 0xf, false); }
+__device__ __forceinline__ double row_ror1_f64(double v) {
+    const int64_t b = __double_as_longlong(v);
+    const int lo = row_ror1((int)(uint32_t)b), hi = row_ror1((int)(uint32_t)((uint64_t)b >> 32));
+    return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+template <int N>
+__device__ __forceinline__ int row_bcast_n(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x150 + N, 0xf, 0xf, false); }
+// Value of lane n (uniform n in 0..15) of each 16-lane row, to every lane of the row.
+__device__ __forceinline__ int row_bcast(int v, int n) {
+    switch (n) {
+        case 0: return row_bcast_n<0>(v);   case 1: return row_bcast_n<1>(v);
+        case 2: return row_bcast_n<2>(v);   case 3: return row_bcast_n<3>(v);
+        case 4: return row_bcast_n<4>(v);   case 5: return row_bcast_n<5>(v);
+        case 6: return row_bcast_n<6>(v);   case 7: return row_bcast_n<7>(v);
+        case 8: return row_bcast_n<8>(v);   case 9: return row_bcast_n<9>(v);
+        case 10: return row_bcast_n<10>(v); case 11: return row_bcast_n<11>(v);
+        case 12: return row_bcast_n<12>(v); case 13: return row_bcast_n<13>(v);
+        case 14: return row_bcast_n<14>(v); default: return row_bcast_n<15>(v);
+    }
+}
+__device__ __forceinline__ double row_bcast_f64(double v, int n) {
+    const int64_t b = __double_as_longlong(v);
+    const int lo = row_bcast((int)(uint32_t)b, n), hi = row_bcast((int)(uint32_t)((uint64_t)b >> 32), n);
+    return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+__device__ __forceinline__ float admit_group(double tau) {
+    if (!(tau < 1.0e300)) return __int_as_float(0x7f800000);
+    return f32_round_up(tau * (1.0 + 0x1p-30)) + 0x1p-125f;
+}
+
+// Sort key and flags of every query: Morton code of its central cell clamped to
+// the occupied box; flag bit 0 = a coordinate is not finite, bit 1 = the central
+// cell lies outside the box (such queries walk alone).
+__global__ __launch_bounds__(256) void k_group_keys(const float* __restrict__ qs, int64_t m, IndexView ix,
+                                                    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                    uint32_t* __restrict__ qflags) {
+    const int f = ix.f;
+    int bits[F_MAX];
+    int maxb = 0;
+    for (int j = 0; j < f; ++j) {
+        const uint32_t span = (uint32_t)(ix.cmax[j] - ix.cmin[j]);
+        bits[j] = span ? 32 - __clz(span) : 0;
+        maxb = max(maxb, bits[j]);
+    }
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
+        uint32_t u[F_MAX];
+        uint32_t fl = 0;
+        for (int j = 0; j < f; ++j) {
+            const float x = qs[i * f + j];
+            int64_t c = 0;
+            if (isfinite(x)) c = exact_floor_div(__dadd_rn((double)x, -(double)ix.o[j]), (double)ix.a[j]);
+            else fl |= 1u;
+            if (c < ix.cmin[j] || c > ix.cmax[j]) fl |= 2u;
+            c = min(max(c, (int64_t)ix.cmin[j]), (int64_t)ix.cmax[j]);
+            u[j] = (uint32_t)(c - ix.cmin[j]);
+        }
+        uint64_t code = 0;
+        for (int b = maxb - 1; b >= 0; --b)
+            for (int j = 0; j < f; ++j)
+                if (b < bits[j]) code = (code << 1) | ((u[j] >> b) & 1u);
+        keys[i] = code;
+        vals[i] = (uint32_t)i;
+        qflags[i] = fl;
+    }
+}
+
+__global__ void k_zero_u32(uint32_t* p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+// Cut the sorted queries into groups: a group starts where the (shifted) key
+// changes, at a query that walks alone, or every GQ positions.
+__device__ __forceinline__ bool group_start(const uint64_t* keys, const uint32_t* vals, const uint32_t* qflags,
+                                            int64_t i, int shift) {
+    if (i == 0 || (i % GQ) == 0) return true;
+    if (qflags[vals[i]] || qflags[vals[i - 1]]) return true;
+    return (keys[i] >> shift) != (keys[i - 1] >> shift);
+}
+
+__global__ __launch_bounds__(256) void k_form_groups(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                                                     const uint32_t* __restrict__ qflags, int64_t m, int shift,
+                                                     uint2* __restrict__ groups, uint32_t* ngroups) {
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
+        if (!group_start(keys, vals, qflags, i, shift)) continue;
+        int64_t j = i + 1;
+        while (j < m && !group_start(keys, vals, qflags, j, shift)) ++j;
+        const uint32_t g = atomicAdd(ngroups, 1u);
+        groups[g] = make_uint2((uint32_t)i, (uint32_t)(j - i));
+    }
+}
+
+struct GroupArgs {
+    PredictArgs p;          // p.order = queries in sorted order
+    const uint2* groups;
+    const uint32_t* counters;  // [0] = number of groups
+    uint32_t* work;            // next group to take
+};
+
+template <int FT>
+struct alignas(16) GroupLds {
+    static constexpr int FS = FT > 0 ? FT : F_MAX;
+    static constexpr int KP = KPad<FT>::value;
+    float q[GQ][FS];
+    int32_t qc[GQ][FS];
+    float x[WAVE][FS];
+    int32_t xid[WAVE];
+    float xn[WAVE];
+    __bf16 frag[WAVE][KP];
+    uint32_t run_begin[WAVE];
+    uint32_t run_pre[WAVE];
+    uint64_t stack[STACK_CAP];
+    int32_t lab[4][K_MAX];
+    int32_t glo[FS], ghi[FS];
+    float og[FS], qlo[FS], qhi[FS];
+};
+
+template <int FT, int KR>
+__global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
+    __shared__ GroupLds<FT> lds_all[GWPB];
+    constexpr int FS = GroupLds<FT>::FS;
+    constexpr int KP = GroupLds<FT>::KP;
+    const PredictArgs& A = G.p;
+    const IndexView& ix = A.ix;
+    const int lane = lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    GroupLds<FT>& S = lds_all[wv];
+    const int f = FT > 0 ? FT : ix.f;
+    const int k = A.k;
+    const int g = lane >> 4, t = lane & 15;
+    const bool prune = !(A.flags & GHN_FLAG_NO_PRUNE);
+    const uint32_t ngroups = G.counters[0];
+
+    for (;;) {
+        uint32_t gid = 0;
+        if (lane == 0) gid = atomicAdd(G.work, 1u);
+        gid = __builtin_amdgcn_readfirstlane(gid);
+        if (gid >= ngroups) break;
+        const uint2 gd = G.groups[gid];
+        const int cnt = (int)gd.y;
+
+        // ---- group set-up: lane r < cnt loads query r
+        bool fin = false;
+        {
+            const bool act = lane < cnt;
+            const int64_t qi = act ? (int64_t)A.order[gd.x + lane] : 0;
+            fin = act;
+            int32_t cc[FS];
+            for (int j = 0; j < f; ++j) {
+                const float x = act ? A.queries[qi * f + j] : 0.0f;
+                fin = fin && isfinite(x);
+                cc[j] = 0;
+                if (act) S.q[lane][j] = x;
+            }
+            for (int j = 0; j < f; ++j) {
+                int64_t c = 0;
+                if (fin) {
+                    const double v = __dadd_rn((double)S.q[lane][j], -(double)ix.o[j]);
+                    c = exact_floor_div(v, (double)ix.a[j]);
+                    c = max(c, (int64_t)ix.cmin[j] - CLAMP);
+                    c = min(c, (int64_t)ix.cmax[j] + CLAMP);
+                }
+                cc[j] = (int32_t)c;
+                if (act) S.qc[lane][j] = cc[j];
+            }
+            // group box of central cells and box of query coordinates (finite queries)
+            for (int j = 0; j < f; ++j) {
+                int32_t lo = fin ? cc[j] : INT32_MAX, hi = fin ? cc[j] : INT32_MIN;
+                float ql = fin ? S.q[lane][j] : __int_as_float(0x7f800000);
+                float qh = fin ? S.q[lane][j] : -__int_as_float(0x7f800000);
+                for (int d = 1; d < WAVE; d <<= 1) {
+                    lo = min(lo, __shfl_xor(lo, d, WAVE));
+                    hi = max(hi, __shfl_xor(hi, d, WAVE));
+                    ql = fminf(ql, __shfl_xor(ql, d, WAVE));
+                    qh = fmaxf(qh, __shfl_xor(qh, d, WAVE));
+                }
+                if (lane == 0) {
+                    S.glo[j] = lo;
+                    S.ghi[j] = hi;
+                    S.qlo[j] = ql;
+                    S.qhi[j] = qh;
+                    S.og[j] = lo <= hi ? (float)((double)ix.o[j] + ((double)lo + (double)hi + 1.0) * 0.5 * (double)ix.a[j]) : 0.0f;
+                }
+            }
+        }
+        const uint64_t fin_mask = ballot(fin);
+        wave_lds_sync();
+
+        // ---- per-slot state (slot i of row g = query 4g + i)
+        double bd[4][KR];
+        int bi[4][KR];
+        double tau[4];
+        int taui[4];
+        float thr[4], qn[4];
+        bool upd[4], done[4];
+        int32_t stopl[4];
+        int64_t cands[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 4 * g + i;
+            const bool live = r < cnt && ((fin_mask >> r) & 1);
+            done[i] = !live;
+            upd[i] = false;
+            stopl[i] = -1;
+            cands[i] = 0;
+            tau[i] = __longlong_as_double(0x7ff0000000000000LL);
+            taui[i] = INT32_MAX;
+            thr[i] = live ? __int_as_float(0x7f800000) : -__int_as_float(0x7f800000);
+#pragma unroll
+            for (int j = 0; j < KR; ++j) { bd[i][j] = tau[i]; bi[i][j] = INT32_MAX; }
+            float s = 0.0f;
+            if (live)
+                for (int j = 0; j < f; ++j) {
+                    const float d = S.q[r][j] - S.og[j];
+                    s = __builtin_fmaf(d, d, s);
+                }
+            qn[i] = s;
+        }
+        // matrix operand of the 16 queries: row l % 16, K = [qh, qh, ql, 0 ...]
+        bf16x8 afr[KP / 32];
+#pragma unroll
+        for (int kb = 0; kb < KP / 32; ++kb) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int kk = 32 * kb + 8 * g + e;
+                const int r = lane & 15;
+                const int part = kk / f, j = kk - part * f;
+                float v = 0.0f;
+                if (part < 3 && r < cnt && ((fin_mask >> r) & 1)) {
+                    const float qp = S.q[r][j] - S.og[j];
+                    const float hi = (float)(__bf16)qp;
+                    v = part == 2 ? (float)(__bf16)(qp - hi) : hi;
+                }
+                afr[kb][e] = (__bf16)v;
+            }
+        }
+        int64_t l0 = 0, lcover = 0;
+        for (int j = 0; j < f; ++j) {
+            const int64_t lo = S.glo[j], hi = S.ghi[j];
+            l0 = max(l0, max((int64_t)ix.cmin[j] - hi, lo - (int64_t)ix.cmax[j]));
+            lcover = max(lcover, max(hi - (int64_t)ix.cmin[j], (int64_t)ix.cmax[j] - lo));
+        }
+        int64_t probes = 0;
+        int64_t l = l0;
+        const bool any_live = (fin_mask & ((cnt >= 64 ? ~0ull : ((1ull << cnt) - 1)))) != 0;
+
+        for (; any_live; ++l) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) upd[i] = false;
+            if (lane == 0) S.stack[0] = ((uint64_t)ix.tree_levels << 40) | ((uint64_t)ix.tree_count[ix.tree_levels] << 32);
+            int sp = 1;
+            wave_lds_sync();
+            while (sp > 0) {
+                --sp;
+                const uint64_t e = S.stack[sp];
+                wave_lds_sync();
+                const int level = (int)(e >> 40);
+                const int count = (int)((e >> 32) & 0xff);
+                const int64_t node = (int64_t)(uint32_t)e + lane;
+                const bool active = lane < count;
+                // largest k-th distance over the live queries (+inf while a buffer is not full)
+                double mt = -1.0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) if (!done[i]) mt = fmax(mt, tau[i]);
+                for (int d = 16; d < WAVE; d <<= 1) mt = fmax(mt, __shfl_xor(mt, d, WAVE));
+                int64_t dmin = 0, dmax = 0;
+                double lb = 0.0;
+                if (active) {
+                    const int32_t* lo = level == 0 ? ix.cell_coord + node * f : ix.node_lo + (ix.tree_off[level] + node) * f;
+                    const int32_t* hi = level == 0 ? lo : ix.node_hi + (ix.tree_off[level] + node) * f;
+                    for (int j = 0; j < f; ++j) {
+                        const int64_t a = lo[j], b = hi[j], ga = S.glo[j], gb = S.ghi[j];
+                        dmin = max(dmin, max(a - gb, ga - b));
+                        dmax = max(dmax, max(ga - a, b - gb));
+                        // distance from the box of query coordinates to the node's region
+                        const double aj = ix.a[j], oj = ix.o[j];
+                        const double below = __dadd_rn(__dadd_rn(__dmul_rn((double)a, aj), oj), -(double)S.qhi[j]);
+                        const double above = __dadd_rn((double)S.qlo[j], -__dadd_rn(__dmul_rn((double)(b + 1), aj), oj));
+                        double gap = below > above ? below : above;
+                        gap = gap > 0.0 ? gap : 0.0;
+                        lb = __dadd_rn(lb, __dmul_rn(gap, gap));
+                    }
+                }
+                const bool close = !prune || !(lb * LB_SHRINK > mt);
+                probes += __popcll(ballot(active));
+                if (level > 0) {
+                    const bool keep = active && dmin <= l && l <= dmax && close;
+                    const uint64_t km = ballot(keep);
+                    if (keep) {
+                        const int64_t c0 = node * WAVE;
+                        const int nc = (int)min((int64_t)WAVE, ix.tree_count[level - 1] - c0);
+                        S.stack[sp + __popcll(km & __lanemask_lt())] =
+                            ((uint64_t)(level - 1) << 40) | ((uint64_t)nc << 32) | (uint32_t)c0;
+                    }
+                    sp += __popcll(km);
+                    wave_lds_sync();
+                    continue;
+                }
+                // cells of layer l: one run of points per kept cell
+                uint32_t rb = 0, rn = 0;
+                if (active && dmin == l && close) {
+                    rb = ix.cell_first[node];
+                    rn = ix.cell_first[node + 1] - rb;
+                }
+                const uint32_t incl = wave_incl_scan(rn);
+                const uint32_t npts = readlane_i32((int)incl, WAVE - 1);
+                if (npts == 0) continue;
+                const uint32_t nrun_incl = wave_incl_scan(rn > 0 ? 1u : 0u);
+                const uint32_t nrun = readlane_i32((int)nrun_incl, WAVE - 1);
+                if (rn > 0) {
+                    S.run_begin[nrun_incl - 1] = rb;
+                    S.run_pre[nrun_incl - 1] = incl - rn;
+                }
+                wave_lds_sync();
+                for (uint32_t base = 0; base < npts; base += WAVE) {
+                    // stage 64 candidates: FP32 copy, id, |x'|^2 and the bf16 K vector
+                    const uint32_t p = base + lane;
+                    const bool valid = p < npts;
+                    float xv[FS];
+                    int id = -1;
+                    float nx = __int_as_float(0x7f800000);
+                    if (valid) {
+                        uint32_t a0 = 0, a1 = nrun;
+                        while (a1 - a0 > 1) {
+                            const uint32_t mid = (a0 + a1) >> 1;
+                            if (S.run_pre[mid] <= p) a0 = mid;
+                            else a1 = mid;
+                        }
+                        const uint32_t pidx = S.run_begin[a0] + (p - S.run_pre[a0]);
+                        load_point<FT>(ix.spts + (size_t)pidx * f, xv, f);
+                        id = ix.sid[pidx];
+                        nx = 0.0f;
+                    }
+                    for (int j = 0; j < f; ++j) {
+                        const float xp = valid ? xv[j] - S.og[j] : 0.0f;
+                        if (valid) nx = __builtin_fmaf(xp, xp, nx);
+                        const float hi = (float)(__bf16)xp;
+                        const __bf16 h16 = (__bf16)hi, l16 = (__bf16)(xp - hi);
+                        S.frag[lane][j] = h16;
+                        S.frag[lane][f + j] = l16;
+                        S.frag[lane][2 * f + j] = h16;
+                        S.x[lane][j] = valid ? xv[j] : 0.0f;
+                    }
+                    for (int kk = 3 * f; kk < KP; ++kk) S.frag[lane][kk] = (__bf16)0.0f;
+                    S.xid[lane] = id;
+                    S.xn[lane] = nx;
+                    wave_lds_sync();
+                    const int nvalid = __popcll(ballot(valid));
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) if (!done[i]) cands[i] += nvalid;
+                    // screen: per slot, a 64-bit mask of the tile's candidates that may enter the
+                    // row's buffer (bit c = candidate c)
+                    uint64_t adm[4] = {0, 0, 0, 0};
+#pragma unroll
+                    for (int cb = 0; cb < WAVE / 16; ++cb) {
+                        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                        const int col = 16 * cb + t;
+#pragma unroll
+                        for (int kb = 0; kb < KP / 32; ++kb) {
+                            const bf16x8 bfr = *(const bf16x8*)&S.frag[col][32 * kb + 8 * g];
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[kb], bfr, acc, 0, 0, 0);
+                        }
+                        const float xn_c = S.xn[col];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const float nsum = qn[i] + xn_c;
+                            const float sv = nsum - 2.0f * acc[i];
+                            const bool flag = sv - __builtin_fmaf(SCREEN_REL, nsum, SCREEN_ABS) <= thr[i];
+                            adm[i] |= ((ballot(flag) >> (16 * g)) & 0xffffull) << (16 * cb);
+                        }
+                    }
+                    // exact FP64 check and insertion, the four rows in parallel
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        uint64_t mrow = adm[i];
+                        while (ballot(mrow != 0)) {
+                            if (mrow != 0) {
+                                const int c = __ffsll((unsigned long long)mrow) - 1;
+                                mrow &= mrow - 1;
+                                const int r = 4 * g + i;
+                                const double cd = dist64<FT>(S.q[r], S.x[c], f);
+                                const int ci = S.xid[c];
+                                if (cd < tau[i] || (cd == tau[i] && ci < taui[i])) {
+                                    // entries larger than the candidate move up one place
+                                    const uint64_t cbits = (uint64_t)__double_as_longlong(cd);
+                                    int ngt = 0;
+#pragma unroll
+                                    for (int j = 0; j < KR; ++j) {
+                                        const int ee = 16 * j + t;
+                                        const uint64_t bb = (uint64_t)__double_as_longlong(bd[i][j]);
+                                        const bool gt = ee < k && (bb > cbits || (bb == cbits && bi[i][j] > ci));
+                                        ngt += __popc((uint32_t)(ballot(gt) >> (16 * g)) & 0xffffu);
+                                    }
+                                    const int pos = k - ngt;
+                                    double rd[KR];
+                                    int ri[KR];
+#pragma unroll
+                                    for (int j = 0; j < KR; ++j) { rd[j] = row_ror1_f64(bd[i][j]); ri[j] = row_ror1(bi[i][j]); }
+#pragma unroll
+                                    for (int j = KR - 1; j >= 0; --j) {
+                                        const int ee = 16 * j + t;
+                                        double nd = rd[j];
+                                        int ni = ri[j];
+                                        if (t == 0) {
+                                            nd = j > 0 ? rd[j > 0 ? j - 1 : 0] : bd[i][j];
+                                            ni = j > 0 ? ri[j > 0 ? j - 1 : 0] : bi[i][j];
+                                        }
+                                        if (ee < k && ee >= pos) {
+                                            bd[i][j] = ee == pos ? cd : nd;
+                                            bi[i][j] = ee == pos ? ci : ni;
+                                        }
+                                    }
+                                    upd[i] = true;
+                                    const int jl = (k - 1) >> 4, tl = (k - 1) & 15;
+                                    double kd = bd[i][0];
+                                    int ki = bi[i][0];
+#pragma unroll
+                                    for (int j = 1; j < KR; ++j) if (j == jl) { kd = bd[i][j]; ki = bi[i][j]; }
+                                    tau[i] = row_bcast_f64(kd, tl);
+                                    taui[i] = row_bcast(ki, tl);
+                                    thr[i] = taui[i] == INT32_MAX ? __int_as_float(0x7f800000) : admit_group(tau[i]);
+                                }
+                            }
+                        }
+                    }
+                    wave_lds_sync();
+                }
+            }
+            // stop rules for every live query of the group, after layer l
+            bool any = false;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (done[i]) continue;
+                const int r = 4 * g + i;
+                const bool full = taui[i] != INT32_MAX;
+                bool stop = l >= lcover;
+                if (!stop && full) {
+                    if (A.stop == GHN_STOP_PAPER) {
+                        stop = !upd[i];
+                    } else {
+                        double r2 = __longlong_as_double(0x7ff0000000000000LL);
+                        for (int j = 0; j < f; ++j) {
+                            const double a = ix.a[j];
+                            const double v = __dadd_rn((double)S.q[r][j], -(double)ix.o[j]);
+                            const int64_t c = S.qc[r][j];
+                            const double glo = __dadd_rn(v, -__dmul_rn((double)(c - l), a));
+                            const double ghi = __dadd_rn(__dmul_rn((double)(c + l + 1), a), -v);
+                            double gg = glo < ghi ? glo : ghi;
+                            if (gg < 0.0) gg = 0.0;
+                            const double g2 = __dmul_rn(gg, gg);
+                            if (g2 < r2) r2 = g2;
+                        }
+                        stop = tau[i] < __dmul_rn(r2, EXACT_SHRINK);
+                    }
+                }
+                if (stop) {
+                    done[i] = true;
+                    stopl[i] = (int32_t)l;
+                    thr[i] = -__int_as_float(0x7f800000);
+                } else {
+                    any = true;
+                }
+            }
+            if (!ballot(any)) break;
+        }
+
+        // ---- outputs, one slot (four queries, one per row) at a time
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 4 * g + i;
+            const bool act = r < cnt;
+            const int64_t qi = act ? (int64_t)A.order[gd.x + r] : 0;
+            const bool live = act && ((fin_mask >> r) & 1);
+            if (act && !live) {
+                for (int j = 0; j < KR; ++j) {
+                    const int ee = 16 * j + t;
+                    if (ee < k) {
+                        A.out_idx[qi * k + ee] = -1;
+                        if (A.out_d2) A.out_d2[qi * k + ee] = __longlong_as_double(0x7ff8000000000000LL);
+                    }
+                }
+                if (t == 0) {
+                    if (ix.task == GHN_CLASSIFY) ((int32_t*)A.out_pred)[qi] = -1;
+                    else ((float*)A.out_pred)[qi] = __int_as_float(0x7fc00000);
+                    if (A.out_stop_layer) A.out_stop_layer[qi] = -1;
+                    if (A.out_cands) A.out_cands[qi] = 0;
+                    if (A.out_probes) A.out_probes[qi] = 0;
+                }
+            }
+            if (live) {
+#pragma unroll
+                for (int j = 0; j < KR; ++j) {
+                    const int ee = 16 * j + t;
+                    if (ee < k) {
+                        A.out_idx[qi * k + ee] = bi[i][j];
+                        if (A.out_d2) A.out_d2[qi * k + ee] = bd[i][j];
+                        S.lab[g][ee] = ((const int32_t*)ix.targets)[bi[i][j]];
+                    }
+                }
+            }
+            wave_lds_sync();
+            if (live) {
+                if (ix.task == GHN_CLASSIFY) {
+                    int best = INT32_MAX, best_n = -1;
+#pragma unroll
+                    for (int j = 0; j < KR; ++j) {
+                        const int ee = 16 * j + t;
+                        if (ee >= k) continue;
+                        const int lab = S.lab[g][ee];
+                        int n = 0;
+                        for (int e2 = 0; e2 < k; ++e2) n += S.lab[g][e2] == lab;
+                        if (n > best_n || (n == best_n && lab < best)) { best = lab; best_n = n; }
+                    }
+                    for (int d = 1; d < 16; d <<= 1) {
+                        const int ob = __shfl_xor(best, d, 16), on = __shfl_xor(best_n, d, 16);
+                        if (on > best_n || (on == best_n && ob < best)) { best = ob; best_n = on; }
+                    }
+                    if (t == 0) ((int32_t*)A.out_pred)[qi] = best;
+                } else if (t == 0) {
+                    double s = 0.0;
+                    for (int e2 = 0; e2 < k; ++e2) s = __dadd_rn(s, (double)__int_as_float(S.lab[g][e2]));
+                    ((float*)A.out_pred)[qi] = (float)(s / (double)k);
+                }
+                if (t == 0) {
+                    if (A.out_stop_layer) A.out_stop_layer[qi] = stopl[i];
+                    if (A.out_cands) A.out_cands[qi] = cands[i];
+                    if (A.out_probes) A.out_probes[qi] = probes;
+                }
+            }
+            wave_lds_sync();
+        }
+    }
+}
+
+template <int FT>
+hipError_t launch_ft(const GroupArgs& a, int blocks, hipStream_t s) {
+    if (a.p.k <= 16) hipLaunchKernelGGL((k_predict_group<FT, 1>), dim3(blocks), dim3(GT), 0, s, a);
+    else if (a.p.k <= 32) hipLaunchKernelGGL((k_predict_group<FT, 2>), dim3(blocks), dim3(GT), 0, s, a);
+    else hipLaunchKernelGGL((k_predict_group<FT, 4>), dim3(blocks), dim3(GT), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t group_ws_bytes(int64_t m) {
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    return 2 * up(m * 8) + 3 * up(m * 4) + up(m * 8) + up(64) + up(radix_sort_temp_bytes(m));
+}
+
+// Sort + group the queries, then walk the groups.  `ws` holds group_ws_bytes(m).
+hipError_t run_grouped(const PredictArgs& pa, int keep_shift_levels, void* ws, hipStream_t s, int* morton_bits) {
+    const IndexView& ix = pa.ix;
+    const int64_t m = pa.m;
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    int bits[F_MAX];
+    int total = 0, maxb = 0;
+    for (int j = 0; j < ix.f; ++j) {
+        const uint32_t span = (uint32_t)(ix.cmax[j] - ix.cmin[j]);
+        bits[j] = span ? 32 - __builtin_clz(span) : 0;
+        total += bits[j];
+        maxb = maxb > bits[j] ? maxb : bits[j];
+    }
+    *morton_bits = total;
+    if (total > 64) return hipErrorInvalidValue;
+    int shift = 0;  // Morton bits of the lowest `keep_shift_levels` bit levels
+    for (int b = 0; b < keep_shift_levels && b < maxb; ++b)
+        for (int j = 0; j < ix.f; ++j) shift += bits[j] > b ? 1 : 0;
+    char* p = (char*)ws;
+    uint64_t* k0 = (uint64_t*)p; p += up(m * 8);
+    uint64_t* k1 = (uint64_t*)p; p += up(m * 8);
+    uint32_t* v0 = (uint32_t*)p; p += up(m * 4);
+    uint32_t* v1 = (uint32_t*)p; p += up(m * 4);
+    uint32_t* qflags = (uint32_t*)p; p += up(m * 4);
+    uint2* groups = (uint2*)p; p += up(m * 8);
+    uint32_t* counters = (uint32_t*)p; p += up(64);
+    void* rtemp = p;
+    int64_t g = (m + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counters, 2);
+    hipLaunchKernelGGL(k_group_keys, dim3((unsigned)g), dim3(256), 0, s, pa.queries, m, ix, k0, v0, qflags);
+    bool alt = false;
+    hipError_t e = radix_sort_pairs(k0, v0, k1, v1, m, total, rtemp, &alt, s);
+    if (e != hipSuccess) return e;
+    const uint64_t* sk = alt ? k1 : k0;
+    const uint32_t* sv = alt ? v1 : v0;
+    hipLaunchKernelGGL(k_form_groups, dim3((unsigned)g), dim3(256), 0, s, sk, sv, qflags, m, shift, groups, counters);
+    GroupArgs ga;
+    ga.p = pa;
+    ga.p.order = sv;
+    ga.groups = groups;
+    ga.counters = counters;
+    ga.work = counters + 1;
+    int64_t blocks = (m + GQ * GWPB - 1) / (GQ * GWPB);
+    if (blocks > 2048) blocks = 2048;
+    switch (ix.f) {
+        case 2: return launch_ft<2>(ga, (int)blocks, s);
+        case 3: return launch_ft<3>(ga, (int)blocks, s);
+        case 4: return launch_ft<4>(ga, (int)blocks, s);
+        case 8: return launch_ft<8>(ga, (int)blocks, s);
+        case 16: return launch_ft<16>(ga, (int)blocks, s);
+        default: return launch_ft<0>(ga, (int)blocks, s);
+    }
+}
+
+}  // namespace ghn

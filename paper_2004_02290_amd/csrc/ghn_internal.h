@@ -34,8 +34,10 @@ struct IndexView {
     const uint32_t* cell_start; // dense: box_cells + 1 offsets into spts; tree: num_cells + 1
     const void* targets;        // n targets, original order
     int64_t box_cells;
-    // tree lookup: occupied cells in Morton order and the bounding boxes above them
+    // occupied cells in key order (Morton for the tree lookup, row-major for the
+    // dense one) and the bounding boxes above them
     int64_t num_cells;
+    const uint32_t* cell_first; // num_cells + 1 offsets into spts
     const int32_t* cell_coord;  // num_cells x f cell ids
     int32_t tree_levels;        // levels above the cells (the root entry's level)
     int64_t tree_count[TREE_LEVELS_MAX];  // nodes per level; level 0 = cells
@@ -124,7 +126,7 @@ hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, 
 hipError_t launch_gather_points(const void* pts, int64_t n, int32_t f, int32_t dtype, const uint32_t* perm,
                                 float* spts, int32_t* sid, hipStream_t s);
 hipError_t launch_dense_cell_start(const uint64_t* sorted_keys, int64_t n, int64_t box_cells,
-                                   uint32_t* cell_start, int64_t* d_stats, hipStream_t s);
+                                   uint32_t* cell_start, hipStream_t s);
 
 // stats[0] += non-empty cells, stats[1] = max points in one cell, over `ncells` offsets.
 hipError_t launch_cell_stats(const uint32_t* cell_start, int64_t ncells, int64_t* d_stats, hipStream_t s);
@@ -155,6 +157,9 @@ struct PredictArgs {
 };
 hipError_t launch_predict_dense(const PredictArgs& a, hipStream_t s);
 hipError_t launch_predict_tree(const PredictArgs& a, hipStream_t s);
+// Grouped walk with the bf16 matrix-core screen: sort, group and walk the queries.
+size_t group_ws_bytes(int64_t m);
+hipError_t run_grouped(const PredictArgs& pa, int group_levels, void* ws, hipStream_t s, int* morton_bits);
 // Spatial sort key of every query (Morton code of its box-clamped central cell).
 hipError_t launch_query_keys(const float* qs, int64_t m, const IndexView& ix, int keep_bits, uint64_t* keys,
                              uint32_t* vals, hipStream_t s);

@@ -164,8 +164,8 @@ __global__ __launch_bounds__(PT) void k_predict_tree(PredictArgs A) {
             if (level == 0) {
                 uint32_t b0 = 0, n0 = 0;
                 if (active && dmin == l && close) {
-                    b0 = ix.cell_start[node];
-                    n0 = ix.cell_start[node + 1] - b0;
+                    b0 = ix.cell_first[node];
+                    n0 = ix.cell_first[node + 1] - b0;
                 }
                 score_runs<FT>(ix, Q.q, f, k, b0, n0, 0u, 0u, s_begin[wv], s_pre[wv], st);
             } else {

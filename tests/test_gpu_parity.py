@@ -350,3 +350,70 @@ def test_bf16_16d_small(ghn):
     ix, _ = _check_exact(ghn, prob)
     assert ix.info.lookup == TREE
     _check_paper(ghn, prob, sample=200)
+
+
+# ---------------------------------------------------------------------------------- bf16 MFMA form
+MFMA = 1
+
+
+def _check_mfma(ghn, prob, sample=None, levels=-1, lookup=None, paper=True, seed=0):
+    ix = _index(ghn, prob, lookup=lookup)
+    got = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_EXACT, prec=MFMA, group_levels=levels)
+    rows = np.arange(prob.m)
+    if sample is not None and sample < prob.m:
+        rows = np.sort(np.random.default_rng(seed).choice(prob.m, sample, replace=False))
+    bi, bd, bp = oracle.bruteforce(prob.points_f32(), prob.targets, prob.task, prob.queries[rows], prob.k)
+    _assert_same({k: v[rows] for k, v in got.items()}, dict(idx=bi, d2=bd, pred=bp), prob.name + " MFMA EXACT")
+    if paper:
+        gp = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_PAPER, prec=MFMA)
+        want = oracle.Grid(prob.points_f32(), prob.targets, prob.task, prob.cell_width).predict(
+            prob.queries[rows], prob.k, oracle.STOP_PAPER)
+        _assert_same({k: v[rows] for k, v in gp.items()}, want, prob.name + " MFMA PAPER", check_layers=True)
+    return ix, got
+
+
+def test_mfma_blobs2d(ghn):
+    _check_mfma(ghn, W.make("blobs2d"))
+
+
+def test_mfma_clusters4d_small(ghn):
+    prob = W.make("clusters4d", n=60_000, m=3_001)
+    for levels in (-1, 0, 2):
+        _check_mfma(ghn, prob, levels=levels, paper=levels == -1)
+
+
+@pytest.mark.parametrize("k", [1, 5, 16, 17, 32, 33, 64])
+def test_mfma_k_values(ghn, k):
+    prob = W.uniform_problem(n=5000, m=300, f=3, k=k, seed=200 + k, width=0.08)
+    _check_mfma(ghn, prob)
+
+
+def test_mfma_ties_far_nonfinite(ghn):
+    lat = W.lattice_problem(n=3000, m=300, f=3, k=12, seed=5)
+    _check_mfma(ghn, lat)
+    reg = W.lattice_problem(n=3000, m=300, f=2, k=20, seed=6, task=W.REGRESS)
+    _check_mfma(ghn, reg)
+    far = W.uniform_problem(n=5000, m=200, f=3, k=5, seed=7, width=0.1)
+    far.queries[:50] *= 1e3
+    far.queries[50:90] -= 37.0
+    _check_mfma(ghn, far)
+    bad = W.uniform_problem(n=1000, m=40, f=2, k=3, seed=8, width=0.1)
+    bad.queries[3, 1] = np.nan
+    ix = _index(ghn, bad)
+    got = _run(ghn, ix, bad.queries, bad.k, ghn.GHN_STOP_EXACT, prec=MFMA)
+    assert (got["idx"][3] == -1).all() and got["pred"][3] == -1
+    ok = np.delete(np.arange(bad.m), 3)
+    bi, bd, bp = oracle.bruteforce(bad.points, bad.targets, bad.task, bad.queries[ok], bad.k)
+    assert np.array_equal(got["idx"][ok], bi) and np.array_equal(got["d2"][ok], bd)
+
+
+@pytest.mark.parametrize("f", [1, 2, 4, 5, 8])
+def test_mfma_dims(ghn, f):
+    width = {1: 0.003, 2: 0.05, 4: 0.2, 5: 0.3, 8: 0.5}[f]
+    prob = W.uniform_problem(n=6000, m=301, f=f, k=9, seed=300 + f, width=width, q_lo=-0.3, q_hi=1.3)
+    _check_mfma(ghn, prob)
+
+
+def test_mfma_skew8d_and_bf16_16d(ghn):
+    _check_mfma(ghn, W.make("skew8d", n=100_000, m=1_000), sample=300)
+    _check_mfma(ghn, W.make("bf16_16d", n=60_000, m=600), sample=200)
