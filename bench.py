@@ -24,30 +24,35 @@ sys.path.insert(0, ROOT)
 
 METRIC = "queries/sec at k=10 on 1 MI355X, BF16-batched vs FP32 form; % HBM/MFMA peak"
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-PREDICT_SRC = os.path.join(ROOT, "paper_2004_02290_amd", "csrc", "ghn_predict.hip")
+CSRC = os.path.join(ROOT, "paper_2004_02290_amd", "csrc")
 
 
 def describe(prob, stop_name):
-    return ("%s: n=%d f=%d %s points, m=%d queries, k=%d, %s, %s stop, FP32 screen + FP64 boundary" % (
+    return ("%s: n=%d f=%d %s points, m=%d queries, k=%d, %s, %s stop" % (
         prob.name, prob.n, prob.f, prob.dtype.upper(), prob.m, prob.k,
         "majority vote" if prob.task == 0 else "mean", stop_name))
 
 
 def source_hash() -> str:
-    with open(PREDICT_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the HIP sources (the kernels the counters were taken on)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, form: str):
     """HBM bytes per launch from the committed rocprofv3 counter runs, if the kernel is unchanged."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    entry = t.get(workload)
-    if not entry or entry.get("predict_source_sha256_16") != source_hash():
+    entry = t.get("%s/%s" % (workload, form))
+    if not entry or entry.get("source_sha256_16") != source_hash():
         return None
     return entry.get("bytes_per_launch")
 
@@ -79,7 +84,9 @@ def main():
     ap.add_argument("--workload", default="clusters4d")
     ap.add_argument("--stop", default="exact", choices=["exact", "paper"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-sort", action="store_true", help="walk queries in input order")
+    ap.add_argument("--sort", action="store_true", help="FP32 form: walk queries in spatial (Morton) order")
+    ap.add_argument("--forms", default="fp32,bf16", help="comma list of forms to time: fp32, bf16")
+    ap.add_argument("--group-levels", type=int, default=-1, help="bf16 form: cell-id bits dropped to group queries")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -118,80 +125,109 @@ def main():
     build_ms = (time.perf_counter() - t0) * 1e3
 
     m, k = prob.m, prob.k
+    f = prob.f
     out_idx = torch.empty((m, k), dtype=torch.int64, device=dev)
     out_pred = torch.empty(m, dtype=torch.int32 if prob.task == 0 else torch.float32, device=dev)
 
-    # Work counts for the algorithmic byte figure (untimed pass with statistics).
-    flags = ghn.GHN_FLAG_NO_SORT if args.no_sort else 0
-    nws = ghn.ghn_predict_workspace_bytes(ix.handle, m, k, stop, ghn.GHN_PREC_FP32, flags)
-    ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dev)
-    st = ix.predict(qs, k, stop=stop, flags=flags, with_d2=False, with_stats=True)
-    torch.cuda.synchronize()
-    cands = int(st["cands"].sum().item())
-    probes = int(st["probes"].sum().item())
-    layers = st["stop_layer"].double()
-    del st
+    def timed(step, ev_mid_needed=False):
+        for _ in range(args.warmup):
+            step(None)
+        torch.cuda.synchronize()
+        ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        evm = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        for i in range(args.steps):
+            ev0[i].record()
+            step(evm[i] if ev_mid_needed else None)
+            ev1[i].record()
+        torch.cuda.synchronize()
+        per = np.array([ev0[i].elapsed_time(ev1[i]) for i in range(args.steps)])
+        ms = float(ev0[0].elapsed_time(ev1[-1])) / args.steps
+        kern = np.array([evm[i].elapsed_time(ev1[i]) for i in range(args.steps)]) if ev_mid_needed else per
+        return ms, float(kern.mean()), per
 
-    # A step = spatial order of the batch (Morton sort) + the walk kernel.  Events
-    # between the two calls time the walk kernel alone, on the stream both run on.
-    order = torch.empty(m, dtype=torch.int32, device=dev)
-    ows = torch.empty(max(ghn.ghn_query_order_workspace_bytes(m), 1), dtype=torch.uint8, device=dev)
+    def stats(prec, flags=0, levels=-1):
+        st = ix.predict(qs, k, stop=stop, prec=prec, flags=flags, with_d2=False, with_stats=True, group_levels=levels)
+        torch.cuda.synchronize()
+        out = dict(cands=int(st["cands"].sum().item()), probes=int(st["probes"].sum().item()),
+                   layers=float(st["stop_layer"].double().mean().item()))
+        del st
+        return out
 
-    def step(ev_mid=None):
-        if args.no_sort:
-            if ev_mid is not None:
-                ev_mid.record()
-            ghn.ghn_predict(ix.handle, qs, k, out_idx, out_pred, None, stop, ghn.GHN_PREC_FP32, flags, ws=ws)
-        else:
-            ghn.ghn_query_order(ix.handle, qs, order, ows)
-            if ev_mid is not None:
-                ev_mid.record()
-            ghn.ghn_predict(ix.handle, qs, k, out_idx, out_pred, None, stop, ghn.GHN_PREC_FP32, flags, order=order)
+    forms = {}
+    if "fp32" in args.forms:
+        # per-query walk; with --sort a step = spatial order (Morton sort) + walk, events
+        # between the two calls time the walk kernel alone on the stream both run on
+        flags = 0 if args.sort else ghn.GHN_FLAG_NO_SORT
+        w = stats(ghn.GHN_PREC_FP32, flags)
+        order = torch.empty(m, dtype=torch.int32, device=dev)
+        ows = torch.empty(max(ghn.ghn_query_order_workspace_bytes(m), 1), dtype=torch.uint8, device=dev)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    evm = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    for i in range(args.steps):
-        ev0[i].record()
-        step(evm[i])
-        ev1[i].record()
-    torch.cuda.synchronize()
-    per = np.array([ev0[i].elapsed_time(ev1[i]) for i in range(args.steps)])
-    walk = np.array([evm[i].elapsed_time(ev1[i]) for i in range(args.steps)])
-    ms = float(ev0[0].elapsed_time(ev1[-1])) / args.steps
-    walk_ms = float(walk.mean())
+        def step32(ev_mid):
+            if args.sort:
+                ghn.ghn_query_order(ix.handle, qs, order, ows)
+                if ev_mid is not None:
+                    ev_mid.record()
+                ghn.ghn_predict(ix.handle, qs, k, out_idx, out_pred, None, stop, ghn.GHN_PREC_FP32, 0, order=order)
+            else:
+                if ev_mid is not None:
+                    ev_mid.record()
+                ghn.ghn_predict(ix.handle, qs, k, out_idx, out_pred, None, stop, ghn.GHN_PREC_FP32, flags)
 
-    f = prob.f
-    alg_bytes = (m * 4 * f + cands * (4 * f + 4) + probes * 4 + m * k * 4 + m * k * 8 + m * 4)
-    achieved = alg_bytes / (walk_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload)
+        ms, kern_ms, per = timed(step32, True)
+        alg_bytes = (m * 4 * f + w["cands"] * (4 * f + 4) + w["probes"] * 4 + m * k * 4 + m * k * 8 + m * 4)
+        achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+        forms["fp32_plain"] = dict(
+            qps=m / (ms * 1e-3), ms_per_step=ms, kernel_ms=kern_ms, per=per, work=w,
+            roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, "fp32"),
+                      "kernel": "k_predict_%s" % ("dense" if ix.info.lookup == 0 else "tree")},
+            alg={"bytes_per_step": alg_bytes})
+    if "bf16" in args.forms:
+        nws = ghn.ghn_predict_workspace_bytes(ix.handle, m, k, stop, ghn.GHN_PREC_BF16_MFMA, 0, args.group_levels)
+        ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dev)
+        w = stats(ghn.GHN_PREC_BF16_MFMA, 0, args.group_levels)
+
+        def step16(ev_mid):
+            ghn.ghn_predict(ix.handle, qs, k, out_idx, out_pred, None, stop, ghn.GHN_PREC_BF16_MFMA, 0, ws=ws,
+                            group_levels=args.group_levels)
+
+        ms, kern_ms, per = timed(step16, False)
+        flops = 2.0 * f * w["cands"]  # algorithmic: 2 f per screened (query, candidate) pair
+        achieved = flops / (ms * 1e-3) / 1e12
+        forms["bf16_batched"] = dict(
+            qps=m / (ms * 1e-3), ms_per_step=ms, kernel_ms=ms, per=per, work=w,
+            roofline={"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": measured_traffic(args.workload, "bf16"),
+                      "kernel": "k_predict_group (timed with its query sort and grouping)"},
+            alg={"flops_per_step": flops, "issued_mfma_flops_per_step": 2.0 * (-(-3 * f // 32) * 32) * w["cands"]})
+
+    best = max(forms, key=lambda name: forms[name]["qps"])
+    B = forms[best]
     line = {
         "metric": METRIC,
-        "value": m / (ms * 1e-3),
+        "value": B["qps"],
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": B["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if best == "fp32_plain" else "bf16+f32+f64",
         "data": "synthetic",
         "config": {"workload": describe(prob, args.stop.upper()), "n": prob.n, "f": f, "m": m, "k": k,
-                   "cell_width": prob.cell_width, "stop": args.stop, "form": "fp32_plain",
-                   "query_order": "input" if args.no_sort else "morton"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
-        "forms": {"fp32_plain_qps": m / (ms * 1e-3), "bf16_batched_qps": None},
-        "walk_kernel_ms": walk_ms,
-        "step_ms_p10_p50_p90": [float(np.percentile(per, 10)), float(np.median(per)), float(np.percentile(per, 90))],
-        "work": {"candidates_per_query": cands / m, "table_reads_per_query": probes / m,
-                 "mean_stop_layer": float(layers.mean().item()), "algorithmic_bytes_per_step": alg_bytes},
+                   "cell_width": prob.cell_width, "stop": args.stop, "form": best,
+                   "lookup": "dense" if ix.info.lookup == 0 else "tree"},
+        "roofline": B["roofline"],
+        "forms": {name: {"qps": v["qps"], "ms_per_step": v["ms_per_step"], "kernel_ms": v["kernel_ms"],
+                         "step_ms_p10_p50_p90": [float(np.percentile(v["per"], 10)), float(np.median(v["per"])),
+                                                 float(np.percentile(v["per"], 90))],
+                         "candidates_per_query": v["work"]["cands"] / m, "index_reads_per_query": v["work"]["probes"] / m,
+                         "mean_stop_layer": v["work"]["layers"], "roofline": v["roofline"], "algorithmic": v["alg"]}
+                  for name, v in forms.items()},
         "build_ms": build_ms,
         "index": {"num_cells": int(ix.info.num_cells), "box_cells": int(ix.info.box_cells),
                   "max_occupancy": int(ix.info.max_occupancy)},

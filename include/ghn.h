@@ -205,6 +205,41 @@ size_t ghn_query_order_workspace_bytes(int64_t m);
 ghn_status ghn_query_order(const ghn_index* index, const float* queries, int64_t m, uint32_t* out_order, void* ws,
                            size_t ws_bytes, void* stream);
 
+/* ---- many independent indexes in one launch -------------------------------------
+ * A batch is a list of (index, queries, k, outputs) items answered by ONE
+ * persistent kernel launch: waves take queries of all items from a shared work
+ * counter, so items of very different size and depth balance across the GPU.
+ * ghn_batch_prepare validates the items, uploads their descriptors into the
+ * caller's device workspace (synchronising `stream`) and returns a HOST handle;
+ * ghn_predict_batched then only launches kernels that read device memory, so
+ * the call can be captured into a graph (hipStreamBeginCapture) and replayed.
+ * Results equal those of ghn_predict on each item with the same options (FP32
+ * screen; the bf16 screen is per index).  All items must share f. */
+typedef struct {
+    const ghn_index* index;
+    const float* queries;  /* m x f float32 */
+    int64_t m;
+    int32_t k;
+    int64_t* out_idx;      /* m x k */
+    double* out_d2;        /* m x k or NULL */
+    void* out_pred;        /* m */
+} ghn_batch_item;
+
+typedef struct ghn_batch ghn_batch;
+
+size_t ghn_batch_workspace_bytes(int32_t n_items);
+/* items and opts are HOST memory; opts may be NULL (EXACT, FP32).  Only the stop
+ * rule and flags of opts are used; prec must be GHN_PREC_FP32.  The workspace
+ * and every item's arrays must stay valid until the batch is destroyed.
+ * Errors: GHN_E_INVALID_ARG, GHN_E_K_GT_N, GHN_E_WORKSPACE, GHN_E_UNSUPPORTED,
+ * GHN_E_HIP. */
+ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const ghn_predict_opts* opts, void* ws,
+                             size_t ws_bytes, void* stream, ghn_batch** out);
+/* Asynchronous on `stream`; allocates nothing.  Batches sharing a workspace
+ * must not run concurrently. */
+ghn_status ghn_predict_batched(const ghn_batch* batch, void* stream);
+void ghn_batch_destroy(ghn_batch* batch);
+
 /* Last error message of the calling thread ("" if none).  Valid until the
  * thread's next failing call. */
 const char* ghn_last_error(void);

@@ -32,7 +32,8 @@ GHN_K_MAX, GHN_F_MAX = 64, 32
 GHN_LOOKUP_AUTO, GHN_LOOKUP_DENSE, GHN_LOOKUP_TREE = -1, 0, 1
 
 EXPORTED = ["ghn_build", "ghn_build_ex", "ghn_index_get_info", "ghn_destroy", "ghn_predict_workspace_bytes", "ghn_predict",
-            "ghn_query_order_workspace_bytes", "ghn_query_order", "ghn_last_error"]
+            "ghn_query_order_workspace_bytes", "ghn_query_order", "ghn_batch_workspace_bytes", "ghn_batch_prepare",
+            "ghn_predict_batched", "ghn_batch_destroy", "ghn_last_error"]
 
 
 class GHNError(RuntimeError):
@@ -58,6 +59,12 @@ class ghn_predict_opts(ctypes.Structure):
                 ("group_levels", ctypes.c_int32)]
 
 
+class ghn_batch_item(ctypes.Structure):
+    _fields_ = [("index", ctypes.c_void_p), ("queries", ctypes.c_void_p), ("m", ctypes.c_int64),
+                ("k", ctypes.c_int32), ("out_idx", ctypes.c_void_p), ("out_d2", ctypes.c_void_p),
+                ("out_pred", ctypes.c_void_p)]
+
+
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError("libghn.so is not built (%s); run __graft_entry__.build() or "
@@ -80,6 +87,15 @@ def _load() -> ctypes.CDLL:
     L.ghn_query_order_workspace_bytes.restype = SZ
     L.ghn_query_order.argtypes = [P, P, I64, P, P, SZ, P]
     L.ghn_query_order.restype = ctypes.c_int
+    L.ghn_batch_workspace_bytes.argtypes = [I32]
+    L.ghn_batch_workspace_bytes.restype = SZ
+    L.ghn_batch_prepare.argtypes = [ctypes.POINTER(ghn_batch_item), I32, ctypes.POINTER(ghn_predict_opts), P, SZ, P,
+                                    ctypes.POINTER(P)]
+    L.ghn_batch_prepare.restype = ctypes.c_int
+    L.ghn_predict_batched.argtypes = [P, P]
+    L.ghn_predict_batched.restype = ctypes.c_int
+    L.ghn_batch_destroy.argtypes = [P]
+    L.ghn_batch_destroy.restype = None
     L.ghn_last_error.argtypes = []
     L.ghn_last_error.restype = ctypes.c_char_p
     return L
@@ -200,6 +216,31 @@ def ghn_query_order(handle, queries: torch.Tensor, out_order: torch.Tensor, ws: 
     m = queries.shape[0]
     ws_bytes = ws.numel() * ws.element_size()
     _check(_lib.ghn_query_order(handle, _ptr(queries), m, _ptr(out_order), _ptr(ws), ws_bytes, _stream(stream)))
+
+
+def ghn_batch_workspace_bytes(n_items: int) -> int:
+    return int(_lib.ghn_batch_workspace_bytes(n_items))
+
+
+def ghn_batch_prepare(items, ws: torch.Tensor, stop=GHN_STOP_EXACT, flags=0, stream=None) -> ctypes.c_void_p:
+    """ghn_batch_prepare: items = [(handle, queries, k, out_idx, out_pred, out_d2 or None), ...]."""
+    arr = (ghn_batch_item * len(items))()
+    for i, (h, q, k, oi, op, od) in enumerate(items):
+        arr[i] = ghn_batch_item(h.value if isinstance(h, ctypes.c_void_p) else h, _ptr(q), q.shape[0], int(k),
+                                _ptr(oi), _ptr(od), _ptr(op))
+    o = _opts(stop, GHN_PREC_FP32, flags)
+    out = ctypes.c_void_p()
+    _check(_lib.ghn_batch_prepare(arr, len(items), ctypes.byref(o), _ptr(ws), ws.numel() * ws.element_size(),
+                                  _stream(stream), ctypes.byref(out)))
+    return out
+
+
+def ghn_predict_batched(batch, stream=None) -> None:
+    _check(_lib.ghn_predict_batched(batch, _stream(stream)))
+
+
+def ghn_batch_destroy(batch) -> None:
+    _lib.ghn_batch_destroy(batch)
 
 
 class Index:

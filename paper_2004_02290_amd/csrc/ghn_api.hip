@@ -11,8 +11,18 @@
 
 struct ghn_index {
     ghn::IndexView view;
+    ghn::IndexView* view_dev;  // device copy of `view` (for batched launches)
     ghn_index_info info;
     std::vector<void*> allocs;
+};
+
+struct ghn_batch {
+    ghn::BatchItem* items_dev;
+    uint64_t* counter_dev;
+    int32_t n_items;
+    int64_t total;
+    int32_t f;
+    int32_t stop;
 };
 
 namespace {
@@ -63,6 +73,84 @@ int64_t dense_limit(int64_t n) {
 extern "C" {
 
 const char* ghn_last_error(void) { return g_err.c_str(); }
+
+size_t ghn_batch_workspace_bytes(int32_t n_items) {
+    if (n_items <= 0) return 0;
+    return (((size_t)n_items * sizeof(ghn::BatchItem) + 255) & ~(size_t)255) + 256;
+}
+
+ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const ghn_predict_opts* opts, void* ws,
+                             size_t ws_bytes, void* stream, ghn_batch** out) {
+    using namespace ghn;
+    if (!out) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: out is NULL");
+    *out = nullptr;
+    if (!items || n_items < 1) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: no items");
+    ghn_predict_opts o = {GHN_STOP_EXACT, GHN_PREC_FP32, 0u, nullptr, nullptr, nullptr, nullptr, -1};
+    if (opts) o = *opts;
+    if (o.stop != GHN_STOP_EXACT && o.stop != GHN_STOP_PAPER) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: bad stop rule %d", o.stop);
+    if (o.prec != GHN_PREC_FP32) return fail(GHN_E_UNSUPPORTED, "ghn_batch_prepare: batches use the FP32 screen");
+    if (o.flags & ~(GHN_FLAG_NO_PRUNE | GHN_FLAG_NO_SORT)) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: unknown flags 0x%x", o.flags);
+    const size_t need = ghn_batch_workspace_bytes(n_items);
+    if (!ws || ws_bytes < need)
+        return fail(GHN_E_WORKSPACE, "ghn_batch_prepare: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
+    if ((uintptr_t)ws % 256) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: workspace must be 256-byte aligned");
+    std::vector<BatchItem> h((size_t)n_items);
+    int64_t total = 0;
+    int32_t f = -1;
+    for (int32_t i = 0; i < n_items; ++i) {
+        const ghn_batch_item& it = items[i];
+        if (!it.index) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: item %d has no index", i);
+        if (f < 0) f = it.index->info.f;
+        if (it.index->info.f != f) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: item %d has f=%d, item 0 f=%d", i, it.index->info.f, f);
+        if (it.m < 0) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: item %d has m < 0", i);
+        if (it.k < 1 || it.k > K_MAX) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: item %d has k=%d outside [1, %d]", i, it.k, K_MAX);
+        if (it.k > it.index->info.n) return fail(GHN_E_K_GT_N, "ghn_batch_prepare: item %d has k=%d > n=%lld", i, it.k, (long long)it.index->info.n);
+        if (it.m > 0 && (!it.queries || !it.out_idx || !it.out_pred))
+            return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: item %d has a NULL array", i);
+        if (((uintptr_t)it.queries % 4) || ((uintptr_t)it.out_idx % 8) || ((uintptr_t)it.out_pred % 4) || ((uintptr_t)it.out_d2 % 8))
+            return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: item %d has a misaligned array", i);
+        BatchItem& b = h[(size_t)i];
+        b.ix = it.index->view_dev;
+        b.io.queries = it.queries;
+        b.io.out_idx = it.out_idx;
+        b.io.out_d2 = it.out_d2;
+        b.io.out_pred = it.out_pred;
+        b.io.out_stop_layer = nullptr;
+        b.io.out_cands = nullptr;
+        b.io.out_probes = nullptr;
+        b.io.k = it.k;
+        b.io.flags = o.flags;
+        b.first = total;
+        b.m = it.m;
+        total += it.m;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "ghn_batch_prepare: pending HIP error");
+    if ((e = hipMemcpyAsync(ws, h.data(), h.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "ghn_batch_prepare: upload");
+    ghn_batch* b = new ghn_batch();
+    b->items_dev = (BatchItem*)ws;
+    b->counter_dev = (uint64_t*)((char*)ws + need - 256);
+    b->n_items = n_items;
+    b->total = total;
+    b->f = f;
+    b->stop = o.stop;
+    *out = b;
+    return GHN_OK;
+}
+
+ghn_status ghn_predict_batched(const ghn_batch* batch, void* stream) {
+    if (!batch) return fail(GHN_E_INVALID_ARG, "ghn_predict_batched: batch is NULL");
+    if (batch->total == 0) return GHN_OK;
+    hipError_t e = ghn::launch_predict_batched(batch->items_dev, batch->n_items, batch->total, batch->f, batch->stop,
+                                               batch->counter_dev, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "ghn_predict_batched: launch");
+    return GHN_OK;
+}
+
+void ghn_batch_destroy(ghn_batch* batch) { delete batch; }
 
 ghn_status ghn_build(const void* points, int64_t n, int32_t f, int32_t dtype, const void* targets, int32_t task,
                      const float* cell_width, int32_t n_width, const float* origin, void* stream,
@@ -244,8 +332,14 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
     if ((e = hipMemcpyAsync(&h, d_small, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess) return hip_fail(e, "ghn_build: readback");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "ghn_build: sync");
 
+    ghn::IndexView* ivd;
+    if (keep.alloc((void**)&ivd, sizeof(IndexView))) return fail(GHN_E_NOMEM, "ghn_build: out of device memory");
+    if ((e = hipMemcpyAsync(ivd, &iv, sizeof iv, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "ghn_build: index view upload");
     ghn_index* ix = new ghn_index();
     ix->view = iv;
+    ix->view_dev = ivd;
     std::memset(&ix->info, 0, sizeof ix->info);
     ix->info.n = n; ix->info.f = f; ix->info.dtype = dtype; ix->info.task = task; ix->info.lookup = lookup;
     ix->info.num_cells = iv.num_cells;
@@ -357,17 +451,17 @@ ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, 
     if (e != hipSuccess) return hip_fail(e, "ghn_predict: pending HIP error");
     PredictArgs pa;
     pa.ix = index->view;
-    pa.queries = queries;
+    pa.io.queries = queries;
     pa.m = m;
-    pa.k = k;
+    pa.io.k = k;
     pa.stop = o.stop;
-    pa.flags = o.flags;
-    pa.out_idx = out_idx;
-    pa.out_d2 = out_d2;
-    pa.out_pred = out_pred;
-    pa.out_stop_layer = o.out_stop_layer;
-    pa.out_cands = o.out_cands;
-    pa.out_probes = o.out_probes;
+    pa.io.flags = o.flags;
+    pa.io.out_idx = out_idx;
+    pa.io.out_d2 = out_d2;
+    pa.io.out_pred = out_pred;
+    pa.io.out_stop_layer = o.out_stop_layer;
+    pa.io.out_cands = o.out_cands;
+    pa.io.out_probes = o.out_probes;
     pa.order = o.order;
     hipStream_t s = (hipStream_t)stream;
     if (o.prec == GHN_PREC_BF16_MFMA) {

@@ -1,0 +1,86 @@
+// Many independent indexes answered in one persistent launch.
+//
+// The queries of all batch items form one index space: item i owns global query
+// positions [first_i, first_i + m_i).  Waves take chunks of positions from one
+// atomic counter (work stealing, so items of very different cost balance), find
+// the item of each position by a binary search over the items' first positions,
+// and walk that query with the item's own index (dense or tree lookup) exactly
+// as the single-index kernels do.  The launch reads only device memory, so it
+// can be captured in a graph and replayed.
+#include "ghn_walk_dense.h"
+#include "ghn_walk_tree.h"
+
+namespace ghn {
+namespace {
+
+constexpr int BPT = 256;
+constexpr int BWPB = BPT / WAVE;
+constexpr int CHUNK = 4;  // queries taken per atomic
+
+__global__ void k_reset_counter(uint64_t* counter) {
+    if (threadIdx.x == 0) *counter = 0;
+}
+
+template <int FT, int STOP>
+__global__ __launch_bounds__(BPT) void k_predict_batched(const BatchItem* __restrict__ items, int n_items,
+                                                         int64_t total, uint64_t* counter) {
+    __shared__ uint32_t s_begin[BWPB][RUN_CAP];
+    __shared__ uint32_t s_pre[BWPB][RUN_CAP];
+    __shared__ uint64_t s_stack[BWPB][TREE_STACK_CAP];
+    const int lane = lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    for (;;) {
+        uint64_t w0 = 0;
+        if (lane == 0) w0 = atomicAdd((unsigned long long*)counter, (unsigned long long)CHUNK);
+        w0 = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(w0 >> 32)) << 32) |
+             (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)w0);
+        if ((int64_t)w0 >= total) break;
+        for (int c = 0; c < CHUNK; ++c) {
+            const int64_t w = (int64_t)w0 + c;
+            if (w >= total) break;
+            int lo = 0, hi = n_items;  // last item whose first position is <= w
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (items[mid].first <= w) lo = mid;
+                else hi = mid;
+            }
+            const BatchItem& it = items[lo];
+            const IndexView& ix = *it.ix;
+            const int64_t qi = w - it.first;
+            if (ix.lookup == LOOKUP_DENSE) walk_dense<FT, STOP>(ix, it.io, qi, s_begin[wv], s_pre[wv]);
+            else walk_tree<FT, STOP>(ix, it.io, qi, s_begin[wv], s_pre[wv], s_stack[wv]);
+        }
+    }
+}
+
+template <int FT>
+hipError_t launch_ft(const BatchItem* items, int n_items, int64_t total, uint64_t* counter, int stop, int blocks,
+                     hipStream_t s) {
+    if (stop == GHN_STOP_PAPER)
+        hipLaunchKernelGGL((k_predict_batched<FT, GHN_STOP_PAPER>), dim3(blocks), dim3(BPT), 0, s, items, n_items,
+                           total, counter);
+    else
+        hipLaunchKernelGGL((k_predict_batched<FT, GHN_STOP_EXACT>), dim3(blocks), dim3(BPT), 0, s, items, n_items,
+                           total, counter);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_predict_batched(const BatchItem* items, int n_items, int64_t total, int f, int stop,
+                                  uint64_t* counter, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
+    int64_t blocks = (total + BWPB * CHUNK - 1) / (BWPB * CHUNK);
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    switch (f) {
+        case 1: return launch_ft<1>(items, n_items, total, counter, stop, (int)blocks, s);
+        case 2: return launch_ft<2>(items, n_items, total, counter, stop, (int)blocks, s);
+        case 3: return launch_ft<3>(items, n_items, total, counter, stop, (int)blocks, s);
+        case 4: return launch_ft<4>(items, n_items, total, counter, stop, (int)blocks, s);
+        case 8: return launch_ft<8>(items, n_items, total, counter, stop, (int)blocks, s);
+        default: return launch_ft<0>(items, n_items, total, counter, stop, (int)blocks, s);
+    }
+}
+
+}  // namespace ghn

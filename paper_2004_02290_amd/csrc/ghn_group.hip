@@ -173,9 +173,9 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     GroupLds<FT>& S = lds_all[wv];
     const int f = FT > 0 ? FT : ix.f;
-    const int k = A.k;
+    const int k = A.io.k;
     const int g = lane >> 4, t = lane & 15;
-    const bool prune = !(A.flags & GHN_FLAG_NO_PRUNE);
+    const bool prune = !(A.io.flags & GHN_FLAG_NO_PRUNE);
     const uint32_t ngroups = G.counters[0];
 
     for (;;) {
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
             fin = act;
             int32_t cc[FS];
             for (int j = 0; j < f; ++j) {
-                const float x = act ? A.queries[qi * f + j] : 0.0f;
+                const float x = act ? A.io.queries[qi * f + j] : 0.0f;
                 fin = fin && isfinite(x);
                 cc[j] = 0;
                 if (act) S.q[lane][j] = x;
@@ -522,16 +522,16 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
                 for (int j = 0; j < KR; ++j) {
                     const int ee = 16 * j + t;
                     if (ee < k) {
-                        A.out_idx[qi * k + ee] = -1;
-                        if (A.out_d2) A.out_d2[qi * k + ee] = __longlong_as_double(0x7ff8000000000000LL);
+                        A.io.out_idx[qi * k + ee] = -1;
+                        if (A.io.out_d2) A.io.out_d2[qi * k + ee] = __longlong_as_double(0x7ff8000000000000LL);
                     }
                 }
                 if (t == 0) {
-                    if (ix.task == GHN_CLASSIFY) ((int32_t*)A.out_pred)[qi] = -1;
-                    else ((float*)A.out_pred)[qi] = __int_as_float(0x7fc00000);
-                    if (A.out_stop_layer) A.out_stop_layer[qi] = -1;
-                    if (A.out_cands) A.out_cands[qi] = 0;
-                    if (A.out_probes) A.out_probes[qi] = 0;
+                    if (ix.task == GHN_CLASSIFY) ((int32_t*)A.io.out_pred)[qi] = -1;
+                    else ((float*)A.io.out_pred)[qi] = __int_as_float(0x7fc00000);
+                    if (A.io.out_stop_layer) A.io.out_stop_layer[qi] = -1;
+                    if (A.io.out_cands) A.io.out_cands[qi] = 0;
+                    if (A.io.out_probes) A.io.out_probes[qi] = 0;
                 }
             }
             if (live) {
@@ -539,8 +539,8 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
                 for (int j = 0; j < KR; ++j) {
                     const int ee = 16 * j + t;
                     if (ee < k) {
-                        A.out_idx[qi * k + ee] = bi[i][j];
-                        if (A.out_d2) A.out_d2[qi * k + ee] = bd[i][j];
+                        A.io.out_idx[qi * k + ee] = bi[i][j];
+                        if (A.io.out_d2) A.io.out_d2[qi * k + ee] = bd[i][j];
                         S.lab[g][ee] = ((const int32_t*)ix.targets)[bi[i][j]];
                     }
                 }
@@ -562,16 +562,16 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
                         const int ob = __shfl_xor(best, d, 16), on = __shfl_xor(best_n, d, 16);
                         if (on > best_n || (on == best_n && ob < best)) { best = ob; best_n = on; }
                     }
-                    if (t == 0) ((int32_t*)A.out_pred)[qi] = best;
+                    if (t == 0) ((int32_t*)A.io.out_pred)[qi] = best;
                 } else if (t == 0) {
                     double s = 0.0;
                     for (int e2 = 0; e2 < k; ++e2) s = __dadd_rn(s, (double)__int_as_float(S.lab[g][e2]));
-                    ((float*)A.out_pred)[qi] = (float)(s / (double)k);
+                    ((float*)A.io.out_pred)[qi] = (float)(s / (double)k);
                 }
                 if (t == 0) {
-                    if (A.out_stop_layer) A.out_stop_layer[qi] = stopl[i];
-                    if (A.out_cands) A.out_cands[qi] = cands[i];
-                    if (A.out_probes) A.out_probes[qi] = probes;
+                    if (A.io.out_stop_layer) A.io.out_stop_layer[qi] = stopl[i];
+                    if (A.io.out_cands) A.io.out_cands[qi] = cands[i];
+                    if (A.io.out_probes) A.io.out_probes[qi] = probes;
                 }
             }
             wave_lds_sync();
@@ -581,8 +581,8 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
 
 template <int FT>
 hipError_t launch_ft(const GroupArgs& a, int blocks, hipStream_t s) {
-    if (a.p.k <= 16) hipLaunchKernelGGL((k_predict_group<FT, 1>), dim3(blocks), dim3(GT), 0, s, a);
-    else if (a.p.k <= 32) hipLaunchKernelGGL((k_predict_group<FT, 2>), dim3(blocks), dim3(GT), 0, s, a);
+    if (a.p.io.k <= 16) hipLaunchKernelGGL((k_predict_group<FT, 1>), dim3(blocks), dim3(GT), 0, s, a);
+    else if (a.p.io.k <= 32) hipLaunchKernelGGL((k_predict_group<FT, 2>), dim3(blocks), dim3(GT), 0, s, a);
     else hipLaunchKernelGGL((k_predict_group<FT, 4>), dim3(blocks), dim3(GT), 0, s, a);
     return hipGetLastError();
 }
@@ -624,7 +624,7 @@ hipError_t run_grouped(const PredictArgs& pa, int keep_shift_levels, void* ws, h
     int64_t g = (m + 255) / 256;
     if (g > 65536) g = 65536;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counters, 2);
-    hipLaunchKernelGGL(k_group_keys, dim3((unsigned)g), dim3(256), 0, s, pa.queries, m, ix, k0, v0, qflags);
+    hipLaunchKernelGGL(k_group_keys, dim3((unsigned)g), dim3(256), 0, s, pa.io.queries, m, ix, k0, v0, qflags);
     bool alt = false;
     hipError_t e = radix_sort_pairs(k0, v0, k1, v1, m, total, rtemp, &alt, s);
     if (e != hipSuccess) return e;

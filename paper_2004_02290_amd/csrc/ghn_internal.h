@@ -140,23 +140,38 @@ hipError_t launch_cell_list(const uint32_t* heads, const uint32_t* rank, int64_t
 hipError_t launch_tree_level(const int32_t* child_lo, const int32_t* child_hi, int64_t nchild, int32_t f,
                              int32_t* node_lo, int32_t* node_hi, int64_t nnode, hipStream_t s);
 
-struct PredictArgs {
-    IndexView ix;
+// Per-call query inputs and outputs (device pointers).
+struct QueryIO {
     const float* queries;
-    int64_t m;
-    int32_t k;
-    int32_t stop;
-    uint32_t flags;
     int64_t* out_idx;
     double* out_d2;
     void* out_pred;
     int32_t* out_stop_layer;
     int64_t* out_cands;
     int64_t* out_probes;
+    int32_t k;
+    uint32_t flags;
+};
+
+struct PredictArgs {
+    IndexView ix;
+    QueryIO io;
+    int64_t m;
+    int32_t stop;
     const uint32_t* order;  // optional processing order of the queries (NULL = 0..m-1)
 };
 hipError_t launch_predict_dense(const PredictArgs& a, hipStream_t s);
 hipError_t launch_predict_tree(const PredictArgs& a, hipStream_t s);
+// One item of a batch over many indexes: global query positions [first, first + m).
+struct BatchItem {
+    const IndexView* ix;  // device copy of the item's index view
+    QueryIO io;
+    int64_t first;
+    int64_t m;
+};
+hipError_t launch_predict_batched(const BatchItem* items, int n_items, int64_t total, int f, int stop,
+                                  uint64_t* counter, hipStream_t s);
+
 // Grouped walk with the bf16 matrix-core screen: sort, group and walk the queries.
 size_t group_ws_bytes(int64_t m);
 hipError_t run_grouped(const PredictArgs& pa, int group_levels, void* ws, hipStream_t s, int* morton_bits);

@@ -11,7 +11,7 @@
 // distance to the node's region is below it.  Each wave walks the tree depth
 // first with a small stack in LDS; the kept cells of layer l are scored with
 // the same gather/screen/buffer machinery as the dense walk.
-#include "ghn_walk.h"
+#include "ghn_walk_tree.h"
 
 namespace ghn {
 namespace {
@@ -19,7 +19,6 @@ namespace {
 constexpr int BT = 256;
 constexpr int PT = 256;  // predict: 4 waves = 4 queries per block
 constexpr int WPB = PT / WAVE;
-constexpr int STACK_CAP = TREE_LEVELS_MAX * WAVE;
 
 __device__ __forceinline__ float load_coord(const void* pts, int64_t idx, int32_t dtype) {
     if (dtype == GHN_BF16) return __uint_as_float((uint32_t)((const uint16_t*)pts)[idx] << 16);
@@ -92,97 +91,17 @@ __global__ __launch_bounds__(BT) void k_tree_level(const int32_t* __restrict__ c
     }
 }
 
-// ------------------------------------------------------------------------------------------
-// Walk.  A stack entry is (level, first node, node count <= 64) packed in 64 bits.
-__device__ __forceinline__ uint64_t pack_entry(int level, uint32_t first, int count) {
-    return ((uint64_t)level << 40) | ((uint64_t)count << 32) | first;
-}
 
 template <int FT, int STOP>
 __global__ __launch_bounds__(PT) void k_predict_tree(PredictArgs A) {
     __shared__ uint32_t s_begin[WPB][RUN_CAP];
     __shared__ uint32_t s_pre[WPB][RUN_CAP];
-    __shared__ uint64_t s_stack[WPB][STACK_CAP];
-    const IndexView& ix = A.ix;
-    const int lane = lane_id();
+    __shared__ uint64_t s_stack[WPB][TREE_STACK_CAP];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int64_t slot = wave_slot(A, WPB);
     if (slot >= A.m) return;
     const int64_t qi = A.order ? (int64_t)A.order[slot] : slot;
-    const int f = FT > 0 ? FT : ix.f;
-    const int k = A.k;
-    const bool prune = !(A.flags & GHN_FLAG_NO_PRUNE);
-
-    Query<FT> Q;
-    setup_query<FT>(ix, A.queries, qi, f, Q);
-    if (!Q.finite) {
-        write_invalid(A, qi);
-        return;
-    }
-    WaveState st;
-    init_state(st);
-    const int top = ix.tree_levels;  // level of the root entries (0 = the cells themselves)
-    uint64_t* stack = s_stack[wv];
-
-    int64_t l = Q.l0;
-    for (;; ++l) {
-        st.updated = false;
-        int sp = 0;
-        if (lane == 0) stack[0] = pack_entry(top, 0u, (int)ix.tree_count[top]);
-        sp = 1;
-        wave_lds_sync();
-        while (sp > 0) {
-            --sp;
-            const uint64_t e = stack[sp];
-            wave_lds_sync();
-            const int level = (int)(e >> 40);
-            const int count = (int)((e >> 32) & 0xff);
-            const uint32_t first = (uint32_t)e;
-            const bool active = lane < count;
-            const int64_t node = (int64_t)first + lane;
-            // Chebyshev range of the node's cells from the central cell, and the
-            // squared distance from the query to the node's region of space.
-            int64_t dmin = 0, dmax = 0;
-            double lb = 0.0;
-            if (active) {
-                const int32_t* lo = level == 0 ? ix.cell_coord + node * f : ix.node_lo + (ix.tree_off[level] + node) * f;
-                const int32_t* hi = level == 0 ? lo : ix.node_hi + (ix.tree_off[level] + node) * f;
-#pragma unroll
-                for (int j = 0; j < (FT > 0 ? FT : F_MAX); ++j) {
-                    if (FT == 0 && j >= f) break;
-                    const int64_t a = lo[j], b = hi[j], cj = Q.c[j];
-                    const int64_t near = cj < a ? a - cj : (cj > b ? cj - b : 0);
-                    const int64_t far = max(cj - a, b - cj);
-                    dmin = max(dmin, near);
-                    dmax = max(dmax, far);
-                    const double g = gap_to_cells(Q.v[j], a, b, (double)ix.a[j]);
-                    lb = __dadd_rn(lb, __dmul_rn(g, g));
-                }
-            }
-            const bool close = !prune || !(lb * LB_SHRINK > st.tau);
-            st.probes += __popcll(ballot(active));
-            if (level == 0) {
-                uint32_t b0 = 0, n0 = 0;
-                if (active && dmin == l && close) {
-                    b0 = ix.cell_first[node];
-                    n0 = ix.cell_first[node + 1] - b0;
-                }
-                score_runs<FT>(ix, Q.q, f, k, b0, n0, 0u, 0u, s_begin[wv], s_pre[wv], st);
-            } else {
-                const bool keep = active && dmin <= l && l <= dmax && close;
-                const uint64_t km = ballot(keep);
-                if (keep) {
-                    const int64_t c0 = node * WAVE;
-                    const int cnt = (int)min((int64_t)WAVE, ix.tree_count[level - 1] - c0);
-                    stack[sp + __popcll(km & __lanemask_lt())] = pack_entry(level - 1, (uint32_t)c0, cnt);
-                }
-                sp += __popcll(km);
-                wave_lds_sync();
-            }
-        }
-        if (stop_after_layer<FT, STOP>(ix, Q, f, k, l, st)) break;
-    }
-    finish_query(A, qi, l, st);
+    walk_tree<FT, STOP>(A.ix, A.io, qi, s_begin[wv], s_pre[wv], s_stack[wv]);
 }
 
 template <int FT>

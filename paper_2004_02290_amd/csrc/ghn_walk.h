@@ -143,19 +143,19 @@ __device__ __forceinline__ void setup_query(const IndexView& ix, const float* qu
 }
 
 // Outputs of a query with a non-finite coordinate.
-__device__ __forceinline__ void write_invalid(const PredictArgs& A, int64_t qi) {
+__device__ __forceinline__ void write_invalid(const IndexView& ix, const QueryIO& io, int64_t qi) {
     const int lane = lane_id();
-    const int k = A.k;
+    const int k = io.k;
     if (lane < k) {
-        A.out_idx[qi * k + lane] = -1;
-        if (A.out_d2) A.out_d2[qi * k + lane] = __longlong_as_double(0x7ff8000000000000LL);
+        io.out_idx[qi * k + lane] = -1;
+        if (io.out_d2) io.out_d2[qi * k + lane] = __longlong_as_double(0x7ff8000000000000LL);
     }
     if (lane == 0) {
-        if (A.ix.task == GHN_CLASSIFY) ((int32_t*)A.out_pred)[qi] = -1;
-        else ((float*)A.out_pred)[qi] = __int_as_float(0x7fc00000);
-        if (A.out_stop_layer) A.out_stop_layer[qi] = -1;
-        if (A.out_cands) A.out_cands[qi] = 0;
-        if (A.out_probes) A.out_probes[qi] = 0;
+        if (ix.task == GHN_CLASSIFY) ((int32_t*)io.out_pred)[qi] = -1;
+        else ((float*)io.out_pred)[qi] = __int_as_float(0x7fc00000);
+        if (io.out_stop_layer) io.out_stop_layer[qi] = -1;
+        if (io.out_cands) io.out_cands[qi] = 0;
+        if (io.out_probes) io.out_probes[qi] = 0;
     }
 }
 
@@ -305,13 +305,13 @@ __device__ __forceinline__ bool stop_after_layer(const IndexView& ix, const Quer
 
 // Neighbours in (distance, id) order, then the majority vote (ties -> smallest
 // label) or the mean (FP64 sum in neighbour order, / k, rounded to FP32).
-__device__ __forceinline__ void finish_query(const PredictArgs& A, int64_t qi, int64_t l, const WaveState& st) {
+__device__ __forceinline__ void finish_query(const IndexView& ix, const QueryIO& io, int64_t qi, int64_t l,
+                                             const WaveState& st) {
     const int lane = lane_id();
-    const int k = A.k;
-    const IndexView& ix = A.ix;
+    const int k = io.k;
     if (lane < k) {
-        A.out_idx[qi * k + lane] = st.bi;
-        if (A.out_d2) A.out_d2[qi * k + lane] = st.bd;
+        io.out_idx[qi * k + lane] = st.bi;
+        if (io.out_d2) io.out_d2[qi * k + lane] = st.bd;
     }
     if (ix.task == GHN_CLASSIFY) {
         const int32_t* lab = (const int32_t*)ix.targets;
@@ -326,18 +326,18 @@ __device__ __forceinline__ void finish_query(const PredictArgs& A, int64_t qi, i
             if (cnt > best_n || (cnt == best_n && label < best)) { best = label; best_n = cnt; }
             todo &= ~same;
         }
-        if (lane == 0) ((int32_t*)A.out_pred)[qi] = best;
+        if (lane == 0) ((int32_t*)io.out_pred)[qi] = best;
     } else {
         const float* y = (const float*)ix.targets;
         const float my = lane < k ? y[st.bi] : 0.0f;
         double s = 0.0;
         for (int t = 0; t < k; ++t) s = __dadd_rn(s, (double)readlane_f32(my, t));
-        if (lane == 0) ((float*)A.out_pred)[qi] = (float)(s / (double)k);
+        if (lane == 0) ((float*)io.out_pred)[qi] = (float)(s / (double)k);
     }
     if (lane == 0) {
-        if (A.out_stop_layer) A.out_stop_layer[qi] = (int32_t)l;
-        if (A.out_cands) A.out_cands[qi] = st.cands;
-        if (A.out_probes) A.out_probes[qi] = st.probes;
+        if (io.out_stop_layer) io.out_stop_layer[qi] = (int32_t)l;
+        if (io.out_cands) io.out_cands[qi] = st.cands;
+        if (io.out_probes) io.out_probes[qi] = st.probes;
     }
 }
 

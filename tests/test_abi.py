@@ -35,6 +35,7 @@ def test_struct_sizes_match_header(ghn):
     # ghn_index_info: 8+4+4+4+4+8+8+8 + 4*32*4 + 8 bytes, ghn_predict_opts: 3*4 + pad + 4*8 + 4 + pad
     assert ctypes.sizeof(ghn.ghn_index_info) == 48 + 4 * 32 * 4 + 8
     assert ctypes.sizeof(ghn.ghn_predict_opts) == 56
+    assert ctypes.sizeof(ghn.ghn_batch_item) == 56  # 3 pointers/ints of 8, k + pad, 3 pointers
 
 
 def _build_raw(ghn, points=1, n=10, f=2, dtype=0, targets=2, task=0, widths=(0.5,), origin=None):

@@ -417,3 +417,92 @@ def test_mfma_dims(ghn, f):
 def test_mfma_skew8d_and_bf16_16d(ghn):
     _check_mfma(ghn, W.make("skew8d", n=100_000, m=1_000), sample=300)
     _check_mfma(ghn, W.make("bf16_16d", n=60_000, m=600), sample=200)
+
+
+# ---------------------------------------------------------------------------------- batches
+def _multi(problems=20, n_hi=30_000, m_hi=3_000, seed=5):
+    return W.make_multi3d(problems=problems, n_hi=n_hi, m_hi=m_hi, seed=seed)
+
+
+def _batch_setup(ghn, probs, stop):
+    import torch
+    idxs, items, outs = [], [], []
+    for p in probs:
+        ix = _index(ghn, p)
+        q = _dev(p.queries)
+        oi = torch.full((p.m, p.k), -7, dtype=torch.int64, device="cuda")
+        op = torch.full((p.m,), -7, dtype=torch.int32, device="cuda")
+        od = torch.zeros((p.m, p.k), dtype=torch.float64, device="cuda")
+        idxs.append(ix)
+        items.append((ix.handle, q, p.k, oi, op, od))
+        outs.append((oi, op, od))
+    ws = torch.empty(ghn.ghn_batch_workspace_bytes(len(items)), dtype=torch.uint8, device="cuda")
+    batch = ghn.ghn_batch_prepare(items, ws, stop=stop)
+    return idxs, items, outs, ws, batch
+
+
+def test_batched_matches_single_and_oracle(ghn):
+    import torch
+    probs = _multi()
+    for stop in (ghn.GHN_STOP_EXACT, ghn.GHN_STOP_PAPER):
+        idxs, items, outs, ws, batch = _batch_setup(ghn, probs, stop)
+        ghn.ghn_predict_batched(batch)
+        torch.cuda.synchronize()
+        for p, ix, (oi, op, od) in zip(probs, idxs, outs):
+            single = _run(ghn, ix, p.queries, p.k, stop)
+            got = dict(idx=oi.cpu().numpy(), pred=op.cpu().numpy(), d2=od.cpu().numpy())
+            _assert_same(got, single, "batched vs single")
+            if stop == ghn.GHN_STOP_EXACT:
+                rows = np.arange(min(p.m, 200))
+                bi, bd, bp = oracle.bruteforce(p.points, p.targets, p.task, p.queries[rows], p.k)
+                _assert_same({k: v[rows] for k, v in got.items()}, dict(idx=bi, d2=bd, pred=bp), "batched vs oracle")
+        ghn.ghn_batch_destroy(batch)
+
+
+def test_batched_graph_replay(ghn):
+    import torch
+    probs = _multi(problems=12, n_hi=20_000, m_hi=2_000, seed=9)
+    idxs, items, outs, ws, batch = _batch_setup(ghn, probs, ghn.GHN_STOP_EXACT)
+    ghn.ghn_predict_batched(batch)
+    torch.cuda.synchronize()
+    want = [(oi.clone(), op.clone(), od.clone()) for oi, op, od in outs]
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            ghn.ghn_predict_batched(batch)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        for oi, op, od in outs:      # eager work between replays
+            oi.fill_(-1); op.fill_(-1); od.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (oi, op, od), (wi, wp, wd) in zip(outs, want):
+            assert torch.equal(oi, wi) and torch.equal(op, wp) and torch.equal(od, wd), rep
+    ghn.ghn_batch_destroy(batch)
+
+
+def test_batch_errors(ghn):
+    import torch
+    probs = _multi(problems=2, n_hi=5_000, m_hi=100, seed=1)
+    idxs, items, outs, ws, batch = _batch_setup(ghn, probs, ghn.GHN_STOP_EXACT)
+    ghn.ghn_batch_destroy(batch)
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ghn.GHNError) as e:
+        ghn.ghn_batch_prepare(items, small)
+    assert e.value.code == -6
+    bad = list(items)
+    h, q, k, oi, op, od = bad[0]
+    bad[0] = (h, q, 10 ** 6, oi, op, od)
+    with pytest.raises(ghn.GHNError) as e:
+        ghn.ghn_batch_prepare(bad, ws)
+    assert e.value.code == -1
+    p4 = W.uniform_problem(n=500, m=10, f=4, k=3, seed=2, width=0.2)
+    ix4 = _index(ghn, p4)
+    mixed = list(items) + [(ix4.handle, _dev(p4.queries), 3, oi, op, od)]
+    ws2 = torch.empty(ghn.ghn_batch_workspace_bytes(len(mixed)), dtype=torch.uint8, device="cuda")
+    with pytest.raises(ghn.GHNError) as e:
+        ghn.ghn_batch_prepare(mixed, ws2)
+    assert e.value.code == -1
