@@ -240,6 +240,33 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
 ghn_status ghn_predict_batched(const ghn_batch* batch, void* stream);
 void ghn_batch_destroy(ghn_batch* batch);
 
+/* ---- autotuning ---------------------------------------------------------------------
+ * Times ghn_predict on a sample of queries for every candidate setting and
+ * returns the fastest: the scalar cell width (each candidate builds an index),
+ * the screen (FP32 per query, in input order or in spatial order; grouped bf16
+ * with 2^s-cell groups, s = 0, 1, 2) and the lookup chosen by the build.  Under
+ * GHN_STOP_EXACT every width gives the same (brute-force) neighbours, so widths
+ * are tuned: `widths` (HOST) lists the candidates, or NULL for six widths
+ * 2^-3 .. 2^2 times the width that puts 8 points in a cell of the points'
+ * bounding box on average.  Under GHN_STOP_PAPER the width is part of the
+ * method: exactly one width must be given and only the execution settings are
+ * tuned.  `trials` (HOST, optional) receives up to max_trials measurements.
+ * Synchronises `stream`; allocates and frees device memory.
+ * Errors: as ghn_build and ghn_predict; GHN_E_UNSUPPORTED if no candidate builds. */
+typedef struct {
+    float cell_width;
+    int32_t lookup;        /* GHN_LOOKUP_DENSE or GHN_LOOKUP_TREE */
+    int32_t prec;          /* ghn_prec */
+    int32_t group_levels;  /* bf16: ghn_predict_opts.group_levels */
+    uint32_t flags;        /* GHN_FLAG_* to pass to ghn_predict */
+    double ms;             /* time of one predict call over the sample, or -1 if the setting failed */
+} ghn_tune_trial;
+
+ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype, const void* targets, int32_t task,
+                        const float* queries, int64_t m, int32_t k, int32_t stop, const float* widths,
+                        int32_t n_widths, ghn_tune_trial* best, ghn_tune_trial* trials, int32_t max_trials,
+                        int32_t* n_trials, void* stream);
+
 /* Last error message of the calling thread ("" if none).  Valid until the
  * thread's next failing call. */
 const char* ghn_last_error(void);

@@ -11,6 +11,8 @@ from __future__ import annotations
 
 import ctypes
 import os
+
+import numpy as np
 from typing import Optional, Sequence, Union
 
 import torch
@@ -33,7 +35,7 @@ GHN_LOOKUP_AUTO, GHN_LOOKUP_DENSE, GHN_LOOKUP_TREE = -1, 0, 1
 
 EXPORTED = ["ghn_build", "ghn_build_ex", "ghn_index_get_info", "ghn_destroy", "ghn_predict_workspace_bytes", "ghn_predict",
             "ghn_query_order_workspace_bytes", "ghn_query_order", "ghn_batch_workspace_bytes", "ghn_batch_prepare",
-            "ghn_predict_batched", "ghn_batch_destroy", "ghn_last_error"]
+            "ghn_predict_batched", "ghn_batch_destroy", "ghn_autotune", "ghn_last_error"]
 
 
 class GHNError(RuntimeError):
@@ -63,6 +65,14 @@ class ghn_batch_item(ctypes.Structure):
     _fields_ = [("index", ctypes.c_void_p), ("queries", ctypes.c_void_p), ("m", ctypes.c_int64),
                 ("k", ctypes.c_int32), ("out_idx", ctypes.c_void_p), ("out_d2", ctypes.c_void_p),
                 ("out_pred", ctypes.c_void_p)]
+
+
+class ghn_tune_trial(ctypes.Structure):
+    _fields_ = [("cell_width", ctypes.c_float), ("lookup", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("group_levels", ctypes.c_int32), ("flags", ctypes.c_uint32), ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 def _load() -> ctypes.CDLL:
@@ -96,6 +106,9 @@ def _load() -> ctypes.CDLL:
     L.ghn_predict_batched.restype = ctypes.c_int
     L.ghn_batch_destroy.argtypes = [P]
     L.ghn_batch_destroy.restype = None
+    L.ghn_autotune.argtypes = [P, I64, I32, I32, P, I32, P, I64, I32, I32, P, I32, ctypes.POINTER(ghn_tune_trial),
+                               ctypes.POINTER(ghn_tune_trial), I32, ctypes.POINTER(I32), P]
+    L.ghn_autotune.restype = ctypes.c_int
     L.ghn_last_error.argtypes = []
     L.ghn_last_error.restype = ctypes.c_char_p
     return L
@@ -241,6 +254,26 @@ def ghn_predict_batched(batch, stream=None) -> None:
 
 def ghn_batch_destroy(batch) -> None:
     _lib.ghn_batch_destroy(batch)
+
+
+def ghn_autotune(points: torch.Tensor, targets: torch.Tensor, task: int, queries: torch.Tensor, k: int,
+                 stop=GHN_STOP_EXACT, widths=None, max_trials: int = 64, stream=None):
+    """ghn_autotune: returns (best trial dict, list of trial dicts)."""
+    n, f = points.shape
+    dtype = GHN_BF16 if points.dtype == torch.bfloat16 else GHN_F32
+    w = None
+    nw = 0
+    if widths is not None:
+        ws_ = [float(x) for x in np.atleast_1d(widths)]
+        w = (ctypes.c_float * len(ws_))(*ws_)
+        nw = len(ws_)
+    best = ghn_tune_trial()
+    trials = (ghn_tune_trial * max_trials)()
+    nt = ctypes.c_int32(0)
+    _check(_lib.ghn_autotune(_ptr(points), n, f, dtype, _ptr(targets), task, _ptr(queries), queries.shape[0], int(k),
+                             int(stop), w, nw, ctypes.byref(best), trials, max_trials, ctypes.byref(nt),
+                             _stream(stream)))
+    return best.as_dict(), [trials[i].as_dict() for i in range(min(nt.value, max_trials))]
 
 
 class Index:

@@ -62,6 +62,8 @@ struct DevPool {
     }
 };
 
+size_t sort_ws_bytes(int64_t m);  // workspace of the spatial query sort (defined below)
+
 // Dense tables larger than this many cells are not built.
 int64_t dense_limit(int64_t n) {
     int64_t lim = 16 * n;
@@ -151,6 +153,95 @@ ghn_status ghn_predict_batched(const ghn_batch* batch, void* stream) {
 }
 
 void ghn_batch_destroy(ghn_batch* batch) { delete batch; }
+
+ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype, const void* targets, int32_t task,
+                        const float* queries, int64_t m, int32_t k, int32_t stop, const float* widths,
+                        int32_t n_widths, ghn_tune_trial* best, ghn_tune_trial* trials, int32_t max_trials,
+                        int32_t* n_trials, void* stream) {
+    using namespace ghn;
+    if (n_trials) *n_trials = 0;
+    if (!best) return fail(GHN_E_INVALID_ARG, "ghn_autotune: best is NULL");
+    if (!points || !targets || !queries) return fail(GHN_E_INVALID_ARG, "ghn_autotune: NULL array");
+    if (n < 1 || f < 1 || f > F_MAX || m < 1) return fail(GHN_E_INVALID_ARG, "ghn_autotune: bad sizes");
+    if (k < 1 || k > K_MAX) return fail(GHN_E_INVALID_ARG, "ghn_autotune: k=%d outside [1, %d]", k, K_MAX);
+    if (k > n) return fail(GHN_E_K_GT_N, "ghn_autotune: k=%d exceeds n=%lld", k, (long long)n);
+    if (stop != GHN_STOP_EXACT && stop != GHN_STOP_PAPER) return fail(GHN_E_INVALID_ARG, "ghn_autotune: bad stop rule");
+    if (stop == GHN_STOP_PAPER && (!widths || n_widths != 1))
+        return fail(GHN_E_INVALID_ARG, "ghn_autotune: the PAPER rule needs exactly one cell width");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<float> cand;
+    if (widths && n_widths > 0) {
+        cand.assign(widths, widths + n_widths);
+    } else {
+        float lo[F_MAX], hi[F_MAX];
+        hipError_t e = coord_range(points, n, f, dtype, lo, hi, s);
+        if (e != hipSuccess) return hip_fail(e, "ghn_autotune: coordinate range");
+        double logvol = 0.0;
+        for (int j = 0; j < f; ++j) {
+            double r = (double)hi[j] - (double)lo[j];
+            logvol += std::log(r > 1e-30 ? r : 1e-30);
+        }
+        const double w0 = std::exp((logvol + std::log(8.0 / (double)n)) / f);
+        for (int i = -3; i <= 2; ++i) cand.push_back((float)(w0 * std::ldexp(1.0, i)));
+    }
+    struct Setting { int32_t prec, levels; uint32_t flags; };
+    std::vector<Setting> settings = {{GHN_PREC_FP32, -1, GHN_FLAG_NO_SORT}, {GHN_PREC_FP32, -1, 0u}};
+    if (stop == GHN_STOP_PAPER) settings.push_back({GHN_PREC_BF16_MFMA, 0, 0u});
+    else for (int lv = 0; lv <= 2; ++lv) settings.push_back({GHN_PREC_BF16_MFMA, lv, 0u});
+
+    // outputs and a workspace large enough for every setting
+    int64_t* oi = nullptr;
+    void* op = nullptr;
+    void* ws = nullptr;
+    size_t ws_bytes = sort_ws_bytes(m) > group_ws_bytes(m) ? sort_ws_bytes(m) : group_ws_bytes(m);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ghn_status result = GHN_OK;
+    bool have_best = false;
+    int32_t nt = 0;
+    if (hipMalloc((void**)&oi, (size_t)m * k * 8) != hipSuccess || hipMalloc(&op, (size_t)m * 4) != hipSuccess ||
+        hipMalloc(&ws, ws_bytes) != hipSuccess || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        result = fail(GHN_E_NOMEM, "ghn_autotune: out of device memory");
+    } else {
+        for (float w : cand) {
+            ghn_index* ix = nullptr;
+            if (ghn_build(points, n, f, dtype, targets, task, &w, 1, nullptr, stream, &ix) != GHN_OK) {
+                if (trials && nt < max_trials) trials[nt] = {w, -1, -1, -1, 0u, -1.0};
+                ++nt;
+                continue;
+            }
+            for (const Setting& st : settings) {
+                ghn_predict_opts o = {stop, st.prec, st.flags, nullptr, nullptr, nullptr, nullptr, st.levels};
+                double ms = -1.0;
+                if (ghn_predict(ix, queries, m, k, &o, oi, nullptr, op, ws, ws_bytes, stream) == GHN_OK &&
+                    hipStreamSynchronize(s) == hipSuccess) {
+                    float best_ms = 1e30f;
+                    for (int rep = 0; rep < 3; ++rep) {
+                        float t = 0.0f;
+                        (void)hipEventRecord(e0, s);
+                        (void)ghn_predict(ix, queries, m, k, &o, oi, nullptr, op, ws, ws_bytes, stream);
+                        (void)hipEventRecord(e1, s);
+                        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess) break;
+                        best_ms = t < best_ms ? t : best_ms;
+                    }
+                    if (best_ms < 1e29f) ms = best_ms;
+                }
+                const ghn_tune_trial tr = {w, ix->info.lookup, st.prec, st.levels, st.flags, ms};
+                if (trials && nt < max_trials) trials[nt] = tr;
+                ++nt;
+                if (ms >= 0.0 && (!have_best || ms < best->ms)) { *best = tr; have_best = true; }
+            }
+            ghn_destroy(ix);
+        }
+        if (!have_best) result = fail(GHN_E_UNSUPPORTED, "ghn_autotune: no candidate setting could be built and run");
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (oi) (void)hipFree(oi);
+    if (op) (void)hipFree(op);
+    if (ws) (void)hipFree(ws);
+    if (n_trials) *n_trials = nt;
+    return result;
+}
 
 ghn_status ghn_build(const void* points, int64_t n, int32_t f, int32_t dtype, const void* targets, int32_t task,
                      const float* cell_width, int32_t n_width, const float* origin, void* stream,

@@ -172,6 +172,9 @@ struct BatchItem {
 hipError_t launch_predict_batched(const BatchItem* items, int n_items, int64_t total, int f, int stop,
                                   uint64_t* counter, hipStream_t s);
 
+// Per-dimension range of the finite coordinates of n points (synchronises s).
+hipError_t coord_range(const void* pts, int64_t n, int32_t f, int32_t dtype, float* lo, float* hi, hipStream_t s);
+
 // Grouped walk with the bf16 matrix-core screen: sort, group and walk the queries.
 size_t group_ws_bytes(int64_t m);
 hipError_t run_grouped(const PredictArgs& pa, int group_levels, void* ws, hipStream_t s, int* morton_bits);

@@ -36,6 +36,7 @@ def test_struct_sizes_match_header(ghn):
     assert ctypes.sizeof(ghn.ghn_index_info) == 48 + 4 * 32 * 4 + 8
     assert ctypes.sizeof(ghn.ghn_predict_opts) == 56
     assert ctypes.sizeof(ghn.ghn_batch_item) == 56  # 3 pointers/ints of 8, k + pad, 3 pointers
+    assert ctypes.sizeof(ghn.ghn_tune_trial) == 32  # 5 x 4 bytes, pad, double
 
 
 def _build_raw(ghn, points=1, n=10, f=2, dtype=0, targets=2, task=0, widths=(0.5,), origin=None):

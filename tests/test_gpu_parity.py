@@ -506,3 +506,28 @@ def test_batch_errors(ghn):
     with pytest.raises(ghn.GHNError) as e:
         ghn.ghn_batch_prepare(mixed, ws2)
     assert e.value.code == -1
+
+
+# ---------------------------------------------------------------------------------- autotune
+def test_autotune_exact_and_paper(ghn, tmp_path):
+    import torch
+    from paper_2004_02290_amd import autotune
+    prob = W.make("clusters4d", n=50_000, m=2_000)
+    pts, tgt, q = _dev(prob.points), _dev(prob.targets), _dev(prob.queries)
+    cache = str(tmp_path / "tune.json")
+    best = autotune.tune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_EXACT, cache_path=cache)
+    assert best["ms"] > 0 and best["cell_width"] > 0
+    assert len(best["trials"]) == 6 * 5
+    again = autotune.tune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_EXACT, cache_path=cache)
+    assert again["cell_width"] == best["cell_width"]  # served from the cache
+    # the tuned setting still returns the brute-force neighbours
+    ix = ghn.Index(pts, tgt, prob.task, best["cell_width"])
+    got = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_EXACT, prec=best["prec"], flags=best["flags"],
+               group_levels=best["group_levels"])
+    bi, bd, bp = oracle.bruteforce(prob.points, prob.targets, prob.task, prob.queries, prob.k)
+    _assert_same(got, dict(idx=bi, d2=bd, pred=bp), "autotuned EXACT")
+    pb, trials = ghn.ghn_autotune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_PAPER, widths=[prob.cell_width])
+    assert abs(pb["cell_width"] - prob.cell_width) < 1e-9 and len(trials) == 3
+    with pytest.raises(ghn.GHNError) as e:
+        ghn.ghn_autotune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_PAPER)
+    assert e.value.code == -1
