@@ -64,10 +64,12 @@ struct DevPool {
 
 size_t sort_ws_bytes(int64_t m);  // workspace of the spatial query sort (defined below)
 
-// Dense tables larger than this many cells are not built.
+// Dense tables larger than this many cells are not built (linear cell indices stay 32-bit).
 int64_t dense_limit(int64_t n) {
     int64_t lim = 16 * n;
-    return lim < (int64_t(1) << 24) ? (int64_t(1) << 24) : lim;
+    if (lim < (int64_t(1) << 24)) lim = int64_t(1) << 24;
+    if (lim > (int64_t(1) << 32) - 2) lim = (int64_t(1) << 32) - 2;
+    return lim;
 }
 
 }  // namespace
@@ -308,7 +310,7 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
         iv.o[j] = o[j];
         iv.cmin[j] = h.minmax[j];
         iv.cmax[j] = h.minmax[F_MAX + j];
-        iv.stride[j] = box;
+        iv.stride[j] = (uint32_t)box;
         const int64_t wj = (int64_t)iv.cmax[j] - iv.cmin[j] + 1;
         if (box > (int64_t(1) << 40) / wj) too_big = true;
         else box *= wj;

@@ -48,7 +48,7 @@ struct IndexView {
     float o[F_MAX];             // origin per dimension
     int32_t cmin[F_MAX];
     int32_t cmax[F_MAX];
-    int64_t stride[F_MAX];      // dense-box linear index stride per dimension (last = 1)
+    uint32_t stride[F_MAX];     // dense-box linear index stride per dimension (last = 1)
 };
 
 // ---------------------------------------------------------------------------------------
@@ -95,6 +95,19 @@ __device__ __forceinline__ double shfl_up1_f64(double v) {
     int lo = shfl_up1_i32(int(uint32_t(b)));
     int hi = shfl_up1_i32(int(uint32_t(uint64_t(b) >> 32)));
     return __longlong_as_double(int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo)));
+}
+
+// Minimum over the wave of a non-negative float (uniform result): DPP row_shr
+// min-scans inside each 16-lane row, then the four row minima.
+__device__ __forceinline__ float wave_min_nonneg(float v) {
+    int m = __float_as_int(v);
+    m = min(m, __builtin_amdgcn_update_dpp(m, m, 0x111, 0xf, 0xf, false));  // row_shr:1
+    m = min(m, __builtin_amdgcn_update_dpp(m, m, 0x112, 0xf, 0xf, false));  // row_shr:2
+    m = min(m, __builtin_amdgcn_update_dpp(m, m, 0x114, 0xf, 0xf, false));  // row_shr:4
+    m = min(m, __builtin_amdgcn_update_dpp(m, m, 0x118, 0xf, 0xf, false));  // row_shr:8
+    const int r0 = __builtin_amdgcn_readlane(m, 15), r1 = __builtin_amdgcn_readlane(m, 31);
+    const int r2 = __builtin_amdgcn_readlane(m, 47), r3 = __builtin_amdgcn_readlane(m, 63);
+    return __int_as_float(min(min(r0, r1), min(r2, r3)));
 }
 
 // Inclusive prefix sum over the wave.

@@ -16,7 +16,7 @@ namespace ghn {
 constexpr int NUM_XCD = 8;
 constexpr double LB_SHRINK = 1.0 - 0x1p-40;    // cell lower bounds are shrunk by this before pruning
 constexpr double EXACT_SHRINK = 1.0 - 0x1p-44; // squared ring distance is shrunk by this (EXACT rule)
-constexpr int RUN_CAP = 2 * WAVE;              // point runs listed per batch
+constexpr int RUN_CAP = 2 * WAVE + 1;          // point runs listed per batch (+ sentinel)
 
 // Smallest float >= x (x >= 0, finite or inf).
 __device__ __forceinline__ float f32_round_up(double x) {
@@ -95,8 +95,8 @@ struct WaveState {
     float t32;      // FP32 admission threshold derived from tau
     int count;      // entries in the buffer (<= k)
     bool updated;   // an insertion happened in the current layer
-    int64_t cands;  // candidates scored
-    int64_t probes; // index entries read to find cells
+    int32_t cands;  // candidates scored
+    int32_t probes; // index entries read to find cells
 };
 
 __device__ __forceinline__ void init_state(WaveState& st) {
@@ -117,8 +117,8 @@ template <int FT>
 struct Query {
     float q[FT > 0 ? FT : F_MAX];
     double v[FT > 0 ? FT : F_MAX];   // q - origin, FP64
-    int64_t c[FT > 0 ? FT : F_MAX];  // central cell id
-    int64_t l0, lcover;
+    int32_t c[FT > 0 ? FT : F_MAX];  // central cell id (|c| < 2^29 after clamping)
+    int32_t l0, lcover;
     bool finite;
 };
 
@@ -136,9 +136,10 @@ __device__ __forceinline__ void setup_query(const IndexView& ix, const float* qu
         int64_t cj = Q.finite ? exact_floor_div(Q.v[j], (double)ix.a[j]) : 0;
         cj = max(cj, (int64_t)ix.cmin[j] - CLAMP);
         cj = min(cj, (int64_t)ix.cmax[j] + CLAMP);
-        Q.c[j] = cj;
-        Q.l0 = max(Q.l0, max((int64_t)ix.cmin[j] - cj, cj - (int64_t)ix.cmax[j]));
-        Q.lcover = max(Q.lcover, max(cj - (int64_t)ix.cmin[j], (int64_t)ix.cmax[j] - cj));
+        const int32_t c32 = (int32_t)cj;
+        Q.c[j] = c32;
+        Q.l0 = max(Q.l0, max(ix.cmin[j] - c32, c32 - ix.cmax[j]));
+        Q.lcover = max(Q.lcover, max(c32 - ix.cmin[j], ix.cmax[j] - c32));
     }
 }
 
@@ -203,8 +204,17 @@ __device__ __forceinline__ void score_chunk(const float* q, int f, int k, const 
     double d64 = 0.0;
     if (adm) d64 = dist64<FT>(q, c.x, f);
     while (mask) {
-        const int src = __ffsll((unsigned long long)mask) - 1;
-        mask &= mask - 1;
+        // nearest admitted candidate first: the buffer then fills with near points
+        // and later candidates fail the (shrinking) threshold without an insertion
+        int src;
+        if (st.count == k || __popcll(mask) <= 2) {
+            src = __ffsll((unsigned long long)mask) - 1;
+        } else {
+            const float mine = ((mask >> lane) & 1) ? d32 : __int_as_float(0x7f800000);
+            const float mn = wave_min_nonneg(mine);
+            src = __ffsll((unsigned long long)(ballot(mine == mn) & mask)) - 1;
+        }
+        mask &= ~(1ull << src);
         const double cd = readlane_f64(d64, src);
         const int ci = readlane_i32(c.id, src);
         if (!(cd < st.tau || (cd == st.tau && ci < st.tau_i))) continue;
@@ -260,22 +270,28 @@ __device__ __forceinline__ void score_runs(const IndexView& ix, const float* q, 
     uint32_t sidx = seg_incl - nseg_l, pofs = pts_incl - npts_l;
     if (n0 > 0) { s_begin[sidx] = b0; s_pre[sidx] = pofs; ++sidx; pofs += n0; }
     if (n1 > 0) { s_begin[sidx] = b1; s_pre[sidx] = pofs; }
+    if (lane == 0) s_pre[nseg] = npts;  // sentinel
     wave_lds_sync();
+    // Chunk [base, base + 64): `seg` is the run holding `base`; the runs that start
+    // inside the chunk are few, so each lane finds its run with one uniform pass.
+    uint32_t seg = 0;
     for (uint32_t base = 0; base < npts; base += WAVE) {
         const uint32_t p = base + lane;
-        uint32_t pidx = 0;
-        if (p < npts) {
-            uint32_t a0 = 0, a1 = nseg;  // last run whose prefix is <= p
-            while (a1 - a0 > 1) {
-                const uint32_t mid = (a0 + a1) >> 1;
-                if (s_pre[mid] <= p) a0 = mid;
-                else a1 = mid;
-            }
-            pidx = s_begin[a0] + (p - s_pre[a0]);
+        const uint32_t end = base + WAVE;
+        uint32_t my = seg;
+        uint32_t s = seg + 1;
+        uint32_t pre_s = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_pre[s]);
+        while (pre_s < end && s < nseg) {
+            if (p >= pre_s) my = s;
+            ++s;
+            pre_s = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_pre[s]);
         }
+        seg = (pre_s == end && s < nseg) ? s : s - 1;
+        const bool valid = p < npts;
+        const uint32_t pidx = valid ? s_begin[my] + (p - s_pre[my]) : 0u;
         Chunk<FT> cur;
-        fetch_chunk<FT>(ix, f, p < npts, pidx, cur);
-        st.cands += __popcll(ballot(cur.valid));
+        fetch_chunk<FT>(ix, f, valid, pidx, cur);
+        st.cands += __popcll(ballot(valid));
         score_chunk<FT>(q, f, k, cur, st);
     }
     wave_lds_sync();
@@ -283,7 +299,7 @@ __device__ __forceinline__ void score_runs(const IndexView& ix, const float* q, 
 
 // Stop rules, checked after every complete layer l.
 template <int FT, int STOP>
-__device__ __forceinline__ bool stop_after_layer(const IndexView& ix, const Query<FT>& Q, int f, int k, int64_t l,
+__device__ __forceinline__ bool stop_after_layer(const IndexView& ix, const Query<FT>& Q, int f, int k, int32_t l,
                                                  const WaveState& st) {
     if (l >= Q.lcover) return true;  // every occupied cell has been visited
     if (st.count != k) return false;
@@ -305,7 +321,7 @@ __device__ __forceinline__ bool stop_after_layer(const IndexView& ix, const Quer
 
 // Neighbours in (distance, id) order, then the majority vote (ties -> smallest
 // label) or the mean (FP64 sum in neighbour order, / k, rounded to FP32).
-__device__ __forceinline__ void finish_query(const IndexView& ix, const QueryIO& io, int64_t qi, int64_t l,
+__device__ __forceinline__ void finish_query(const IndexView& ix, const QueryIO& io, int64_t qi, int32_t l,
                                              const WaveState& st) {
     const int lane = lane_id();
     const int k = io.k;

@@ -38,70 +38,81 @@ __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& i
 
     const int L = f - 1;  // the run dimension
     const double aL = ix.a[L];
-    int64_t l = Q.l0;
+    int32_t l = Q.l0;
     for (;; ++l) {
         st.updated = false;
         // Range of ids per dimension: layer box c +- l clipped to the occupied box.
-        int64_t lo[FT > 0 ? FT : F_MAX], w[FT > 0 ? FT : F_MAX];
+        int32_t lo[FT > 0 ? FT : F_MAX], w[FT > 0 ? FT : F_MAX];
         int64_t rows = 1;
         bool empty = false;
 #pragma unroll
         for (int j = 0; j < (FT > 0 ? FT : F_MAX); ++j) {
             if (FT == 0 && j >= f) break;
-            const int64_t a0 = max(Q.c[j] - l, (int64_t)ix.cmin[j]);
-            const int64_t b0 = min(Q.c[j] + l, (int64_t)ix.cmax[j]);
+            const int32_t a0 = max(Q.c[j] - l, ix.cmin[j]);
+            const int32_t b0 = min(Q.c[j] + l, ix.cmax[j]);
             lo[j] = a0;
             w[j] = b0 - a0 + 1;
             if (b0 < a0) empty = true;
-            if (j < L) rows *= (b0 >= a0 ? (b0 - a0 + 1) : 0);
+            if (j < L) rows *= (b0 >= a0 ? (int64_t)(b0 - a0 + 1) : 0);
         }
         if (!empty) {
-            const bool small = rows < (int64_t(1) << 32);
+            // row decode by multiply-high with ceil(2^32 / w): exact while rem * w < 2^32
+            int32_t wmax = 1;
+            uint32_t mag[FT > 1 ? FT - 1 : 1];
+#pragma unroll
+            for (int j = 0; j < (FT > 1 ? FT - 1 : (FT == 1 ? 0 : F_MAX - 1)); ++j) {
+                if (FT == 0 && j >= L) break;
+                wmax = max(wmax, w[j]);
+                mag[FT > 1 ? j : 0] = w[j] > 1 ? (uint32_t)(0xffffffffu / (uint32_t)w[j]) + 1u : 0u;
+            }
+            const bool small = FT > 0 && rows * (int64_t)wmax < (int64_t(1) << 32);
             for (int64_t rb = 0; rb < rows; rb += WAVE) {
                 const int64_t r = rb + lane;
                 uint32_t b0 = 0, n0 = 0, b1 = 0, n1 = 0, probes_l = 0;
                 if (r < rows) {
                     // decode row r: ids of dimensions 0..L-1, the last of them fastest
-                    int64_t maxoff = 0, lin = 0;
+                    int32_t maxoff = 0;
+                    uint32_t lin = 0;
                     double lb = 0.0;
                     uint64_t rem64 = (uint64_t)r;
                     uint32_t rem32 = (uint32_t)r;
 #pragma unroll
                     for (int j = (FT > 0 ? FT - 2 : F_MAX - 2); j >= 0; --j) {
                         if (FT == 0 && j > L - 1) continue;
-                        int64_t digit;
+                        int32_t digit;
                         if (small) {
                             const uint32_t wj = (uint32_t)w[j];
-                            digit = rem32 % wj;
-                            rem32 /= wj;
+                            const uint32_t qd = wj > 1 ? __umulhi(rem32, mag[FT > 1 ? j : 0]) : rem32;
+                            digit = (int32_t)(rem32 - qd * wj);
+                            rem32 = qd;
                         } else {
-                            digit = (int64_t)(rem64 % (uint64_t)w[j]);
+                            digit = (int32_t)(rem64 % (uint64_t)w[j]);
                             rem64 /= (uint64_t)w[j];
                         }
-                        const int64_t oj = lo[j] + digit;
+                        const int32_t oj = lo[j] + digit;
                         maxoff = max(maxoff, oj > Q.c[j] ? oj - Q.c[j] : Q.c[j] - oj);
-                        lin += (oj - ix.cmin[j]) * ix.stride[j];
+                        lin += (uint32_t)(oj - ix.cmin[j]) * ix.stride[j];
                         const double g = gap_to_cells(Q.v[j], oj, oj, (double)ix.a[j]);
                         lb = __dadd_rn(lb, __dmul_rn(g, g));
                     }
                     const bool pass_row = !prune || !(lb * LB_SHRINK > st.tau);
                     if (pass_row) {
-                        const int64_t cL = Q.c[L];
-                        const int64_t lo_l = lo[L], hi_l = lo[L] + w[L] - 1;
+                        const int32_t cL = Q.c[L];
+                        const int32_t lo_l = lo[L], hi_l = lo[L] + w[L] - 1;
                         if (maxoff == l) {
                             // shell row: every cell of the run [c-l, c+l] inside the box
-                            int64_t ta = lo_l, tb = hi_l;
+                            int32_t ta = lo_l, tb = hi_l;
                             if (prune && st.tau < 1.0e300) {
                                 const double room = st.tau / LB_SHRINK - lb;
                                 const double G = sqrt(room > 0.0 ? room : 0.0);
                                 const double ub = floor((Q.v[L] + G) / aL) + 1.0;
                                 const double lb_t = ceil((Q.v[L] - G) / aL) - 2.0;
-                                if (ub < (double)tb) tb = (int64_t)ub;
-                                if (lb_t > (double)ta) ta = (int64_t)lb_t;
+                                if (ub < (double)tb) tb = (int32_t)ub;
+                                if (lb_t > (double)ta) ta = (int32_t)lb_t;
                             }
                             if (ta <= tb) {
-                                const uint32_t s0 = ix.cell_start[lin + (ta - ix.cmin[L])];
-                                const uint32_t s1 = ix.cell_start[lin + (tb - ix.cmin[L]) + 1];
+                                const uint32_t s0 = ix.cell_start[lin + (uint32_t)(ta - ix.cmin[L])];
+                                const uint32_t s1 = ix.cell_start[lin + (uint32_t)(tb - ix.cmin[L]) + 1];
                                 b0 = s0;
                                 n0 = s1 - s0;
                                 probes_l += 2;
@@ -109,14 +120,14 @@ __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& i
                         } else {
                             // interior row: only the end cells c-l and c+l belong to layer l
                             for (int e = 0; e < 2; ++e) {
-                                const int64_t t = e == 0 ? cL - l : cL + l;
+                                const int32_t t = e == 0 ? cL - l : cL + l;
                                 if (t < lo_l || t > hi_l) continue;
                                 if (prune) {
                                     const double g = gap_to_cells(Q.v[L], t, t, aL);
                                     if (__dadd_rn(lb, __dmul_rn(g, g)) * LB_SHRINK > st.tau) continue;
                                 }
-                                const uint32_t s0 = ix.cell_start[lin + (t - ix.cmin[L])];
-                                const uint32_t s1 = ix.cell_start[lin + (t - ix.cmin[L]) + 1];
+                                const uint32_t s0 = ix.cell_start[lin + (uint32_t)(t - ix.cmin[L])];
+                                const uint32_t s1 = ix.cell_start[lin + (uint32_t)(t - ix.cmin[L]) + 1];
                                 probes_l += 2;
                                 if (e == 0) { b0 = s0; n0 = s1 - s0; }
                                 else { b1 = s0; n1 = s1 - s0; }

@@ -38,7 +38,7 @@ __device__ __forceinline__ void walk_tree(const IndexView& ix, const QueryIO& io
     init_state(st);
     const int top = ix.tree_levels;  // level of the root entries (0 = the cells themselves)
 
-    int64_t l = Q.l0;
+    int32_t l = Q.l0;
     for (;; ++l) {
         st.updated = false;
         int sp = 0;
@@ -56,7 +56,7 @@ __device__ __forceinline__ void walk_tree(const IndexView& ix, const QueryIO& io
             const int64_t node = (int64_t)first + lane;
             // Chebyshev range of the node's cells from the central cell, and the
             // squared distance from the query to the node's region of space.
-            int64_t dmin = 0, dmax = 0;
+            int32_t dmin = 0, dmax = 0;
             double lb = 0.0;
             if (active) {
                 const int32_t* lo = level == 0 ? ix.cell_coord + node * f : ix.node_lo + (ix.tree_off[level] + node) * f;
@@ -64,9 +64,9 @@ __device__ __forceinline__ void walk_tree(const IndexView& ix, const QueryIO& io
 #pragma unroll
                 for (int j = 0; j < (FT > 0 ? FT : F_MAX); ++j) {
                     if (FT == 0 && j >= f) break;
-                    const int64_t a = lo[j], b = hi[j], cj = Q.c[j];
-                    const int64_t near = cj < a ? a - cj : (cj > b ? cj - b : 0);
-                    const int64_t far = max(cj - a, b - cj);
+                    const int32_t a = lo[j], b = hi[j], cj = Q.c[j];
+                    const int32_t near = cj < a ? a - cj : (cj > b ? cj - b : 0);
+                    const int32_t far = max(cj - a, b - cj);
                     dmin = max(dmin, near);
                     dmax = max(dmax, far);
                     const double g = gap_to_cells(Q.v[j], a, b, (double)ix.a[j]);
