@@ -26,6 +26,7 @@ __global__ __launch_bounds__(BPT) void k_predict_batched(const BatchItem* __rest
                                                          int64_t total, uint64_t* counter) {
     __shared__ uint32_t s_begin[BWPB][RUN_CAP];
     __shared__ uint32_t s_pre[BWPB][RUN_CAP];
+    __shared__ uint32_t s_key[BWPB][RUN_CAP];
     __shared__ uint64_t s_stack[BWPB][TREE_STACK_CAP];
     const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -47,7 +48,7 @@ __global__ __launch_bounds__(BPT) void k_predict_batched(const BatchItem* __rest
             const BatchItem& it = items[lo];
             const IndexView& ix = *it.ix;
             const int64_t qi = w - it.first;
-            if (ix.lookup == LOOKUP_DENSE) walk_dense<FT, STOP>(ix, it.io, qi, s_begin[wv], s_pre[wv]);
+            if (ix.lookup == LOOKUP_DENSE) walk_dense<FT, STOP>(ix, it.io, qi, s_begin[wv], s_pre[wv], s_key[wv]);
             else walk_tree<FT, STOP>(ix, it.io, qi, s_begin[wv], s_pre[wv], s_stack[wv]);
         }
     }

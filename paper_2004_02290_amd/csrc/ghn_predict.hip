@@ -12,11 +12,12 @@ template <int FT, int STOP>
 __global__ __launch_bounds__(PT) void k_predict_dense(PredictArgs A) {
     __shared__ uint32_t s_begin[WPB][RUN_CAP];
     __shared__ uint32_t s_pre[WPB][RUN_CAP];
+    __shared__ uint32_t s_key[WPB][RUN_CAP];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int64_t slot = wave_slot(A, WPB);
     if (slot >= A.m) return;
     const int64_t qi = A.order ? (int64_t)A.order[slot] : slot;
-    walk_dense<FT, STOP>(A.ix, A.io, qi, s_begin[wv], s_pre[wv]);
+    walk_dense<FT, STOP>(A.ix, A.io, qi, s_begin[wv], s_pre[wv], s_key[wv]);
 }
 
 // Sort key of a query: Morton interleave of its central cell id clamped to the

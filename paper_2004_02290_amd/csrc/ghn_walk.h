@@ -252,13 +252,41 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Key of a run for the nearest-first order: its distance lower bound (>= 0,
+// already shrunk), rounded down to FP32 with the low 7 bits cleared; the bit
+// pattern orders like the value and the low bits carry the run's slot.
+__device__ __forceinline__ uint32_t lb_key(double lb) {
+    float f = (float)lb;
+    if ((double)f > lb) f = __uint_as_float(__float_as_uint(f) - 1u);
+    return __float_as_uint(f) & ~127u;
+}
+
+// Ascending bitonic sort of one 32-bit key per lane over blocks of `width`
+// lanes (a power of two <= 64; lanes past the data hold 0xffffffff).
+__device__ __forceinline__ uint32_t wave_sort_asc(uint32_t key, int lane, int width) {
+    for (int size = 2; size <= width; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const uint32_t other = (uint32_t)__shfl_xor((int)key, stride, WAVE);
+            const bool up = (lane & size) == 0;
+            const bool low = (lane & stride) == 0;
+            key = low == up ? min(key, other) : max(key, other);
+        }
+    }
+    return key;
+}
+
 // Lane-held runs of points (begin b0/b1, length n0/n1; 0 = none) are listed in
 // the wave's LDS arrays and scored in 64-wide chunks, each lane finding its
 // point by a binary search over the run prefixes.
+//
+// With `order` set the runs carry lower-bound keys (lb_key of a lower bound of
+// every point's distance in the run): they are scored nearest run first, and
+// before each chunk the runs whose bound exceeds the current k-th distance are
+// cut off the end of the list (none of their points could enter the buffer).
 template <int FT>
 __device__ __forceinline__ void score_runs(const IndexView& ix, const float* q, int f, int k, uint32_t b0, uint32_t n0,
-                                           uint32_t b1, uint32_t n1, uint32_t* s_begin, uint32_t* s_pre,
-                                           WaveState& st) {
+                                           uint32_t key0, uint32_t b1, uint32_t n1, uint32_t key1, bool order,
+                                           uint32_t* s_begin, uint32_t* s_pre, uint32_t* s_key, WaveState& st) {
     const int lane = lane_id();
     const uint32_t nseg_l = (n0 > 0) + (n1 > 0);
     const uint32_t npts_l = n0 + n1;
@@ -268,14 +296,44 @@ __device__ __forceinline__ void score_runs(const IndexView& ix, const float* q, 
     const uint32_t npts = readlane_i32((int)pts_incl, WAVE - 1);
     if (npts == 0) return;
     uint32_t sidx = seg_incl - nseg_l, pofs = pts_incl - npts_l;
-    if (n0 > 0) { s_begin[sidx] = b0; s_pre[sidx] = pofs; ++sidx; pofs += n0; }
-    if (n1 > 0) { s_begin[sidx] = b1; s_pre[sidx] = pofs; }
+    const bool sorted = order && nseg > 1 && nseg <= WAVE;
+    float lbk = __int_as_float(0x7f800000);  // sorted: this lane's run bound (lanes < nseg)
+    if (sorted) {
+        if (n0 > 0) { s_begin[sidx] = b0; s_pre[sidx] = n0; s_key[sidx] = key0 | sidx; ++sidx; }
+        if (n1 > 0) { s_begin[sidx] = b1; s_pre[sidx] = n1; s_key[sidx] = key1 | sidx; }
+        wave_lds_sync();
+        uint32_t key = (uint32_t)lane < nseg ? s_key[lane] : 0xffffffffu;
+        int width = 2;
+        while ((uint32_t)width < nseg) width <<= 1;
+        key = wave_sort_asc(key, lane, width);
+        uint32_t rb = 0, rn = 0;
+        if ((uint32_t)lane < nseg) {
+            rb = s_begin[key & 127u];
+            rn = s_pre[key & 127u];
+            lbk = __uint_as_float(key & ~127u);
+        }
+        const uint32_t incl = wave_incl_scan(rn);
+        wave_lds_sync();
+        if ((uint32_t)lane < nseg) { s_begin[lane] = rb; s_pre[lane] = incl - rn; }
+    } else {
+        if (n0 > 0) { s_begin[sidx] = b0; s_pre[sidx] = pofs; ++sidx; pofs += n0; }
+        if (n1 > 0) { s_begin[sidx] = b1; s_pre[sidx] = pofs; }
+    }
     if (lane == 0) s_pre[nseg] = npts;  // sentinel
     wave_lds_sync();
     // Chunk [base, base + 64): `seg` is the run holding `base`; the runs that start
     // inside the chunk are few, so each lane finds its run with one uniform pass.
     uint32_t seg = 0;
-    for (uint32_t base = 0; base < npts; base += WAVE) {
+    uint32_t limit = npts;
+    for (uint32_t base = 0; base < limit; base += WAVE) {
+        if (sorted) {
+            const uint64_t far = ballot((double)lbk > st.tau);
+            if (far) {
+                const uint32_t cut = (uint32_t)(__ffsll((unsigned long long)far) - 1);
+                limit = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_pre[cut]);
+                if (base >= limit) break;
+            }
+        }
         const uint32_t p = base + lane;
         const uint32_t end = base + WAVE;
         uint32_t my = seg;
@@ -287,7 +345,7 @@ __device__ __forceinline__ void score_runs(const IndexView& ix, const float* q, 
             pre_s = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_pre[s]);
         }
         seg = (pre_s == end && s < nseg) ? s : s - 1;
-        const bool valid = p < npts;
+        const bool valid = p < limit;
         const uint32_t pidx = valid ? s_begin[my] + (p - s_pre[my]) : 0u;
         Chunk<FT> cur;
         fetch_chunk<FT>(ix, f, valid, pidx, cur);

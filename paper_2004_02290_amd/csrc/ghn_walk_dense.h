@@ -21,7 +21,7 @@ namespace ghn {
 
 template <int FT, int STOP>
 __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& io, int64_t qi,
-                                           uint32_t* s_begin, uint32_t* s_pre) {
+                                           uint32_t* s_begin, uint32_t* s_pre, uint32_t* s_key) {
     const int lane = lane_id();
     const int f = FT > 0 ? FT : ix.f;
     const int k = io.k;
@@ -68,7 +68,7 @@ __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& i
             const bool small = FT > 0 && rows * (int64_t)wmax < (int64_t(1) << 32);
             for (int64_t rb = 0; rb < rows; rb += WAVE) {
                 const int64_t r = rb + lane;
-                uint32_t b0 = 0, n0 = 0, b1 = 0, n1 = 0, probes_l = 0;
+                uint32_t b0 = 0, n0 = 0, b1 = 0, n1 = 0, key0 = 0, key1 = 0, probes_l = 0;
                 if (r < rows) {
                     // decode row r: ids of dimensions 0..L-1, the last of them fastest
                     int32_t maxoff = 0;
@@ -116,27 +116,33 @@ __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& i
                                 b0 = s0;
                                 n0 = s1 - s0;
                                 probes_l += 2;
+                                if (prune) {
+                                    const double g = gap_to_cells(Q.v[L], ta, tb, aL);
+                                    key0 = lb_key(__dadd_rn(lb, __dmul_rn(g, g)) * LB_SHRINK);
+                                }
                             }
                         } else {
                             // interior row: only the end cells c-l and c+l belong to layer l
                             for (int e = 0; e < 2; ++e) {
                                 const int32_t t = e == 0 ? cL - l : cL + l;
                                 if (t < lo_l || t > hi_l) continue;
+                                double lbe = 0.0;
                                 if (prune) {
                                     const double g = gap_to_cells(Q.v[L], t, t, aL);
-                                    if (__dadd_rn(lb, __dmul_rn(g, g)) * LB_SHRINK > st.tau) continue;
+                                    lbe = __dadd_rn(lb, __dmul_rn(g, g)) * LB_SHRINK;
+                                    if (lbe > st.tau) continue;
                                 }
                                 const uint32_t s0 = ix.cell_start[lin + (uint32_t)(t - ix.cmin[L])];
                                 const uint32_t s1 = ix.cell_start[lin + (uint32_t)(t - ix.cmin[L]) + 1];
                                 probes_l += 2;
-                                if (e == 0) { b0 = s0; n0 = s1 - s0; }
-                                else { b1 = s0; n1 = s1 - s0; }
+                                if (e == 0) { b0 = s0; n0 = s1 - s0; key0 = lb_key(lbe); }
+                                else { b1 = s0; n1 = s1 - s0; key1 = lb_key(lbe); }
                             }
                         }
                     }
                 }
                 st.probes += wave_sum_u32(probes_l);
-                score_runs<FT>(ix, Q.q, f, k, b0, n0, b1, n1, s_begin, s_pre, st);
+                score_runs<FT>(ix, Q.q, f, k, b0, n0, key0, b1, n1, key1, prune, s_begin, s_pre, s_key, st);
             }
         }
         if (stop_after_layer<FT, STOP>(ix, Q, f, k, l, st)) break;

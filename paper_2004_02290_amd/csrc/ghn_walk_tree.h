@@ -81,7 +81,7 @@ __device__ __forceinline__ void walk_tree(const IndexView& ix, const QueryIO& io
                     b0 = ix.cell_first[node];
                     n0 = ix.cell_first[node + 1] - b0;
                 }
-                score_runs<FT>(ix, Q.q, f, k, b0, n0, 0u, 0u, s_begin, s_pre, st);
+                score_runs<FT>(ix, Q.q, f, k, b0, n0, 0u, 0u, 0u, 0u, false, s_begin, s_pre, nullptr, st);
             } else {
                 const bool keep = active && dmin <= l && l <= dmax && close;
                 const uint64_t km = ballot(keep);
