@@ -57,6 +57,41 @@ def measured_traffic(workload: str, form: str):
     return entry.get("bytes_per_launch")
 
 
+def write_traffic(pmc_dir: str, workloads) -> None:
+    """Turn rocprofv3 --pmc runs into HBM bytes per launch (profiles/traffic.json).
+
+    Expects <pmc_dir>/<tag>/pmc_counter_collection.csv for the tags fetch_copy,
+    write_copy (FETCH_SIZE / WRITE_SIZE of `bench.py --copy-calib`) and
+    fetch_<workload>, write_<workload> (the same counters over a bench run).  The
+    counters (KiB per dispatch) are scaled by what they read for the 1 GiB copy.
+    """
+    import csv
+
+    def values(tag, name_part):
+        with open(os.path.join(pmc_dir, tag, "pmc_counter_collection.csv")) as fh:
+            return [float(r["Counter_Value"]) for r in csv.DictReader(fh) if name_part in r["Kernel_Name"]]
+
+    copy_bytes = float(1 << 30)
+    cf, cw = values("fetch_copy", "copyBuffer"), values("write_copy", "copyBuffer")
+    fetch_scale = copy_bytes / (float(np.mean(cf)) * 1024.0)
+    write_scale = copy_bytes / (float(np.mean(cw)) * 1024.0)
+    out = {"copy_calibration": {"bytes": copy_bytes, "fetch_kib": float(np.mean(cf)), "write_kib": float(np.mean(cw)),
+                                "fetch_scale": fetch_scale, "write_scale": write_scale}}
+    for w in workloads:
+        for form, kname in (("fp32", "k_predict_dense"), ("fp32", "k_predict_tree"), ("bf16", "k_predict_group")):
+            fv, wv = values("fetch_" + w, kname), values("write_" + w, kname)
+            if not fv or not wv:
+                continue
+            fk, wk = float(np.mean(fv)), float(np.mean(wv))
+            out["%s/%s" % (w, form)] = {
+                "kernel": kname, "dispatches": len(fv), "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
+                "bytes_per_launch": fk * 1024.0 * fetch_scale + wk * 1024.0 * write_scale,
+                "source_sha256_16": source_hash()}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1, sort_keys=True)
+    print(json.dumps(out, indent=1, sort_keys=True))
+
+
 def cpu_baseline(prob, target_s: float = 15.0):
     """The oracle's grid walk (EXACT rule) on a bounded query sample, all host threads."""
     import oracle
@@ -200,9 +235,15 @@ def main():
     ap.add_argument("--group-levels", type=int, default=-1, help="bf16 form: cell-id bits dropped to group queries")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
+    ap.add_argument("--write-traffic", metavar="PMC_DIR",
+                    help="no GPU work: write profiles/traffic.json from rocprofv3 --pmc output for --workload "
+                         "(a comma list)")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(args.write_traffic, args.workload.split(","))
+        return
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; run with --gpus 1", file=sys.stderr)
+        print("bench.py: this benchmark measures one GPU only; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -243,22 +284,23 @@ def main():
     out_idx = torch.empty((m, k), dtype=torch.int64, device=dev)
     out_pred = torch.empty(m, dtype=torch.int32 if prob.task == 0 else torch.float32, device=dev)
 
-    def timed(step, ev_mid_needed=False):
+    def timed(step):
+        """Warm up, then time `steps` calls; each call also gets a (begin, end) event pair
+        that the library records around its walk kernel on the same stream."""
         for _ in range(args.warmup):
             step(None)
         torch.cuda.synchronize()
-        ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-        evm = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-        ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        ev0, ev1, wb, we = mk(), mk(), mk(), mk()
         torch.cuda.synchronize()
         for i in range(args.steps):
             ev0[i].record()
-            step(evm[i] if ev_mid_needed else None)
+            step((wb[i], we[i]))
             ev1[i].record()
         torch.cuda.synchronize()
         per = np.array([ev0[i].elapsed_time(ev1[i]) for i in range(args.steps)])
         ms = float(ev0[0].elapsed_time(ev1[-1])) / args.steps
-        kern = np.array([evm[i].elapsed_time(ev1[i]) for i in range(args.steps)]) if ev_mid_needed else per
+        kern = np.array([wb[i].elapsed_time(we[i]) for i in range(args.steps)])
         return ms, float(kern.mean()), per
 
     def stats(prec, flags=0, levels=-1):
@@ -278,18 +320,16 @@ def main():
         order = torch.empty(m, dtype=torch.int32, device=dev)
         ows = torch.empty(max(ghn.ghn_query_order_workspace_bytes(m), 1), dtype=torch.uint8, device=dev)
 
-        def step32(ev_mid):
+        def step32(evs):
             if args.sort:
                 ghn.ghn_query_order(ix.handle, qs, order, ows)
-                if ev_mid is not None:
-                    ev_mid.record()
-                ghn.ghn_predict(ix.handle, qs, k, out_idx, out_pred, None, stop, ghn.GHN_PREC_FP32, 0, order=order)
+                ghn.ghn_predict(ix.handle, qs, k, out_idx, out_pred, None, stop, ghn.GHN_PREC_FP32, 0, order=order,
+                                walk_events=evs)
             else:
-                if ev_mid is not None:
-                    ev_mid.record()
-                ghn.ghn_predict(ix.handle, qs, k, out_idx, out_pred, None, stop, ghn.GHN_PREC_FP32, flags)
+                ghn.ghn_predict(ix.handle, qs, k, out_idx, out_pred, None, stop, ghn.GHN_PREC_FP32, flags,
+                                walk_events=evs)
 
-        ms, kern_ms, per = timed(step32, True)
+        ms, kern_ms, per = timed(step32)
         alg_bytes = (m * 4 * f + w["cands"] * (4 * f + 4) + w["probes"] * 4 + m * k * 4 + m * k * 8 + m * 4)
         achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
         forms["fp32_plain"] = dict(
@@ -303,18 +343,18 @@ def main():
         ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dev)
         w = stats(ghn.GHN_PREC_BF16_MFMA, 0, args.group_levels)
 
-        def step16(ev_mid):
+        def step16(evs):
             ghn.ghn_predict(ix.handle, qs, k, out_idx, out_pred, None, stop, ghn.GHN_PREC_BF16_MFMA, 0, ws=ws,
-                            group_levels=args.group_levels)
+                            group_levels=args.group_levels, walk_events=evs)
 
-        ms, kern_ms, per = timed(step16, False)
+        ms, kern_ms, per = timed(step16)
         flops = 2.0 * f * w["cands"]  # algorithmic: 2 f per screened (query, candidate) pair
-        achieved = flops / (ms * 1e-3) / 1e12
+        achieved = flops / (kern_ms * 1e-3) / 1e12
         forms["bf16_batched"] = dict(
-            qps=m / (ms * 1e-3), ms_per_step=ms, kernel_ms=ms, per=per, work=w,
+            qps=m / (ms * 1e-3), ms_per_step=ms, kernel_ms=kern_ms, per=per, work=w,
             roofline={"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                       "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": measured_traffic(args.workload, "bf16"),
-                      "kernel": "k_predict_group (timed with its query sort and grouping)"},
+                      "kernel": "k_predict_group"},
             alg={"flops_per_step": flops, "issued_mfma_flops_per_step": 2.0 * (-(-3 * f // 32) * 32) * w["cands"]})
 
     best = max(forms, key=lambda name: forms[name]["qps"])

@@ -49,7 +49,7 @@ extern "C" {
 typedef enum {
     GHN_OK = 0,
     GHN_E_INVALID_ARG = -1,  /* bad size, null pointer, bad enum, width <= 0 or not finite */
-    GHN_E_UNSUPPORTED = -2,  /* valid request this build cannot serve */
+    GHN_E_UNSUPPORTED = -2,  /* valid request this library cannot serve */
     GHN_E_K_GT_N = -3,       /* k larger than the number of training points */
     GHN_E_NONFINITE = -4,    /* a training point has a NaN or infinite coordinate */
     GHN_E_KEY_OVERFLOW = -5, /* cell ids span more than the key can hold */
@@ -164,6 +164,9 @@ typedef struct {
                                 (blocks of 2^group_levels cells per dimension) are walked
                                 together, up to 16 per group; -1 = automatic (1).  The PAPER
                                 rule always groups by identical central cell. */
+    void* walk_event_begin;  /* optional hipEvent_t: recorded on the stream right before the walk
+                                kernel (the exploration launch, after any query sort/grouping) */
+    void* walk_event_end;    /* optional hipEvent_t: recorded right after the walk kernel */
 } ghn_predict_opts;
 
 /* Bytes of device workspace ghn_predict needs for these arguments (the bf16

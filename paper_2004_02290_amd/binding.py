@@ -58,7 +58,8 @@ class ghn_predict_opts(ctypes.Structure):
     _fields_ = [("stop", ctypes.c_int32), ("prec", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("out_stop_layer", ctypes.c_void_p), ("out_cands", ctypes.c_void_p),
                 ("out_probes", ctypes.c_void_p), ("order", ctypes.c_void_p),
-                ("group_levels", ctypes.c_int32)]
+                ("group_levels", ctypes.c_int32), ("walk_event_begin", ctypes.c_void_p),
+                ("walk_event_end", ctypes.c_void_p)]
 
 
 class ghn_batch_item(ctypes.Structure):
@@ -195,10 +196,20 @@ def ghn_destroy(handle) -> None:
     _lib.ghn_destroy(handle)
 
 
+def _event(ev):
+    """Raw hipEvent_t of a torch.cuda.Event (recorded once so that it exists), or None."""
+    if ev is None:
+        return None
+    if not ev.cuda_event:
+        ev.record()
+    return ctypes.c_void_p(ev.cuda_event)
+
+
 def _opts(stop, prec, flags, out_stop_layer=None, out_cands=None, out_probes=None, order=None,
-          group_levels=-1) -> ghn_predict_opts:
+          group_levels=-1, walk_events=None) -> ghn_predict_opts:
+    ev0, ev1 = walk_events if walk_events is not None else (None, None)
     return ghn_predict_opts(int(stop), int(prec), int(flags), _ptr(out_stop_layer), _ptr(out_cands),
-                            _ptr(out_probes), _ptr(order), int(group_levels))
+                            _ptr(out_probes), _ptr(order), int(group_levels), _event(ev0), _event(ev1))
 
 
 def ghn_predict_workspace_bytes(handle, m: int, k: int, stop=GHN_STOP_EXACT, prec=GHN_PREC_FP32, flags=0,
@@ -211,10 +222,13 @@ def ghn_predict(handle, queries: torch.Tensor, k: int, out_idx: torch.Tensor, ou
                 out_d2: Optional[torch.Tensor] = None, stop=GHN_STOP_EXACT, prec=GHN_PREC_FP32, flags=0,
                 out_stop_layer: Optional[torch.Tensor] = None, out_cands: Optional[torch.Tensor] = None,
                 out_probes: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
-                order: Optional[torch.Tensor] = None, group_levels: int = -1, stream=None) -> None:
-    """ghn_predict into caller-provided outputs (int64 idx m x k, pred m, optional float64 d2 m x k)."""
+                order: Optional[torch.Tensor] = None, group_levels: int = -1, stream=None,
+                walk_events=None) -> None:
+    """ghn_predict into caller-provided outputs (int64 idx m x k, pred m, optional float64 d2 m x k).
+
+    walk_events: optional (begin, end) pair of torch.cuda.Event recorded around the walk kernel."""
     m = queries.shape[0]
-    o = _opts(stop, prec, flags, out_stop_layer, out_cands, out_probes, order, group_levels)
+    o = _opts(stop, prec, flags, out_stop_layer, out_cands, out_probes, order, group_levels, walk_events)
     ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
     _check(_lib.ghn_predict(handle, _ptr(queries), m, k, ctypes.byref(o), _ptr(out_idx), _ptr(out_d2),
                             _ptr(out_pred), _ptr(ws), ws_bytes, _stream(stream)))

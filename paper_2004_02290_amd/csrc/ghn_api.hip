@@ -89,7 +89,7 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
     if (!out) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: out is NULL");
     *out = nullptr;
     if (!items || n_items < 1) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: no items");
-    ghn_predict_opts o = {GHN_STOP_EXACT, GHN_PREC_FP32, 0u, nullptr, nullptr, nullptr, nullptr, -1};
+    ghn_predict_opts o = {GHN_STOP_EXACT, GHN_PREC_FP32, 0u, nullptr, nullptr, nullptr, nullptr, -1, nullptr, nullptr};
     if (opts) o = *opts;
     if (o.stop != GHN_STOP_EXACT && o.stop != GHN_STOP_PAPER) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: bad stop rule %d", o.stop);
     if (o.prec != GHN_PREC_FP32) return fail(GHN_E_UNSUPPORTED, "ghn_batch_prepare: batches use the FP32 screen");
@@ -530,7 +530,7 @@ ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, 
     if (m < 0) return fail(GHN_E_INVALID_ARG, "ghn_predict: m=%lld < 0", (long long)m);
     if (k < 1 || k > K_MAX) return fail(GHN_E_INVALID_ARG, "ghn_predict: k=%d outside [1, %d]", k, K_MAX);
     if (k > index->info.n) return fail(GHN_E_K_GT_N, "ghn_predict: k=%d exceeds n=%lld", k, (long long)index->info.n);
-    ghn_predict_opts o = {GHN_STOP_EXACT, GHN_PREC_FP32, 0u, nullptr, nullptr, nullptr, nullptr, -1};
+    ghn_predict_opts o = {GHN_STOP_EXACT, GHN_PREC_FP32, 0u, nullptr, nullptr, nullptr, nullptr, -1, nullptr, nullptr};
     if (opts) o = *opts;
     if (o.stop != GHN_STOP_EXACT && o.stop != GHN_STOP_PAPER) return fail(GHN_E_INVALID_ARG, "ghn_predict: bad stop rule %d", o.stop);
     if (o.prec != GHN_PREC_FP32 && o.prec != GHN_PREC_BF16_MFMA) return fail(GHN_E_INVALID_ARG, "ghn_predict: bad precision %d", o.prec);
@@ -565,7 +565,7 @@ ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, 
         if (m >= (int64_t(1) << 32)) return fail(GHN_E_INVALID_ARG, "ghn_predict: m=%lld too large for one call", (long long)m);
         const int levels = o.stop == GHN_STOP_PAPER ? 0 : (o.group_levels < 0 ? 1 : o.group_levels);
         int bits = 0;
-        e = run_grouped(pa, levels, ws, s, &bits);
+        e = run_grouped(pa, levels, ws, s, &bits, (hipEvent_t)o.walk_event_begin, (hipEvent_t)o.walk_event_end);
         if (bits > 64) return fail(GHN_E_UNSUPPORTED, "ghn_predict: the Morton code of the cell ids needs %d bits (> 64)", bits);
         if (e != hipSuccess) return hip_fail(e, "ghn_predict: grouped walk");
         return GHN_OK;
@@ -579,8 +579,12 @@ ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, 
         if ((e = sort_queries(index, queries, m, ws, &order, s)) != hipSuccess) return hip_fail(e, "ghn_predict: query sort");
         pa.order = order;
     }
+    if (o.walk_event_begin && (e = hipEventRecord((hipEvent_t)o.walk_event_begin, s)) != hipSuccess)
+        return hip_fail(e, "ghn_predict: walk_event_begin");
     e = index->view.lookup == LOOKUP_DENSE ? launch_predict_dense(pa, s) : launch_predict_tree(pa, s);
     if (e != hipSuccess) return hip_fail(e, "ghn_predict: launch");
+    if (o.walk_event_end && (e = hipEventRecord((hipEvent_t)o.walk_event_end, s)) != hipSuccess)
+        return hip_fail(e, "ghn_predict: walk_event_end");
     return GHN_OK;
 }
 

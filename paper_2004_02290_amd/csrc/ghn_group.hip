@@ -13,11 +13,14 @@
 // Candidates are staged 64 at a time in LDS, centred on the group box and split
 // into bf16 hi + lo parts.  v_mfma_f32_16x16x32_bf16 forms the 16 x 64 tile of
 // q'.x' with K = [qh, qh, ql] . [xh, xl, xh] (the lo x lo term is dropped), and
-// the screen value is s = |q'|^2 + |x'|^2 - 2 q'.x' in FP32.  With round-to-
-// nearest splits |s - d| <= 2^-16 (|q'|^2 + |x'|^2) (Jacobian of the split and of
-// the FP32 accumulation over 3f terms; see the design notes); a candidate is
-// re-scored in FP64 only if s - 2^-12 (|q'|^2 + |x'|^2) is within the query's
-// k-th distance, so the selected set is the exact FP64 one.
+// the screen value is s = |q'|^2 + |x'|^2 - 2 q'.x' in FP32.  Error bound, with
+// N = |q'|^2 + |x'|^2 and u = 2^-8 (bf16 round to nearest): each split leaves a
+// residue |x' - h - l| <= u^2 |x'|, so the residues and the dropped lo x lo term
+// move q'.x' by at most 3 u^2 sum |q'_j x'_j| <= 1.5 u^2 N, i.e. s by 3 u^2 N;
+// the FP32 accumulation over 3f <= 96 terms, the norms and the centring add less
+// than 2^-17 N.  So |s - d| < 2^-14.4 N, and a candidate is re-scored in FP64
+// whenever s - 2^-12 N - 2^-100 is within the query's k-th distance (the 2^-100
+// covers underflow): the selected set is the exact FP64 one.
 //
 // In the result tile, lane l holds column l % 16 and rows 4 (l / 16) + i: the
 // 16-lane DPP row g holds queries 4g .. 4g+3.  Each query's size-k buffer lives
@@ -595,7 +598,8 @@ size_t group_ws_bytes(int64_t m) {
 }
 
 // Sort + group the queries, then walk the groups.  `ws` holds group_ws_bytes(m).
-hipError_t run_grouped(const PredictArgs& pa, int keep_shift_levels, void* ws, hipStream_t s, int* morton_bits) {
+hipError_t run_grouped(const PredictArgs& pa, int keep_shift_levels, void* ws, hipStream_t s, int* morton_bits,
+                       hipEvent_t ev_begin, hipEvent_t ev_end) {
     const IndexView& ix = pa.ix;
     const int64_t m = pa.m;
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
@@ -639,14 +643,17 @@ hipError_t run_grouped(const PredictArgs& pa, int keep_shift_levels, void* ws, h
     ga.work = counters + 1;
     int64_t blocks = (m + GQ * GWPB - 1) / (GQ * GWPB);
     if (blocks > 2048) blocks = 2048;
+    if (ev_begin && (e = hipEventRecord(ev_begin, s)) != hipSuccess) return e;
     switch (ix.f) {
-        case 2: return launch_ft<2>(ga, (int)blocks, s);
-        case 3: return launch_ft<3>(ga, (int)blocks, s);
-        case 4: return launch_ft<4>(ga, (int)blocks, s);
-        case 8: return launch_ft<8>(ga, (int)blocks, s);
-        case 16: return launch_ft<16>(ga, (int)blocks, s);
-        default: return launch_ft<0>(ga, (int)blocks, s);
+        case 2: e = launch_ft<2>(ga, (int)blocks, s); break;
+        case 3: e = launch_ft<3>(ga, (int)blocks, s); break;
+        case 4: e = launch_ft<4>(ga, (int)blocks, s); break;
+        case 8: e = launch_ft<8>(ga, (int)blocks, s); break;
+        case 16: e = launch_ft<16>(ga, (int)blocks, s); break;
+        default: e = launch_ft<0>(ga, (int)blocks, s); break;
     }
+    if (e == hipSuccess && ev_end) e = hipEventRecord(ev_end, s);
+    return e;
 }
 
 }  // namespace ghn

@@ -190,7 +190,8 @@ hipError_t coord_range(const void* pts, int64_t n, int32_t f, int32_t dtype, flo
 
 // Grouped walk with the bf16 matrix-core screen: sort, group and walk the queries.
 size_t group_ws_bytes(int64_t m);
-hipError_t run_grouped(const PredictArgs& pa, int group_levels, void* ws, hipStream_t s, int* morton_bits);
+hipError_t run_grouped(const PredictArgs& pa, int group_levels, void* ws, hipStream_t s, int* morton_bits,
+                       hipEvent_t ev_begin, hipEvent_t ev_end);
 // Spatial sort key of every query (Morton code of its box-clamped central cell).
 hipError_t launch_query_keys(const float* qs, int64_t m, const IndexView& ix, int keep_bits, uint64_t* keys,
                              uint32_t* vals, hipStream_t s);
