@@ -361,6 +361,19 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
     if ((e = hipMemcpyAsync(tg, targets, (size_t)n * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(e, "ghn_build: targets");
     iv.spts = spts; iv.sid = sid; iv.targets = tg;
 
+    // bf16 screen records, centred on the occupied box
+    iv.sp = f <= 8 ? 8 : (f <= 16 ? 16 : 32);
+    for (int j = 0; j < F_MAX; ++j) iv.c0[j] = 0.0f;
+    for (int j = 0; j < f; ++j)
+        iv.c0[j] = (float)((double)o[j] + ((double)iv.cmin[j] + (double)iv.cmax[j] + 1.0) * 0.5 * (double)a[j]);
+    uint16_t* srec;
+    float* sxn;
+    if (keep.alloc((void**)&srec, (size_t)n * 2 * iv.sp * 2) || keep.alloc((void**)&sxn, (size_t)n * 4))
+        return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the screen records");
+    if ((e = launch_screen_records(iv, srec, sxn, s)) != hipSuccess) return hip_fail(e, "ghn_build: screen records");
+    iv.srec = srec;
+    iv.sxn = sxn;
+
     // 4. occupied cells (both lookups): heads of equal-key runs, their ranks, first
     //    points and ids, then the bounding-box levels above them
     uint32_t *heads, *rank;
@@ -444,7 +457,8 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
         ix->info.cell_width[j] = a[j];
         ix->info.origin[j] = o[j];
     }
-    ix->info.device_bytes = (size_t)n * f * 4 + (size_t)n * 4 + (size_t)n * 4 + table_bytes;
+    ix->info.device_bytes = (size_t)n * f * 4 + (size_t)n * 4 + (size_t)n * 4 + table_bytes +
+                           (size_t)n * 2 * iv.sp * 2 + (size_t)n * 4;
     keep.release(ix->allocs);
     *out = ix;
     return GHN_OK;

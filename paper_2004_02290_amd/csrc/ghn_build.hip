@@ -226,6 +226,35 @@ __global__ __launch_bounds__(BT) void k_gather_points(const void* pts, int64_t n
     }
 }
 
+// bf16 round to nearest, ties to even, of a finite float.
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// Screen record of every point (cell order): x' = fl32(x - c0), hi = bf16(x'),
+// lo = bf16(x' - hi), dimensions f..sp-1 zero; xn = |x'|^2 (FP64 sum, rounded).
+__global__ __launch_bounds__(BT) void k_screen_records(IndexView iv, uint16_t* __restrict__ rec,
+                                                       float* __restrict__ xn) {
+    const int f = iv.f, sp = iv.sp;
+    for (int64_t r = blockIdx.x * (int64_t)BT + threadIdx.x; r < iv.n; r += (int64_t)gridDim.x * BT) {
+        double nn = 0.0;
+        uint16_t* out = rec + r * 2 * sp;
+        for (int j = 0; j < sp; ++j) {
+            uint16_t h = 0, l = 0;
+            if (j < f) {
+                const float xp = iv.spts[r * f + j] - iv.c0[j];
+                h = bf16_rne(xp);
+                l = bf16_rne(xp - __uint_as_float((uint32_t)h << 16));
+                nn += (double)xp * (double)xp;
+            }
+            out[j] = h;
+            out[sp + j] = l;
+        }
+        xn[r] = (float)nn;
+    }
+}
+
 // cell_start[L] = first position whose key is >= L, for L in [0, box_cells].
 __global__ __launch_bounds__(BT) void k_dense_cell_start(const uint64_t* __restrict__ keys, int64_t n,
                                                          int64_t box_cells, uint32_t* __restrict__ cs) {
@@ -324,6 +353,11 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void
 hipError_t launch_gather_points(const void* pts, int64_t n, int32_t f, int32_t dtype, const uint32_t* perm,
                                 float* spts, int32_t* sid, hipStream_t s) {
     hipLaunchKernelGGL(k_gather_points, dim3(grid_for(n, BT)), dim3(BT), 0, s, pts, n, f, dtype, perm, spts, sid);
+    return hipGetLastError();
+}
+
+hipError_t launch_screen_records(const IndexView& iv, uint16_t* rec, float* xn, hipStream_t s) {
+    hipLaunchKernelGGL(k_screen_records, dim3(grid_for(iv.n, BT)), dim3(BT), 0, s, iv, rec, xn);
     return hipGetLastError();
 }
 

@@ -10,17 +10,27 @@
 // as in the per-query walk.  Under the PAPER rule the group is a single cell,
 // so group layers are the queries' layers.
 //
-// Candidates are staged 64 at a time in LDS, centred on the group box and split
-// into bf16 hi + lo parts.  v_mfma_f32_16x16x32_bf16 forms the 16 x 64 tile of
-// q'.x' with K = [qh, qh, ql] . [xh, xl, xh] (the lo x lo term is dropped), and
-// the screen value is s = |q'|^2 + |x'|^2 - 2 q'.x' in FP32.  Error bound, with
-// N = |q'|^2 + |x'|^2 and u = 2^-8 (bf16 round to nearest): each split leaves a
-// residue |x' - h - l| <= u^2 |x'|, so the residues and the dropped lo x lo term
-// move q'.x' by at most 3 u^2 sum |q'_j x'_j| <= 1.5 u^2 N, i.e. s by 3 u^2 N;
-// the FP32 accumulation over 3f <= 96 terms, the norms and the centring add less
-// than 2^-17 N.  So |s - d| < 2^-14.4 N, and a candidate is re-scored in FP64
-// whenever s - 2^-12 N - 2^-100 is within the query's k-th distance (the 2^-100
-// covers underflow): the selected set is the exact FP64 one.
+// The distance step is a matrix-core contraction.  At build time every point
+// gets a screen record: x' = fl32(x - c0) (c0 = centre of the occupied box)
+// split into bf16 parts h = bf16(x'), l = bf16(x' - h), padded to sp = 8, 16 or
+// 32 dimensions, plus xn = |x'|^2.  v_mfma_f32_16x16x32_bf16 then forms, for 16
+// queries x 16 candidates at a time, acc = (1 - R) xn - A - 2 q'.x' with
+// K = [qh, qh, ql] . [xh, xl, xh] (the lo x lo term is dropped): each lane loads
+// its 16-byte slice of a record straight into the B operand, the query parts
+// sit in the A operand for the whole walk, and the norms enter as the
+// accumulator's initial value.  A pair is admitted when acc <= thr - (1 - R) qn,
+// i.e. when s - R (qn + xn) - A <= thr with s = qn + xn - 2 q'.x' and thr the
+// query's FP32 admission threshold above its k-th FP64 distance.
+//
+// Error bound, with N = |q'|^2 + |x'|^2 and u = 2^-8 (bf16 round to nearest):
+// each split leaves |x' - h - l| <= u^2 |x'|, so the residues and the dropped
+// lo x lo term move q'.x' by at most 3 u^2 sum |q'_j x'_j| <= 1.5 u^2 N, i.e. s
+// by 3 u^2 N = 2^-14.4 N; the FP32 accumulation of at most 6 sp / 2 + 1 terms
+// whose magnitudes sum to at most 2N adds at most 97 * 2^-23 N < 2^-15.4 N; the
+// centring (one FP32 rounding per coordinate) and the FP32 norms add below
+// 2^-20 N.  So |s - d| < 2^-13.8 N, and R = 2^-12 (A = 2^-100 for underflow)
+// admits every pair whose FP64 distance can still enter the buffer; admitted
+// pairs are re-scored in FP64, so the selected set is the exact FP64 one.
 //
 // In the result tile, lane l holds column l % 16 and rows 4 (l / 16) + i: the
 // 16-lane DPP row g holds queries 4g .. 4g+3.  Each query's size-k buffer lives
@@ -40,11 +50,6 @@ constexpr int GQ = 16;           // queries per group
 constexpr int STACK_CAP = TREE_LEVELS_MAX * WAVE;
 constexpr float SCREEN_REL = 0x1p-12f;   // admission margin, relative to |q'|^2 + |x'|^2
 constexpr float SCREEN_ABS = 0x1p-100f;  // absolute margin (FP32 underflow)
-
-template <int FT>
-struct KPad {
-    static constexpr int value = FT > 0 ? ((3 * FT + 31) / 32) * 32 : ((3 * F_MAX + 31) / 32) * 32;
-};
 
 // ---- row (16-lane) DPP helpers -------------------------------------------------------------
 __device__ __forceinline__ int row_ror1(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x121, 0xf, 0xf, false); }
@@ -150,26 +155,90 @@ struct GroupArgs {
 template <int FT>
 struct alignas(16) GroupLds {
     static constexpr int FS = FT > 0 ? FT : F_MAX;
-    static constexpr int KP = KPad<FT>::value;
     float q[GQ][FS];
     int32_t qc[GQ][FS];
-    float x[WAVE][FS];
-    int32_t xid[WAVE];
-    float xn[WAVE];
-    __bf16 frag[WAVE][KP];
-    uint32_t run_begin[WAVE];
-    uint32_t run_pre[WAVE];
+    uint32_t run_begin[WAVE + 1];
+    uint32_t run_pre[WAVE + 1];
     uint64_t stack[STACK_CAP];
     int32_t lab[4][K_MAX];
     int32_t glo[FS], ghi[FS];
-    float og[FS], qlo[FS], qhi[FS];
+    float qlo[FS], qhi[FS];
+    double ad[FS], od[FS];  // cell width and origin (FP64), read inside the walk
 };
 
-template <int FT, int KR>
+// Operand layout of the screen for padded dimension SP (K = [qh, qh, ql] . [xh, xl, xh]
+// cut into blocks of 32).  Lane group g = lane / 16 supplies 8 consecutive K values of
+// each block: record chunk (8 bf16 = 16 bytes) b_chunk() of its candidate, or zeros
+// (-1), and the query part a_part() (0 = hi, 1 = lo, -1 = zeros) of dimensions
+// a_dim() .. a_dim() + 7.
+template <int SP> struct Screen;
+template <> struct Screen<8> {
+    static constexpr int NKB = 1, NCH = 1;
+    __device__ static int chunk(int c, int g) { return g == 1 ? 1 : 0; }
+    __device__ static int b_src(int kb, int g) { return g == 3 ? -1 : 0; }
+    __device__ static int a_part(int kb, int g) { return g == 3 ? -1 : (g == 2 ? 1 : 0); }
+    __device__ static int a_dim(int kb, int g) { return 0; }
+};
+template <> struct Screen<16> {
+    static constexpr int NKB = 2, NCH = 1;
+    __device__ static int chunk(int c, int g) { return g; }
+    __device__ static int b_src(int kb, int g) { return kb == 0 ? 0 : (g < 2 ? 0 : -1); }
+    __device__ static int a_part(int kb, int g) { return kb == 0 ? 0 : (g < 2 ? 1 : -1); }
+    __device__ static int a_dim(int kb, int g) { return kb == 0 ? 8 * (g & 1) : 8 * g; }
+};
+template <> struct Screen<32> {
+    static constexpr int NKB = 3, NCH = 2;
+    __device__ static int chunk(int c, int g) { return c == 0 ? g : 4 + g; }
+    __device__ static int b_src(int kb, int g) { return kb == 1 ? 1 : 0; }
+    __device__ static int a_part(int kb, int g) { return kb == 2 ? 1 : 0; }
+    __device__ static int a_dim(int kb, int g) { return 8 * g; }
+};
+
+__device__ __forceinline__ double shfl_f64(double v, int src) {
+    const int64_t b = __double_as_longlong(v);
+    const int lo = __shfl((int)(uint32_t)b, src, WAVE), hi = __shfl((int)(uint32_t)((uint64_t)b >> 32), src, WAVE);
+    return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// Screen of column block cb of a tile: lane (g, t) fetches the record slices of
+// candidate 16 cb + t (its run position came from lane 16 cb + t) and the result is
+// acc[i] = (1 - R) xn - A - 2 q'.x' for query 4 g + i of the group.
+template <int FT, int SP>
+__device__ __forceinline__ floatx4 screen_block(const IndexView& ix, const bf16x8* afr, uint32_t pidx, float xinit,
+                                                uint32_t base, uint32_t npts, int cb, int g, int t) {
+    using SC = Screen<SP>;
+    const uint32_t pc = (uint32_t)__shfl((int)pidx, 16 * cb + t, WAVE);
+    const float xi = __shfl(xinit, 16 * cb + t, WAVE);
+    const bool vc = base + 16 * cb + t < npts;
+    bf16x8 ld[SC::NCH];
+#pragma unroll
+    for (int c = 0; c < SC::NCH; ++c) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) ld[c][e] = (__bf16)0.0f;
+        if (vc && (SC::NCH > 1 || SC::b_src(0, g) >= 0))
+            ld[c] = *(const bf16x8*)(ix.srec + (size_t)pc * (2 * SP) + 8 * SC::chunk(c, g));
+    }
+    floatx4 acc = {xi, xi, xi, xi};
+#pragma unroll
+    for (int kb = 0; kb < SC::NKB; ++kb) {
+        const int src = SC::b_src(kb, g);
+        bf16x8 bb = ld[(SC::NCH > 1 && src > 0) ? SC::NCH - 1 : 0];
+        if (src < 0) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) bb[e] = (__bf16)0.0f;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[kb], bb, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+template <int FT, int SP, int KR>
 __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
     __shared__ GroupLds<FT> lds_all[GWPB];
     constexpr int FS = GroupLds<FT>::FS;
-    constexpr int KP = GroupLds<FT>::KP;
+    using SC = Screen<SP>;
+    constexpr int NKB = SC::NKB;
+    constexpr int NCH = SC::NCH;
     const PredictArgs& A = G.p;
     const IndexView& ix = A.ix;
     const int lane = lane_id();
@@ -180,6 +249,7 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
     const int g = lane >> 4, t = lane & 15;
     const bool prune = !(A.io.flags & GHN_FLAG_NO_PRUNE);
     const uint32_t ngroups = G.counters[0];
+    const float inf = __int_as_float(0x7f800000);
 
     for (;;) {
         uint32_t gid = 0;
@@ -216,8 +286,8 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
             // group box of central cells and box of query coordinates (finite queries)
             for (int j = 0; j < f; ++j) {
                 int32_t lo = fin ? cc[j] : INT32_MAX, hi = fin ? cc[j] : INT32_MIN;
-                float ql = fin ? S.q[lane][j] : __int_as_float(0x7f800000);
-                float qh = fin ? S.q[lane][j] : -__int_as_float(0x7f800000);
+                float ql = fin ? S.q[lane][j] : inf;
+                float qh = fin ? S.q[lane][j] : -inf;
                 for (int d = 1; d < WAVE; d <<= 1) {
                     lo = min(lo, __shfl_xor(lo, d, WAVE));
                     hi = max(hi, __shfl_xor(hi, d, WAVE));
@@ -229,7 +299,8 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
                     S.ghi[j] = hi;
                     S.qlo[j] = ql;
                     S.qhi[j] = qh;
-                    S.og[j] = lo <= hi ? (float)((double)ix.o[j] + ((double)lo + (double)hi + 1.0) * 0.5 * (double)ix.a[j]) : 0.0f;
+                    S.ad[j] = (double)ix.a[j];
+                    S.od[j] = (double)ix.o[j];
                 }
             }
         }
@@ -241,10 +312,10 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
         int bi[4][KR];
         double tau[4];
         int taui[4];
-        float thr[4], qn[4];
+        float thr[4], qn[4], bnd[4];
         bool upd[4], done[4];
         int32_t stopl[4];
-        int64_t cands[4];
+        int32_t cands[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int r = 4 * g + i;
@@ -255,43 +326,47 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
             cands[i] = 0;
             tau[i] = __longlong_as_double(0x7ff0000000000000LL);
             taui[i] = INT32_MAX;
-            thr[i] = live ? __int_as_float(0x7f800000) : -__int_as_float(0x7f800000);
+            thr[i] = live ? inf : -inf;
 #pragma unroll
             for (int j = 0; j < KR; ++j) { bd[i][j] = tau[i]; bi[i][j] = INT32_MAX; }
             float s = 0.0f;
             if (live)
                 for (int j = 0; j < f; ++j) {
-                    const float d = S.q[r][j] - S.og[j];
+                    const float d = S.q[r][j] - ix.c0[j];
                     s = __builtin_fmaf(d, d, s);
                 }
             qn[i] = s;
+            bnd[i] = thr[i];
         }
-        // matrix operand of the 16 queries: row l % 16, K = [qh, qh, ql, 0 ...]
-        bf16x8 afr[KP / 32];
+        // A operand of the 16 queries (row lane % 16): -2 x their bf16 parts
+        bf16x8 afr[NKB];
+        {
+            const int r = lane & 15;
+            const bool rlive = r < cnt && ((fin_mask >> r) & 1);
 #pragma unroll
-        for (int kb = 0; kb < KP / 32; ++kb) {
+            for (int kb = 0; kb < NKB; ++kb) {
+                const int part = SC::a_part(kb, g), d0 = SC::a_dim(kb, g);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int kk = 32 * kb + 8 * g + e;
-                const int r = lane & 15;
-                const int part = kk / f, j = kk - part * f;
-                float v = 0.0f;
-                if (part < 3 && r < cnt && ((fin_mask >> r) & 1)) {
-                    const float qp = S.q[r][j] - S.og[j];
-                    const float hi = (float)(__bf16)qp;
-                    v = part == 2 ? (float)(__bf16)(qp - hi) : hi;
+                for (int e = 0; e < 8; ++e) {
+                    const int j = d0 + e;
+                    float v = 0.0f;
+                    if (part >= 0 && rlive && j < f) {
+                        const float qp = S.q[r][j] - ix.c0[j];
+                        const float hi = (float)(__bf16)qp;
+                        v = part == 1 ? (float)(__bf16)(qp - hi) : hi;
+                    }
+                    afr[kb][e] = (__bf16)(-2.0f * v);
                 }
-                afr[kb][e] = (__bf16)v;
             }
         }
-        int64_t l0 = 0, lcover = 0;
+        int32_t l0 = 0, lcover = 0;
         for (int j = 0; j < f; ++j) {
-            const int64_t lo = S.glo[j], hi = S.ghi[j];
-            l0 = max(l0, max((int64_t)ix.cmin[j] - hi, lo - (int64_t)ix.cmax[j]));
-            lcover = max(lcover, max(hi - (int64_t)ix.cmin[j], (int64_t)ix.cmax[j] - lo));
+            const int32_t lo = S.glo[j], hi = S.ghi[j];
+            l0 = max(l0, max(ix.cmin[j] - hi, lo - ix.cmax[j]));
+            lcover = max(lcover, max(hi - ix.cmin[j], ix.cmax[j] - lo));
         }
-        int64_t probes = 0;
-        int64_t l = l0;
+        int32_t probes = 0;
+        int32_t l = l0;
         const bool any_live = (fin_mask & ((cnt >= 64 ? ~0ull : ((1ull << cnt) - 1)))) != 0;
 
         for (; any_live; ++l) {
@@ -306,24 +381,25 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
                 wave_lds_sync();
                 const int level = (int)(e >> 40);
                 const int count = (int)((e >> 32) & 0xff);
-                const int64_t node = (int64_t)(uint32_t)e + lane;
+                const uint32_t node = (uint32_t)e + lane;
                 const bool active = lane < count;
                 // largest k-th distance over the live queries (+inf while a buffer is not full)
                 double mt = -1.0;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) if (!done[i]) mt = fmax(mt, tau[i]);
                 for (int d = 16; d < WAVE; d <<= 1) mt = fmax(mt, __shfl_xor(mt, d, WAVE));
-                int64_t dmin = 0, dmax = 0;
+                int32_t dmin = 0, dmax = 0;
                 double lb = 0.0;
                 if (active) {
-                    const int32_t* lo = level == 0 ? ix.cell_coord + node * f : ix.node_lo + (ix.tree_off[level] + node) * f;
-                    const int32_t* hi = level == 0 ? lo : ix.node_hi + (ix.tree_off[level] + node) * f;
+                    const int32_t* lo = level == 0 ? ix.cell_coord + (size_t)node * f
+                                                   : ix.node_lo + (size_t)(ix.tree_off[level] + node) * f;
+                    const int32_t* hi = level == 0 ? lo : ix.node_hi + (size_t)(ix.tree_off[level] + node) * f;
                     for (int j = 0; j < f; ++j) {
-                        const int64_t a = lo[j], b = hi[j], ga = S.glo[j], gb = S.ghi[j];
+                        const int32_t a = lo[j], b = hi[j], ga = S.glo[j], gb = S.ghi[j];
                         dmin = max(dmin, max(a - gb, ga - b));
                         dmax = max(dmax, max(ga - a, b - gb));
                         // distance from the box of query coordinates to the node's region
-                        const double aj = ix.a[j], oj = ix.o[j];
+                        const double aj = S.ad[j], oj = S.od[j];
                         const double below = __dadd_rn(__dadd_rn(__dmul_rn((double)a, aj), oj), -(double)S.qhi[j]);
                         const double above = __dadd_rn((double)S.qlo[j], -__dadd_rn(__dmul_rn((double)(b + 1), aj), oj));
                         double gap = below > above ? below : above;
@@ -337,7 +413,7 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
                     const bool keep = active && dmin <= l && l <= dmax && close;
                     const uint64_t km = ballot(keep);
                     if (keep) {
-                        const int64_t c0 = node * WAVE;
+                        const int64_t c0 = (int64_t)node * WAVE;
                         const int nc = (int)min((int64_t)WAVE, ix.tree_count[level - 1] - c0);
                         S.stack[sp + __popcll(km & __lanemask_lt())] =
                             ((uint64_t)(level - 1) << 40) | ((uint64_t)nc << 32) | (uint32_t)c0;
@@ -361,84 +437,84 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
                     S.run_begin[nrun_incl - 1] = rb;
                     S.run_pre[nrun_incl - 1] = incl - rn;
                 }
+                if (lane == 0) S.run_pre[nrun] = npts;  // sentinel
                 wave_lds_sync();
+                uint32_t seg = 0;
                 for (uint32_t base = 0; base < npts; base += WAVE) {
-                    // stage 64 candidates: FP32 copy, id, |x'|^2 and the bf16 K vector
+                    // candidate base + lane: its run (one uniform pass over the runs that
+                    // start inside this tile), record position and initial accumulator
                     const uint32_t p = base + lane;
+                    const uint32_t end = base + WAVE;
+                    uint32_t my = seg;
+                    uint32_t s = seg + 1;
+                    uint32_t pre_s = (uint32_t)__builtin_amdgcn_readfirstlane((int)S.run_pre[s]);
+                    while (pre_s < end && s < nrun) {
+                        if (p >= pre_s) my = s;
+                        ++s;
+                        pre_s = (uint32_t)__builtin_amdgcn_readfirstlane((int)S.run_pre[s]);
+                    }
+                    seg = (pre_s == end && s < nrun) ? s : s - 1;
                     const bool valid = p < npts;
-                    float xv[FS];
-                    int id = -1;
-                    float nx = __int_as_float(0x7f800000);
+                    uint32_t pidx = 0;
+                    float xinit = __int_as_float(0x7fc00000);  // NaN: never admitted
                     if (valid) {
-                        uint32_t a0 = 0, a1 = nrun;
-                        while (a1 - a0 > 1) {
-                            const uint32_t mid = (a0 + a1) >> 1;
-                            if (S.run_pre[mid] <= p) a0 = mid;
-                            else a1 = mid;
-                        }
-                        const uint32_t pidx = S.run_begin[a0] + (p - S.run_pre[a0]);
-                        load_point<FT>(ix.spts + (size_t)pidx * f, xv, f);
-                        id = ix.sid[pidx];
-                        nx = 0.0f;
+                        pidx = S.run_begin[my] + (p - S.run_pre[my]);
+                        const float xn = ix.sxn[pidx];
+                        xinit = __builtin_fmaf(-SCREEN_REL, xn, xn) - SCREEN_ABS;
                     }
-                    for (int j = 0; j < f; ++j) {
-                        const float xp = valid ? xv[j] - S.og[j] : 0.0f;
-                        if (valid) nx = __builtin_fmaf(xp, xp, nx);
-                        const float hi = (float)(__bf16)xp;
-                        const __bf16 h16 = (__bf16)hi, l16 = (__bf16)(xp - hi);
-                        S.frag[lane][j] = h16;
-                        S.frag[lane][f + j] = l16;
-                        S.frag[lane][2 * f + j] = h16;
-                        S.x[lane][j] = valid ? xv[j] : 0.0f;
-                    }
-                    for (int kk = 3 * f; kk < KP; ++kk) S.frag[lane][kk] = (__bf16)0.0f;
-                    S.xid[lane] = id;
-                    S.xn[lane] = nx;
-                    wave_lds_sync();
                     const int nvalid = __popcll(ballot(valid));
 #pragma unroll
                     for (int i = 0; i < 4; ++i) if (!done[i]) cands[i] += nvalid;
-                    // screen: per slot, a 64-bit mask of the tile's candidates that may enter the
-                    // row's buffer (bit c = candidate c)
-                    uint64_t adm[4] = {0, 0, 0, 0};
+                    // Fast path: the 16 x 64 screen of the tile (lane (g, t) holds candidate
+                    // 16 cb + t of column block cb); most tiles admit nothing once the
+                    // buffers are full.
+                    uint64_t any = 0;
 #pragma unroll
-                    for (int cb = 0; cb < WAVE / 16; ++cb) {
-                        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-                        const int col = 16 * cb + t;
+                    for (int cb = 0; cb < 4; ++cb) {
+                        const floatx4 acc = screen_block<FT, SP>(ix, afr, pidx, xinit, base, npts, cb, g, t);
 #pragma unroll
-                        for (int kb = 0; kb < KP / 32; ++kb) {
-                            const bf16x8 bfr = *(const bf16x8*)&S.frag[col][32 * kb + 8 * g];
-                            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[kb], bfr, acc, 0, 0, 0);
-                        }
-                        const float xn_c = S.xn[col];
+                        for (int i = 0; i < 4; ++i) any |= ballot(acc[i] <= bnd[i]);
+                    }
+                    if (!any) continue;
+                    // Slow path, one column block at a time: the screen again (with the
+                    // thresholds as they shrink), then the exact FP64 check and insertion
+                    // of the admitted pairs, the four rows in parallel.
+#pragma unroll 1
+                    for (int cb = 0; cb < 4; ++cb) {
+                        const floatx4 acc = screen_block<FT, SP>(ix, afr, pidx, xinit, base, npts, cb, g, t);
+                        const uint32_t pcb = (uint32_t)__shfl((int)pidx, 16 * cb + t, WAVE);
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
-                            const float nsum = qn[i] + xn_c;
-                            const float sv = nsum - 2.0f * acc[i];
-                            const bool flag = sv - __builtin_fmaf(SCREEN_REL, nsum, SCREEN_ABS) <= thr[i];
-                            adm[i] |= ((ballot(flag) >> (16 * g)) & 0xffffull) << (16 * cb);
-                        }
-                    }
-                    // exact FP64 check and insertion, the four rows in parallel
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        uint64_t mrow = adm[i];
-                        while (ballot(mrow != 0)) {
-                            if (mrow != 0) {
-                                const int c = __ffsll((unsigned long long)mrow) - 1;
-                                mrow &= mrow - 1;
-                                const int r = 4 * g + i;
-                                const double cd = dist64<FT>(S.q[r], S.x[c], f);
-                                const int ci = S.xid[c];
-                                if (cd < tau[i] || (cd == tau[i] && ci < taui[i])) {
+                            const uint64_t M = ballot(acc[i] <= bnd[i]);
+                            if (!M) continue;
+                            double cd = __longlong_as_double(0x7ff0000000000000LL);
+                            int ci = INT32_MAX;
+                            if ((M >> lane) & 1) {
+                                float xv[FS];
+                                load_point<FT>(ix.spts + (size_t)pcb * f, xv, f);
+                                cd = dist64<FT>(S.q[4 * g + i], xv, f);
+                                ci = ix.sid[pcb];
+                            }
+                            uint32_t mrow = (uint32_t)(M >> (16 * g)) & 0xffffu;
+                            while (ballot(mrow != 0)) {
+                                bool have = false;
+                                int src = lane;
+                                if (mrow) {
+                                    have = true;
+                                    src = 16 * g + __ffs(mrow) - 1;
+                                    mrow &= mrow - 1;
+                                }
+                                const double cdb = shfl_f64(cd, src);
+                                const int cib = __shfl(ci, src, WAVE);
+                                if (have && (cdb < tau[i] || (cdb == tau[i] && cib < taui[i]))) {
                                     // entries larger than the candidate move up one place
-                                    const uint64_t cbits = (uint64_t)__double_as_longlong(cd);
+                                    const uint64_t cbits = (uint64_t)__double_as_longlong(cdb);
                                     int ngt = 0;
 #pragma unroll
                                     for (int j = 0; j < KR; ++j) {
                                         const int ee = 16 * j + t;
                                         const uint64_t bb = (uint64_t)__double_as_longlong(bd[i][j]);
-                                        const bool gt = ee < k && (bb > cbits || (bb == cbits && bi[i][j] > ci));
+                                        const bool gt = ee < k && (bb > cbits || (bb == cbits && bi[i][j] > cib));
                                         ngt += __popc((uint32_t)(ballot(gt) >> (16 * g)) & 0xffffu);
                                     }
                                     const int pos = k - ngt;
@@ -456,8 +532,8 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
                                             ni = j > 0 ? ri[j > 0 ? j - 1 : 0] : bi[i][j];
                                         }
                                         if (ee < k && ee >= pos) {
-                                            bd[i][j] = ee == pos ? cd : nd;
-                                            bi[i][j] = ee == pos ? ci : ni;
+                                            bd[i][j] = ee == pos ? cdb : nd;
+                                            bi[i][j] = ee == pos ? cib : ni;
                                         }
                                     }
                                     upd[i] = true;
@@ -468,13 +544,14 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
                                     for (int j = 1; j < KR; ++j) if (j == jl) { kd = bd[i][j]; ki = bi[i][j]; }
                                     tau[i] = row_bcast_f64(kd, tl);
                                     taui[i] = row_bcast(ki, tl);
-                                    thr[i] = taui[i] == INT32_MAX ? __int_as_float(0x7f800000) : admit_group(tau[i]);
+                                    thr[i] = taui[i] == INT32_MAX ? inf : admit_group(tau[i]);
+                                    bnd[i] = thr[i] == inf ? inf : thr[i] - (1.0f - SCREEN_REL) * qn[i];
                                 }
                             }
                         }
                     }
-                    wave_lds_sync();
                 }
+                wave_lds_sync();
             }
             // stop rules for every live query of the group, after layer l
             bool any = false;
@@ -490,9 +567,9 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
                     } else {
                         double r2 = __longlong_as_double(0x7ff0000000000000LL);
                         for (int j = 0; j < f; ++j) {
-                            const double a = ix.a[j];
-                            const double v = __dadd_rn((double)S.q[r][j], -(double)ix.o[j]);
-                            const int64_t c = S.qc[r][j];
+                            const double a = S.ad[j];
+                            const double v = __dadd_rn((double)S.q[r][j], -S.od[j]);
+                            const int32_t c = S.qc[r][j];
                             const double glo = __dadd_rn(v, -__dmul_rn((double)(c - l), a));
                             const double ghi = __dadd_rn(__dmul_rn((double)(c + l + 1), a), -v);
                             double gg = glo < ghi ? glo : ghi;
@@ -506,7 +583,8 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
                 if (stop) {
                     done[i] = true;
                     stopl[i] = (int32_t)l;
-                    thr[i] = -__int_as_float(0x7f800000);
+                    thr[i] = -inf;
+                    bnd[i] = -inf;
                 } else {
                     any = true;
                 }
@@ -582,12 +660,21 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
     }
 }
 
+template <int FT, int SP>
+hipError_t launch_k(const GroupArgs& a, int blocks, hipStream_t s) {
+    if (a.p.io.k <= 16) hipLaunchKernelGGL((k_predict_group<FT, SP, 1>), dim3(blocks), dim3(GT), 0, s, a);
+    else if (a.p.io.k <= 32) hipLaunchKernelGGL((k_predict_group<FT, SP, 2>), dim3(blocks), dim3(GT), 0, s, a);
+    else hipLaunchKernelGGL((k_predict_group<FT, SP, 4>), dim3(blocks), dim3(GT), 0, s, a);
+    return hipGetLastError();
+}
+
 template <int FT>
 hipError_t launch_ft(const GroupArgs& a, int blocks, hipStream_t s) {
-    if (a.p.io.k <= 16) hipLaunchKernelGGL((k_predict_group<FT, 1>), dim3(blocks), dim3(GT), 0, s, a);
-    else if (a.p.io.k <= 32) hipLaunchKernelGGL((k_predict_group<FT, 2>), dim3(blocks), dim3(GT), 0, s, a);
-    else hipLaunchKernelGGL((k_predict_group<FT, 4>), dim3(blocks), dim3(GT), 0, s, a);
-    return hipGetLastError();
+    constexpr int SP = FT <= 8 ? 8 : (FT <= 16 ? 16 : 32);
+    if (FT > 0) return launch_k<FT, SP>(a, blocks, s);
+    if (a.p.ix.sp == 8) return launch_k<0, 8>(a, blocks, s);
+    if (a.p.ix.sp == 16) return launch_k<0, 16>(a, blocks, s);
+    return launch_k<0, 32>(a, blocks, s);
 }
 
 }  // namespace

@@ -49,6 +49,13 @@ struct IndexView {
     int32_t cmin[F_MAX];
     int32_t cmax[F_MAX];
     uint32_t stride[F_MAX];     // dense-box linear index stride per dimension (last = 1)
+    // bf16 screen records (grouped matrix-core screen): per point in cell order,
+    // x' = fl32(x - c0) split as hi = bf16(x'), lo = bf16(x' - hi), stored as
+    // [hi(sp), lo(sp)] with the dimensions past f zero, and xn = |x'|^2 in FP32
+    const uint16_t* srec;       // n x 2 sp
+    const float* sxn;           // n
+    int32_t sp;                 // padded dimension: 8, 16 or 32
+    float c0[F_MAX];            // screen centre (centre of the occupied box)
 };
 
 // ---------------------------------------------------------------------------------------
@@ -138,6 +145,7 @@ hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, 
                             int64_t n, int nbits, void* temp, bool* result_in_alt, hipStream_t s);
 hipError_t launch_gather_points(const void* pts, int64_t n, int32_t f, int32_t dtype, const uint32_t* perm,
                                 float* spts, int32_t* sid, hipStream_t s);
+hipError_t launch_screen_records(const IndexView& iv, uint16_t* rec, float* xn, hipStream_t s);
 hipError_t launch_dense_cell_start(const uint64_t* sorted_keys, int64_t n, int64_t box_cells,
                                    uint32_t* cell_start, hipStream_t s);
 
