@@ -164,6 +164,7 @@ struct alignas(16) GroupLds {
     int32_t glo[FS], ghi[FS];
     float qlo[FS], qhi[FS];
     double ad[FS], od[FS];  // cell width and origin (FP64), read inside the walk
+    double qd[GQ][FS];      // the queries in FP64 (exact), for the re-rank
 };
 
 // Operand layout of the screen for padded dimension SP (K = [qh, qh, ql] . [xh, xl, xh]
@@ -205,9 +206,9 @@ __device__ __forceinline__ double shfl_f64(double v, int src) {
 // acc[i] = (1 - R) xn - A - 2 q'.x' for query 4 g + i of the group.
 template <int FT, int SP>
 __device__ __forceinline__ floatx4 screen_block(const IndexView& ix, const bf16x8* afr, uint32_t pidx, float xinit,
-                                                uint32_t base, uint32_t npts, int cb, int g, int t) {
+                                                uint32_t base, uint32_t npts, int cb, int g, int t, uint32_t& pc) {
     using SC = Screen<SP>;
-    const uint32_t pc = (uint32_t)__shfl((int)pidx, 16 * cb + t, WAVE);
+    pc = (uint32_t)__shfl((int)pidx, 16 * cb + t, WAVE);
     const float xi = __shfl(xinit, 16 * cb + t, WAVE);
     const bool vc = base + 16 * cb + t < npts;
     bf16x8 ld[SC::NCH];
@@ -233,7 +234,7 @@ __device__ __forceinline__ floatx4 screen_block(const IndexView& ix, const bf16x
 }
 
 template <int FT, int SP, int KR>
-__global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
+__global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
     __shared__ GroupLds<FT> lds_all[GWPB];
     constexpr int FS = GroupLds<FT>::FS;
     using SC = Screen<SP>;
@@ -270,7 +271,7 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
                 const float x = act ? A.io.queries[qi * f + j] : 0.0f;
                 fin = fin && isfinite(x);
                 cc[j] = 0;
-                if (act) S.q[lane][j] = x;
+                if (act) { S.q[lane][j] = x; S.qd[lane][j] = (double)x; }
             }
             for (int j = 0; j < f; ++j) {
                 int64_t c = 0;
@@ -469,30 +470,39 @@ __global__ __launch_bounds__(GT) void k_predict_group(GroupArgs G) {
                     // 16 cb + t of column block cb); most tiles admit nothing once the
                     // buffers are full.
                     uint64_t any = 0;
+                    floatx4 accs[4];
+                    uint32_t pcs[4];
 #pragma unroll
                     for (int cb = 0; cb < 4; ++cb) {
-                        const floatx4 acc = screen_block<FT, SP>(ix, afr, pidx, xinit, base, npts, cb, g, t);
+                        accs[cb] = screen_block<FT, SP>(ix, afr, pidx, xinit, base, npts, cb, g, t, pcs[cb]);
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) any |= ballot(acc[i] <= bnd[i]);
+                        for (int i = 0; i < 4; ++i) any |= ballot(accs[cb][i] <= bnd[i]);
                     }
                     if (!any) continue;
-                    // Slow path, one column block at a time: the screen again (with the
-                    // thresholds as they shrink), then the exact FP64 check and insertion
-                    // of the admitted pairs, the four rows in parallel.
-#pragma unroll 1
-                    for (int cb = 0; cb < 4; ++cb) {
-                        const floatx4 acc = screen_block<FT, SP>(ix, afr, pidx, xinit, base, npts, cb, g, t);
-                        const uint32_t pcb = (uint32_t)__shfl((int)pidx, 16 * cb + t, WAVE);
+                    // Slow path, per slot and column block (with the thresholds as they
+                    // shrink): the exact FP64 check and insertion of the admitted pairs,
+                    // the four rows in parallel.
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const uint64_t M = ballot(acc[i] <= bnd[i]);
+                    for (int i = 0; i < 4; ++i) {
+#pragma unroll 1
+                        for (int cb = 0; cb < 4; ++cb) {
+                            const float av = cb == 0 ? accs[0][i] : (cb == 1 ? accs[1][i] : (cb == 2 ? accs[2][i] : accs[3][i]));
+                            const uint32_t pcb = cb == 0 ? pcs[0] : (cb == 1 ? pcs[1] : (cb == 2 ? pcs[2] : pcs[3]));
+                            const uint64_t M = ballot(av <= bnd[i]);
                             if (!M) continue;
                             double cd = __longlong_as_double(0x7ff0000000000000LL);
                             int ci = INT32_MAX;
                             if ((M >> lane) & 1) {
                                 float xv[FS];
                                 load_point<FT>(ix.spts + (size_t)pcb * f, xv, f);
-                                cd = dist64<FT>(S.q[4 * g + i], xv, f);
+                                const double* qd = S.qd[4 * g + i];
+                                cd = 0.0;
+#pragma unroll
+                                for (int j = 0; j < FS; ++j) {
+                                    if (FT == 0 && j >= f) break;
+                                    const double d = __dadd_rn(qd[j], -(double)xv[j]);
+                                    cd = __dadd_rn(cd, __dmul_rn(d, d));
+                                }
                                 ci = ix.sid[pcb];
                             }
                             uint32_t mrow = (uint32_t)(M >> (16 * g)) & 0xffffu;
