@@ -165,6 +165,8 @@ struct alignas(16) GroupLds {
     float qlo[FS], qhi[FS];
     double ad[FS], od[FS];  // cell width and origin (FP64), read inside the walk
     double qd[GQ][FS];      // the queries in FP64 (exact), for the re-rank
+    float tq[GQ];           // per query: FP32 threshold >= its k-th distance (+inf while the
+                            // buffer is not full), -1 once done or when invalid
 };
 
 // Operand layout of the screen for padded dimension SP (K = [qh, qh, ql] . [xh, xl, xh]
@@ -194,6 +196,18 @@ template <> struct Screen<32> {
     __device__ static int a_part(int kb, int g) { return kb == 2 ? 1 : 0; }
     __device__ static int a_dim(int kb, int g) { return 8 * g; }
 };
+
+// FP32 values at or below / at or above an FP64 value, one extra ulp outward.
+__device__ __forceinline__ float f32_below(double x) {
+    float r = (float)x;
+    if ((double)r > x) r = nextafterf(r, -INFINITY);
+    return nextafterf(r, -INFINITY);
+}
+__device__ __forceinline__ float f32_above(double x) {
+    float r = (float)x;
+    if ((double)r < x) r = nextafterf(r, INFINITY);
+    return nextafterf(r, INFINITY);
+}
 
 __device__ __forceinline__ double shfl_f64(double v, int src) {
     const int64_t b = __double_as_longlong(v);
@@ -306,6 +320,7 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
             }
         }
         const uint64_t fin_mask = ballot(fin);
+        if (lane < GQ) S.tq[lane] = fin ? inf : -1.0f;
         wave_lds_sync();
 
         // ---- per-slot state (slot i of row g = query 4g + i)
@@ -423,9 +438,41 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                     wave_lds_sync();
                     continue;
                 }
-                // cells of layer l: one run of points per kept cell
+                // cells of layer l: one run of points per kept cell.  With several
+                // queries a cell is kept only if some live query's own lower bound to
+                // it is within that query's threshold (the bound from the box of the
+                // group's queries above is weaker).  FP32 bounds: the cell's region is
+                // rounded outward and the sum shrunk by (1 - 2^-18), which covers the
+                // rounding of f <= 32 differences, squares and sums.  (Up to 8
+                // dimensions, where the cell bounds fit in registers.)
+                bool keepc = active && dmin == l && close;
+                if (FT > 0 && FT <= 8 && prune && cnt > 1 && ballot(keepc)) {
+                    float clo[FS], chi[FS];
+                    if (keepc) {
+                        const int32_t* cid = ix.cell_coord + (size_t)node * f;
+                        for (int j = 0; j < f; ++j) {
+                            const double aj = S.ad[j], oj = S.od[j];
+                            const int32_t c = cid[j];
+                            clo[j] = f32_below(__dadd_rn(__dmul_rn((double)c, aj), oj));
+                            chi[j] = f32_above(__dadd_rn(__dmul_rn((double)(c + 1), aj), oj));
+                        }
+                    }
+                    bool need = false;
+                    for (int r = 0; r < cnt; ++r) {
+                        const float tq = S.tq[r];
+                        if (!(tq >= 0.0f)) continue;
+                        float lbq = 0.0f;
+                        for (int j = 0; j < f; ++j) {
+                            const float q = S.q[r][j];
+                            const float gp = fmaxf(fmaxf(clo[j] - q, q - chi[j]), 0.0f);
+                            lbq = __builtin_fmaf(gp, gp, lbq);
+                        }
+                        need = need || lbq * (1.0f - 0x1p-18f) <= tq;
+                    }
+                    keepc = keepc && need;
+                }
                 uint32_t rb = 0, rn = 0;
-                if (active && dmin == l && close) {
+                if (keepc) {
                     rb = ix.cell_first[node];
                     rn = ix.cell_first[node + 1] - rb;
                 }
@@ -556,6 +603,7 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                                     taui[i] = row_bcast(ki, tl);
                                     thr[i] = taui[i] == INT32_MAX ? inf : admit_group(tau[i]);
                                     bnd[i] = thr[i] == inf ? inf : thr[i] - (1.0f - SCREEN_REL) * qn[i];
+                                    if (t == 0) S.tq[4 * g + i] = thr[i];
                                 }
                             }
                         }
@@ -595,6 +643,7 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                     stopl[i] = (int32_t)l;
                     thr[i] = -inf;
                     bnd[i] = -inf;
+                    if (t == 0) S.tq[r] = -1.0f;
                 } else {
                     any = true;
                 }
