@@ -35,10 +35,19 @@ def describe(prob, stop_name):
         "majority vote" if prob.task == 0 else "mean", stop_name))
 
 
-def source_hash() -> str:
-    """Hash of the HIP sources (the kernels the counters were taken on)."""
+# Sources each walk kernel is compiled from (its traffic figure is void once they change).
+KERNEL_SOURCES = {
+    "k_predict_dense": ["ghn_predict.hip", "ghn_walk_dense.h", "ghn_walk.h", "ghn_internal.h"],
+    "k_predict_tree": ["ghn_tree.hip", "ghn_walk_tree.h", "ghn_walk.h", "ghn_internal.h"],
+    "k_predict_group": ["ghn_group.hip", "ghn_walk.h", "ghn_internal.h"],
+    "k_predict_batched": ["ghn_batch.hip", "ghn_walk_dense.h", "ghn_walk_tree.h", "ghn_walk.h", "ghn_internal.h"],
+}
+
+
+def source_hash(kernel: str) -> str:
+    """Hash of the HIP sources of `kernel` (the code the counters were taken on)."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
+    for name in KERNEL_SOURCES[kernel]:
         with open(os.path.join(CSRC, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -52,7 +61,9 @@ def measured_traffic(workload: str, form: str):
     except (OSError, ValueError):
         return None
     entry = t.get("%s/%s" % (workload, form))
-    if not entry or entry.get("source_sha256_16") != source_hash():
+    if not entry or entry.get("kernel") not in KERNEL_SOURCES:
+        return None
+    if entry.get("source_sha256_16") != source_hash(entry["kernel"]):
         return None
     return entry.get("bytes_per_launch")
 
@@ -86,7 +97,7 @@ def write_traffic(pmc_dir: str, workloads) -> None:
             out["%s/%s" % (w, form)] = {
                 "kernel": kname, "dispatches": len(fv), "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
                 "bytes_per_launch": fk * 1024.0 * fetch_scale + wk * 1024.0 * write_scale,
-                "source_sha256_16": source_hash()}
+                "source_sha256_16": source_hash(kname)}
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(out, fh, indent=1, sort_keys=True)
     print(json.dumps(out, indent=1, sort_keys=True))

@@ -162,7 +162,8 @@ typedef struct {
     int32_t group_levels;    /* bf16 screen, EXACT rule: queries whose central cells agree
                                 after dropping the lowest group_levels bits of every cell id
                                 (blocks of 2^group_levels cells per dimension) are walked
-                                together, up to 16 per group; -1 = automatic (1).  The PAPER
+                                together, up to 16 per group; -1 = automatic (3 with 12 or
+                                more dimensions, else 1).  The PAPER
                                 rule always groups by identical central cell. */
     void* walk_event_begin;  /* optional hipEvent_t: recorded on the stream right before the walk
                                 kernel (the exploration launch, after any query sort/grouping) */

@@ -189,7 +189,7 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
     struct Setting { int32_t prec, levels; uint32_t flags; };
     std::vector<Setting> settings = {{GHN_PREC_FP32, -1, GHN_FLAG_NO_SORT}, {GHN_PREC_FP32, -1, 0u}};
     if (stop == GHN_STOP_PAPER) settings.push_back({GHN_PREC_BF16_MFMA, 0, 0u});
-    else for (int lv = 0; lv <= 2; ++lv) settings.push_back({GHN_PREC_BF16_MFMA, lv, 0u});
+    else for (int lv = 0; lv <= 3; ++lv) settings.push_back({GHN_PREC_BF16_MFMA, lv, 0u});
 
     // outputs and a workspace large enough for every setting
     int64_t* oi = nullptr;
@@ -212,7 +212,7 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
                 continue;
             }
             for (const Setting& st : settings) {
-                ghn_predict_opts o = {stop, st.prec, st.flags, nullptr, nullptr, nullptr, nullptr, st.levels};
+                ghn_predict_opts o = {stop, st.prec, st.flags, nullptr, nullptr, nullptr, nullptr, st.levels, nullptr, nullptr};
                 double ms = -1.0;
                 if (ghn_predict(ix, queries, m, k, &o, oi, nullptr, op, ws, ws_bytes, stream) == GHN_OK &&
                     hipStreamSynchronize(s) == hipSuccess) {
@@ -577,7 +577,7 @@ ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, 
             return fail(GHN_E_WORKSPACE, "ghn_predict: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
         if ((uintptr_t)ws % 256) return fail(GHN_E_INVALID_ARG, "ghn_predict: workspace must be 256-byte aligned");
         if (m >= (int64_t(1) << 32)) return fail(GHN_E_INVALID_ARG, "ghn_predict: m=%lld too large for one call", (long long)m);
-        const int levels = o.stop == GHN_STOP_PAPER ? 0 : (o.group_levels < 0 ? 1 : o.group_levels);
+        const int levels = o.stop == GHN_STOP_PAPER ? 0 : (o.group_levels >= 0 ? o.group_levels : (index->info.f >= 12 ? 3 : 1));
         int bits = 0;
         e = run_grouped(pa, levels, ws, s, &bits, (hipEvent_t)o.walk_event_begin, (hipEvent_t)o.walk_event_end);
         if (bits > 64) return fail(GHN_E_UNSUPPORTED, "ghn_predict: the Morton code of the cell ids needs %d bits (> 64)", bits);

@@ -517,7 +517,7 @@ def test_autotune_exact_and_paper(ghn, tmp_path):
     cache = str(tmp_path / "tune.json")
     best = autotune.tune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_EXACT, cache_path=cache)
     assert best["ms"] > 0 and best["cell_width"] > 0
-    assert len(best["trials"]) == 6 * 5
+    assert len(best["trials"]) == 6 * 6  # widths x (2 FP32 settings + bf16 at 4 grouping levels)
     again = autotune.tune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_EXACT, cache_path=cache)
     assert again["cell_width"] == best["cell_width"]  # served from the cache
     # the tuned setting still returns the brute-force neighbours
