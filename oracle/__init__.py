@@ -19,6 +19,7 @@ SRC = os.path.join(HERE, "ghn_oracle.cpp")
 LIB = os.path.join(HERE, "libghn_oracle.so")
 
 CLASSIFY, REGRESS = 0, 1
+REGRESS_MEDIAN = 2  # regression with the median of the k targets
 STOP_EXACT, STOP_PAPER = 0, 1
 
 _lib = None
@@ -61,6 +62,8 @@ def lib() -> ctypes.CDLL:
         L.ghn_oracle_grid_trace.restype = I32
         L.ghn_oracle_grid_free.argtypes = [P]
         L.ghn_oracle_grid_free.restype = None
+        L.ghn_oracle_cell_measure.argtypes = [P, I64, I32, P, P, P]
+        L.ghn_oracle_cell_measure.restype = I32
         _lib = L
     return _lib
 
@@ -82,6 +85,18 @@ def _widths(widths, f):
 
 def _targets(targets, task):
     return np.ascontiguousarray(targets, dtype=np.int32 if task == CLASSIFY else np.float32)
+
+
+def cell_measure(points):
+    """The paper's cell measurement rule: (width float32[f], origin float32[f], splits int64[f])."""
+    x = _f32(points)
+    n, f = x.shape
+    w = np.empty(f, dtype=np.float32)
+    o = np.empty(f, dtype=np.float32)
+    s = np.empty(f, dtype=np.int64)
+    if lib().ghn_oracle_cell_measure(_p(x), n, f, _p(w), _p(o), _p(s)) != 0:
+        raise ValueError("oracle cell_measure rejected its arguments")
+    return w, o, s
 
 
 def cells(points, widths, origin=None) -> np.ndarray:

@@ -24,8 +24,13 @@
 //              force).
 //     Both rules also stop once every stored cell has been visited.
 //   * prediction (Section I, Section III-D): majority class of the k neighbours
-//     (ties -> smallest label) or their mean (FP64 sum in result order, / k,
-//     rounded to FP32).
+//     (ties -> smallest label), their mean (FP64 sum in result order, / k,
+//     rounded to FP32) or their median (the paper names both statistics for
+//     regression): the middle target in IEEE total order, or for even k the
+//     FP64 mean of the two middle targets rounded to FP32.
+//   * cell measurements (Section III-A, Fig. 3): per dimension the largest
+//     number of equal splits of the range covered by the points that leaves no
+//     split empty; the split width is the cell measurement.
 //   * brute force: the plain KNN definition (Section I) over all n points.
 //
 // Distances are squared Euclidean, d(q,x) = sum_j (q_j - x_j)^2 computed in FP64
@@ -44,7 +49,7 @@
 
 namespace {
 
-enum { TASK_CLASSIFY = 0, TASK_REGRESS = 1 };
+enum { TASK_CLASSIFY = 0, TASK_REGRESS = 1, TASK_REGRESS_MEDIAN = 2 };
 enum { STOP_EXACT = 0, STOP_PAPER = 1 };
 
 // Exact floor of v / a for a > 0, v finite, via fmod (exact in IEEE arithmetic):
@@ -106,6 +111,13 @@ bool buffer_offer(std::vector<Cand>& buf, int k, const Cand& c) {
     return true;
 }
 
+// Integer key ordering floats as IEEE total order.
+int64_t total_key(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    return (u & 0x80000000u) ? -(int64_t)(u & 0x7fffffffu) - 1 : (int64_t)u;
+}
+
 void predict_from(const std::vector<Cand>& buf, int k, int task, const void* targets,
                   void* out_pred, int64_t qi) {
     if (task == TASK_CLASSIFY) {
@@ -117,11 +129,20 @@ void predict_from(const std::vector<Cand>& buf, int k, int task, const void* tar
         for (const auto& kv : count)  // ascending label order: first maximum = smallest label
             if (kv.second > best_n) { best = kv.first; best_n = kv.second; }
         ((int32_t*)out_pred)[qi] = best;
-    } else {
+    } else if (task == TASK_REGRESS) {
         const float* y = (const float*)targets;
         double s = 0.0;
         for (int t = 0; t < k; ++t) s = s + (double)y[buf[t].second];
         ((float*)out_pred)[qi] = (float)(s / (double)k);
+    } else {
+        // median in IEEE total order (negative NaN < -inf < ... < +inf < NaN)
+        const float* y = (const float*)targets;
+        std::vector<float> v;
+        for (int t = 0; t < k; ++t) v.push_back(y[buf[t].second]);
+        std::sort(v.begin(), v.end(), [](float a, float b) { return total_key(a) < total_key(b); });
+        const float mid = (k % 2) ? v[(size_t)k / 2]
+                                  : (float)(((double)v[(size_t)k / 2 - 1] + (double)v[(size_t)k / 2]) / 2.0);
+        ((float*)out_pred)[qi] = mid;
     }
 }
 
@@ -328,5 +349,43 @@ int32_t ghn_oracle_grid_trace(const void* h, const float* q, int32_t k, int32_t 
 }
 
 void ghn_oracle_grid_free(void* h) { delete (Grid*)h; }
+
+// The paper's cell measurement rule (Section III-A, Fig. 3), per dimension j:
+// the range [mn, mx] covered by the points is cut into s equal splits of width
+// w = fl32((mx - mn) / s); a point x belongs to split min(floor((x - mn) / w), s - 1)
+// (exact floor; the last split is closed at mx).  The answer is the largest s
+// that leaves no split empty, found here by trying every s from the number of
+// distinct values down to 1.  The grid origin is mn, so cells are the splits.
+// A dimension whose points all coincide gets s = 1 and width 1.
+int ghn_oracle_cell_measure(const float* pts, int64_t n, int32_t f, float* width, float* origin, int64_t* splits) {
+    if (n < 1 || f < 1) return -1;
+    for (int j = 0; j < f; ++j) {
+        std::vector<double> v((size_t)n);
+        for (int64_t i = 0; i < n; ++i) v[(size_t)i] = (double)pts[i * f + j];
+        std::sort(v.begin(), v.end());
+        const double mn = v.front(), mx = v.back();
+        const int64_t distinct = (int64_t)(std::unique(v.begin(), v.end()) - v.begin());
+        origin[j] = (float)mn;
+        splits[j] = 1;
+        width[j] = 1.0f;
+        if (!(mx > mn)) continue;
+        for (int64_t s = distinct; s >= 1; --s) {
+            const float w = (float)((mx - mn) / (double)s);
+            if (!(w > 0.0f)) continue;
+            std::vector<char> hit((size_t)s, 0);
+            for (int64_t i = 0; i < n; ++i) {
+                int64_t c = floor_div((double)pts[i * f + j] - mn, (double)w);
+                if (c > s - 1) c = s - 1;
+                hit[(size_t)c] = 1;
+            }
+            if (std::find(hit.begin(), hit.end(), 0) == hit.end()) {
+                splits[j] = s;
+                width[j] = w;
+                break;
+            }
+        }
+    }
+    return 0;
+}
 
 }  // extern "C"

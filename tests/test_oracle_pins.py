@@ -8,7 +8,10 @@
   random float32 inputs;
 * the grid walk under the EXACT rule equals brute force; under the PAPER rule
   it equals an independent set-based re-statement of the rule;
-* vote and mean closed forms.
+* vote, mean and median closed forms;
+* the cell measurement rule (Section III-A): closed forms (evenly spaced
+  values, two values, a constant dimension, a case where 3 splits fail while 4
+  succeed) and an exact-rational brute force over every split count.
 """
 import json
 import math
@@ -209,6 +212,78 @@ def test_vote_ties_and_mean_closed_form():
     _, _, mean = oracle.bruteforce(pts, y, oracle.REGRESS, q, 4)
     want = np.float32((float(y[0]) + float(y[1]) + float(y[2]) + float(y[3])) / 4.0)
     assert mean[0] == want
+
+
+def test_median_closed_form():
+    # neighbours of q = 0 on a line, in distance order 0, 1, 2, 3, 4
+    pts = np.array([[0.0], [1.0], [2.0], [3.0], [4.0], [9.0]], np.float32)
+    q = np.array([[0.0]], np.float32)
+    y = np.array([5.0, -1.0, 3.0, 3.0, -7.5, 100.0], np.float32)
+    for k, want in [(1, 5.0), (2, 2.0), (3, 3.0), (4, 3.0), (5, 3.0), (6, 3.0)]:
+        _, _, med = oracle.bruteforce(pts, y, oracle.REGRESS_MEDIAN, q, k)
+        assert med[0] == np.float32(want), (k, med[0])
+    # even k: mean of the two middle values, one rounding to float32
+    y2 = np.array([1.0, 2.0 ** -24, 7.0, 8.0, 0.0, 0.0], np.float32)
+    _, _, med = oracle.bruteforce(pts, y2, oracle.REGRESS_MEDIAN, q, 2)
+    assert med[0] == np.float32((1.0 + 2.0 ** -24) / 2.0)
+    g = oracle.Grid(pts, y, oracle.REGRESS_MEDIAN, 1.0)
+    assert g.predict(q, 3)["pred"][0] == np.float32(3.0)
+
+
+# ----------------------------------------------------------------------------- cell measurements
+def _measure_fraction(col):
+    """Largest s such that no equal split of [min, max] is empty, exact rationals."""
+    v = [float(x) for x in col]
+    mn, mx = min(v), max(v)
+    if mx == mn:
+        return 1, np.float32(1.0)
+    for s in range(len(set(v)), 0, -1):
+        w = np.float32((mx - mn) / s)  # FP64 quotient, rounded to float32
+        if not w > 0:
+            continue
+        fw = Fraction(float(w))
+        hit = set()
+        for x in v:
+            c = math.floor((Fraction(x) - Fraction(mn)) / fw)
+            hit.add(min(c, s - 1))
+        if len(hit) == s:
+            return s, w
+    raise AssertionError("s = 1 always succeeds")
+
+
+def test_cell_measure_closed_forms():
+    # 3 equal splits of [0.28, 0.981] leave the middle one empty, 4 fill all four
+    col = np.array([0.28, 0.485, 0.75, 0.981], np.float32)
+    w, o, s = oracle.cell_measure(col.reshape(-1, 1))
+    assert s[0] == 4 and o[0] == col[0]
+    assert w[0] == np.float32((float(col[3]) - float(col[0])) / 4)
+    # evenly spaced values 0..m: one value per split, m + 1 splits
+    for m in (1, 2, 7, 10, 33):
+        x = np.arange(m + 1, dtype=np.float32).reshape(-1, 1)
+        w, o, s = oracle.cell_measure(x)
+        assert s[0] == m + 1 and w[0] == np.float32(m / (m + 1)) and o[0] == 0.0
+    # a constant dimension: one split, width 1; dimensions are independent
+    x = np.array([[3.0, -1.0], [3.0, 2.0], [3.0, 0.5]], np.float32)
+    w, o, s = oracle.cell_measure(x)
+    assert list(s) == [1, 3] and w[0] == 1.0 and o[0] == 3.0 and o[1] == -1.0
+
+
+def test_cell_measure_matches_exact_bruteforce():
+    rng = np.random.default_rng(11)
+    for case in range(150):
+        n = int(rng.integers(1, 14))
+        f = int(rng.integers(1, 4))
+        if case % 3 == 0:
+            x = rng.integers(-8, 9, (n, f)) * 0.25      # duplicates, exact ties
+        elif case % 3 == 1:
+            x = rng.uniform(-4, 4, (n, f))
+        else:
+            x = rng.normal(0, 1, (n, f)) ** 3            # uneven gaps
+        x = x.astype(np.float32)
+        w, o, s = oracle.cell_measure(x)
+        for j in range(f):
+            sj, wj = _measure_fraction(x[:, j])
+            assert s[j] == sj and w[j] == wj and o[j] == x[:, j].min(), (case, j)
 
 
 # ----------------------------------------------------------------------------- grid walk
