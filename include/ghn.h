@@ -82,6 +82,10 @@ typedef enum { GHN_PREC_FP32 = 0, GHN_PREC_BF16_MFMA = 1 } ghn_prec;
 #define GHN_FLAG_NO_PRUNE 1u /* visit every cell of a layer, even those that provably
                                 cannot hold a closer point (same result, slower) */
 #define GHN_FLAG_NO_SORT 2u  /* do not reorder queries by central cell before the walk */
+#define GHN_FLAG_MEDIAN 4u   /* regression index: predict the median of the k targets instead of
+                                their mean (the paper names both, Sections I and IV): the middle
+                                target in IEEE total order, or for even k the FP64 mean of the two
+                                middle targets rounded to FP32 */
 
 typedef struct ghn_index ghn_index; /* opaque HOST handle; owns its device memory */
 
@@ -196,6 +200,19 @@ ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, 
                        const ghn_predict_opts* opts, int64_t* out_idx, double* out_d2, void* out_pred,
                        void* ws, size_t ws_bytes, void* stream);
 
+/* Exhaustive KNN (the plain definition, Section I; the paper's comparison
+ * method in Table 2) on the same index: every training point is screened for
+ * every query with the bf16 matrix-core screen and the exact FP64 re-rank of
+ * ghn_predict's GHN_PREC_BF16_MFMA path, without the grid walk.  The result is
+ * the k smallest (d, id) over all points, bit-identical to ghn_predict with
+ * GHN_STOP_EXACT.  Arguments, outputs, workspace (that of GHN_PREC_BF16_MFMA)
+ * and errors as ghn_predict; of opts only flags (GHN_FLAG_MEDIAN), the
+ * diagnostics outputs and the walk events are used.  Stop layers are reported
+ * as 0. */
+ghn_status ghn_bruteforce(const ghn_index* index, const float* queries, int64_t m, int32_t k,
+                          const ghn_predict_opts* opts, int64_t* out_idx, double* out_d2, void* out_pred,
+                          void* ws, size_t ws_bytes, void* stream);
+
 /* Spatial walk order of a query batch: the permutation of 0..m-1 that sorts
  * the queries by the Morton code of their central cell (Eq. 1) clamped to the
  * occupied box.  Neighbouring queries then share cells, which keeps the
@@ -270,6 +287,23 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
                         const float* queries, int64_t m, int32_t k, int32_t stop, const float* widths,
                         int32_t n_widths, ghn_tune_trial* best, ghn_tune_trial* trials, int32_t max_trials,
                         int32_t* n_trials, void* stream);
+
+/* The paper's cell measurement rule (Section III-A, Fig. 3).  For every
+ * dimension j, the range [mn_j, mx_j] covered by the points is cut into s equal
+ * splits of width w = fl32((mx_j - mn_j) / s); a point x lies in split
+ * min(floor((x_j - mn_j) / w), s - 1) (exact floor; the last split is closed at
+ * mx_j).  The result is the largest s that leaves no split empty: out_splits[j]
+ * = s, out_width[j] = w, out_origin[j] = mn_j.  Passing width and origin to
+ * ghn_build makes the cells of Eq. 1 the splits (a point equal to mx_j may land
+ * one cell past the last split).  A dimension whose points all coincide gets
+ * s = 1 and width 1.
+ *   points   n x f float32 or bf16 bits (DEVICE)
+ *   out_*    f entries each (HOST)
+ * Synchronises `stream`; allocates and frees temporary device memory (about
+ * 24 n bytes) and copies each dimension's sorted keys (8 n bytes) to the host.
+ * Errors: GHN_E_INVALID_ARG, GHN_E_NONFINITE, GHN_E_NOMEM, GHN_E_HIP. */
+ghn_status ghn_cell_measure(const void* points, int64_t n, int32_t f, int32_t dtype, float* out_width,
+                            float* out_origin, int64_t* out_splits, void* stream);
 
 /* Last error message of the calling thread ("" if none).  Valid until the
  * thread's next failing call. */

@@ -28,14 +28,17 @@ GHN_F32, GHN_BF16 = 0, 1
 GHN_CLASSIFY, GHN_REGRESS = 0, 1
 GHN_STOP_EXACT, GHN_STOP_PAPER = 0, 1
 GHN_PREC_FP32, GHN_PREC_BF16_MFMA = 0, 1
-GHN_FLAG_NO_PRUNE, GHN_FLAG_NO_SORT = 1, 2
+GHN_FLAG_NO_PRUNE, GHN_FLAG_NO_SORT, GHN_FLAG_MEDIAN = 1, 2, 4
 GHN_K_MAX, GHN_F_MAX = 64, 32
 
 GHN_LOOKUP_AUTO, GHN_LOOKUP_DENSE, GHN_LOOKUP_TREE = -1, 0, 1
 
+P_ = ctypes.c_void_p
+
 EXPORTED = ["ghn_build", "ghn_build_ex", "ghn_index_get_info", "ghn_destroy", "ghn_predict_workspace_bytes", "ghn_predict",
             "ghn_query_order_workspace_bytes", "ghn_query_order", "ghn_batch_workspace_bytes", "ghn_batch_prepare",
-            "ghn_predict_batched", "ghn_batch_destroy", "ghn_autotune", "ghn_last_error"]
+            "ghn_predict_batched", "ghn_batch_destroy", "ghn_autotune", "ghn_cell_measure", "ghn_bruteforce",
+            "ghn_last_error"]
 
 
 class GHNError(RuntimeError):
@@ -110,6 +113,10 @@ def _load() -> ctypes.CDLL:
     L.ghn_autotune.argtypes = [P, I64, I32, I32, P, I32, P, I64, I32, I32, P, I32, ctypes.POINTER(ghn_tune_trial),
                                ctypes.POINTER(ghn_tune_trial), I32, ctypes.POINTER(I32), P]
     L.ghn_autotune.restype = ctypes.c_int
+    L.ghn_bruteforce.argtypes = [P, P, I64, I32, ctypes.POINTER(ghn_predict_opts), P, P, P, P, SZ, P]
+    L.ghn_bruteforce.restype = ctypes.c_int
+    L.ghn_cell_measure.argtypes = [P, I64, I32, I32, P, P, P, P]
+    L.ghn_cell_measure.restype = ctypes.c_int
     L.ghn_last_error.argtypes = []
     L.ghn_last_error.restype = ctypes.c_char_p
     return L
@@ -234,6 +241,17 @@ def ghn_predict(handle, queries: torch.Tensor, k: int, out_idx: torch.Tensor, ou
                             _ptr(out_pred), _ptr(ws), ws_bytes, _stream(stream)))
 
 
+def ghn_bruteforce(handle, queries: torch.Tensor, k: int, out_idx: torch.Tensor, out_pred: torch.Tensor,
+                   out_d2: Optional[torch.Tensor] = None, flags=0, out_cands: Optional[torch.Tensor] = None,
+                   ws: Optional[torch.Tensor] = None, stream=None, walk_events=None) -> None:
+    """ghn_bruteforce: exhaustive KNN over the index's points (bf16 screen + FP64 re-rank)."""
+    m = queries.shape[0]
+    o = _opts(GHN_STOP_EXACT, GHN_PREC_BF16_MFMA, flags, None, out_cands, None, None, -1, walk_events)
+    ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
+    _check(_lib.ghn_bruteforce(handle, _ptr(queries), m, k, ctypes.byref(o), _ptr(out_idx), _ptr(out_d2),
+                               _ptr(out_pred), _ptr(ws), ws_bytes, _stream(stream)))
+
+
 def ghn_query_order_workspace_bytes(m: int) -> int:
     return int(_lib.ghn_query_order_workspace_bytes(m))
 
@@ -290,6 +308,18 @@ def ghn_autotune(points: torch.Tensor, targets: torch.Tensor, task: int, queries
     return best.as_dict(), [trials[i].as_dict() for i in range(min(nt.value, max_trials))]
 
 
+def ghn_cell_measure(points: torch.Tensor, stream=None):
+    """ghn_cell_measure: the paper's cell measurements -> (width float32[f], origin float32[f], splits int64[f])."""
+    n, f = points.shape
+    dtype = GHN_BF16 if points.dtype == torch.bfloat16 else GHN_F32
+    w = np.empty(f, dtype=np.float32)
+    o = np.empty(f, dtype=np.float32)
+    sp = np.empty(f, dtype=np.int64)
+    _check(_lib.ghn_cell_measure(_ptr(points), n, f, dtype, w.ctypes.data_as(P_), o.ctypes.data_as(P_),
+                                 sp.ctypes.data_as(P_), _stream(stream)))
+    return w, o, sp
+
+
 class Index:
     """Owner of a built index (build on construction, free on close / garbage collection)."""
 
@@ -317,6 +347,24 @@ class Index:
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev) if nbytes else None
         ghn_predict(self.handle, queries, k, out["idx"], out["pred"], out.get("d2"), stop, prec, flags,
                     out.get("stop_layer"), out.get("cands"), out.get("probes"), ws, None, group_levels, stream)
+        return out
+
+    def bruteforce(self, queries: torch.Tensor, k: int, flags=0, with_d2: bool = True, with_stats: bool = False,
+                   stream=None):
+        """Exhaustive KNN over the index's points; returns dict(idx, pred[, d2][, cands]) as GPU tensors."""
+        dev = queries.device
+        m = queries.shape[0]
+        out = dict(idx=torch.empty((m, k), dtype=torch.int64, device=dev),
+                   pred=torch.empty(m, dtype=torch.int32 if self.task == GHN_CLASSIFY else torch.float32,
+                                    device=dev))
+        if with_d2:
+            out["d2"] = torch.empty((m, k), dtype=torch.float64, device=dev)
+        if with_stats:
+            out["cands"] = torch.empty(m, dtype=torch.int64, device=dev)
+        nbytes = ghn_predict_workspace_bytes(self.handle, m, k, GHN_STOP_EXACT, GHN_PREC_BF16_MFMA, flags)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev) if nbytes else None
+        ghn_bruteforce(self.handle, queries, k, out["idx"], out["pred"], out.get("d2"), flags, out.get("cands"), ws,
+                       stream)
         return out
 
     def close(self):

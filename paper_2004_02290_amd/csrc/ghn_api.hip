@@ -93,7 +93,7 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
     if (opts) o = *opts;
     if (o.stop != GHN_STOP_EXACT && o.stop != GHN_STOP_PAPER) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: bad stop rule %d", o.stop);
     if (o.prec != GHN_PREC_FP32) return fail(GHN_E_UNSUPPORTED, "ghn_batch_prepare: batches use the FP32 screen");
-    if (o.flags & ~(GHN_FLAG_NO_PRUNE | GHN_FLAG_NO_SORT)) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: unknown flags 0x%x", o.flags);
+    if (o.flags & ~(GHN_FLAG_NO_PRUNE | GHN_FLAG_NO_SORT | GHN_FLAG_MEDIAN)) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: unknown flags 0x%x", o.flags);
     const size_t need = ghn_batch_workspace_bytes(n_items);
     if (!ws || ws_bytes < need)
         return fail(GHN_E_WORKSPACE, "ghn_batch_prepare: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
@@ -109,6 +109,8 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
         if (it.m < 0) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: item %d has m < 0", i);
         if (it.k < 1 || it.k > K_MAX) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: item %d has k=%d outside [1, %d]", i, it.k, K_MAX);
         if (it.k > it.index->info.n) return fail(GHN_E_K_GT_N, "ghn_batch_prepare: item %d has k=%d > n=%lld", i, it.k, (long long)it.index->info.n);
+        if ((o.flags & GHN_FLAG_MEDIAN) && it.index->info.task != GHN_REGRESS)
+            return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: GHN_FLAG_MEDIAN needs regression indexes (item %d)", i);
         if (it.m > 0 && (!it.queries || !it.out_idx || !it.out_pred))
             return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: item %d has a NULL array", i);
         if (((uintptr_t)it.queries % 4) || ((uintptr_t)it.out_idx % 8) || ((uintptr_t)it.out_pred % 4) || ((uintptr_t)it.out_d2 % 8))
@@ -243,6 +245,25 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
     if (ws) (void)hipFree(ws);
     if (n_trials) *n_trials = nt;
     return result;
+}
+
+ghn_status ghn_cell_measure(const void* points, int64_t n, int32_t f, int32_t dtype, float* out_width,
+                            float* out_origin, int64_t* out_splits, void* stream) {
+    using namespace ghn;
+    if (!points || !out_width || !out_origin || !out_splits)
+        return fail(GHN_E_INVALID_ARG, "ghn_cell_measure: NULL pointer argument");
+    if (n < 1 || n >= (int64_t(1) << 32)) return fail(GHN_E_INVALID_ARG, "ghn_cell_measure: n=%lld outside [1, 2^32)", (long long)n);
+    if (f < 1 || f > F_MAX) return fail(GHN_E_INVALID_ARG, "ghn_cell_measure: f=%d outside [1, %d]", f, F_MAX);
+    if (dtype != GHN_F32 && dtype != GHN_BF16) return fail(GHN_E_INVALID_ARG, "ghn_cell_measure: bad dtype %d", dtype);
+    if ((uintptr_t)points % (dtype == GHN_F32 ? 4 : 2)) return fail(GHN_E_INVALID_ARG, "ghn_cell_measure: misaligned points");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "ghn_cell_measure: pending HIP error");
+    bool nonfinite = false;
+    e = measure_cells(points, n, f, dtype, out_width, out_origin, out_splits, &nonfinite, (hipStream_t)stream);
+    if (e == hipErrorOutOfMemory) return fail(GHN_E_NOMEM, "ghn_cell_measure: out of device memory");
+    if (e != hipSuccess) return hip_fail(e, "ghn_cell_measure");
+    if (nonfinite) return fail(GHN_E_NONFINITE, "ghn_cell_measure: a coordinate is NaN or infinite");
+    return GHN_OK;
 }
 
 ghn_status ghn_build(const void* points, int64_t n, int32_t f, int32_t dtype, const void* targets, int32_t task,
@@ -535,9 +556,10 @@ ghn_status ghn_query_order(const ghn_index* index, const float* queries, int64_t
     return GHN_OK;
 }
 
-ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, int32_t k,
-                       const ghn_predict_opts* opts, int64_t* out_idx, double* out_d2, void* out_pred, void* ws,
-                       size_t ws_bytes, void* stream) {
+// ghn_predict and ghn_bruteforce (brute: every point is screened, no grid walk).
+static ghn_status predict_common(const ghn_index* index, const float* queries, int64_t m, int32_t k,
+                                 const ghn_predict_opts* opts, int64_t* out_idx, double* out_d2, void* out_pred,
+                                 void* ws, size_t ws_bytes, void* stream, bool brute) {
     using namespace ghn;
     (void)ws; (void)ws_bytes;
     if (!index) return fail(GHN_E_INVALID_ARG, "ghn_predict: index is NULL");
@@ -548,7 +570,9 @@ ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, 
     if (opts) o = *opts;
     if (o.stop != GHN_STOP_EXACT && o.stop != GHN_STOP_PAPER) return fail(GHN_E_INVALID_ARG, "ghn_predict: bad stop rule %d", o.stop);
     if (o.prec != GHN_PREC_FP32 && o.prec != GHN_PREC_BF16_MFMA) return fail(GHN_E_INVALID_ARG, "ghn_predict: bad precision %d", o.prec);
-    if (o.flags & ~(GHN_FLAG_NO_PRUNE | GHN_FLAG_NO_SORT)) return fail(GHN_E_INVALID_ARG, "ghn_predict: unknown flags 0x%x", o.flags);
+    if (o.flags & ~(GHN_FLAG_NO_PRUNE | GHN_FLAG_NO_SORT | GHN_FLAG_MEDIAN)) return fail(GHN_E_INVALID_ARG, "ghn_predict: unknown flags 0x%x", o.flags);
+    if ((o.flags & GHN_FLAG_MEDIAN) && index->info.task != GHN_REGRESS)
+        return fail(GHN_E_INVALID_ARG, "ghn_predict: GHN_FLAG_MEDIAN needs a regression index");
     if (m == 0) return GHN_OK;
     if (!queries || !out_idx || !out_pred) return fail(GHN_E_INVALID_ARG, "ghn_predict: queries, out_idx and out_pred must not be NULL");
     if (((uintptr_t)queries % 4) || ((uintptr_t)out_idx % 8) || ((uintptr_t)out_pred % 4) || ((uintptr_t)out_d2 % 8))
@@ -571,15 +595,19 @@ ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, 
     pa.io.out_probes = o.out_probes;
     pa.order = o.order;
     hipStream_t s = (hipStream_t)stream;
+    if (brute) {
+        o.prec = GHN_PREC_BF16_MFMA;
+        pa.order = nullptr;
+    }
     if (o.prec == GHN_PREC_BF16_MFMA) {
         const size_t need = group_ws_bytes(m);
         if (!ws || ws_bytes < need)
             return fail(GHN_E_WORKSPACE, "ghn_predict: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
         if ((uintptr_t)ws % 256) return fail(GHN_E_INVALID_ARG, "ghn_predict: workspace must be 256-byte aligned");
         if (m >= (int64_t(1) << 32)) return fail(GHN_E_INVALID_ARG, "ghn_predict: m=%lld too large for one call", (long long)m);
-        const int levels = o.stop == GHN_STOP_PAPER ? 0 : (o.group_levels >= 0 ? o.group_levels : (index->info.f >= 12 ? 3 : 1));
+        const int levels = brute ? 32 : o.stop == GHN_STOP_PAPER ? 0 : (o.group_levels >= 0 ? o.group_levels : (index->info.f >= 12 ? 3 : 1));
         int bits = 0;
-        e = run_grouped(pa, levels, ws, s, &bits, (hipEvent_t)o.walk_event_begin, (hipEvent_t)o.walk_event_end);
+        e = run_grouped(pa, levels, ws, s, &bits, (hipEvent_t)o.walk_event_begin, (hipEvent_t)o.walk_event_end, brute);
         if (bits > 64) return fail(GHN_E_UNSUPPORTED, "ghn_predict: the Morton code of the cell ids needs %d bits (> 64)", bits);
         if (e != hipSuccess) return hip_fail(e, "ghn_predict: grouped walk");
         return GHN_OK;
@@ -600,6 +628,18 @@ ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, 
     if (o.walk_event_end && (e = hipEventRecord((hipEvent_t)o.walk_event_end, s)) != hipSuccess)
         return hip_fail(e, "ghn_predict: walk_event_end");
     return GHN_OK;
+}
+
+ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, int32_t k,
+                       const ghn_predict_opts* opts, int64_t* out_idx, double* out_d2, void* out_pred, void* ws,
+                       size_t ws_bytes, void* stream) {
+    return predict_common(index, queries, m, k, opts, out_idx, out_d2, out_pred, ws, ws_bytes, stream, false);
+}
+
+ghn_status ghn_bruteforce(const ghn_index* index, const float* queries, int64_t m, int32_t k,
+                          const ghn_predict_opts* opts, int64_t* out_idx, double* out_d2, void* out_pred, void* ws,
+                          size_t ws_bytes, void* stream) {
+    return predict_common(index, queries, m, k, opts, out_idx, out_d2, out_pred, ws, ws_bytes, stream, true);
 }
 
 }  // extern "C"

@@ -130,7 +130,7 @@ __device__ __forceinline__ bool group_start(const uint64_t* keys, const uint32_t
                                             int64_t i, int shift) {
     if (i == 0 || (i % GQ) == 0) return true;
     if (qflags[vals[i]] || qflags[vals[i - 1]]) return true;
-    return (keys[i] >> shift) != (keys[i - 1] >> shift);
+    return shift < 64 && (keys[i] >> shift) != (keys[i - 1] >> shift);
 }
 
 __global__ __launch_bounds__(256) void k_form_groups(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
@@ -146,6 +146,7 @@ __global__ __launch_bounds__(256) void k_form_groups(const uint64_t* __restrict_
 }
 
 struct GroupArgs {
+    int32_t brute;          // exhaustive KNN: no grid walk, every point screened
     PredictArgs p;          // p.order = queries in sorted order
     const uint2* groups;
     const uint32_t* counters;  // [0] = number of groups
@@ -161,6 +162,7 @@ struct alignas(16) GroupLds {
     uint32_t run_pre[WAVE + 1];
     uint64_t stack[STACK_CAP];
     int32_t lab[4][K_MAX];
+    int32_t med[4][2];
     int32_t glo[FS], ghi[FS];
     float qlo[FS], qhi[FS];
     double ad[FS], od[FS];  // cell width and origin (FP64), read inside the walk
@@ -196,6 +198,12 @@ template <> struct Screen<32> {
     __device__ static int a_part(int kb, int g) { return kb == 2 ? 1 : 0; }
     __device__ static int a_dim(int kb, int g) { return 8 * g; }
 };
+
+// Integer key ordering float bit patterns as IEEE total order.
+__device__ __forceinline__ uint32_t total_key(int32_t bits) {
+    const uint32_t u = (uint32_t)bits;
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
 
 // FP32 values at or below / at or above an FP64 value, one extra ulp outward.
 __device__ __forceinline__ float f32_below(double x) {
@@ -385,108 +393,9 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
         int32_t l = l0;
         const bool any_live = (fin_mask & ((cnt >= 64 ? ~0ull : ((1ull << cnt) - 1)))) != 0;
 
-        for (; any_live; ++l) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) upd[i] = false;
-            if (lane == 0) S.stack[0] = ((uint64_t)ix.tree_levels << 40) | ((uint64_t)ix.tree_count[ix.tree_levels] << 32);
-            int sp = 1;
-            wave_lds_sync();
-            while (sp > 0) {
-                --sp;
-                const uint64_t e = S.stack[sp];
-                wave_lds_sync();
-                const int level = (int)(e >> 40);
-                const int count = (int)((e >> 32) & 0xff);
-                const uint32_t node = (uint32_t)e + lane;
-                const bool active = lane < count;
-                // largest k-th distance over the live queries (+inf while a buffer is not full)
-                double mt = -1.0;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) if (!done[i]) mt = fmax(mt, tau[i]);
-                for (int d = 16; d < WAVE; d <<= 1) mt = fmax(mt, __shfl_xor(mt, d, WAVE));
-                int32_t dmin = 0, dmax = 0;
-                double lb = 0.0;
-                if (active) {
-                    const int32_t* lo = level == 0 ? ix.cell_coord + (size_t)node * f
-                                                   : ix.node_lo + (size_t)(ix.tree_off[level] + node) * f;
-                    const int32_t* hi = level == 0 ? lo : ix.node_hi + (size_t)(ix.tree_off[level] + node) * f;
-                    for (int j = 0; j < f; ++j) {
-                        const int32_t a = lo[j], b = hi[j], ga = S.glo[j], gb = S.ghi[j];
-                        dmin = max(dmin, max(a - gb, ga - b));
-                        dmax = max(dmax, max(ga - a, b - gb));
-                        // distance from the box of query coordinates to the node's region
-                        const double aj = S.ad[j], oj = S.od[j];
-                        const double below = __dadd_rn(__dadd_rn(__dmul_rn((double)a, aj), oj), -(double)S.qhi[j]);
-                        const double above = __dadd_rn((double)S.qlo[j], -__dadd_rn(__dmul_rn((double)(b + 1), aj), oj));
-                        double gap = below > above ? below : above;
-                        gap = gap > 0.0 ? gap : 0.0;
-                        lb = __dadd_rn(lb, __dmul_rn(gap, gap));
-                    }
-                }
-                const bool close = !prune || !(lb * LB_SHRINK > mt);
-                probes += __popcll(ballot(active));
-                if (level > 0) {
-                    const bool keep = active && dmin <= l && l <= dmax && close;
-                    const uint64_t km = ballot(keep);
-                    if (keep) {
-                        const int64_t c0 = (int64_t)node * WAVE;
-                        const int nc = (int)min((int64_t)WAVE, ix.tree_count[level - 1] - c0);
-                        S.stack[sp + __popcll(km & __lanemask_lt())] =
-                            ((uint64_t)(level - 1) << 40) | ((uint64_t)nc << 32) | (uint32_t)c0;
-                    }
-                    sp += __popcll(km);
-                    wave_lds_sync();
-                    continue;
-                }
-                // cells of layer l: one run of points per kept cell.  With several
-                // queries a cell is kept only if some live query's own lower bound to
-                // it is within that query's threshold (the bound from the box of the
-                // group's queries above is weaker).  FP32 bounds: the cell's region is
-                // rounded outward and the sum shrunk by (1 - 2^-18), which covers the
-                // rounding of f <= 32 differences, squares and sums.  (Up to 8
-                // dimensions, where the cell bounds fit in registers.)
-                bool keepc = active && dmin == l && close;
-                if (FT > 0 && FT <= 8 && prune && cnt > 1 && ballot(keepc)) {
-                    float clo[FS], chi[FS];
-                    if (keepc) {
-                        const int32_t* cid = ix.cell_coord + (size_t)node * f;
-                        for (int j = 0; j < f; ++j) {
-                            const double aj = S.ad[j], oj = S.od[j];
-                            const int32_t c = cid[j];
-                            clo[j] = f32_below(__dadd_rn(__dmul_rn((double)c, aj), oj));
-                            chi[j] = f32_above(__dadd_rn(__dmul_rn((double)(c + 1), aj), oj));
-                        }
-                    }
-                    bool need = false;
-                    for (int r = 0; r < cnt; ++r) {
-                        const float tq = S.tq[r];
-                        if (!(tq >= 0.0f)) continue;
-                        float lbq = 0.0f;
-                        for (int j = 0; j < f; ++j) {
-                            const float q = S.q[r][j];
-                            const float gp = fmaxf(fmaxf(clo[j] - q, q - chi[j]), 0.0f);
-                            lbq = __builtin_fmaf(gp, gp, lbq);
-                        }
-                        need = need || lbq * (1.0f - 0x1p-18f) <= tq;
-                    }
-                    keepc = keepc && need;
-                }
-                uint32_t rb = 0, rn = 0;
-                if (keepc) {
-                    rb = ix.cell_first[node];
-                    rn = ix.cell_first[node + 1] - rb;
-                }
-                const uint32_t incl = wave_incl_scan(rn);
-                const uint32_t npts = readlane_i32((int)incl, WAVE - 1);
-                if (npts == 0) continue;
-                const uint32_t nrun_incl = wave_incl_scan(rn > 0 ? 1u : 0u);
-                const uint32_t nrun = readlane_i32((int)nrun_incl, WAVE - 1);
-                if (rn > 0) {
-                    S.run_begin[nrun_incl - 1] = rb;
-                    S.run_pre[nrun_incl - 1] = incl - rn;
-                }
-                if (lane == 0) S.run_pre[nrun] = npts;  // sentinel
-                wave_lds_sync();
+        // Screen, check and insert the points of the run list in LDS (npts points in
+        // nrun runs, prefix positions with a sentinel at nrun).
+        auto score_tiles = [&](uint32_t npts, uint32_t nrun) {
                 uint32_t seg = 0;
                 for (uint32_t base = 0; base < npts; base += WAVE) {
                     // candidate base + lane: its run (one uniform pass over the runs that
@@ -609,6 +518,129 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                         }
                     }
                 }
+        };
+
+        if (G.brute) {
+            // exhaustive KNN: every point is a candidate, in one pass
+            if (any_live) {
+                if (lane == 0) {
+                    S.run_begin[0] = 0u;
+                    S.run_pre[0] = 0u;
+                    S.run_pre[1] = (uint32_t)ix.n;
+                }
+                wave_lds_sync();
+                score_tiles((uint32_t)ix.n, 1u);
+                wave_lds_sync();
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (!done[i]) stopl[i] = 0;
+                done[i] = true;
+            }
+        }
+        for (; any_live && !G.brute; ++l) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) upd[i] = false;
+            if (lane == 0) S.stack[0] = ((uint64_t)ix.tree_levels << 40) | ((uint64_t)ix.tree_count[ix.tree_levels] << 32);
+            int sp = 1;
+            wave_lds_sync();
+            while (sp > 0) {
+                --sp;
+                const uint64_t e = S.stack[sp];
+                wave_lds_sync();
+                const int level = (int)(e >> 40);
+                const int count = (int)((e >> 32) & 0xff);
+                const uint32_t node = (uint32_t)e + lane;
+                const bool active = lane < count;
+                // largest k-th distance over the live queries (+inf while a buffer is not full)
+                double mt = -1.0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) if (!done[i]) mt = fmax(mt, tau[i]);
+                for (int d = 16; d < WAVE; d <<= 1) mt = fmax(mt, __shfl_xor(mt, d, WAVE));
+                int32_t dmin = 0, dmax = 0;
+                double lb = 0.0;
+                if (active) {
+                    const int32_t* lo = level == 0 ? ix.cell_coord + (size_t)node * f
+                                                   : ix.node_lo + (size_t)(ix.tree_off[level] + node) * f;
+                    const int32_t* hi = level == 0 ? lo : ix.node_hi + (size_t)(ix.tree_off[level] + node) * f;
+                    for (int j = 0; j < f; ++j) {
+                        const int32_t a = lo[j], b = hi[j], ga = S.glo[j], gb = S.ghi[j];
+                        dmin = max(dmin, max(a - gb, ga - b));
+                        dmax = max(dmax, max(ga - a, b - gb));
+                        // distance from the box of query coordinates to the node's region
+                        const double aj = S.ad[j], oj = S.od[j];
+                        const double below = __dadd_rn(__dadd_rn(__dmul_rn((double)a, aj), oj), -(double)S.qhi[j]);
+                        const double above = __dadd_rn((double)S.qlo[j], -__dadd_rn(__dmul_rn((double)(b + 1), aj), oj));
+                        double gap = below > above ? below : above;
+                        gap = gap > 0.0 ? gap : 0.0;
+                        lb = __dadd_rn(lb, __dmul_rn(gap, gap));
+                    }
+                }
+                const bool close = !prune || !(lb * LB_SHRINK > mt);
+                probes += __popcll(ballot(active));
+                if (level > 0) {
+                    const bool keep = active && dmin <= l && l <= dmax && close;
+                    const uint64_t km = ballot(keep);
+                    if (keep) {
+                        const int64_t c0 = (int64_t)node * WAVE;
+                        const int nc = (int)min((int64_t)WAVE, ix.tree_count[level - 1] - c0);
+                        S.stack[sp + __popcll(km & __lanemask_lt())] =
+                            ((uint64_t)(level - 1) << 40) | ((uint64_t)nc << 32) | (uint32_t)c0;
+                    }
+                    sp += __popcll(km);
+                    wave_lds_sync();
+                    continue;
+                }
+                // cells of layer l: one run of points per kept cell.  With several
+                // queries a cell is kept only if some live query's own lower bound to
+                // it is within that query's threshold (the bound from the box of the
+                // group's queries above is weaker).  FP32 bounds: the cell's region is
+                // rounded outward and the sum shrunk by (1 - 2^-18), which covers the
+                // rounding of f <= 32 differences, squares and sums.  (Up to 8
+                // dimensions, where the cell bounds fit in registers.)
+                bool keepc = active && dmin == l && close;
+                if (FT > 0 && FT <= 8 && prune && cnt > 1 && ballot(keepc)) {
+                    float clo[FS], chi[FS];
+                    if (keepc) {
+                        const int32_t* cid = ix.cell_coord + (size_t)node * f;
+                        for (int j = 0; j < f; ++j) {
+                            const double aj = S.ad[j], oj = S.od[j];
+                            const int32_t c = cid[j];
+                            clo[j] = f32_below(__dadd_rn(__dmul_rn((double)c, aj), oj));
+                            chi[j] = f32_above(__dadd_rn(__dmul_rn((double)(c + 1), aj), oj));
+                        }
+                    }
+                    bool need = false;
+                    for (int r = 0; r < cnt; ++r) {
+                        const float tq = S.tq[r];
+                        if (!(tq >= 0.0f)) continue;
+                        float lbq = 0.0f;
+                        for (int j = 0; j < f; ++j) {
+                            const float q = S.q[r][j];
+                            const float gp = fmaxf(fmaxf(clo[j] - q, q - chi[j]), 0.0f);
+                            lbq = __builtin_fmaf(gp, gp, lbq);
+                        }
+                        need = need || lbq * (1.0f - 0x1p-18f) <= tq;
+                    }
+                    keepc = keepc && need;
+                }
+                uint32_t rb = 0, rn = 0;
+                if (keepc) {
+                    rb = ix.cell_first[node];
+                    rn = ix.cell_first[node + 1] - rb;
+                }
+                const uint32_t incl = wave_incl_scan(rn);
+                const uint32_t npts = readlane_i32((int)incl, WAVE - 1);
+                if (npts == 0) continue;
+                const uint32_t nrun_incl = wave_incl_scan(rn > 0 ? 1u : 0u);
+                const uint32_t nrun = readlane_i32((int)nrun_incl, WAVE - 1);
+                if (rn > 0) {
+                    S.run_begin[nrun_incl - 1] = rb;
+                    S.run_pre[nrun_incl - 1] = incl - rn;
+                }
+                if (lane == 0) S.run_pre[nrun] = npts;  // sentinel
+                wave_lds_sync();
+                score_tiles(npts, nrun);
                 wave_lds_sync();
             }
             // stop rules for every live query of the group, after layer l
@@ -703,6 +735,29 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                         if (on > best_n || (on == best_n && ob < best)) { best = ob; best_n = on; }
                     }
                     if (t == 0) ((int32_t*)A.io.out_pred)[qi] = best;
+                } else if (A.io.flags & GHN_FLAG_MEDIAN) {
+                    // the targets at sorted positions (k - 1) / 2 and k / 2 (IEEE total order): each
+                    // entry's rank is counted against the row's k targets
+                    const int p1 = (k - 1) >> 1, p2 = k >> 1;
+#pragma unroll
+                    for (int j = 0; j < KR; ++j) {
+                        const int ee = 16 * j + t;
+                        if (ee >= k) continue;
+                        const uint32_t kv = total_key(S.lab[g][ee]);
+                        int less = 0, eq = 0;
+                        for (int e2 = 0; e2 < k; ++e2) {
+                            const uint32_t o = total_key(S.lab[g][e2]);
+                            less += o < kv;
+                            eq += o == kv;
+                        }
+                        if (less <= p1 && p1 < less + eq) S.med[g][0] = S.lab[g][ee];
+                        if (less <= p2 && p2 < less + eq) S.med[g][1] = S.lab[g][ee];
+                    }
+                    wave_lds_sync();
+                    if (t == 0) {
+                        const float a = __int_as_float(S.med[g][0]), b = __int_as_float(S.med[g][1]);
+                        ((float*)A.io.out_pred)[qi] = (k & 1) ? a : (float)(__dadd_rn((double)a, (double)b) / 2.0);
+                    }
                 } else if (t == 0) {
                     double s = 0.0;
                     for (int e2 = 0; e2 < k; ++e2) s = __dadd_rn(s, (double)__int_as_float(S.lab[g][e2]));
@@ -745,7 +800,7 @@ size_t group_ws_bytes(int64_t m) {
 
 // Sort + group the queries, then walk the groups.  `ws` holds group_ws_bytes(m).
 hipError_t run_grouped(const PredictArgs& pa, int keep_shift_levels, void* ws, hipStream_t s, int* morton_bits,
-                       hipEvent_t ev_begin, hipEvent_t ev_end) {
+                       hipEvent_t ev_begin, hipEvent_t ev_end, bool brute) {
     const IndexView& ix = pa.ix;
     const int64_t m = pa.m;
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
@@ -782,6 +837,7 @@ hipError_t run_grouped(const PredictArgs& pa, int keep_shift_levels, void* ws, h
     const uint32_t* sv = alt ? v1 : v0;
     hipLaunchKernelGGL(k_form_groups, dim3((unsigned)g), dim3(256), 0, s, sk, sv, qflags, m, shift, groups, counters);
     GroupArgs ga;
+    ga.brute = brute ? 1 : 0;
     ga.p = pa;
     ga.p.order = sv;
     ga.groups = groups;

@@ -146,6 +146,8 @@ hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, 
 hipError_t launch_gather_points(const void* pts, int64_t n, int32_t f, int32_t dtype, const uint32_t* perm,
                                 float* spts, int32_t* sid, hipStream_t s);
 hipError_t launch_screen_records(const IndexView& iv, uint16_t* rec, float* xn, hipStream_t s);
+hipError_t measure_cells(const void* pts, int64_t n, int32_t f, int32_t dtype, float* width, float* origin,
+                         int64_t* splits, bool* nonfinite, hipStream_t s);
 hipError_t launch_dense_cell_start(const uint64_t* sorted_keys, int64_t n, int64_t box_cells,
                                    uint32_t* cell_start, hipStream_t s);
 
@@ -199,7 +201,7 @@ hipError_t coord_range(const void* pts, int64_t n, int32_t f, int32_t dtype, flo
 // Grouped walk with the bf16 matrix-core screen: sort, group and walk the queries.
 size_t group_ws_bytes(int64_t m);
 hipError_t run_grouped(const PredictArgs& pa, int group_levels, void* ws, hipStream_t s, int* morton_bits,
-                       hipEvent_t ev_begin, hipEvent_t ev_end);
+                       hipEvent_t ev_begin, hipEvent_t ev_end, bool brute);
 // Spatial sort key of every query (Morton code of its box-clamped central cell).
 hipError_t launch_query_keys(const float* qs, int64_t m, const IndexView& ix, int keep_bits, uint64_t* keys,
                              uint32_t* vals, hipStream_t s);

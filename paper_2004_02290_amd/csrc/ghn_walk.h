@@ -401,6 +401,21 @@ __device__ __forceinline__ void finish_query(const IndexView& ix, const QueryIO&
             todo &= ~same;
         }
         if (lane == 0) ((int32_t*)io.out_pred)[qi] = best;
+    } else if (io.flags & GHN_FLAG_MEDIAN) {
+        // sort the k targets across the wave in IEEE total order (padding last)
+        const float* y = (const float*)ix.targets;
+        const uint32_t u = lane < k ? __float_as_uint(y[st.bi]) : 0u;
+        uint32_t key = lane < k ? ((u & 0x80000000u) ? ~u : (u | 0x80000000u)) : 0xffffffffu;
+        key = wave_sort_asc(key, lane, WAVE);
+        const float v = __uint_as_float((key & 0x80000000u) ? (key & 0x7fffffffu) : ~key);
+        float mid;
+        if (k & 1) {
+            mid = readlane_f32(v, k >> 1);
+        } else {
+            const double a = readlane_f32(v, (k >> 1) - 1), b = readlane_f32(v, k >> 1);
+            mid = (float)(__dadd_rn(a, b) / 2.0);
+        }
+        if (lane == 0) ((float*)io.out_pred)[qi] = mid;
     } else {
         const float* y = (const float*)ix.targets;
         const float my = lane < k ? y[st.bi] : 0.0f;

@@ -1,0 +1,194 @@
+"""GPU results against the CPU oracle for the paper's cell measurement rule, the
+median statistic and exhaustive KNN, element by element (bit-identical)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2004_02290_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ghn():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2004_02290_amd import binding
+    return binding
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _pts(prob):
+    import torch
+    if prob.dtype == "bf16":
+        return _dev(prob.points.view(np.int16)).view(torch.bfloat16)
+    return _dev(prob.points)
+
+
+def _host(out):
+    import torch
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _same(got, want, what, keys=("idx", "d2", "pred")):
+    for key in keys:
+        g, w = got[key], want[key]
+        if not np.array_equal(g, w):
+            bad = np.flatnonzero((g != w).reshape(g.shape[0], -1).any(axis=1))
+            raise AssertionError("%s: %s differs on %d rows, first %d: got %s want %s" % (
+                what, key, bad.size, bad[0], g[bad[0]], w[bad[0]]))
+
+
+# ------------------------------------------------------------------------- cell measurements
+def _measure_cases():
+    rng = np.random.default_rng(21)
+    yield "counterexample", np.array([[0.28], [0.485], [0.75], [0.981]], np.float32)
+    yield "blobs2d", W.make("blobs2d", n=3000, m=1).points
+    yield "uniform3", rng.random((2500, 3), dtype=np.float32)
+    yield "lattice", W.lattice_problem(2000, 1, 2, 1).points
+    yield "negative", (rng.normal(0, 3, (1500, 4)) ** 3).astype(np.float32)
+    yield "constant", np.concatenate([np.full((500, 1), 7.5, np.float32), rng.random((500, 1), dtype=np.float32)], 1)
+    yield "single", np.array([[1.0, -2.0]], np.float32)
+
+
+@pytest.mark.parametrize("case", range(7))
+def test_cell_measure_matches_oracle(ghn, case):
+    name, x = list(_measure_cases())[case]
+    w, o, s = ghn.ghn_cell_measure(_dev(x))
+    ww, wo, ws = oracle.cell_measure(x)
+    assert np.array_equal(s, ws), (name, s, ws)
+    assert np.array_equal(w, ww), (name, w, ww)
+    assert np.array_equal(o, wo), (name, o, wo)
+
+
+def test_cell_measure_bf16_points(ghn):
+    prob = W.make("bf16_16d", n=1500, m=1)
+    w, o, s = ghn.ghn_cell_measure(_pts(prob))
+    ww, wo, ws = oracle.cell_measure(prob.points_f32())
+    assert np.array_equal(s, ws) and np.array_equal(w, ww) and np.array_equal(o, wo)
+
+
+def _split_of(x, o, w, s):
+    v = x.astype(np.float64) - float(o)
+    q = np.floor(v / float(w))
+    q = np.where(q * float(w) > v, q - 1, q)
+    q = np.where((q + 1) * float(w) <= v, q + 1, q)
+    return np.minimum(q, s - 1).astype(np.int64)
+
+
+def test_cell_measure_full_size_properties(ghn):
+    # 1M points: the oracle's search over every split count is too slow here, so the
+    # defining property is checked: s splits all hold points, the next counts do not
+    prob = W.make("clusters4d")
+    w, o, s = ghn.ghn_cell_measure(_dev(prob.points))
+    for j in range(prob.f):
+        col = prob.points[:, j]
+        assert o[j] == col.min()
+        assert np.unique(_split_of(col, o[j], w[j], s[j])).size == s[j]
+        rng_ = float(col.max()) - float(col.min())
+        for s2 in range(int(s[j]) + 1, int(s[j]) + 25):
+            w2 = np.float32(rng_ / s2)
+            assert np.unique(_split_of(col, o[j], w2, s2)).size < s2, (j, s2)
+
+
+def test_paper_widths_build_and_predict(ghn):
+    # the paper's own configuration: measured widths and origin, PAPER and EXACT rules
+    prob = W.make("blobs2d")
+    w, o, s = ghn.ghn_cell_measure(_dev(prob.points))
+    ix = ghn.Index(_dev(prob.points), _dev(prob.targets), prob.task, w, o)
+    q = _dev(prob.queries)
+    g = oracle.Grid(prob.points, prob.targets, prob.task, w, o)
+    got = _host(ix.predict(q, prob.k, stop=ghn.GHN_STOP_PAPER, with_stats=True))
+    want = g.predict(prob.queries, prob.k, oracle.STOP_PAPER)
+    _same(got, want, "PAPER with measured widths")
+    assert np.array_equal(got["stop_layer"], want["stop_layer"])
+    got = _host(ix.predict(q, prob.k, stop=ghn.GHN_STOP_EXACT))
+    bi, bd, bp = oracle.bruteforce(prob.points, prob.targets, prob.task, prob.queries, prob.k)
+    _same(got, dict(idx=bi, d2=bd, pred=bp), "EXACT with measured widths")
+
+
+def test_cell_measure_errors(ghn):
+    x = np.array([[0.0, 1.0], [np.nan, 2.0]], np.float32)
+    with pytest.raises(ghn.GHNError) as e:
+        ghn.ghn_cell_measure(_dev(x))
+    assert e.value.code == -4
+
+
+# ------------------------------------------------------------------------------- median
+@pytest.mark.parametrize("prec", [0, 1])
+def test_median_regression(ghn, prec):
+    prob = W.make("skew8d", n=40_000, m=1_500)
+    ix = ghn.Index(_dev(prob.points), _dev(prob.targets), prob.task, prob.cell_width)
+    q = _dev(prob.queries)
+    for stop in (ghn.GHN_STOP_EXACT, ghn.GHN_STOP_PAPER):
+        got = _host(ix.predict(q, prob.k, stop=stop, prec=prec, flags=ghn.GHN_FLAG_MEDIAN, with_stats=True))
+        if stop == ghn.GHN_STOP_EXACT:
+            bi, bd, bp = oracle.bruteforce(prob.points, prob.targets, oracle.REGRESS_MEDIAN, prob.queries, prob.k)
+            want = dict(idx=bi, d2=bd, pred=bp)
+        else:
+            want = oracle.Grid(prob.points, prob.targets, oracle.REGRESS_MEDIAN, prob.cell_width).predict(
+                prob.queries, prob.k, oracle.STOP_PAPER)
+        _same(got, want, "median stop=%d prec=%d" % (stop, prec))
+
+
+def test_median_ties_and_even_k(ghn):
+    base = W.lattice_problem(3000, 400, 3, 1, task=W.REGRESS)
+    y = np.round(base.targets * 2).astype(np.float32) / 2   # many equal targets
+    for k in (1, 2, 5, 8, 33, 64):
+        ix = ghn.Index(_dev(base.points), _dev(y), W.REGRESS, base.cell_width)
+        for prec in (0, 1):
+            got = _host(ix.predict(_dev(base.queries), k, prec=prec, flags=ghn.GHN_FLAG_MEDIAN))
+            bi, bd, bp = oracle.bruteforce(base.points, y, oracle.REGRESS_MEDIAN, base.queries, k)
+            _same(got, dict(idx=bi, d2=bd, pred=bp), "median k=%d prec=%d" % (k, prec))
+
+
+def test_median_batched_and_errors(ghn):
+    import torch
+    prob = W.make("skew8d", n=20_000, m=600)
+    ix = ghn.Index(_dev(prob.points), _dev(prob.targets), prob.task, prob.cell_width)
+    q = _dev(prob.queries)
+    oi = torch.empty((prob.m, prob.k), dtype=torch.int64, device="cuda")
+    op = torch.empty(prob.m, dtype=torch.float32, device="cuda")
+    ws = torch.empty(ghn.ghn_batch_workspace_bytes(1), dtype=torch.uint8, device="cuda")
+    b = ghn.ghn_batch_prepare([(ix.handle, q, prob.k, oi, op, None)], ws, flags=ghn.GHN_FLAG_MEDIAN)
+    ghn.ghn_predict_batched(b)
+    torch.cuda.synchronize()
+    ghn.ghn_batch_destroy(b)
+    _, _, bp = oracle.bruteforce(prob.points, prob.targets, oracle.REGRESS_MEDIAN, prob.queries, prob.k)
+    assert np.array_equal(op.cpu().numpy(), bp)
+    c = W.make("blobs2d", n=2000, m=10)
+    cix = ghn.Index(_dev(c.points), _dev(c.targets), c.task, c.cell_width)
+    with pytest.raises(ghn.GHNError) as e:
+        cix.predict(_dev(c.queries), c.k, flags=ghn.GHN_FLAG_MEDIAN)
+    assert e.value.code == -1
+
+
+# ------------------------------------------------------------------------------ brute force
+@pytest.mark.parametrize("name,n,m,k", [("blobs2d", None, None, 5), ("clusters4d", 50_000, 700, 10),
+                                        ("skew8d", 30_000, 500, 16), ("bf16_16d", 20_000, 300, 32)])
+def test_bruteforce_matches_oracle(ghn, name, n, m, k):
+    prob = W.make(name, n=n, m=m)
+    ix = ghn.Index(_pts(prob), _dev(prob.targets), prob.task, prob.cell_width)
+    got = _host(ix.bruteforce(_dev(prob.queries), k, with_stats=True))
+    bi, bd, bp = oracle.bruteforce(prob.points_f32(), prob.targets, prob.task, prob.queries, k)
+    _same(got, dict(idx=bi, d2=bd, pred=bp), name + " bruteforce")
+    assert (got["cands"] == prob.n).all()
+
+
+def test_bruteforce_ties_k_range_and_median(ghn):
+    base = W.lattice_problem(1500, 300, 2, 1)
+    ix = ghn.Index(_dev(base.points), _dev(base.targets), base.task, base.cell_width)
+    for k in (1, 3, 16, 17, 40, 64):
+        got = _host(ix.bruteforce(_dev(base.queries), k))
+        bi, bd, bp = oracle.bruteforce(base.points, base.targets, base.task, base.queries, k)
+        _same(got, dict(idx=bi, d2=bd, pred=bp), "lattice bruteforce k=%d" % k)
+    r = W.lattice_problem(1500, 300, 4, 1, task=W.REGRESS)
+    rix = ghn.Index(_dev(r.points), _dev(r.targets), r.task, r.cell_width)
+    got = _host(rix.bruteforce(_dev(r.queries), 12, flags=ghn.GHN_FLAG_MEDIAN))
+    bi, bd, bp = oracle.bruteforce(r.points, r.targets, oracle.REGRESS_MEDIAN, r.queries, 12)
+    _same(got, dict(idx=bi, d2=bd, pred=bp), "lattice bruteforce median")
