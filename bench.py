@@ -122,6 +122,52 @@ def cpu_baseline(prob, target_s: float = 15.0):
                       % (sample, prob.m)}
 
 
+def paper_study(args, ghn, W, torch):
+    """The paper's own configuration: cell measurements by its rule (Section III-A) and its
+    stop rule, against the EXACT rule (equal to brute force) on the same index.  Reports
+    the share of queries whose PAPER neighbours differ (misses) and predictions differ."""
+    prob = W.make(args.workload)
+    dev = torch.device("cuda:0")
+    if prob.dtype == "bf16":
+        pts = torch.from_numpy(prob.points.view(np.int16)).to(dev).view(torch.bfloat16)
+    else:
+        pts = torch.from_numpy(prob.points).to(dev)
+    tgt = torch.from_numpy(prob.targets).to(dev)
+    qs = torch.from_numpy(prob.queries).to(dev)
+    t0 = time.perf_counter()
+    w, o, splits = ghn.ghn_cell_measure(pts)
+    measure_ms = (time.perf_counter() - t0) * 1e3
+    rows = []
+    for label, widths, origin in (("paper_rule_widths", w, o), ("about_8_per_cell", prob.cell_width, None)):
+        try:
+            ix = ghn.Index(pts, tgt, prob.task, widths, origin)
+        except ghn.GHNError as e:  # e.g. cell ids too wide for the 64-bit Morton key of the tree
+            rows.append({"grid": label, "build_error": str(e)})
+            continue
+        res = {}
+        for name, stop in (("exact", ghn.GHN_STOP_EXACT), ("paper", ghn.GHN_STOP_PAPER)):
+            ix.predict(qs, prob.k, stop=stop, with_d2=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ix.predict(qs, prob.k, stop=stop, with_d2=False, with_stats=True)
+            torch.cuda.synchronize()
+            res[name] = dict(ms=(time.perf_counter() - t0) * 1e3, idx=r["idx"], pred=r["pred"],
+                             layers=float(r["stop_layer"].double().mean().item()),
+                             cands=float(r["cands"].double().mean().item()))
+        same_set = (torch.sort(res["paper"]["idx"], dim=1)[0] == torch.sort(res["exact"]["idx"], dim=1)[0]).all(1)
+        rows.append({"grid": label, "num_cells": int(ix.info.num_cells),
+                     "query_miss_rate": float(1.0 - same_set.double().mean().item()),
+                     "prediction_differs_rate": float((res["paper"]["pred"] != res["exact"]["pred"]).double()
+                                                      .mean().item()),
+                     "exact_ms": res["exact"]["ms"], "paper_ms": res["paper"]["ms"],
+                     "exact_mean_layers": res["exact"]["layers"], "paper_mean_layers": res["paper"]["layers"],
+                     "exact_cands_per_query": res["exact"]["cands"], "paper_cands_per_query": res["paper"]["cands"]})
+        ix.close()
+    print(json.dumps({"study": "PAPER stop rule vs EXACT (= brute force)", "workload": describe(prob, "both"),
+                      "cell_measure_ms": measure_ms, "paper_rule_splits": [int(x) for x in splits],
+                      "paper_rule_widths": [float(x) for x in w], "grids": rows}), flush=True)
+
+
 def bench_multi(args, ghn, W, torch):
     """Many independent 3-D problems: per-index launches vs one batched launch (and its graph replay)."""
     probs = W.make_multi3d()
@@ -242,10 +288,13 @@ def main():
     ap.add_argument("--stop", default="exact", choices=["exact", "paper"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sort", action="store_true", help="FP32 form: walk queries in spatial (Morton) order")
-    ap.add_argument("--forms", default="fp32,bf16", help="comma list of forms to time: fp32, bf16")
+    ap.add_argument("--forms", default="fp32,bf16",
+                    help="comma list of forms to time: fp32, bf16 (GHN walks), brute (exhaustive KNN, reported beside)")
     ap.add_argument("--group-levels", type=int, default=-1, help="bf16 form: cell-id bits dropped to group queries")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
+    ap.add_argument("--paper-study", action="store_true",
+                    help="instead of the benchmark: the paper's cell measurements and stop rule against EXACT")
     ap.add_argument("--write-traffic", metavar="PMC_DIR",
                     help="no GPU work: write profiles/traffic.json from rocprofv3 --pmc output for --workload "
                          "(a comma list)")
@@ -273,6 +322,9 @@ def main():
 
     if args.workload == "multi3d":
         bench_multi(args, ghn, W, torch)
+        return
+    if args.paper_study:
+        paper_study(args, ghn, W, torch)
         return
     prob = W.make(args.workload)
     stop = ghn.GHN_STOP_EXACT if args.stop == "exact" else ghn.GHN_STOP_PAPER
@@ -368,7 +420,26 @@ def main():
                       "kernel": "k_predict_group"},
             alg={"flops_per_step": flops, "issued_mfma_flops_per_step": 2.0 * (-(-3 * f // 32) * 32) * w["cands"]})
 
-    best = max(forms, key=lambda name: forms[name]["qps"])
+    if "brute" in args.forms:
+        # exhaustive KNN (the paper's comparison method) on the same GPU and index data
+        nws = ghn.ghn_predict_workspace_bytes(ix.handle, m, k, stop, ghn.GHN_PREC_BF16_MFMA, 0)
+        ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dev)
+
+        def stepb(evs):
+            ghn.ghn_bruteforce(ix.handle, qs, k, out_idx, out_pred, None, 0, None, ws, walk_events=evs)
+
+        ms, kern_ms, per = timed(stepb)
+        pairs = float(m) * float(prob.n)
+        flops = 2.0 * f * pairs
+        achieved = flops / (kern_ms * 1e-3) / 1e12
+        forms["bruteforce_bf16"] = dict(
+            qps=m / (ms * 1e-3), ms_per_step=ms, kernel_ms=kern_ms, per=per,
+            work=dict(cands=pairs, probes=0, layers=0.0),
+            roofline={"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": None, "kernel": "k_predict_group"},
+            alg={"flops_per_step": flops})
+    walk_forms = [name for name in forms if name != "bruteforce_bf16"]
+    best = max(walk_forms, key=lambda name: forms[name]["qps"])
     B = forms[best]
     line = {
         "metric": METRIC,

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "ghn_internal.h"
@@ -352,9 +353,6 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
             const uint32_t span = (uint32_t)(iv.cmax[j] - iv.cmin[j]);
             nbits += span ? 32 - __builtin_clz(span) : 0;
         }
-        if (nbits > 64)
-            return fail(GHN_E_KEY_OVERFLOW, "ghn_build: the Morton code of the cell ids needs %d bits (> 64); use a "
-                        "larger cell width", nbits);
     }
 
     // 3. keys, sort, gather
@@ -370,14 +368,36 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
     if (keep.alloc((void**)&spts, (size_t)n * f * 4) || keep.alloc((void**)&sid, (size_t)n * 4) ||
         keep.alloc(&tg, (size_t)n * 4))
         return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the index");
-    e = lookup == GHN_LOOKUP_DENSE ? launch_dense_keys(points, n, f, dtype, iv, keys, vals, s)
-                                   : launch_morton_keys(points, n, dtype, iv, keys, vals, s);
-    if (e != hipSuccess) return hip_fail(e, "ghn_build: keys");
-    bool in_alt = false;
-    if ((e = radix_sort_pairs(keys, vals, keys2, vals2, n, nbits, rtemp, &in_alt, s)) != hipSuccess)
-        return hip_fail(e, "ghn_build: radix sort");
-    const uint64_t* skeys = in_alt ? keys2 : keys;
-    const uint32_t* perm = in_alt ? vals2 : vals;
+    const uint64_t* skeys = nullptr;
+    const uint32_t* perm = nullptr;
+    if (lookup == GHN_LOOKUP_DENSE || nbits <= 64) {
+        e = lookup == GHN_LOOKUP_DENSE ? launch_dense_keys(points, n, f, dtype, iv, keys, vals, s)
+                                       : launch_morton_keys(points, n, dtype, iv, nbits, 0, nullptr, keys, vals, s);
+        if (e != hipSuccess) return hip_fail(e, "ghn_build: keys");
+        bool in_alt = false;
+        if ((e = radix_sort_pairs(keys, vals, keys2, vals2, n, nbits, rtemp, &in_alt, s)) != hipSuccess)
+            return hip_fail(e, "ghn_build: radix sort");
+        skeys = in_alt ? keys2 : keys;
+        perm = in_alt ? vals2 : vals;
+    } else {
+        // wide Morton codes: stable LSD sort one 64-bit word at a time, least significant
+        // word first, each pass recomputing its word in the order of the previous pass
+        uint64_t *ka = keys, *kb = keys2;
+        uint32_t *va = vals, *vb = vals2;
+        const int nw = (nbits + 63) / 64;
+        for (int w = nw - 1; w >= 0; --w) {
+            const int wbits = w == 0 ? nbits - 64 * (nw - 1) : 64;
+            if ((e = launch_morton_keys(points, n, dtype, iv, nbits, w, perm, ka, va, s)) != hipSuccess)
+                return hip_fail(e, "ghn_build: keys");
+            bool in_alt = false;
+            if ((e = radix_sort_pairs(ka, va, kb, vb, n, wbits, rtemp, &in_alt, s)) != hipSuccess)
+                return hip_fail(e, "ghn_build: radix sort");
+            if (in_alt) { std::swap(ka, kb); std::swap(va, vb); }
+            perm = va;  // the sorted order; the next word is written to the other buffers
+            std::swap(ka, kb);
+            std::swap(va, vb);
+        }
+    }
     if ((e = launch_gather_points(points, n, f, dtype, perm, spts, sid, s)) != hipSuccess) return hip_fail(e, "ghn_build: gather");
     if ((e = hipMemcpyAsync(tg, targets, (size_t)n * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(e, "ghn_build: targets");
     iv.spts = spts; iv.sid = sid; iv.targets = tg;
@@ -402,7 +422,8 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
     if (tmp.alloc((void**)&heads, n * 4) || tmp.alloc((void**)&rank, n * 4) ||
         tmp.alloc(&stemp, exclusive_scan_temp_bytes(n)))
         return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the cell list");
-    if ((e = launch_cell_heads(skeys, n, heads, s)) != hipSuccess) return hip_fail(e, "ghn_build: heads");
+    e = skeys ? launch_cell_heads(skeys, n, heads, s) : launch_cell_heads_ids(iv, n, heads, s);
+    if (e != hipSuccess) return hip_fail(e, "ghn_build: heads");
     if ((e = exclusive_scan_u32(heads, rank, n, stemp, s)) != hipSuccess) return hip_fail(e, "ghn_build: scan");
     uint32_t last[2] = {0, 0};
     if ((e = hipMemcpyAsync(&last[0], rank + n - 1, 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
@@ -608,7 +629,6 @@ static ghn_status predict_common(const ghn_index* index, const float* queries, i
         const int levels = brute ? 32 : o.stop == GHN_STOP_PAPER ? 0 : (o.group_levels >= 0 ? o.group_levels : (index->info.f >= 12 ? 3 : 1));
         int bits = 0;
         e = run_grouped(pa, levels, ws, s, &bits, (hipEvent_t)o.walk_event_begin, (hipEvent_t)o.walk_event_end, brute);
-        if (bits > 64) return fail(GHN_E_UNSUPPORTED, "ghn_predict: the Morton code of the cell ids needs %d bits (> 64)", bits);
         if (e != hipSuccess) return hip_fail(e, "ghn_predict: grouped walk");
         return GHN_OK;
     }

@@ -92,12 +92,14 @@ __global__ __launch_bounds__(256) void k_group_keys(const float* __restrict__ qs
                                                     uint32_t* __restrict__ qflags) {
     const int f = ix.f;
     int bits[F_MAX];
-    int maxb = 0;
+    int maxb = 0, total = 0;
     for (int j = 0; j < f; ++j) {
         const uint32_t span = (uint32_t)(ix.cmax[j] - ix.cmin[j]);
         bits[j] = span ? 32 - __clz(span) : 0;
         maxb = max(maxb, bits[j]);
+        total += bits[j];
     }
+    const int drop = total > 64 ? total - 64 : 0;
     for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
         uint32_t u[F_MAX];
         uint32_t fl = 0;
@@ -110,10 +112,14 @@ __global__ __launch_bounds__(256) void k_group_keys(const float* __restrict__ qs
             c = min(max(c, (int64_t)ix.cmin[j]), (int64_t)ix.cmax[j]);
             u[j] = (uint32_t)(c - ix.cmin[j]);
         }
-        uint64_t code = 0;
+        uint64_t code = 0;  // the top 64 bits of the code
+        int pos = total;
         for (int b = maxb - 1; b >= 0; --b)
             for (int j = 0; j < f; ++j)
-                if (b < bits[j]) code = (code << 1) | ((u[j] >> b) & 1u);
+                if (b < bits[j]) {
+                    --pos;
+                    if (pos >= drop) code = (code << 1) | ((u[j] >> b) & 1u);
+                }
         keys[i] = code;
         vals[i] = (uint32_t)i;
         qflags[i] = fl;
@@ -126,20 +132,35 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 
 // Cut the sorted queries into groups: a group starts where the (shifted) key
 // changes, at a query that walks alone, or every GQ positions.
+// Under the PAPER rule a group must share one central cell; when the sort key is a
+// truncated code (more than 64 bits), equal keys do not imply equal cells, so the
+// cell ids are compared too (`exact`).
+__device__ __forceinline__ bool same_cell(const float* qs, const IndexView& ix, uint32_t a, uint32_t b) {
+    for (int j = 0; j < ix.f; ++j) {
+        const double o = ix.o[j], w = ix.a[j];
+        if (exact_floor_div(__dadd_rn((double)qs[(int64_t)a * ix.f + j], -o), w) !=
+            exact_floor_div(__dadd_rn((double)qs[(int64_t)b * ix.f + j], -o), w))
+            return false;
+    }
+    return true;
+}
+
 __device__ __forceinline__ bool group_start(const uint64_t* keys, const uint32_t* vals, const uint32_t* qflags,
-                                            int64_t i, int shift) {
+                                            int64_t i, int shift, const float* qs, const IndexView& ix, bool exact) {
     if (i == 0 || (i % GQ) == 0) return true;
     if (qflags[vals[i]] || qflags[vals[i - 1]]) return true;
-    return shift < 64 && (keys[i] >> shift) != (keys[i - 1] >> shift);
+    if (shift < 64 && (keys[i] >> shift) != (keys[i - 1] >> shift)) return true;
+    return exact && !same_cell(qs, ix, vals[i], vals[i - 1]);
 }
 
 __global__ __launch_bounds__(256) void k_form_groups(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
                                                      const uint32_t* __restrict__ qflags, int64_t m, int shift,
+                                                     const float* __restrict__ qs, IndexView ix, int exact,
                                                      uint2* __restrict__ groups, uint32_t* ngroups) {
     for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
-        if (!group_start(keys, vals, qflags, i, shift)) continue;
+        if (!group_start(keys, vals, qflags, i, shift, qs, ix, exact)) continue;
         int64_t j = i + 1;
-        while (j < m && !group_start(keys, vals, qflags, j, shift)) ++j;
+        while (j < m && !group_start(keys, vals, qflags, j, shift, qs, ix, exact)) ++j;
         const uint32_t g = atomicAdd(ngroups, 1u);
         groups[g] = make_uint2((uint32_t)i, (uint32_t)(j - i));
     }
@@ -813,10 +834,12 @@ hipError_t run_grouped(const PredictArgs& pa, int keep_shift_levels, void* ws, h
         maxb = maxb > bits[j] ? maxb : bits[j];
     }
     *morton_bits = total;
-    if (total > 64) return hipErrorInvalidValue;
     int shift = 0;  // Morton bits of the lowest `keep_shift_levels` bit levels
     for (int b = 0; b < keep_shift_levels && b < maxb; ++b)
         for (int j = 0; j < ix.f; ++j) shift += bits[j] > b ? 1 : 0;
+    // codes wider than 64 bits are kept to their top 64 bits (coarser groups)
+    const int kbits = total > 64 ? 64 : total;
+    shift = total > 64 ? (shift > total - 64 ? shift - (total - 64) : 0) : shift;
     char* p = (char*)ws;
     uint64_t* k0 = (uint64_t*)p; p += up(m * 8);
     uint64_t* k1 = (uint64_t*)p; p += up(m * 8);
@@ -831,11 +854,13 @@ hipError_t run_grouped(const PredictArgs& pa, int keep_shift_levels, void* ws, h
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counters, 2);
     hipLaunchKernelGGL(k_group_keys, dim3((unsigned)g), dim3(256), 0, s, pa.io.queries, m, ix, k0, v0, qflags);
     bool alt = false;
-    hipError_t e = radix_sort_pairs(k0, v0, k1, v1, m, total, rtemp, &alt, s);
+    hipError_t e = radix_sort_pairs(k0, v0, k1, v1, m, kbits, rtemp, &alt, s);
     if (e != hipSuccess) return e;
     const uint64_t* sk = alt ? k1 : k0;
     const uint32_t* sv = alt ? v1 : v0;
-    hipLaunchKernelGGL(k_form_groups, dim3((unsigned)g), dim3(256), 0, s, sk, sv, qflags, m, shift, groups, counters);
+    const int exact = pa.stop == GHN_STOP_PAPER && total > 64 ? 1 : 0;
+    hipLaunchKernelGGL(k_form_groups, dim3((unsigned)g), dim3(256), 0, s, sk, sv, qflags, m, shift, pa.io.queries,
+                       ix, exact, groups, counters);
     GroupArgs ga;
     ga.brute = brute ? 1 : 0;
     ga.p = pa;

@@ -155,8 +155,9 @@ hipError_t launch_dense_cell_start(const uint64_t* sorted_keys, int64_t n, int64
 hipError_t launch_cell_stats(const uint32_t* cell_start, int64_t ncells, int64_t* d_stats, hipStream_t s);
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* temp, hipStream_t s);
 size_t exclusive_scan_temp_bytes(int64_t n);
-hipError_t launch_morton_keys(const void* pts, int64_t n, int32_t dtype, const IndexView& iv, uint64_t* keys,
-                              uint32_t* vals, hipStream_t s);
+hipError_t launch_morton_keys(const void* pts, int64_t n, int32_t dtype, const IndexView& iv, int nbits, int word,
+                              const uint32_t* order, uint64_t* keys, uint32_t* vals, hipStream_t s);
+hipError_t launch_cell_heads_ids(const IndexView& iv, int64_t n, uint32_t* heads, hipStream_t s);
 hipError_t launch_cell_heads(const uint64_t* sorted_keys, int64_t n, uint32_t* heads, hipStream_t s);
 hipError_t launch_cell_list(const uint32_t* heads, const uint32_t* rank, int64_t n, const IndexView& iv,
                             uint32_t* cell_start, int32_t* cell_coord, hipStream_t s);

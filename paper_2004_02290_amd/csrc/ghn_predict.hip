@@ -45,10 +45,14 @@ __global__ __launch_bounds__(256) void k_query_keys(const float* __restrict__ qs
             c = min(max(c, (int64_t)ix.cmin[j]), (int64_t)ix.cmax[j]);
             u[j] = (uint32_t)(c - ix.cmin[j]);
         }
+        int pos = total;  // only the top keep_bits bits of the code are formed
         for (int b = maxb - 1; b >= 0; --b)
             for (int j = 0; j < f; ++j)
-                if (b < bits[j]) code = (code << 1) | ((u[j] >> b) & 1u);
-        keys[i] = code >> drop;
+                if (b < bits[j]) {
+                    --pos;
+                    if (pos >= drop) code = (code << 1) | ((u[j] >> b) & 1u);
+                }
+        keys[i] = code;
         vals[i] = (uint32_t)i;
     }
 }

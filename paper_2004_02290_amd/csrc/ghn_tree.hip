@@ -25,9 +25,12 @@ __device__ __forceinline__ float load_coord(const void* pts, int64_t idx, int32_
     return ((const float*)pts)[idx];
 }
 
-// Morton code of every point's cell: bit b of dimension j (ids relative to the
-// box minimum) for b from the top down, dimensions in order inside each bit.
+// Morton code of a cell: bit b of dimension j (ids relative to the box minimum)
+// for b from the top down, dimensions in order inside each bit; nbits bits in all.
+// Codes wider than 64 bits are handled a 64-bit word at a time: word w (0 = the
+// most significant) holds code bits [64 (W - 1 - w), 64 (W - w)), W = ceil(nbits / 64).
 __global__ __launch_bounds__(BT) void k_morton_keys(const void* pts, int64_t n, int32_t dtype, IndexView iv,
+                                                    int nbits, int word, const uint32_t* __restrict__ order,
                                                     uint64_t* keys, uint32_t* vals) {
     const int f = iv.f;
     int bits[F_MAX];
@@ -37,19 +40,40 @@ __global__ __launch_bounds__(BT) void k_morton_keys(const void* pts, int64_t n, 
         bits[j] = span ? 32 - __clz(span) : 0;
         maxb = max(maxb, bits[j]);
     }
+    const int nw = (nbits + 63) / 64;
+    const int lo = 64 * (nw - 1 - word), hi = min(lo + 64, nbits);
     for (int64_t i = blockIdx.x * (int64_t)BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) {
+        const uint32_t p = order ? order[i] : (uint32_t)i;
         uint32_t u[F_MAX];
         for (int j = 0; j < f; ++j) {
-            const float x = load_coord(pts, i * f + j, dtype);
+            const float x = load_coord(pts, (int64_t)p * f + j, dtype);
             const int64_t c = exact_floor_div(__dadd_rn((double)x, -(double)iv.o[j]), (double)iv.a[j]);
             u[j] = (uint32_t)(c - iv.cmin[j]);
         }
         uint64_t code = 0;
+        int pos = nbits;
         for (int b = maxb - 1; b >= 0; --b)
             for (int j = 0; j < f; ++j)
-                if (b < bits[j]) code = (code << 1) | ((u[j] >> b) & 1u);
+                if (b < bits[j]) {
+                    --pos;
+                    if (pos >= lo && pos < hi) code = (code << 1) | ((u[j] >> b) & 1u);
+                }
         keys[i] = code;
-        vals[i] = (uint32_t)i;
+        vals[i] = p;
+    }
+}
+
+// Cell boundaries of points in cell order, from their cell ids (any code width).
+__global__ __launch_bounds__(BT) void k_cell_heads_ids(IndexView iv, int64_t n, uint32_t* heads) {
+    const int f = iv.f;
+    for (int64_t i = blockIdx.x * (int64_t)BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) {
+        bool head = i == 0;
+        for (int j = 0; j < f && !head; ++j) {
+            const double o = iv.o[j], a = iv.a[j];
+            head = exact_floor_div(__dadd_rn((double)iv.spts[i * f + j], -o), a) !=
+                   exact_floor_div(__dadd_rn((double)iv.spts[(i - 1) * f + j], -o), a);
+        }
+        heads[i] = head ? 1u : 0u;
     }
 }
 
@@ -123,9 +147,15 @@ int grid_for(int64_t work, int threads, int cap = 65536) {
 
 }  // namespace
 
-hipError_t launch_morton_keys(const void* pts, int64_t n, int32_t dtype, const IndexView& iv, uint64_t* keys,
-                              uint32_t* vals, hipStream_t s) {
-    hipLaunchKernelGGL(k_morton_keys, dim3(grid_for(n, BT)), dim3(BT), 0, s, pts, n, dtype, iv, keys, vals);
+hipError_t launch_morton_keys(const void* pts, int64_t n, int32_t dtype, const IndexView& iv, int nbits, int word,
+                              const uint32_t* order, uint64_t* keys, uint32_t* vals, hipStream_t s) {
+    hipLaunchKernelGGL(k_morton_keys, dim3(grid_for(n, BT)), dim3(BT), 0, s, pts, n, dtype, iv, nbits, word, order,
+                       keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_heads_ids(const IndexView& iv, int64_t n, uint32_t* heads, hipStream_t s) {
+    hipLaunchKernelGGL(k_cell_heads_ids, dim3(grid_for(n, BT)), dim3(BT), 0, s, iv, n, heads);
     return hipGetLastError();
 }
 

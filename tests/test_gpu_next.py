@@ -1,5 +1,6 @@
-"""GPU results against the CPU oracle for the paper's cell measurement rule, the
-median statistic and exhaustive KNN, element by element (bit-identical)."""
+"""GPU results against the CPU oracle for the paper's cell measurement rule (and
+the wide cell codes its fine grids need), the median statistic and exhaustive
+KNN, element by element (bit-identical)."""
 import numpy as np
 import pytest
 
@@ -110,6 +111,31 @@ def test_paper_widths_build_and_predict(ghn):
     got = _host(ix.predict(q, prob.k, stop=ghn.GHN_STOP_EXACT))
     bi, bd, bp = oracle.bruteforce(prob.points, prob.targets, prob.task, prob.queries, prob.k)
     _same(got, dict(idx=bi, d2=bd, pred=bp), "EXACT with measured widths")
+
+
+@pytest.mark.parametrize("f,n,m,width", [(8, 6000, 400, 0.0025), (16, 4000, 300, 0.01), (32, 1500, 200, 0.05)])
+def test_wide_cell_codes(ghn, f, n, m, width):
+    # fine grids (such as the paper's rule gives on clustered data) whose Morton codes need
+    # more than 64 bits: multi-word sort on build, top-64-bit keys for query order and groups
+    rng = np.random.default_rng(f)
+    c = rng.random((4, f))
+    pts = (c[rng.integers(0, 4, n)] + rng.normal(0, 0.01, (n, f))).astype(np.float32)
+    qs = (c[rng.integers(0, 4, m)] + rng.normal(0, 0.02, (m, f))).astype(np.float32)
+    lab = rng.integers(0, 5, n).astype(np.int32)
+    cid = np.floor(pts.astype(np.float64) / width).astype(np.int64)
+    bits = sum(int(x).bit_length() for x in cid.max(0) - cid.min(0))
+    assert bits > 64, bits
+    ix = ghn.Index(_dev(pts), _dev(lab), 0, width)
+    assert ix.info.lookup == 1
+    k = 7
+    bi, bd, bp = oracle.bruteforce(pts, lab, 0, qs, k)
+    want_paper = oracle.Grid(pts, lab, 0, width).predict(qs, k, oracle.STOP_PAPER)
+    for prec in (0, 1):
+        got = _host(ix.predict(_dev(qs), k, prec=prec))
+        _same(got, dict(idx=bi, d2=bd, pred=bp), "wide f=%d EXACT prec=%d" % (f, prec))
+        got = _host(ix.predict(_dev(qs), k, stop=ghn.GHN_STOP_PAPER, prec=prec, with_stats=True))
+        _same(got, want_paper, "wide f=%d PAPER prec=%d" % (f, prec))
+        assert np.array_equal(got["stop_layer"], want_paper["stop_layer"])
 
 
 def test_cell_measure_errors(ghn):

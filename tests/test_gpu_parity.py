@@ -269,10 +269,8 @@ def test_build_errors(ghn):
     assert e.value.code == -2
     ix = ghn.Index(_dev(spread), _dev(lab), 0, 0.01)  # automatic choice falls back to the tree
     assert ix.info.lookup == 1
-    wide = np.random.default_rng(1).random((200, 32)).astype(np.float32)  # 32 dims x 4 bits > 64
-    with pytest.raises(ghn.GHNError) as e:
-        ghn.Index(_dev(wide), _dev(np.zeros(200, np.int32)), 0, 0.1)
-    assert e.value.code == -5
+    wide = np.random.default_rng(1).random((200, 32)).astype(np.float32)  # 32 dims x 4 bits: 128-bit codes
+    assert ghn.Index(_dev(wide), _dev(np.zeros(200, np.int32)), 0, 0.1).info.lookup == 1
     with pytest.raises(ghn.GHNError) as e:
         ghn.Index(_dev(pts), _dev(lab), 0, 0.1, lookup=7)
     assert e.value.code == -1
