@@ -139,6 +139,12 @@ def paper_study(args, ghn, W, torch):
     measure_ms = (time.perf_counter() - t0) * 1e3
     rows = []
     for label, widths, origin in (("paper_rule_widths", w, o), ("about_8_per_cell", prob.cell_width, None)):
+        print("paper study: %s grid" % label, file=sys.stderr, flush=True)
+        if label == "paper_rule_widths" and int(splits.max()) > 4096:
+            # a query in a sparse region walks about (neighbour radius / finest width) layers
+            rows.append({"grid": label, "skipped": "the rule gives %d splits in a dimension (width %.3g); queries in "
+                         "sparse regions would walk thousands of layers" % (int(splits.max()), float(w.min()))})
+            continue
         try:
             ix = ghn.Index(pts, tgt, prob.task, widths, origin)
         except ghn.GHNError as e:  # e.g. cell ids too wide for the 64-bit Morton key of the tree
