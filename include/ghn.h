@@ -305,6 +305,34 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
 ghn_status ghn_cell_measure(const void* points, int64_t n, int32_t f, int32_t dtype, float* out_width,
                             float* out_origin, int64_t* out_splits, void* stream);
 
+/* ---- persistence and insertion ---------------------------------------------------
+ * The model of the method is the training data plus the grid parameters (Section
+ * III-A, Algorithm 1); the grid itself is rebuilt from them, deterministically.
+ *
+ * ghn_index_save writes an index into HOST memory (ghn_index_save_bytes(index)
+ * bytes): a versioned header (cell widths, origin, task, lookup, dtype), the
+ * points in their original row order as float32 (bf16 points widen exactly) and
+ * the targets.  ghn_index_load rebuilds the index from such a buffer (HOST);
+ * predictions of the loaded index equal those of the saved one.  Both
+ * synchronise `stream`.  Errors: GHN_E_INVALID_ARG (NULL, bad magic, version or
+ * size), GHN_E_WORKSPACE (save buffer too small), GHN_E_NOMEM, GHN_E_HIP, and
+ * ghn_build's errors on load. */
+size_t ghn_index_save_bytes(const ghn_index* index);
+ghn_status ghn_index_save(const ghn_index* index, void* buffer, size_t bytes, void* stream);
+ghn_status ghn_index_load(const void* buffer, size_t bytes, void* stream, ghn_index** out);
+
+/* Insert n_new training points (DEVICE, n_new x f, float32 or bf16 bits) and their
+ * targets (DEVICE, int32 labels or float32 values as the index's task) into an
+ * index: Algorithm 1 appends every point to its cell.  The new points get row
+ * ids n .. n + n_new - 1.  The index is rebuilt with its cell widths, origin and
+ * lookup choice (GHN_LOOKUP_AUTO may pick the other lookup if the occupied box
+ * grew), so the result equals ghn_build on all points; the cost is one build of
+ * n + n_new points.  The handle stays valid (its device memory is replaced:
+ * batches prepared with it must be prepared again); on error the index is
+ * unchanged.  Synchronises `stream`.  Errors: as ghn_build. */
+ghn_status ghn_insert(ghn_index* index, const void* points, int64_t n_new, int32_t dtype, const void* targets,
+                      void* stream);
+
 /* Last error message of the calling thread ("" if none).  Valid until the
  * thread's next failing call. */
 const char* ghn_last_error(void);

@@ -38,7 +38,7 @@ P_ = ctypes.c_void_p
 EXPORTED = ["ghn_build", "ghn_build_ex", "ghn_index_get_info", "ghn_destroy", "ghn_predict_workspace_bytes", "ghn_predict",
             "ghn_query_order_workspace_bytes", "ghn_query_order", "ghn_batch_workspace_bytes", "ghn_batch_prepare",
             "ghn_predict_batched", "ghn_batch_destroy", "ghn_autotune", "ghn_cell_measure", "ghn_bruteforce",
-            "ghn_last_error"]
+            "ghn_index_save_bytes", "ghn_index_save", "ghn_index_load", "ghn_insert", "ghn_last_error"]
 
 
 class GHNError(RuntimeError):
@@ -115,6 +115,14 @@ def _load() -> ctypes.CDLL:
     L.ghn_autotune.restype = ctypes.c_int
     L.ghn_bruteforce.argtypes = [P, P, I64, I32, ctypes.POINTER(ghn_predict_opts), P, P, P, P, SZ, P]
     L.ghn_bruteforce.restype = ctypes.c_int
+    L.ghn_index_save_bytes.argtypes = [P]
+    L.ghn_index_save_bytes.restype = SZ
+    L.ghn_index_save.argtypes = [P, P, SZ, P]
+    L.ghn_index_save.restype = ctypes.c_int
+    L.ghn_index_load.argtypes = [P, SZ, P, ctypes.POINTER(P)]
+    L.ghn_index_load.restype = ctypes.c_int
+    L.ghn_insert.argtypes = [P, P, I64, I32, P, P]
+    L.ghn_insert.restype = ctypes.c_int
     L.ghn_cell_measure.argtypes = [P, I64, I32, I32, P, P, P, P]
     L.ghn_cell_measure.restype = ctypes.c_int
     L.ghn_last_error.argtypes = []
@@ -308,6 +316,28 @@ def ghn_autotune(points: torch.Tensor, targets: torch.Tensor, task: int, queries
     return best.as_dict(), [trials[i].as_dict() for i in range(min(nt.value, max_trials))]
 
 
+def ghn_index_save(handle, stream=None) -> bytes:
+    """ghn_index_save: the index as bytes (header, points in original order, targets)."""
+    nbytes = int(_lib.ghn_index_save_bytes(handle))
+    buf = ctypes.create_string_buffer(nbytes)
+    _check(_lib.ghn_index_save(handle, ctypes.cast(buf, P_), nbytes, _stream(stream)))
+    return buf.raw
+
+
+def ghn_index_load(data: bytes, stream=None):
+    """ghn_index_load: a handle rebuilt from ghn_index_save's bytes."""
+    h = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(data, len(data))
+    _check(_lib.ghn_index_load(ctypes.cast(buf, P_), len(data), _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def ghn_insert(handle, points: torch.Tensor, targets: torch.Tensor, stream=None) -> None:
+    """ghn_insert: append points (n_new x f, float32 or bfloat16) and their targets to an index."""
+    dtype = GHN_BF16 if points.dtype == torch.bfloat16 else GHN_F32
+    _check(_lib.ghn_insert(handle, _ptr(points), points.shape[0], dtype, _ptr(targets), _stream(stream)))
+
+
 def ghn_cell_measure(points: torch.Tensor, stream=None):
     """ghn_cell_measure: the paper's cell measurements -> (width float32[f], origin float32[f], splits int64[f])."""
     n, f = points.shape
@@ -348,6 +378,24 @@ class Index:
         ghn_predict(self.handle, queries, k, out["idx"], out["pred"], out.get("d2"), stop, prec, flags,
                     out.get("stop_layer"), out.get("cands"), out.get("probes"), ws, None, group_levels, stream)
         return out
+
+    @classmethod
+    def load(cls, data: bytes, stream=None) -> "Index":
+        """An index rebuilt from save()'s bytes."""
+        self = cls.__new__(cls)
+        self.handle = ghn_index_load(data, stream)
+        self.info = ghn_index_get_info(self.handle)
+        self.task = self.info.task
+        return self
+
+    def save(self, stream=None) -> bytes:
+        return ghn_index_save(self.handle, stream)
+
+    def insert(self, points: torch.Tensor, targets: torch.Tensor, stream=None) -> None:
+        if points.dim() != 2 or points.shape[1] != self.info.f or targets.shape[0] != points.shape[0]:
+            raise ValueError("insert: points must be n_new x %d with n_new targets" % self.info.f)
+        ghn_insert(self.handle, points, targets, stream)
+        self.info = ghn_index_get_info(self.handle)
 
     def bruteforce(self, queries: torch.Tensor, k: int, flags=0, with_d2: bool = True, with_stats: bool = False,
                    stream=None):

@@ -15,6 +15,7 @@ struct ghn_index {
     ghn::IndexView* view_dev;  // device copy of `view` (for batched launches)
     ghn_index_info info;
     std::vector<void*> allocs;
+    int32_t want_lookup;       // the lookup asked for at build (GHN_LOOKUP_AUTO may re-choose on insert)
 };
 
 struct ghn_batch {
@@ -502,6 +503,7 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
     ix->info.device_bytes = (size_t)n * f * 4 + (size_t)n * 4 + (size_t)n * 4 + table_bytes +
                            (size_t)n * 2 * iv.sp * 2 + (size_t)n * 4;
     keep.release(ix->allocs);
+    ix->want_lookup = want_lookup;
     *out = ix;
     return GHN_OK;
 }
@@ -660,6 +662,147 @@ ghn_status ghn_bruteforce(const ghn_index* index, const float* queries, int64_t 
                           const ghn_predict_opts* opts, int64_t* out_idx, double* out_d2, void* out_pred, void* ws,
                           size_t ws_bytes, void* stream) {
     return predict_common(index, queries, m, k, opts, out_idx, out_d2, out_pred, ws, ws_bytes, stream, true);
+}
+
+// ---- persistence and insertion: the model is the training data plus the grid
+// parameters (Section III-A); the grid is rebuilt from them, deterministically.
+
+namespace {
+
+struct SavedHeader {
+    char magic[8];           // "GHNIDX01"
+    uint32_t version;        // 1
+    int32_t f;
+    int64_t n;
+    int32_t dtype;           // ghn_dtype of the points as built
+    int32_t task;
+    int32_t want_lookup;
+    int32_t reserved;
+    float width[GHN_F_MAX];
+    float origin[GHN_F_MAX];
+};
+static_assert(sizeof(SavedHeader) == 296, "saved index header layout");
+
+// Points of an index in their original row order (float32, n x f) into `out`.
+hipError_t original_points(const ghn_index* index, float* out, hipStream_t s) {
+    return ghn::launch_unsort_points(index->view.spts, index->view.sid, index->info.n, index->info.f, out, s);
+}
+
+// Replace the contents of `dst` by those of `src` (which is consumed).
+void adopt(ghn_index* dst, ghn_index* src) {
+    for (void* p : dst->allocs) (void)hipFree(p);
+    *dst = *src;
+    src->allocs.clear();
+    delete src;
+}
+
+}  // namespace
+
+size_t ghn_index_save_bytes(const ghn_index* index) {
+    if (!index) return 0;
+    return sizeof(SavedHeader) + (size_t)index->info.n * index->info.f * 4 + (size_t)index->info.n * 4;
+}
+
+ghn_status ghn_index_save(const ghn_index* index, void* buffer, size_t bytes, void* stream) {
+    using namespace ghn;
+    if (!index || !buffer) return fail(GHN_E_INVALID_ARG, "ghn_index_save: NULL argument");
+    const size_t need = ghn_index_save_bytes(index);
+    if (bytes < need) return fail(GHN_E_WORKSPACE, "ghn_index_save: %zu bytes needed, %zu given", need, bytes);
+    const int64_t n = index->info.n;
+    const int32_t f = index->info.f;
+    SavedHeader h;
+    std::memset(&h, 0, sizeof h);
+    std::memcpy(h.magic, "GHNIDX01", 8);
+    h.version = 1;
+    h.f = f;
+    h.n = n;
+    h.dtype = index->info.dtype;
+    h.task = index->info.task;
+    h.want_lookup = index->want_lookup;
+    for (int j = 0; j < f; ++j) { h.width[j] = index->info.cell_width[j]; h.origin[j] = index->info.origin[j]; }
+    hipStream_t s = (hipStream_t)stream;
+    DevPool tmp;
+    float* pts = nullptr;
+    if (tmp.alloc((void**)&pts, (size_t)n * f * 4)) return fail(GHN_E_NOMEM, "ghn_index_save: out of device memory");
+    char* out = (char*)buffer;
+    std::memcpy(out, &h, sizeof h);
+    hipError_t e;
+    if ((e = original_points(index, pts, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(out + sizeof h, pts, (size_t)n * f * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(out + sizeof h + (size_t)n * f * 4, index->view.targets, (size_t)n * 4,
+                            hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "ghn_index_save");
+    return GHN_OK;
+}
+
+ghn_status ghn_index_load(const void* buffer, size_t bytes, void* stream, ghn_index** out) {
+    using namespace ghn;
+    if (!out) return fail(GHN_E_INVALID_ARG, "ghn_index_load: out is NULL");
+    *out = nullptr;
+    if (!buffer || bytes < sizeof(SavedHeader)) return fail(GHN_E_INVALID_ARG, "ghn_index_load: buffer too small");
+    SavedHeader h;
+    std::memcpy(&h, buffer, sizeof h);
+    if (std::memcmp(h.magic, "GHNIDX01", 8) != 0 || h.version != 1)
+        return fail(GHN_E_INVALID_ARG, "ghn_index_load: not a saved index (bad magic or version)");
+    if (h.f < 1 || h.f > GHN_F_MAX || h.n < 1 || h.n >= (int64_t(1) << 31))
+        return fail(GHN_E_INVALID_ARG, "ghn_index_load: corrupt header (n=%lld, f=%d)", (long long)h.n, h.f);
+    const size_t need = sizeof h + (size_t)h.n * h.f * 4 + (size_t)h.n * 4;
+    if (bytes < need) return fail(GHN_E_INVALID_ARG, "ghn_index_load: %zu bytes needed, %zu given", need, bytes);
+    hipStream_t s = (hipStream_t)stream;
+    DevPool tmp;
+    void *pts = nullptr, *tg = nullptr;
+    if (tmp.alloc(&pts, (size_t)h.n * h.f * 4) || tmp.alloc(&tg, (size_t)h.n * 4))
+        return fail(GHN_E_NOMEM, "ghn_index_load: out of device memory");
+    const char* in = (const char*)buffer;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(pts, in + sizeof h, (size_t)h.n * h.f * 4, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(tg, in + sizeof h + (size_t)h.n * h.f * 4, (size_t)h.n * 4, hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+        return hip_fail(e, "ghn_index_load: upload");
+    ghn_build_opts bo = {h.want_lookup};
+    ghn_status st = ghn_build_ex(pts, h.n, h.f, GHN_F32, tg, h.task, h.width, h.f, h.origin, &bo, stream, out);
+    if (st != GHN_OK) return st;
+    (*out)->info.dtype = h.dtype;
+    return GHN_OK;
+}
+
+ghn_status ghn_insert(ghn_index* index, const void* points, int64_t n_new, int32_t dtype, const void* targets,
+                      void* stream) {
+    using namespace ghn;
+    if (!index) return fail(GHN_E_INVALID_ARG, "ghn_insert: index is NULL");
+    if (n_new < 0) return fail(GHN_E_INVALID_ARG, "ghn_insert: n_new < 0");
+    if (n_new == 0) return GHN_OK;
+    if (!points || !targets) return fail(GHN_E_INVALID_ARG, "ghn_insert: points and targets must not be NULL");
+    if (dtype != GHN_F32 && dtype != GHN_BF16) return fail(GHN_E_INVALID_ARG, "ghn_insert: bad dtype %d", dtype);
+    if (((uintptr_t)points % (dtype == GHN_BF16 ? 2 : 4)) || ((uintptr_t)targets % 4))
+        return fail(GHN_E_INVALID_ARG, "ghn_insert: misaligned points or targets");
+    const int64_t n = index->info.n, total = n + n_new;
+    const int32_t f = index->info.f;
+    if (total >= (int64_t(1) << 31)) return fail(GHN_E_INVALID_ARG, "ghn_insert: %lld points in all (>= 2^31)", (long long)total);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "ghn_insert: pending HIP error");
+    hipStream_t s = (hipStream_t)stream;
+    DevPool tmp;
+    float* pts = nullptr;
+    void* tg = nullptr;
+    if (tmp.alloc((void**)&pts, (size_t)total * f * 4) || tmp.alloc(&tg, (size_t)total * 4))
+        return fail(GHN_E_NOMEM, "ghn_insert: out of device memory");
+    if ((e = original_points(index, pts, s)) != hipSuccess ||
+        (e = launch_widen_points(points, n_new * f, dtype, pts + (size_t)n * f, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(tg, index->view.targets, (size_t)n * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync((char*)tg + (size_t)n * 4, targets, (size_t)n_new * 4, hipMemcpyDeviceToDevice, s)) !=
+            hipSuccess)
+        return hip_fail(e, "ghn_insert: staging");
+    ghn_build_opts bo = {index->want_lookup};
+    ghn_index* fresh = nullptr;
+    const ghn_status st = ghn_build_ex(pts, total, f, GHN_F32, tg, index->info.task, index->info.cell_width, f,
+                                       index->info.origin, &bo, stream, &fresh);
+    if (st != GHN_OK) return st;  // the index is left as it was
+    const int32_t dt = index->info.dtype == GHN_BF16 && dtype == GHN_BF16 ? GHN_BF16 : GHN_F32;
+    adopt(index, fresh);
+    index->info.dtype = dt;
+    return GHN_OK;
 }
 
 }  // extern "C"

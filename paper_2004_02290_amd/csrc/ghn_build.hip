@@ -226,6 +226,19 @@ __global__ __launch_bounds__(BT) void k_gather_points(const void* pts, int64_t n
     }
 }
 
+// Points back in their original row order: out[sid[r]] = spts[r].
+__global__ __launch_bounds__(BT) void k_unsort_points(const float* __restrict__ spts, const int32_t* __restrict__ sid,
+                                                      int64_t n, int32_t f, float* __restrict__ out) {
+    for (int64_t r = blockIdx.x * (int64_t)BT + threadIdx.x; r < n; r += (int64_t)gridDim.x * BT)
+        for (int j = 0; j < f; ++j) out[(int64_t)sid[r] * f + j] = spts[r * f + j];
+}
+
+// Points as float32 (bf16 widened exactly).
+__global__ __launch_bounds__(BT) void k_widen_points(const void* pts, int64_t count, int32_t dtype, float* __restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)BT + threadIdx.x; i < count; i += (int64_t)gridDim.x * BT)
+        out[i] = load_coord(pts, i, dtype);
+}
+
 // bf16 round to nearest, ties to even, of a finite float.
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
     const uint32_t u = __float_as_uint(x);
@@ -353,6 +366,16 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void
 hipError_t launch_gather_points(const void* pts, int64_t n, int32_t f, int32_t dtype, const uint32_t* perm,
                                 float* spts, int32_t* sid, hipStream_t s) {
     hipLaunchKernelGGL(k_gather_points, dim3(grid_for(n, BT)), dim3(BT), 0, s, pts, n, f, dtype, perm, spts, sid);
+    return hipGetLastError();
+}
+
+hipError_t launch_unsort_points(const float* spts, const int32_t* sid, int64_t n, int32_t f, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_unsort_points, dim3(grid_for(n, BT)), dim3(BT), 0, s, spts, sid, n, f, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_widen_points(const void* pts, int64_t count, int32_t dtype, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_widen_points, dim3(grid_for(count, BT)), dim3(BT), 0, s, pts, count, dtype, out);
     return hipGetLastError();
 }
 

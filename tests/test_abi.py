@@ -84,3 +84,14 @@ def test_predict_rejects_null_index(ghn):
 
 def test_destroy_null_is_noop(ghn):
     ghn.lib().ghn_destroy(None)
+
+
+def test_load_rejects_bad_buffers(ghn):
+    lib = ghn._lib
+    out = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(b"not an index" * 40)
+    assert lib.ghn_index_load(ctypes.cast(buf, ctypes.c_void_p), 12, None, ctypes.byref(out)) == -1
+    assert lib.ghn_index_load(ctypes.cast(buf, ctypes.c_void_p), len(buf), None, ctypes.byref(out)) == -1
+    assert not out.value
+    assert lib.ghn_index_save_bytes(None) == 0
+    assert lib.ghn_insert(None, None, 1, 0, None, None) == -1

@@ -218,3 +218,71 @@ def test_bruteforce_ties_k_range_and_median(ghn):
     got = _host(rix.bruteforce(_dev(r.queries), 12, flags=ghn.GHN_FLAG_MEDIAN))
     bi, bd, bp = oracle.bruteforce(r.points, r.targets, oracle.REGRESS_MEDIAN, r.queries, 12)
     _same(got, dict(idx=bi, d2=bd, pred=bp), "lattice bruteforce median")
+
+
+# ----------------------------------------------------------------------- save / load / insert
+def _all_forms(ghn, ix, q, k):
+    out = {}
+    for stop in (ghn.GHN_STOP_EXACT, ghn.GHN_STOP_PAPER):
+        for prec in (0, 1):
+            out[(stop, prec)] = _host(ix.predict(q, k, stop=stop, prec=prec, with_stats=True))
+    return out
+
+
+@pytest.mark.parametrize("name,n,m", [("clusters4d", 40_000, 800), ("bf16_16d", 20_000, 300)])
+def test_save_load_roundtrip(ghn, name, n, m):
+    prob = W.make(name, n=n, m=m)
+    ix = ghn.Index(_pts(prob), _dev(prob.targets), prob.task, prob.cell_width)
+    data = ix.save()
+    back = ghn.Index.load(data)
+    for key in ("n", "f", "dtype", "task", "lookup", "num_cells"):
+        assert getattr(back.info, key) == getattr(ix.info, key), key
+    q = _dev(prob.queries)
+    a, b = _all_forms(ghn, ix, q, prob.k), _all_forms(ghn, back, q, prob.k)
+    for key in a:
+        _same(b[key], a[key], "%s loaded %s" % (name, key), keys=("idx", "d2", "pred", "stop_layer"))
+
+
+def test_insert_matches_fresh_build(ghn):
+    import torch
+    prob = W.make("clusters4d", n=30_000, m=600)
+    pts, tgt = prob.points, prob.targets
+    # the last chunk lies partly outside the first chunk's box, so the box grows
+    extra = (pts[:2000] * 1.7 - 0.3).astype(np.float32)
+    all_pts = np.concatenate([pts, extra])
+    all_tgt = np.concatenate([tgt, tgt[:2000]])
+    cut = [0, 18_000, 27_000, all_pts.shape[0]]
+    ix = ghn.Index(_dev(all_pts[:cut[1]]), _dev(all_tgt[:cut[1]]), prob.task, prob.cell_width)
+    for a, b in zip(cut[1:-1], cut[2:]):
+        ix.insert(_dev(all_pts[a:b]), _dev(all_tgt[a:b]))
+    assert ix.info.n == all_pts.shape[0]
+    fresh = ghn.Index(_dev(all_pts), _dev(all_tgt), prob.task, prob.cell_width)
+    assert ix.info.num_cells == fresh.info.num_cells and ix.info.lookup == fresh.info.lookup
+    q = _dev(prob.queries)
+    a, b = _all_forms(ghn, ix, q, prob.k), _all_forms(ghn, fresh, q, prob.k)
+    for key in a:
+        _same(a[key], b[key], "inserted vs fresh %s" % (key,), keys=("idx", "d2", "pred", "stop_layer"))
+    bi, bd, bp = oracle.bruteforce(all_pts, all_tgt, prob.task, prob.queries, prob.k)
+    _same(a[(ghn.GHN_STOP_EXACT, 0)], dict(idx=bi, d2=bd, pred=bp), "inserted EXACT vs oracle")
+    want = oracle.Grid(all_pts, all_tgt, prob.task, prob.cell_width).predict(prob.queries, prob.k, oracle.STOP_PAPER)
+    _same(a[(ghn.GHN_STOP_PAPER, 0)], want, "inserted PAPER vs oracle", keys=("idx", "d2", "pred", "stop_layer"))
+    with pytest.raises(ValueError):
+        ix.insert(_dev(all_pts[:5, :3]), _dev(all_tgt[:5]))
+
+
+def test_insert_bf16_and_bad_load(ghn):
+    import torch
+    prob = W.make("bf16_16d", n=12_000, m=200)
+    half = prob.n // 2
+    ix = ghn.Index(_dev(prob.points[:half].view(np.int16)).view(torch.bfloat16), _dev(prob.targets[:half]),
+                   prob.task, prob.cell_width)
+    ix.insert(_dev(prob.points[half:].view(np.int16)).view(torch.bfloat16), _dev(prob.targets[half:]))
+    assert ix.info.dtype == ghn.GHN_BF16
+    got = _host(ix.predict(_dev(prob.queries), prob.k))
+    bi, bd, bp = oracle.bruteforce(prob.points_f32(), prob.targets, prob.task, prob.queries, prob.k)
+    _same(got, dict(idx=bi, d2=bd, pred=bp), "bf16 insert")
+    data = bytearray(ix.save())
+    data[0] ^= 0xFF
+    with pytest.raises(ghn.GHNError) as e:
+        ghn.Index.load(bytes(data))
+    assert e.value.code == -1
