@@ -330,6 +330,7 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
     bool too_big = false;
     for (int j = f - 1; j >= 0; --j) {
         iv.a[j] = a[j];
+        iv.ainv[j] = 1.0 / (double)a[j];
         iv.o[j] = o[j];
         iv.cmin[j] = h.minmax[j];
         iv.cmax[j] = h.minmax[F_MAX + j];

@@ -45,6 +45,7 @@ struct IndexView {
     const int32_t* node_lo;     // per node, f lowest cell ids of its subtree
     const int32_t* node_hi;     // per node, f highest cell ids
     float a[F_MAX];             // cell width per dimension
+    double ainv[F_MAX];         // 1 / a (FP64), for quotient estimates that are then corrected exactly
     float o[F_MAX];             // origin per dimension
     int32_t cmin[F_MAX];
     int32_t cmax[F_MAX];
@@ -62,6 +63,18 @@ struct IndexView {
 // Exact floor of v / a (a > 0 finite, v finite): the largest integer t with t * a <= v.
 // The FP64 quotient is rounded, so the candidate is checked against exact products; for
 // |t| < 2^29 and an FP32 width, t * a is exact in FP64.
+// The same with the quotient estimated as v * (1 / a): the estimate is within one of
+// the floor, and the exact product checks correct it.
+__device__ __forceinline__ int64_t exact_floor_div_r(double v, double a, double ainv) {
+    double t = floor(v * ainv);
+    if (!(fabs(t) < 4.0e18)) return t > 0 ? int64_t(4000000000000000000LL) : -int64_t(4000000000000000000LL);
+    if (fabs(t) < 536870912.0) {
+        if (__dmul_rn(t, a) > v) t -= 1.0;
+        else if (__dmul_rn(t + 1.0, a) <= v) t += 1.0;
+    }
+    return int64_t(t);
+}
+
 __device__ __forceinline__ int64_t exact_floor_div(double v, double a) {
     double t = floor(v / a);
     if (!(fabs(t) < 4.0e18)) return t > 0 ? int64_t(4000000000000000000LL) : -int64_t(4000000000000000000LL);

@@ -133,7 +133,7 @@ __device__ __forceinline__ void setup_query(const IndexView& ix, const float* qu
         Q.q[j] = queries[qi * f + j];
         Q.finite = Q.finite && isfinite(Q.q[j]);
         Q.v[j] = __dadd_rn((double)Q.q[j], -(double)ix.o[j]);
-        int64_t cj = Q.finite ? exact_floor_div(Q.v[j], (double)ix.a[j]) : 0;
+        int64_t cj = Q.finite ? exact_floor_div_r(Q.v[j], (double)ix.a[j], ix.ainv[j]) : 0;
         cj = max(cj, (int64_t)ix.cmin[j] - CLAMP);
         cj = min(cj, (int64_t)ix.cmax[j] + CLAMP);
         const int32_t c32 = (int32_t)cj;

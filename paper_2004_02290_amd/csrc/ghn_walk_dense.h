@@ -38,6 +38,7 @@ __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& i
 
     const int L = f - 1;  // the run dimension
     const double aL = ix.a[L];
+    const double aLinv = ix.ainv[L];
     int32_t l = Q.l0;
     for (;; ++l) {
         st.updated = false;
@@ -103,10 +104,12 @@ __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& i
                             // shell row: every cell of the run [c-l, c+l] inside the box
                             int32_t ta = lo_l, tb = hi_l;
                             if (prune && st.tau < 1.0e300) {
-                                const double room = st.tau / LB_SHRINK - lb;
+                                // conservative: tau (1 + 2^-39) >= tau / LB_SHRINK, and the
+                                // reciprocal's rounding is far inside the +1 / -2 slack
+                                const double room = __dmul_rn(st.tau, 1.0 + 0x1p-39) - lb;
                                 const double G = sqrt(room > 0.0 ? room : 0.0);
-                                const double ub = floor((Q.v[L] + G) / aL) + 1.0;
-                                const double lb_t = ceil((Q.v[L] - G) / aL) - 2.0;
+                                const double ub = floor((Q.v[L] + G) * aLinv) + 1.0;
+                                const double lb_t = ceil((Q.v[L] - G) * aLinv) - 2.0;
                                 if (ub < (double)tb) tb = (int32_t)ub;
                                 if (lb_t > (double)ta) ta = (int32_t)lb_t;
                             }
