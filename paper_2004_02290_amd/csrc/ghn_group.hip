@@ -734,7 +734,7 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                     if (ee < k) {
                         A.io.out_idx[qi * k + ee] = bi[i][j];
                         if (A.io.out_d2) A.io.out_d2[qi * k + ee] = bd[i][j];
-                        S.lab[g][ee] = ((const int32_t*)ix.targets)[bi[i][j]];
+                        S.lab[g][ee] = (uint32_t)bi[i][j] < (uint64_t)ix.n ? ((const int32_t*)ix.targets)[bi[i][j]] : 0;
                     }
                 }
             }

@@ -383,13 +383,16 @@ __device__ __forceinline__ void finish_query(const IndexView& ix, const QueryIO&
                                              const WaveState& st) {
     const int lane = lane_id();
     const int k = io.k;
+    // every walk ends with k entries (k <= n and the box-covered stop); the guard only
+    // keeps a broken invariant from reading outside the targets
+    const bool have = lane < k && (uint32_t)st.bi < (uint64_t)ix.n;
     if (lane < k) {
         io.out_idx[qi * k + lane] = st.bi;
         if (io.out_d2) io.out_d2[qi * k + lane] = st.bd;
     }
     if (ix.task == GHN_CLASSIFY) {
         const int32_t* lab = (const int32_t*)ix.targets;
-        const int my = lane < k ? lab[st.bi] : INT32_MAX;
+        const int my = have ? lab[st.bi] : INT32_MAX;
         uint64_t todo = ballot(lane < k);
         int best = INT32_MAX, best_n = -1;
         while (todo) {
@@ -404,7 +407,7 @@ __device__ __forceinline__ void finish_query(const IndexView& ix, const QueryIO&
     } else if (io.flags & GHN_FLAG_MEDIAN) {
         // sort the k targets across the wave in IEEE total order (padding last)
         const float* y = (const float*)ix.targets;
-        const uint32_t u = lane < k ? __float_as_uint(y[st.bi]) : 0u;
+        const uint32_t u = have ? __float_as_uint(y[st.bi]) : 0u;
         uint32_t key = lane < k ? ((u & 0x80000000u) ? ~u : (u | 0x80000000u)) : 0xffffffffu;
         key = wave_sort_asc(key, lane, WAVE);
         const float v = __uint_as_float((key & 0x80000000u) ? (key & 0x7fffffffu) : ~key);
@@ -418,7 +421,7 @@ __device__ __forceinline__ void finish_query(const IndexView& ix, const QueryIO&
         if (lane == 0) ((float*)io.out_pred)[qi] = mid;
     } else {
         const float* y = (const float*)ix.targets;
-        const float my = lane < k ? y[st.bi] : 0.0f;
+        const float my = have ? y[st.bi] : 0.0f;
         double s = 0.0;
         for (int t = 0; t < k; ++t) s = __dadd_rn(s, (double)readlane_f32(my, t));
         if (lane == 0) ((float*)io.out_pred)[qi] = (float)(s / (double)k);
