@@ -48,6 +48,8 @@ constexpr int GT = 256;          // threads per block
 constexpr int GWPB = GT / WAVE;  // groups (waves) per block
 constexpr int GQ = 16;           // queries per group
 constexpr int STACK_CAP = TREE_LEVELS_MAX * WAVE;
+constexpr int QFLUSH = WAVE;               // queued pairs that trigger the exact check
+constexpr int QCAP = GQ * WAVE + QFLUSH;   // one tile can admit every pair
 constexpr float SCREEN_REL = 0x1p-12f;   // admission margin, relative to |q'|^2 + |x'|^2
 constexpr float SCREEN_ABS = 0x1p-100f;  // absolute margin (FP32 underflow)
 
@@ -190,6 +192,8 @@ struct alignas(16) GroupLds {
     double qd[GQ][FS];      // the queries in FP64 (exact), for the re-rank
     float tq[GQ];           // per query: FP32 threshold >= its k-th distance (+inf while the
                             // buffer is not full), -1 once done or when invalid
+    uint32_t qp[QCAP];      // queue of admitted pairs: point position in cell order
+    uint8_t qr[QCAP];       //                          and query row of the group
 };
 
 // Operand layout of the screen for padded dimension SP (K = [qh, qh, ql] . [xh, xl, xh]
@@ -416,9 +420,105 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
 
         // Screen, check and insert the points of the run list in LDS (npts points in
         // nrun runs, prefix positions with a sentinel at nrun).
-        auto score_tiles = [&](uint32_t npts, uint32_t nrun) {
+        // Exact FP64 check and insertion of the queued pairs, 64 at a time: each lane
+        // scores one pair, then each 16-lane row inserts its query's pairs one by one
+        // (the four rows in parallel, one slot at a time).  Deferring the check is
+        // exact: thresholds only lag (a superset is admitted), and every queue is
+        // flushed before a layer's stop test, so the buffer after layer l and whether
+        // layer l changed it do not depend on when pairs are inserted.
+        int qcount = 0;
+        auto flush = [&]() {
+            wave_lds_sync();
+            for (int qb = 0; qb < qcount; qb += WAVE) {
+                const int e = qb + lane;
+                int r = -1;
+                double cd = __longlong_as_double(0x7ff0000000000000LL);
+                int ci = INT32_MAX;
+                if (e < qcount) {
+                    r = S.qr[e];
+                    const uint32_t pc = S.qp[e];
+                    float xv[FS];
+                    load_point<FT>(ix.spts + (size_t)pc * f, xv, f);
+                    const double* qd = S.qd[r];
+                    cd = 0.0;
+#pragma unroll
+                    for (int j = 0; j < FS; ++j) {
+                        if (FT == 0 && j >= f) break;
+                        const double d = __dadd_rn(qd[j], -(double)xv[j]);
+                        cd = __dadd_rn(cd, __dmul_rn(d, d));
+                    }
+                    ci = ix.sid[pc];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint64_t m0 = ballot(r == i), m1 = ballot(r == 4 + i), m2 = ballot(r == 8 + i),
+                                   m3 = ballot(r == 12 + i);
+                    uint64_t mrow = g == 0 ? m0 : (g == 1 ? m1 : (g == 2 ? m2 : m3));
+                    while (ballot(mrow != 0)) {
+                        bool have = false;
+                        int src = lane;
+                        if (mrow) {
+                            have = true;
+                            src = __ffsll((unsigned long long)mrow) - 1;
+                            mrow &= mrow - 1;
+                        }
+                        const double cdb = shfl_f64(cd, src);
+                        const int cib = __shfl(ci, src, WAVE);
+                        if (have && (cdb < tau[i] || (cdb == tau[i] && cib < taui[i]))) {
+                            // entries larger than the candidate move up one place
+                            const uint64_t cbits = (uint64_t)__double_as_longlong(cdb);
+                            int ngt = 0;
+#pragma unroll
+                            for (int j = 0; j < KR; ++j) {
+                                const int ee = 16 * j + t;
+                                const uint64_t bb = (uint64_t)__double_as_longlong(bd[i][j]);
+                                const bool gt = ee < k && (bb > cbits || (bb == cbits && bi[i][j] > cib));
+                                ngt += __popc((uint32_t)(ballot(gt) >> (16 * g)) & 0xffffu);
+                            }
+                            const int pos = k - ngt;
+                            double rd[KR];
+                            int ri[KR];
+#pragma unroll
+                            for (int j = 0; j < KR; ++j) { rd[j] = row_ror1_f64(bd[i][j]); ri[j] = row_ror1(bi[i][j]); }
+#pragma unroll
+                            for (int j = KR - 1; j >= 0; --j) {
+                                const int ee = 16 * j + t;
+                                double nd = rd[j];
+                                int ni = ri[j];
+                                if (t == 0) {
+                                    nd = j > 0 ? rd[j > 0 ? j - 1 : 0] : bd[i][j];
+                                    ni = j > 0 ? ri[j > 0 ? j - 1 : 0] : bi[i][j];
+                                }
+                                if (ee < k && ee >= pos) {
+                                    bd[i][j] = ee == pos ? cdb : nd;
+                                    bi[i][j] = ee == pos ? cib : ni;
+                                }
+                            }
+                            upd[i] = true;
+                            const int jl = (k - 1) >> 4, tl = (k - 1) & 15;
+                            double kd = bd[i][0];
+                            int ki = bi[i][0];
+#pragma unroll
+                            for (int j = 1; j < KR; ++j) if (j == jl) { kd = bd[i][j]; ki = bi[i][j]; }
+                            tau[i] = row_bcast_f64(kd, tl);
+                            taui[i] = row_bcast(ki, tl);
+                            thr[i] = taui[i] == INT32_MAX ? inf : admit_group(tau[i]);
+                            bnd[i] = thr[i] == inf ? inf : thr[i] - (1.0f - SCREEN_REL) * qn[i];
+                            if (t == 0) S.tq[4 * g + i] = thr[i];
+                        }
+                    }
+                }
+            }
+            qcount = 0;
+            wave_lds_sync();
+        };
+
+        // Screen the points of the run list in LDS (npts points in nrun runs, prefix
+        // positions with a sentinel at nrun) and queue the admitted pairs; `last`
+        // flushes the queue at the end (with npts = 0 it only flushes).
+        auto score_tiles = [&](uint32_t npts, uint32_t nrun, bool last) {
                 uint32_t seg = 0;
-                for (uint32_t base = 0; base < npts; base += WAVE) {
+                for (uint32_t base = 0; base < npts || (last && base == 0); base += WAVE) {
                     // candidate base + lane: its run (one uniform pass over the runs that
                     // start inside this tile), record position and initial accumulator
                     const uint32_t p = base + lane;
@@ -455,89 +555,23 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
 #pragma unroll
                         for (int i = 0; i < 4; ++i) any |= ballot(accs[cb][i] <= bnd[i]);
                     }
-                    if (!any) continue;
-                    // Slow path, per slot and column block (with the thresholds as they
-                    // shrink): the exact FP64 check and insertion of the admitted pairs,
-                    // the four rows in parallel.
+                    if (any) {
+                        // queue the admitted pairs (query row, point position)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-#pragma unroll 1
                         for (int cb = 0; cb < 4; ++cb) {
-                            const float av = cb == 0 ? accs[0][i] : (cb == 1 ? accs[1][i] : (cb == 2 ? accs[2][i] : accs[3][i]));
-                            const uint32_t pcb = cb == 0 ? pcs[0] : (cb == 1 ? pcs[1] : (cb == 2 ? pcs[2] : pcs[3]));
-                            const uint64_t M = ballot(av <= bnd[i]);
-                            if (!M) continue;
-                            double cd = __longlong_as_double(0x7ff0000000000000LL);
-                            int ci = INT32_MAX;
-                            if ((M >> lane) & 1) {
-                                float xv[FS];
-                                load_point<FT>(ix.spts + (size_t)pcb * f, xv, f);
-                                const double* qd = S.qd[4 * g + i];
-                                cd = 0.0;
 #pragma unroll
-                                for (int j = 0; j < FS; ++j) {
-                                    if (FT == 0 && j >= f) break;
-                                    const double d = __dadd_rn(qd[j], -(double)xv[j]);
-                                    cd = __dadd_rn(cd, __dmul_rn(d, d));
+                            for (int i = 0; i < 4; ++i) {
+                                const uint64_t M = ballot(accs[cb][i] <= bnd[i]);
+                                if ((M >> lane) & 1) {
+                                    const int pos = qcount + __popcll(M & __lanemask_lt());
+                                    S.qp[pos] = pcs[cb];
+                                    S.qr[pos] = (uint8_t)(4 * g + i);
                                 }
-                                ci = ix.sid[pcb];
-                            }
-                            uint32_t mrow = (uint32_t)(M >> (16 * g)) & 0xffffu;
-                            while (ballot(mrow != 0)) {
-                                bool have = false;
-                                int src = lane;
-                                if (mrow) {
-                                    have = true;
-                                    src = 16 * g + __ffs(mrow) - 1;
-                                    mrow &= mrow - 1;
-                                }
-                                const double cdb = shfl_f64(cd, src);
-                                const int cib = __shfl(ci, src, WAVE);
-                                if (have && (cdb < tau[i] || (cdb == tau[i] && cib < taui[i]))) {
-                                    // entries larger than the candidate move up one place
-                                    const uint64_t cbits = (uint64_t)__double_as_longlong(cdb);
-                                    int ngt = 0;
-#pragma unroll
-                                    for (int j = 0; j < KR; ++j) {
-                                        const int ee = 16 * j + t;
-                                        const uint64_t bb = (uint64_t)__double_as_longlong(bd[i][j]);
-                                        const bool gt = ee < k && (bb > cbits || (bb == cbits && bi[i][j] > cib));
-                                        ngt += __popc((uint32_t)(ballot(gt) >> (16 * g)) & 0xffffu);
-                                    }
-                                    const int pos = k - ngt;
-                                    double rd[KR];
-                                    int ri[KR];
-#pragma unroll
-                                    for (int j = 0; j < KR; ++j) { rd[j] = row_ror1_f64(bd[i][j]); ri[j] = row_ror1(bi[i][j]); }
-#pragma unroll
-                                    for (int j = KR - 1; j >= 0; --j) {
-                                        const int ee = 16 * j + t;
-                                        double nd = rd[j];
-                                        int ni = ri[j];
-                                        if (t == 0) {
-                                            nd = j > 0 ? rd[j > 0 ? j - 1 : 0] : bd[i][j];
-                                            ni = j > 0 ? ri[j > 0 ? j - 1 : 0] : bi[i][j];
-                                        }
-                                        if (ee < k && ee >= pos) {
-                                            bd[i][j] = ee == pos ? cdb : nd;
-                                            bi[i][j] = ee == pos ? cib : ni;
-                                        }
-                                    }
-                                    upd[i] = true;
-                                    const int jl = (k - 1) >> 4, tl = (k - 1) & 15;
-                                    double kd = bd[i][0];
-                                    int ki = bi[i][0];
-#pragma unroll
-                                    for (int j = 1; j < KR; ++j) if (j == jl) { kd = bd[i][j]; ki = bi[i][j]; }
-                                    tau[i] = row_bcast_f64(kd, tl);
-                                    taui[i] = row_bcast(ki, tl);
-                                    thr[i] = taui[i] == INT32_MAX ? inf : admit_group(tau[i]);
-                                    bnd[i] = thr[i] == inf ? inf : thr[i] - (1.0f - SCREEN_REL) * qn[i];
-                                    if (t == 0) S.tq[4 * g + i] = thr[i];
-                                }
+                                qcount += __popcll(M);
                             }
                         }
                     }
+                    if (qcount >= QFLUSH || (last && qcount > 0 && base + WAVE >= npts)) flush();
                 }
         };
 
@@ -550,7 +584,7 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                     S.run_pre[1] = (uint32_t)ix.n;
                 }
                 wave_lds_sync();
-                score_tiles((uint32_t)ix.n, 1u);
+                score_tiles((uint32_t)ix.n, 1u, true);
                 wave_lds_sync();
             }
 #pragma unroll
@@ -661,9 +695,10 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                 }
                 if (lane == 0) S.run_pre[nrun] = npts;  // sentinel
                 wave_lds_sync();
-                score_tiles(npts, nrun);
+                score_tiles(npts, nrun, false);
                 wave_lds_sync();
             }
+            score_tiles(0u, 0u, true);  // pending exact checks belong to layer l
             // stop rules for every live query of the group, after layer l
             bool any = false;
 #pragma unroll
