@@ -286,3 +286,46 @@ def test_insert_bf16_and_bad_load(ghn):
     with pytest.raises(ghn.GHNError) as e:
         ghn.Index.load(bytes(data))
     assert e.value.code == -1
+
+
+# ------------------------------------------------------------------------------ graph capture
+def test_predict_graph_replay(ghn):
+    # ghn_predict launches only kernels (no memset nodes): the FP32 walk with its query
+    # sort and the grouped bf16 screen are captured once and replayed
+    import torch
+    prob = W.make("clusters4d", n=40_000, m=5_000)
+    ix = ghn.Index(_dev(prob.points), _dev(prob.targets), prob.task, prob.cell_width)
+    q = _dev(prob.queries)
+    m, k = prob.m, prob.k
+    runs = []
+    for prec in (ghn.GHN_PREC_FP32, ghn.GHN_PREC_BF16_MFMA):
+        oi = torch.empty((m, k), dtype=torch.int64, device="cuda")
+        op = torch.empty(m, dtype=torch.int32, device="cuda")
+        od = torch.empty((m, k), dtype=torch.float64, device="cuda")
+        nb = ghn.ghn_predict_workspace_bytes(ix.handle, m, k, ghn.GHN_STOP_EXACT, prec, 0)
+        ws = torch.empty(max(nb, 1), dtype=torch.uint8, device="cuda")
+        runs.append((prec, oi, op, od, ws))
+    want = {}
+    for prec, oi, op, od, ws in runs:
+        ghn.ghn_predict(ix.handle, q, k, oi, op, od, ghn.GHN_STOP_EXACT, prec, 0, ws=ws)
+        torch.cuda.synchronize()
+        want[prec] = (oi.clone(), op.clone(), od.clone())
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            for prec, oi, op, od, ws in runs:
+                ghn.ghn_predict(ix.handle, q, k, oi, op, od, ghn.GHN_STOP_EXACT, prec, 0, ws=ws)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        for prec, oi, op, od, ws in runs:      # eager work between replays
+            oi.fill_(-1); op.fill_(-1); od.zero_(); ws.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for prec, oi, op, od, ws in runs:
+            wi, wp, wd = want[prec]
+            assert torch.equal(oi, wi) and torch.equal(op, wp) and torch.equal(od, wd), (rep, prec)
+    bi, bd, bp = oracle.bruteforce(prob.points, prob.targets, prob.task, prob.queries, k)
+    assert np.array_equal(want[ghn.GHN_PREC_FP32][0].cpu().numpy(), bi)
