@@ -376,7 +376,8 @@ def main():
         st = ix.predict(qs, k, stop=stop, prec=prec, flags=flags, with_d2=False, with_stats=True, group_levels=levels)
         torch.cuda.synchronize()
         out = dict(cands=int(st["cands"].sum().item()), probes=int(st["probes"].sum().item()),
-                   layers=float(st["stop_layer"].double().mean().item()))
+                   layers=float(st["stop_layer"].double().mean().item()),
+                   rerank=float(st["rerank"].double().mean().item()))
         del st
         return out
 
@@ -425,6 +426,14 @@ def main():
                       "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": measured_traffic(args.workload, "bf16"),
                       "kernel": "k_predict_group"},
             alg={"flops_per_step": flops, "issued_mfma_flops_per_step": 2.0 * (-(-3 * f // 32) * 32) * w["cands"]})
+        # the screen's distance error against FP64, on a query sample against points spread over the index
+        ns = min(m, 2048)
+        ea, er = ghn.ghn_screen_error(ix.handle, qs[:ns], sample=8192)
+        forms["bf16_batched"]["screen_error"] = {
+            "max_abs": float(ea.max().item()), "max_rel": float(er.max().item()), "mean_rel": float(er.mean().item()),
+            "bound_rel": 2.0 ** -13.8, "admission_margin_rel": 2.0 ** -12,
+            "sample": "first %d queries x %d points spread over the index; rel = |s - d| / (|q'|^2 + |x'|^2)"
+                      % (ns, min(8192, prob.n))}
 
     if "brute" in args.forms:
         # exhaustive KNN (the paper's comparison method) on the same GPU and index data
@@ -468,7 +477,9 @@ def main():
                          "step_ms_p10_p50_p90": [float(np.percentile(v["per"], 10)), float(np.median(v["per"])),
                                                  float(np.percentile(v["per"], 90))],
                          "candidates_per_query": v["work"]["cands"] / m, "index_reads_per_query": v["work"]["probes"] / m,
-                         "mean_stop_layer": v["work"]["layers"], "roofline": v["roofline"], "algorithmic": v["alg"]}
+                         "mean_stop_layer": v["work"]["layers"], "rerank_per_query": v["work"].get("rerank"),
+                         "roofline": v["roofline"], "algorithmic": v["alg"],
+                         **({"screen_error": v["screen_error"]} if "screen_error" in v else {})}
                   for name, v in forms.items()},
         "build_ms": build_ms,
         "index": {"num_cells": int(ix.info.num_cells), "box_cells": int(ix.info.box_cells),

@@ -172,6 +172,8 @@ typedef struct {
     void* walk_event_begin;  /* optional hipEvent_t: recorded on the stream right before the walk
                                 kernel (the exploration launch, after any query sort/grouping) */
     void* walk_event_end;    /* optional hipEvent_t: recorded right after the walk kernel */
+    int64_t* out_rerank;     /* optional, m int64: candidates re-scored in FP64 per query (those the
+                                FP32 or bf16 screen could not rule out: the re-rank band) */
 } ghn_predict_opts;
 
 /* Bytes of device workspace ghn_predict needs for these arguments (the bf16
@@ -306,6 +308,17 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
  * Errors: GHN_E_INVALID_ARG, GHN_E_NONFINITE, GHN_E_NOMEM, GHN_E_HIP. */
 ghn_status ghn_cell_measure(const void* points, int64_t n, int32_t f, int32_t dtype, float* out_width,
                             float* out_origin, int64_t* out_splits, void* stream);
+
+/* Diagnostic of the GHN_PREC_BF16_MFMA screen: for every query (DEVICE, m x f
+ * float32), its screen value s = |q'|^2 + |x'|^2 - 2 q'.x' (the screen's bf16
+ * operands and matrix instruction) against the exact FP64 distance d, over
+ * min(sample, n) points spread evenly over the index.  out_abs[q] = max |s - d|,
+ * out_rel[q] = max |s - d| / (|q'|^2 + |x'|^2) (DEVICE, m float32 each; NaN for
+ * a query with a non-finite coordinate).  The screen admits with a margin of
+ * 2^-12 (|q'|^2 + |x'|^2); its proven error is below 2^-13.8 of that norm sum.
+ * Asynchronous on `stream`.  Errors: GHN_E_INVALID_ARG, GHN_E_HIP. */
+ghn_status ghn_screen_error(const ghn_index* index, const float* queries, int64_t m, int64_t sample,
+                            float* out_abs, float* out_rel, void* stream);
 
 /* ---- persistence and insertion ---------------------------------------------------
  * The model of the method is the training data plus the grid parameters (Section

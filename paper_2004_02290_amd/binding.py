@@ -38,7 +38,8 @@ P_ = ctypes.c_void_p
 EXPORTED = ["ghn_build", "ghn_build_ex", "ghn_index_get_info", "ghn_destroy", "ghn_predict_workspace_bytes", "ghn_predict",
             "ghn_query_order_workspace_bytes", "ghn_query_order", "ghn_batch_workspace_bytes", "ghn_batch_prepare",
             "ghn_predict_batched", "ghn_batch_destroy", "ghn_autotune", "ghn_cell_measure", "ghn_bruteforce",
-            "ghn_index_save_bytes", "ghn_index_save", "ghn_index_load", "ghn_insert", "ghn_last_error"]
+            "ghn_index_save_bytes", "ghn_index_save", "ghn_index_load", "ghn_insert", "ghn_screen_error",
+            "ghn_last_error"]
 
 
 class GHNError(RuntimeError):
@@ -62,7 +63,7 @@ class ghn_predict_opts(ctypes.Structure):
                 ("out_stop_layer", ctypes.c_void_p), ("out_cands", ctypes.c_void_p),
                 ("out_probes", ctypes.c_void_p), ("order", ctypes.c_void_p),
                 ("group_levels", ctypes.c_int32), ("walk_event_begin", ctypes.c_void_p),
-                ("walk_event_end", ctypes.c_void_p)]
+                ("walk_event_end", ctypes.c_void_p), ("out_rerank", ctypes.c_void_p)]
 
 
 class ghn_batch_item(ctypes.Structure):
@@ -123,6 +124,8 @@ def _load() -> ctypes.CDLL:
     L.ghn_index_load.restype = ctypes.c_int
     L.ghn_insert.argtypes = [P, P, I64, I32, P, P]
     L.ghn_insert.restype = ctypes.c_int
+    L.ghn_screen_error.argtypes = [P, P, I64, I64, P, P, P]
+    L.ghn_screen_error.restype = ctypes.c_int
     L.ghn_cell_measure.argtypes = [P, I64, I32, I32, P, P, P, P]
     L.ghn_cell_measure.restype = ctypes.c_int
     L.ghn_last_error.argtypes = []
@@ -221,10 +224,11 @@ def _event(ev):
 
 
 def _opts(stop, prec, flags, out_stop_layer=None, out_cands=None, out_probes=None, order=None,
-          group_levels=-1, walk_events=None) -> ghn_predict_opts:
+          group_levels=-1, walk_events=None, out_rerank=None) -> ghn_predict_opts:
     ev0, ev1 = walk_events if walk_events is not None else (None, None)
     return ghn_predict_opts(int(stop), int(prec), int(flags), _ptr(out_stop_layer), _ptr(out_cands),
-                            _ptr(out_probes), _ptr(order), int(group_levels), _event(ev0), _event(ev1))
+                            _ptr(out_probes), _ptr(order), int(group_levels), _event(ev0), _event(ev1),
+                            _ptr(out_rerank))
 
 
 def ghn_predict_workspace_bytes(handle, m: int, k: int, stop=GHN_STOP_EXACT, prec=GHN_PREC_FP32, flags=0,
@@ -238,12 +242,13 @@ def ghn_predict(handle, queries: torch.Tensor, k: int, out_idx: torch.Tensor, ou
                 out_stop_layer: Optional[torch.Tensor] = None, out_cands: Optional[torch.Tensor] = None,
                 out_probes: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
                 order: Optional[torch.Tensor] = None, group_levels: int = -1, stream=None,
-                walk_events=None) -> None:
+                walk_events=None, out_rerank: Optional[torch.Tensor] = None) -> None:
     """ghn_predict into caller-provided outputs (int64 idx m x k, pred m, optional float64 d2 m x k).
 
     walk_events: optional (begin, end) pair of torch.cuda.Event recorded around the walk kernel."""
     m = queries.shape[0]
-    o = _opts(stop, prec, flags, out_stop_layer, out_cands, out_probes, order, group_levels, walk_events)
+    o = _opts(stop, prec, flags, out_stop_layer, out_cands, out_probes, order, group_levels, walk_events,
+              out_rerank)
     ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
     _check(_lib.ghn_predict(handle, _ptr(queries), m, k, ctypes.byref(o), _ptr(out_idx), _ptr(out_d2),
                             _ptr(out_pred), _ptr(ws), ws_bytes, _stream(stream)))
@@ -338,6 +343,15 @@ def ghn_insert(handle, points: torch.Tensor, targets: torch.Tensor, stream=None)
     _check(_lib.ghn_insert(handle, _ptr(points), points.shape[0], dtype, _ptr(targets), _stream(stream)))
 
 
+def ghn_screen_error(handle, queries: torch.Tensor, sample: int = 4096, stream=None):
+    """ghn_screen_error: per query (max |s - d|, max |s - d| / (|q'|^2 + |x'|^2)) as float32 GPU tensors."""
+    m = queries.shape[0]
+    ea = torch.empty(m, dtype=torch.float32, device=queries.device)
+    er = torch.empty(m, dtype=torch.float32, device=queries.device)
+    _check(_lib.ghn_screen_error(handle, _ptr(queries), m, int(sample), _ptr(ea), _ptr(er), _stream(stream)))
+    return ea, er
+
+
 def ghn_cell_measure(points: torch.Tensor, stream=None):
     """ghn_cell_measure: the paper's cell measurements -> (width float32[f], origin float32[f], splits int64[f])."""
     n, f = points.shape
@@ -373,10 +387,12 @@ class Index:
             out["stop_layer"] = torch.empty(m, dtype=torch.int32, device=dev)
             out["cands"] = torch.empty(m, dtype=torch.int64, device=dev)
             out["probes"] = torch.empty(m, dtype=torch.int64, device=dev)
+            out["rerank"] = torch.empty(m, dtype=torch.int64, device=dev)
         nbytes = ghn_predict_workspace_bytes(self.handle, m, k, stop, prec, flags, group_levels)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev) if nbytes else None
         ghn_predict(self.handle, queries, k, out["idx"], out["pred"], out.get("d2"), stop, prec, flags,
-                    out.get("stop_layer"), out.get("cands"), out.get("probes"), ws, None, group_levels, stream)
+                    out.get("stop_layer"), out.get("cands"), out.get("probes"), ws, None, group_levels, stream,
+                    out_rerank=out.get("rerank"))
         return out
 
     @classmethod

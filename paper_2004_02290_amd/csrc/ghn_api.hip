@@ -126,6 +126,7 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
         b.io.out_stop_layer = nullptr;
         b.io.out_cands = nullptr;
         b.io.out_probes = nullptr;
+        b.io.out_rerank = nullptr;
         b.io.k = it.k;
         b.io.flags = o.flags;
         b.first = total;
@@ -617,6 +618,7 @@ static ghn_status predict_common(const ghn_index* index, const float* queries, i
     pa.io.out_stop_layer = o.out_stop_layer;
     pa.io.out_cands = o.out_cands;
     pa.io.out_probes = o.out_probes;
+    pa.io.out_rerank = o.out_rerank;
     pa.order = o.order;
     hipStream_t s = (hipStream_t)stream;
     if (brute) {
@@ -663,6 +665,22 @@ ghn_status ghn_bruteforce(const ghn_index* index, const float* queries, int64_t 
                           const ghn_predict_opts* opts, int64_t* out_idx, double* out_d2, void* out_pred, void* ws,
                           size_t ws_bytes, void* stream) {
     return predict_common(index, queries, m, k, opts, out_idx, out_d2, out_pred, ws, ws_bytes, stream, true);
+}
+
+ghn_status ghn_screen_error(const ghn_index* index, const float* queries, int64_t m, int64_t sample,
+                            float* out_abs, float* out_rel, void* stream) {
+    using namespace ghn;
+    if (!index || !queries || !out_abs || !out_rel) return fail(GHN_E_INVALID_ARG, "ghn_screen_error: NULL argument");
+    if (m < 0) return fail(GHN_E_INVALID_ARG, "ghn_screen_error: m < 0");
+    if (sample < 1 || sample >= (int64_t(1) << 31))
+        return fail(GHN_E_INVALID_ARG, "ghn_screen_error: sample=%lld outside [1, 2^31)", (long long)sample);
+    if (((uintptr_t)queries % 4) || ((uintptr_t)out_abs % 4) || ((uintptr_t)out_rel % 4))
+        return fail(GHN_E_INVALID_ARG, "ghn_screen_error: misaligned array");
+    if (m == 0) return GHN_OK;
+    const int64_t nsamp = sample < index->info.n ? sample : index->info.n;
+    hipError_t e = launch_screen_error(index->view, queries, m, (uint32_t)nsamp, out_abs, out_rel, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "ghn_screen_error");
+    return GHN_OK;
 }
 
 // ---- persistence and insertion: the model is the training data plus the grid

@@ -365,6 +365,7 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
         bool upd[4], done[4];
         int32_t stopl[4];
         int32_t cands[4];
+        int32_t rer[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int r = 4 * g + i;
@@ -373,6 +374,7 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
             upd[i] = false;
             stopl[i] = -1;
             cands[i] = 0;
+            rer[i] = 0;
             tau[i] = __longlong_as_double(0x7ff0000000000000LL);
             taui[i] = INT32_MAX;
             thr[i] = live ? inf : -inf;
@@ -568,6 +570,7 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                                     S.qr[pos] = (uint8_t)(4 * g + i);
                                 }
                                 qcount += __popcll(M);
+                                rer[i] += __popc((uint32_t)(M >> (16 * g)) & 0xffffu);
                             }
                         }
                     }
@@ -760,6 +763,7 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                     if (A.io.out_stop_layer) A.io.out_stop_layer[qi] = -1;
                     if (A.io.out_cands) A.io.out_cands[qi] = 0;
                     if (A.io.out_probes) A.io.out_probes[qi] = 0;
+                    if (A.io.out_rerank) A.io.out_rerank[qi] = 0;
                 }
             }
             if (live) {
@@ -823,11 +827,131 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                     if (A.io.out_stop_layer) A.io.out_stop_layer[qi] = stopl[i];
                     if (A.io.out_cands) A.io.out_cands[qi] = cands[i];
                     if (A.io.out_probes) A.io.out_probes[qi] = probes;
+                    if (A.io.out_rerank) A.io.out_rerank[qi] = rer[i];
                 }
             }
             wave_lds_sync();
         }
     }
+}
+
+// Diagnostic: the grouped screen's error against the exact FP64 distance.  One wave
+// takes 16 consecutive queries and `nsamp` points spread evenly over the index (cell
+// order), forms s = |q'|^2 + |x'|^2 - 2 q'.x' with the screen's operands and matrix
+// instruction (screen_block, accumulator started at |x'|^2), and records per query
+// max |s - d| and max |s - d| / (|q'|^2 + |x'|^2).
+template <int FT, int SP>
+__global__ __launch_bounds__(GT) void k_screen_error(IndexView ix, const float* __restrict__ qs, int64_t m,
+                                                     uint32_t nsamp, float* __restrict__ out_abs,
+                                                     float* __restrict__ out_rel) {
+    constexpr int FS = FT > 0 ? FT : F_MAX;
+    using SC = Screen<SP>;
+    constexpr int NKB = SC::NKB;
+    __shared__ double sqd[GWPB][GQ][FS];
+    const int lane = lane_id(), g = lane >> 4, t = lane & 15;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int f = FT > 0 ? FT : ix.f;
+    const int64_t q0 = ((int64_t)blockIdx.x * GWPB + wv) * GQ;
+    if (q0 >= m) return;
+    const int cnt = (int)min((int64_t)GQ, m - q0);
+    bool fin = lane < cnt;
+    for (int j = 0; j < f; ++j) {
+        const float x = lane < cnt ? qs[(q0 + lane) * f + j] : 0.0f;
+        fin = fin && isfinite(x);
+        if (lane < GQ) sqd[wv][lane][j] = (double)x;
+    }
+    const uint64_t fin_mask = ballot(fin);
+    wave_lds_sync();
+    bf16x8 afr[NKB];
+    {
+        const int r = lane & 15;
+        const bool rlive = (fin_mask >> r) & 1;
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb) {
+            const int part = SC::a_part(kb, g), d0 = SC::a_dim(kb, g);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int j = d0 + e;
+                float v = 0.0f;
+                if (part >= 0 && rlive && j < f) {
+                    const float qp = (float)sqd[wv][r][j] - ix.c0[j];
+                    const float hi = (float)(__bf16)qp;
+                    v = part == 1 ? (float)(__bf16)(qp - hi) : hi;
+                }
+                afr[kb][e] = (__bf16)(-2.0f * v);
+            }
+        }
+    }
+    float qn[4], mabs[4], mrel[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float sq = 0.0f;
+        if ((fin_mask >> (4 * g + i)) & 1)
+            for (int j = 0; j < f; ++j) {
+                const float d = (float)sqd[wv][4 * g + i][j] - ix.c0[j];
+                sq = __builtin_fmaf(d, d, sq);
+            }
+        qn[i] = sq;
+        mabs[i] = 0.0f;
+        mrel[i] = 0.0f;
+    }
+    for (uint32_t base = 0; base < nsamp; base += WAVE) {
+        const uint32_t p = base + lane;
+        const bool valid = p < nsamp;
+        const uint32_t pidx = valid ? (uint32_t)((uint64_t)p * (uint64_t)ix.n / nsamp) : 0u;
+        const float xn = valid ? ix.sxn[pidx] : 0.0f;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            uint32_t pc;
+            const floatx4 acc = screen_block<FT, SP>(ix, afr, pidx, xn, base, nsamp, cb, g, t, pc);
+            const float xnc = __shfl(xn, 16 * cb + t, WAVE);
+            if (base + 16 * cb + t >= nsamp) continue;
+            float xv[FS];
+            load_point<FT>(ix.spts + (size_t)pc * f, xv, f);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (!((fin_mask >> (4 * g + i)) & 1)) continue;
+                double d = 0.0;
+                for (int j = 0; j < f; ++j) {
+                    const double dj = __dadd_rn(sqd[wv][4 * g + i][j], -(double)xv[j]);
+                    d = __dadd_rn(d, __dmul_rn(dj, dj));
+                }
+                const double err = fabs(__dadd_rn((double)acc[i] + (double)qn[i], -d));
+                mabs[i] = fmaxf(mabs[i], (float)err);
+                mrel[i] = fmaxf(mrel[i], (float)(err / ((double)qn[i] + (double)xnc)));
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        for (int d = 1; d < 16; d <<= 1) {
+            mabs[i] = fmaxf(mabs[i], __shfl_xor(mabs[i], d, 16));
+            mrel[i] = fmaxf(mrel[i], __shfl_xor(mrel[i], d, 16));
+        }
+        const int r = 4 * g + i;
+        if (t == 0 && r < cnt) {
+            const bool ok = (fin_mask >> r) & 1;
+            out_abs[q0 + r] = ok ? mabs[i] : __int_as_float(0x7fc00000);
+            out_rel[q0 + r] = ok ? mrel[i] : __int_as_float(0x7fc00000);
+        }
+    }
+}
+
+template <int FT>
+hipError_t launch_err(const IndexView& ix, const float* qs, int64_t m, uint32_t nsamp, float* out_abs,
+                      float* out_rel, hipStream_t s) {
+    constexpr int SP = FT <= 8 ? 8 : (FT <= 16 ? 16 : 32);
+    const int64_t blocks = (m + GQ * GWPB - 1) / (GQ * GWPB);
+    if (FT > 0) {
+        hipLaunchKernelGGL((k_screen_error<FT, SP>), dim3((unsigned)blocks), dim3(GT), 0, s, ix, qs, m, nsamp, out_abs, out_rel);
+    } else if (ix.sp == 8) {
+        hipLaunchKernelGGL((k_screen_error<0, 8>), dim3((unsigned)blocks), dim3(GT), 0, s, ix, qs, m, nsamp, out_abs, out_rel);
+    } else if (ix.sp == 16) {
+        hipLaunchKernelGGL((k_screen_error<0, 16>), dim3((unsigned)blocks), dim3(GT), 0, s, ix, qs, m, nsamp, out_abs, out_rel);
+    } else {
+        hipLaunchKernelGGL((k_screen_error<0, 32>), dim3((unsigned)blocks), dim3(GT), 0, s, ix, qs, m, nsamp, out_abs, out_rel);
+    }
+    return hipGetLastError();
 }
 
 template <int FT, int SP>
@@ -916,6 +1040,18 @@ hipError_t run_grouped(const PredictArgs& pa, int keep_shift_levels, void* ws, h
     }
     if (e == hipSuccess && ev_end) e = hipEventRecord(ev_end, s);
     return e;
+}
+
+hipError_t launch_screen_error(const IndexView& ix, const float* qs, int64_t m, uint32_t nsamp, float* out_abs,
+                               float* out_rel, hipStream_t s) {
+    switch (ix.f) {
+        case 2: return launch_err<2>(ix, qs, m, nsamp, out_abs, out_rel, s);
+        case 3: return launch_err<3>(ix, qs, m, nsamp, out_abs, out_rel, s);
+        case 4: return launch_err<4>(ix, qs, m, nsamp, out_abs, out_rel, s);
+        case 8: return launch_err<8>(ix, qs, m, nsamp, out_abs, out_rel, s);
+        case 16: return launch_err<16>(ix, qs, m, nsamp, out_abs, out_rel, s);
+        default: return launch_err<0>(ix, qs, m, nsamp, out_abs, out_rel, s);
+    }
 }
 
 }  // namespace ghn

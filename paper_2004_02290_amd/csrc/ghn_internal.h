@@ -188,6 +188,7 @@ struct QueryIO {
     int32_t* out_stop_layer;
     int64_t* out_cands;
     int64_t* out_probes;
+    int64_t* out_rerank;
     int32_t k;
     uint32_t flags;
 };
@@ -216,6 +217,8 @@ hipError_t coord_range(const void* pts, int64_t n, int32_t f, int32_t dtype, flo
 
 // Grouped walk with the bf16 matrix-core screen: sort, group and walk the queries.
 size_t group_ws_bytes(int64_t m);
+hipError_t launch_screen_error(const IndexView& ix, const float* qs, int64_t m, uint32_t nsamp, float* out_abs,
+                               float* out_rel, hipStream_t s);
 hipError_t run_grouped(const PredictArgs& pa, int group_levels, void* ws, hipStream_t s, int* morton_bits,
                        hipEvent_t ev_begin, hipEvent_t ev_end, bool brute);
 // Spatial sort key of every query (Morton code of its box-clamped central cell).

@@ -97,6 +97,7 @@ struct WaveState {
     bool updated;   // an insertion happened in the current layer
     int32_t cands;  // candidates scored
     int32_t probes; // index entries read to find cells
+    int32_t rerank; // candidates re-scored in FP64
 };
 
 __device__ __forceinline__ void init_state(WaveState& st) {
@@ -109,6 +110,7 @@ __device__ __forceinline__ void init_state(WaveState& st) {
     st.updated = false;
     st.cands = 0;
     st.probes = 0;
+    st.rerank = 0;
 }
 
 // Query set-up: coordinates, central cell (Eq. 1, clamped to CLAMP cells outside
@@ -157,6 +159,7 @@ __device__ __forceinline__ void write_invalid(const IndexView& ix, const QueryIO
         if (io.out_stop_layer) io.out_stop_layer[qi] = -1;
         if (io.out_cands) io.out_cands[qi] = 0;
         if (io.out_probes) io.out_probes[qi] = 0;
+        if (io.out_rerank) io.out_rerank[qi] = 0;
     }
 }
 
@@ -201,6 +204,7 @@ __device__ __forceinline__ void score_chunk(const float* q, int f, int k, const 
     const bool adm = c.valid && d32 <= st.t32;
     uint64_t mask = ballot(adm);
     if (mask == 0) return;
+    st.rerank += __popcll(mask);
     double d64 = 0.0;
     if (adm) d64 = dist64<FT>(q, c.x, f);
     while (mask) {
@@ -430,6 +434,7 @@ __device__ __forceinline__ void finish_query(const IndexView& ix, const QueryIO&
         if (io.out_stop_layer) io.out_stop_layer[qi] = (int32_t)l;
         if (io.out_cands) io.out_cands[qi] = st.cands;
         if (io.out_probes) io.out_probes[qi] = st.probes;
+        if (io.out_rerank) io.out_rerank[qi] = st.rerank;
     }
 }
 

@@ -33,9 +33,9 @@ def test_every_declared_symbol_is_exported(ghn):
 
 def test_struct_sizes_match_header(ghn):
     # ghn_index_info: 8+4+4+4+4+8+8+8 + 4*32*4 + 8 bytes
-    # ghn_predict_opts: 3*4 + pad + 4*8 + 4 + pad + 2*8
+    # ghn_predict_opts: 3*4 + pad + 4*8 + 4 + pad + 3*8
     assert ctypes.sizeof(ghn.ghn_index_info) == 48 + 4 * 32 * 4 + 8
-    assert ctypes.sizeof(ghn.ghn_predict_opts) == 72
+    assert ctypes.sizeof(ghn.ghn_predict_opts) == 80
     assert ctypes.sizeof(ghn.ghn_batch_item) == 56  # 3 pointers/ints of 8, k + pad, 3 pointers
     assert ctypes.sizeof(ghn.ghn_tune_trial) == 32  # 5 x 4 bytes, pad, double
 

@@ -329,3 +329,33 @@ def test_predict_graph_replay(ghn):
             assert torch.equal(oi, wi) and torch.equal(op, wp) and torch.equal(od, wd), (rep, prec)
     bi, bd, bp = oracle.bruteforce(prob.points, prob.targets, prob.task, prob.queries, k)
     assert np.array_equal(want[ghn.GHN_PREC_FP32][0].cpu().numpy(), bi)
+
+
+# ------------------------------------------------------------------- screen error and re-rank band
+BOUND_REL = 2.0 ** -13.8   # proven bound of |s - d| / (|q'|^2 + |x'|^2) for the bf16 screen
+
+
+def _offset_problem(seed, f, lo, hi, n=20_000, m=256):
+    rng = np.random.default_rng(seed)
+    pts = rng.uniform(lo, hi, (n, f)).astype(np.float32)
+    qs = rng.uniform(lo, hi, (m, f)).astype(np.float32)
+    lab = rng.integers(0, 3, n).astype(np.int32)
+    return W.Problem("offset", pts, lab, qs, 8, W.CLASSIFY, float(np.float32((hi - lo) / 30.0)))
+
+
+@pytest.mark.parametrize("case", ["clusters4d", "bf16_16d", "skew8d", "far", "wide"])
+def test_screen_error_within_bound(ghn, case):
+    if case == "far":
+        prob = _offset_problem(1, 4, 1000.0, 1000.5)     # large coordinates, small spread
+    elif case == "wide":
+        prob = _offset_problem(2, 3, -1000.0, 1000.0)    # large spread
+    else:
+        prob = W.make(case, n=30_000, m=512)
+    ix = ghn.Index(_pts(prob), _dev(prob.targets), prob.task, prob.cell_width)
+    ea, er = ghn.ghn_screen_error(ix.handle, _dev(prob.queries), sample=4096)
+    ea, er = ea.cpu().numpy(), er.cpu().numpy()
+    assert np.isfinite(er).all() and er.max() < BOUND_REL, (case, er.max(), BOUND_REL)
+    # the exact re-rank: at least k candidates are re-scored in FP64, never more than scored
+    for prec in (0, 1):
+        got = _host(ix.predict(_dev(prob.queries), prob.k, prec=prec, with_stats=True))
+        assert (got["rerank"] >= prob.k).all() and (got["rerank"] <= got["cands"]).all(), (case, prec)
