@@ -174,6 +174,40 @@ def paper_study(args, ghn, W, torch):
                       "paper_rule_widths": [float(x) for x in w], "grids": rows}), flush=True)
 
 
+def cpu_more(prob, target_s: float = 5.0):
+    """More CPU figures of the oracle: the grid walk on one thread and exhaustive KNN on all
+    threads, each on a bounded query sample, plus the host description."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    out = {"host": {"nproc": os.cpu_count(), "omp_threads": threads, "cpu_model": model}}
+
+    def timed(fn, pilot):
+        t0 = time.perf_counter()
+        fn(pilot)
+        dt = time.perf_counter() - t0
+        count = int(min(prob.m, max(pilot, pilot * target_s / max(dt, 1e-6))))
+        t0 = time.perf_counter()
+        fn(count)
+        return count, time.perf_counter() - t0
+
+    g = oracle.Grid(prob.points_f32(), prob.targets, prob.task, prob.cell_width)
+    c, dt = timed(lambda c: g.predict(prob.queries[:c], prob.k, oracle.STOP_EXACT, nthreads=1), 8)
+    g.close()
+    out["grid_1_thread"] = {"value": c / dt, "unit": "queries/s", "sample": "first %d queries" % c}
+    pts = prob.points_f32()
+    c, dt = timed(lambda c: oracle.bruteforce(pts, prob.targets, prob.task, prob.queries[:c], prob.k,
+                                              nthreads=threads), max(threads, 4))
+    out["bruteforce_all_threads"] = {"value": c / dt, "unit": "queries/s", "threads": threads,
+                                     "sample": "first %d queries" % c}
+    return out
+
+
 def bench_multi(args, ghn, W, torch):
     """Many independent 3-D problems: per-index launches vs one batched launch (and its graph replay)."""
     probs = W.make_multi3d()
@@ -487,6 +521,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob)
+        line["cpu_oracle_more"] = cpu_more(prob)
     ix.close()
     print(json.dumps(line), flush=True)
 
