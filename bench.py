@@ -319,6 +319,43 @@ def bench_multi(args, ghn, W, torch):
     print(json.dumps(line), flush=True)
 
 
+def query_parts(prob, qs, ix, ghn, torch, stop, sort32, levels16, reps=3):
+    """Each half of a mixed query set (cluster / uniform background) timed on its own, both forms."""
+    out = {}
+    k = prob.k
+    for name, val in (("cluster", 1), ("uniform", 0)):
+        sel = torch.from_numpy(np.nonzero(prob.query_part == val)[0]).to(qs.device)
+        q = qs.index_select(0, sel).contiguous()
+        mq = int(q.shape[0])
+        if mq == 0:
+            continue
+        oi = torch.empty((mq, k), dtype=torch.int64, device=qs.device)
+        op = torch.empty(mq, dtype=torch.int32 if prob.task == 0 else torch.float32, device=qs.device)
+        part = {"queries": mq}
+        for form, prec, flags, levels in (("fp32_plain", ghn.GHN_PREC_FP32, 0 if sort32 else ghn.GHN_FLAG_NO_SORT, -1),
+                                          ("bf16_batched", ghn.GHN_PREC_BF16_MFMA, 0, levels16)):
+            nws = ghn.ghn_predict_workspace_bytes(ix.handle, mq, k, stop, prec, flags, levels)
+            ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=qs.device)
+            st = ix.predict(q, k, stop=stop, prec=prec, flags=flags, with_d2=False, with_stats=True,
+                            group_levels=levels)
+            torch.cuda.synchronize()
+            cands = float(st["cands"].double().mean().item())
+            layers = float(st["stop_layer"].double().mean().item())
+            del st
+            ms = []
+            for _ in range(reps + 1):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                ghn.ghn_predict(ix.handle, q, k, oi, op, None, stop, prec, flags, ws=ws, group_levels=levels,
+                                walk_events=(e0, e1))
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            kern = float(np.mean(ms[1:]))
+            part[form] = {"kernel_ms": kern, "qps_kernel": mq / (kern * 1e-3), "candidates_per_query": cands,
+                          "mean_stop_layer": layers}
+        out[name] = part
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,6 +368,12 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16",
                     help="comma list of forms to time: fp32, bf16 (GHN walks), brute (exhaustive KNN, reported beside)")
     ap.add_argument("--group-levels", type=int, default=-1, help="bf16 form: cell-id bits dropped to group queries")
+    ap.add_argument("--autotune", choices=("auto", "on", "off"), default="auto",
+                    help="pick the cell width (and each form's settings) with ghn_autotune on a query sample "
+                         "before the timed region; auto = on for skew8d")
+    ap.add_argument("--tune-queries", type=int, default=32768, help="query sample size for --autotune")
+    ap.add_argument("--cell-width", type=float, default=None,
+                    help="cell width to build with (default: the workload's calibrated width, or the autotuned one)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--paper-study", action="store_true",
@@ -377,13 +420,42 @@ def main():
     qs = torch.from_numpy(prob.queries).to(dev)
     torch.cuda.synchronize()
 
-    t0 = time.perf_counter()
-    ix = ghn.Index(pts, tgt, prob.task, prob.cell_width)
-    torch.cuda.synchronize()
-    build_ms = (time.perf_counter() - t0) * 1e3
-
     m, k = prob.m, prob.k
     f = prob.f
+    width = prob.cell_width if args.cell_width is None else args.cell_width
+    tuned = None
+    sort32, levels16 = args.sort, args.group_levels
+    if args.autotune == "on" or (args.autotune == "auto" and args.workload == "skew8d" and args.cell_width is None):
+        # widths around the calibrated one (under PAPER only execution settings are tuned);
+        # the chosen width is the fastest setting's, then each form takes its own best trial there
+        widths = [prob.cell_width] if stop == ghn.GHN_STOP_PAPER else \
+            [prob.cell_width * 2.0 ** (i / 2.0) for i in range(-2, 5)]
+        ns = min(m, args.tune_queries)
+        print("autotune: %d widths on %d queries" % (len(widths), ns), file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        best, trials = ghn.ghn_autotune(pts, tgt, prob.task, qs[:ns], k, stop, widths)
+        torch.cuda.synchronize()
+        tune_ms = (time.perf_counter() - t0) * 1e3
+        width = float(best["cell_width"])
+        at_w = [t for t in trials if t["cell_width"] == best["cell_width"] and t["ms"] >= 0]
+        b32 = min((t for t in at_w if t["prec"] == ghn.GHN_PREC_FP32), key=lambda t: t["ms"], default=None)
+        b16 = min((t for t in at_w if t["prec"] == ghn.GHN_PREC_BF16_MFMA), key=lambda t: t["ms"], default=None)
+        if b32 is not None:
+            sort32 = not (b32["flags"] & ghn.GHN_FLAG_NO_SORT)
+        if b16 is not None:
+            levels16 = int(b16["group_levels"])
+        tuned = {"cell_width": width, "tune_ms": tune_ms, "sample_queries": ns, "widths_tried": widths,
+                 "fp32_sort": sort32, "bf16_group_levels": levels16,
+                 "trials": [{"w": t["cell_width"], "prec": "fp32" if t["prec"] == ghn.GHN_PREC_FP32 else "bf16",
+                             "lookup": t["lookup"], "levels": t["group_levels"], "flags": t["flags"],
+                             "ms": t["ms"]} for t in trials]}
+        print("autotune: width %.6g (calibrated %.6g), %.1f s" % (width, prob.cell_width, tune_ms * 1e-3),
+              file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    ix = ghn.Index(pts, tgt, prob.task, width)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
     out_idx = torch.empty((m, k), dtype=torch.int64, device=dev)
     out_pred = torch.empty(m, dtype=torch.int32 if prob.task == 0 else torch.float32, device=dev)
 
@@ -419,13 +491,13 @@ def main():
     if "fp32" in args.forms:
         # per-query walk; with --sort a step = spatial order (Morton sort) + walk, events
         # between the two calls time the walk kernel alone on the stream both run on
-        flags = 0 if args.sort else ghn.GHN_FLAG_NO_SORT
+        flags = 0 if sort32 else ghn.GHN_FLAG_NO_SORT
         w = stats(ghn.GHN_PREC_FP32, flags)
         order = torch.empty(m, dtype=torch.int32, device=dev)
         ows = torch.empty(max(ghn.ghn_query_order_workspace_bytes(m), 1), dtype=torch.uint8, device=dev)
 
         def step32(evs):
-            if args.sort:
+            if sort32:
                 ghn.ghn_query_order(ix.handle, qs, order, ows)
                 ghn.ghn_predict(ix.handle, qs, k, out_idx, out_pred, None, stop, ghn.GHN_PREC_FP32, 0, order=order,
                                 walk_events=evs)
@@ -443,13 +515,13 @@ def main():
                       "kernel": "k_predict_%s" % ("dense" if ix.info.lookup == 0 else "tree")},
             alg={"bytes_per_step": alg_bytes})
     if "bf16" in args.forms:
-        nws = ghn.ghn_predict_workspace_bytes(ix.handle, m, k, stop, ghn.GHN_PREC_BF16_MFMA, 0, args.group_levels)
+        nws = ghn.ghn_predict_workspace_bytes(ix.handle, m, k, stop, ghn.GHN_PREC_BF16_MFMA, 0, levels16)
         ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dev)
-        w = stats(ghn.GHN_PREC_BF16_MFMA, 0, args.group_levels)
+        w = stats(ghn.GHN_PREC_BF16_MFMA, 0, levels16)
 
         def step16(evs):
             ghn.ghn_predict(ix.handle, qs, k, out_idx, out_pred, None, stop, ghn.GHN_PREC_BF16_MFMA, 0, ws=ws,
-                            group_levels=args.group_levels, walk_events=evs)
+                            group_levels=levels16, walk_events=evs)
 
         ms, kern_ms, per = timed(step16)
         flops = 2.0 * f * w["cands"]  # algorithmic: 2 f per screened (query, candidate) pair
@@ -504,7 +576,7 @@ def main():
         "dtype": "f32" if best == "fp32_plain" else "bf16+f32+f64",
         "data": "synthetic",
         "config": {"workload": describe(prob, args.stop.upper()), "n": prob.n, "f": f, "m": m, "k": k,
-                   "cell_width": prob.cell_width, "stop": args.stop, "form": best,
+                   "cell_width": width, "stop": args.stop, "form": best,
                    "lookup": "dense" if ix.info.lookup == 0 else "tree"},
         "roofline": B["roofline"],
         "forms": {name: {"qps": v["qps"], "ms_per_step": v["ms_per_step"], "kernel_ms": v["kernel_ms"],
@@ -519,6 +591,11 @@ def main():
         "index": {"num_cells": int(ix.info.num_cells), "box_cells": int(ix.info.box_cells),
                   "max_occupancy": int(ix.info.max_occupancy)},
     }
+    if tuned is not None:
+        line["config"]["cell_width_source"] = "autotuned"
+        line["autotune"] = tuned
+    if prob.query_part is not None:
+        line["query_parts"] = query_parts(prob, qs, ix, ghn, torch, stop, sort32, levels16)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob)
         line["cpu_oracle_more"] = cpu_more(prob)

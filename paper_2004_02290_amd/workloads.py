@@ -37,6 +37,7 @@ class Problem:
     task: int                   # CLASSIFY or REGRESS
     cell_width: float           # scalar width used for every dimension
     dtype: str = "f32"          # storage type of `points`: "f32" or "bf16"
+    query_part: Optional[np.ndarray] = None  # per query: 1 drawn from a cluster, 0 from the uniform background
 
     @property
     def n(self) -> int:
@@ -132,17 +133,18 @@ def make(name: str, n: Optional[int] = None, m: Optional[int] = None,
     if name == "skew8d":
         r_c, r_pa, r_pn, r_y, r_qa, r_qn = _streams(seed, 6)
         centers = r_c.random((w["centers"], f))
-        pts = _skewed(r_pa, r_pn, centers, w["sigma"], n, clustered_frac=0.9)
+        pts, _ = _skewed(r_pa, r_pn, centers, w["sigma"], n, clustered_frac=0.9)
         y = np.sin(2.0 * np.pi * pts.astype(np.float64)).sum(axis=1)
         y = (y + r_y.normal(0.0, 0.01, size=n)).astype(np.float32)
-        qs = _skewed(r_qa, r_qn, centers, w["sigma"], m, clustered_frac=0.5)
-        return Problem(name, pts, y, qs, w["k"], REGRESS, width)
+        qs, part = _skewed(r_qa, r_qn, centers, w["sigma"], m, clustered_frac=0.5)
+        return Problem(name, pts, y, qs, w["k"], REGRESS, width, query_part=part.astype(np.int8))
 
     raise KeyError(name)
 
 
 def _skewed(r_assign, r_noise, centers, sigma, count, clustered_frac):
-    """`clustered_frac` of the rows from the Gaussian clusters, the rest uniform on [0,1)^f."""
+    """`clustered_frac` of the rows from the Gaussian clusters, the rest uniform on [0,1)^f.
+    Returns the rows and, per row, whether it came from a cluster."""
     f = centers.shape[1]
     is_cluster = r_assign.random(count) < clustered_frac
     lab = r_assign.integers(0, centers.shape[0], size=count)
@@ -150,7 +152,7 @@ def _skewed(r_assign, r_noise, centers, sigma, count, clustered_frac):
     nc = int(is_cluster.sum())
     x[is_cluster] = (centers[lab[is_cluster]] + r_noise.normal(0.0, sigma, size=(nc, f))).astype(np.float32)
     x[~is_cluster] = r_noise.random((count - nc, f)).astype(np.float32)
-    return x
+    return x, is_cluster
 
 
 def make_multi3d(problems: Optional[int] = None, n_hi: Optional[int] = None,
