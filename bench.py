@@ -372,6 +372,9 @@ def main():
                     help="pick the cell width (and each form's settings) with ghn_autotune on a query sample "
                          "before the timed region; auto = on for skew8d")
     ap.add_argument("--tune-queries", type=int, default=32768, help="query sample size for --autotune")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time the forms only: no autotuning and no per-half runs (for profiler runs, so the "
+                         "walk kernels' dispatches are all of the timed configuration)")
     ap.add_argument("--cell-width", type=float, default=None,
                     help="cell width to build with (default: the workload's calibrated width, or the autotuned one)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -425,7 +428,8 @@ def main():
     width = prob.cell_width if args.cell_width is None else args.cell_width
     tuned = None
     sort32, levels16 = args.sort, args.group_levels
-    if args.autotune == "on" or (args.autotune == "auto" and args.workload == "skew8d" and args.cell_width is None):
+    if args.autotune == "on" or (args.autotune == "auto" and args.workload == "skew8d" and args.cell_width is None
+                                    and not args.no_extras):
         # widths around the calibrated one (under PAPER only execution settings are tuned);
         # the chosen width is the fastest setting's, then each form takes its own best trial there
         widths = [prob.cell_width] if stop == ghn.GHN_STOP_PAPER else \
@@ -594,7 +598,7 @@ def main():
     if tuned is not None:
         line["config"]["cell_width_source"] = "autotuned"
         line["autotune"] = tuned
-    if prob.query_part is not None:
+    if prob.query_part is not None and not args.no_extras:
         line["query_parts"] = query_parts(prob, qs, ix, ghn, torch, stop, sort32, levels16)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob)
