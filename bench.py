@@ -365,8 +365,10 @@ def main():
     ap.add_argument("--stop", default="exact", choices=["exact", "paper"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sort", action="store_true", help="FP32 form: walk queries in spatial (Morton) order")
-    ap.add_argument("--forms", default="fp32,bf16",
-                    help="comma list of forms to time: fp32, bf16 (GHN walks), brute (exhaustive KNN, reported beside)")
+    ap.add_argument("--forms", default=None,
+                    help="comma list of forms to time: fp32, bf16, persistent (GHN walks; persistent = the FP32 walk "
+                         "through the batched persistent launch), brute (exhaustive KNN, reported beside); default "
+                         "fp32,bf16, plus persistent for skew8d")
     ap.add_argument("--group-levels", type=int, default=-1, help="bf16 form: cell-id bits dropped to group queries")
     ap.add_argument("--autotune", choices=("auto", "on", "off"), default="auto",
                     help="pick the cell width (and each form's settings) with ghn_autotune on a query sample "
@@ -413,6 +415,8 @@ def main():
         paper_study(args, ghn, W, torch)
         return
     prob = W.make(args.workload)
+    if args.forms is None:
+        args.forms = "fp32,bf16" + (",persistent" if args.workload == "skew8d" else "")
     stop = ghn.GHN_STOP_EXACT if args.stop == "exact" else ghn.GHN_STOP_PAPER
     dev = torch.device("cuda:0")
     if prob.dtype == "bf16":
@@ -545,6 +549,29 @@ def main():
             "sample": "first %d queries x %d points spread over the index; rel = |s - d| / (|q'|^2 + |x'|^2)"
                       % (ns, min(8192, prob.n))}
 
+    if "persistent" in args.forms:
+        # the same FP32 walk, queries in input order, through the batched persistent launch
+        # (waves take queries from an atomic counter until none are left)
+        w = stats(ghn.GHN_PREC_FP32, ghn.GHN_FLAG_NO_SORT)
+        bws = torch.empty(max(ghn.ghn_batch_workspace_bytes(1), 1), dtype=torch.uint8, device=dev)
+        batch = ghn.ghn_batch_prepare([(ix.handle, qs, k, out_idx, out_pred, None)], bws, stop)
+
+        def stepp(evs):
+            if evs:
+                evs[0].record()
+            ghn.ghn_predict_batched(batch)
+            if evs:
+                evs[1].record()
+
+        ms, kern_ms, per = timed(stepp)
+        ghn.ghn_batch_destroy(batch)
+        alg_bytes = (m * 4 * f + w["cands"] * (4 * f + 4) + w["probes"] * 4 + m * k * 4 + m * k * 8 + m * 4)
+        achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+        forms["fp32_persistent"] = dict(
+            qps=m / (ms * 1e-3), ms_per_step=ms, kernel_ms=kern_ms, per=per, work=w,
+            roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_predict_batched"},
+            alg={"bytes_per_step": alg_bytes, "timed": "counter reset + persistent kernel"})
     if "brute" in args.forms:
         # exhaustive KNN (the paper's comparison method) on the same GPU and index data
         nws = ghn.ghn_predict_workspace_bytes(ix.handle, m, k, stop, ghn.GHN_PREC_BF16_MFMA, 0)
@@ -577,7 +604,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if best == "fp32_plain" else "bf16+f32+f64",
+        "dtype": "f32" if best.startswith("fp32") else "bf16+f32+f64",
         "data": "synthetic",
         "config": {"workload": describe(prob, args.stop.upper()), "n": prob.n, "f": f, "m": m, "k": k,
                    "cell_width": width, "stop": args.stop, "form": best,

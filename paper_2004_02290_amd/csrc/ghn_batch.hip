@@ -28,6 +28,7 @@ __global__ __launch_bounds__(BPT) void k_predict_batched(const BatchItem* __rest
     __shared__ uint32_t s_pre[BWPB][RUN_CAP];
     __shared__ uint32_t s_key[BWPB][RUN_CAP];
     __shared__ uint64_t s_stack[BWPB][TREE_STACK_CAP];
+    __shared__ uint64_t s_pend[BWPB][FT == 8 ? TREE_PEND_CAP : 1];
     const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     for (;;) {
@@ -49,7 +50,10 @@ __global__ __launch_bounds__(BPT) void k_predict_batched(const BatchItem* __rest
             const IndexView& ix = *it.ix;
             const int64_t qi = w - it.first;
             if (ix.lookup == LOOKUP_DENSE) walk_dense<FT, STOP>(ix, it.io, qi, s_begin[wv], s_pre[wv], s_key[wv]);
-            else walk_tree<FT, STOP>(ix, it.io, qi, s_begin[wv], s_pre[wv], s_stack[wv]);
+            // the tree walk's pending list only where it costs no occupancy: the f = 8
+            // instance already runs at two waves per SIMD; the others hold the dense walk
+            // at three or four, which the extra state would lower
+            else walk_tree<FT, STOP, FT == 8>(ix, it.io, qi, s_begin[wv], s_pre[wv], s_stack[wv], s_pend[wv]);
         }
     }
 }

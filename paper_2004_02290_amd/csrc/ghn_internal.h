@@ -117,17 +117,21 @@ __device__ __forceinline__ double shfl_up1_f64(double v) {
     return __longlong_as_double(int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo)));
 }
 
-// Minimum over the wave of a non-negative float (uniform result): DPP row_shr
+// Minimum over the wave of a non-negative int (uniform result): DPP row_shr
 // min-scans inside each 16-lane row, then the four row minima.
-__device__ __forceinline__ float wave_min_nonneg(float v) {
-    int m = __float_as_int(v);
+__device__ __forceinline__ int wave_min_nonneg_i32(int m) {
     m = min(m, __builtin_amdgcn_update_dpp(m, m, 0x111, 0xf, 0xf, false));  // row_shr:1
     m = min(m, __builtin_amdgcn_update_dpp(m, m, 0x112, 0xf, 0xf, false));  // row_shr:2
     m = min(m, __builtin_amdgcn_update_dpp(m, m, 0x114, 0xf, 0xf, false));  // row_shr:4
     m = min(m, __builtin_amdgcn_update_dpp(m, m, 0x118, 0xf, 0xf, false));  // row_shr:8
     const int r0 = __builtin_amdgcn_readlane(m, 15), r1 = __builtin_amdgcn_readlane(m, 31);
     const int r2 = __builtin_amdgcn_readlane(m, 47), r3 = __builtin_amdgcn_readlane(m, 63);
-    return __int_as_float(min(min(r0, r1), min(r2, r3)));
+    return min(min(r0, r1), min(r2, r3));
+}
+
+// The same for a non-negative float (its bit pattern orders like the value).
+__device__ __forceinline__ float wave_min_nonneg(float v) {
+    return __int_as_float(wave_min_nonneg_i32(__float_as_int(v)));
 }
 
 // Inclusive prefix sum over the wave.

@@ -121,11 +121,15 @@ __global__ __launch_bounds__(PT) void k_predict_tree(PredictArgs A) {
     __shared__ uint32_t s_begin[WPB][RUN_CAP];
     __shared__ uint32_t s_pre[WPB][RUN_CAP];
     __shared__ uint64_t s_stack[WPB][TREE_STACK_CAP];
+    __shared__ uint64_t s_pend[WPB][FT != 16 ? TREE_PEND_CAP : 1];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int64_t slot = wave_slot(A, WPB);
     if (slot >= A.m) return;
     const int64_t qi = A.order ? (int64_t)A.order[slot] : slot;
-    walk_tree<FT, STOP>(A.ix, A.io, qi, s_begin[wv], s_pre[wv], s_stack[wv]);
+    // At f = 16 the pending-list state lifts the kernel past 168 VGPRs (3 -> 2 waves per
+    // SIMD), which costs more than the revisits it saves there: that instance walks each
+    // layer from the root.
+    walk_tree<FT, STOP, FT != 16>(A.ix, A.io, qi, s_begin[wv], s_pre[wv], s_stack[wv], s_pend[wv]);
 }
 
 template <int FT>

@@ -336,6 +336,29 @@ def test_tree_equals_dense(ghn):
         _assert_same(a, b, "dense vs tree", check_layers=True)
 
 
+def test_tree_walk_many_layers_and_pending_overflow(ghn):
+    """Multi-layer tree walks against the grid oracle, stop layers included: the
+    skewed 8-D mix (uniform-background queries walk up to about ten layers) and
+    sparse 12-D data with k = 64, where a query defers more blocks to later layers
+    than the per-wave pending list holds (those walks fall back to walking every
+    later layer from the root).  The 12-D grid also fits the dense table, whose
+    walk shares no lookup code with the tree."""
+    skew = W.make("skew8d", n=200_000, m=400)
+    assert _index(ghn, skew).info.lookup == TREE
+    wide = W.uniform_problem(n=400_000, m=160, f=12, k=64, seed=77, width=0.3)
+    for prob in (skew, wide):
+        ix = _index(ghn, prob, lookup=TREE)
+        g = oracle.Grid(prob.points_f32(), prob.targets, prob.task, prob.cell_width)
+        for stop, ostop in ((ghn.GHN_STOP_EXACT, oracle.STOP_EXACT), (ghn.GHN_STOP_PAPER, oracle.STOP_PAPER)):
+            got = _run(ghn, ix, prob.queries, prob.k, stop)
+            want = g.predict(prob.queries, prob.k, ostop)
+            _assert_same(got, want, "%s tree walk, stop %d" % (prob.name, stop), check_layers=True)
+            if prob is wide:
+                dense = _run(ghn, _index(ghn, prob, lookup=0), prob.queries, prob.k, stop)
+                _assert_same(got, dense, "12-D tree vs dense, stop %d" % stop, check_layers=True)
+        g.close()
+
+
 def test_skew8d_regression_small(ghn):
     prob = W.make("skew8d", n=100_000, m=1_000)
     ix, _ = _check_exact(ghn, prob)
@@ -429,7 +452,7 @@ def _batch_setup(ghn, probs, stop):
         ix = _index(ghn, p)
         q = _dev(p.queries)
         oi = torch.full((p.m, p.k), -7, dtype=torch.int64, device="cuda")
-        op = torch.full((p.m,), -7, dtype=torch.int32, device="cuda")
+        op = torch.full((p.m,), -7, dtype=torch.int32 if p.task == W.CLASSIFY else torch.float32, device="cuda")
         od = torch.zeros((p.m, p.k), dtype=torch.float64, device="cuda")
         idxs.append(ix)
         items.append((ix.handle, q, p.k, oi, op, od))
@@ -454,6 +477,28 @@ def test_batched_matches_single_and_oracle(ghn):
                 rows = np.arange(min(p.m, 200))
                 bi, bd, bp = oracle.bruteforce(p.points, p.targets, p.task, p.queries[rows], p.k)
                 _assert_same({k: v[rows] for k, v in got.items()}, dict(idx=bi, d2=bd, pred=bp), "batched vs oracle")
+        ghn.ghn_batch_destroy(batch)
+
+
+def test_batched_tree_f8(ghn):
+    """8-D tree indexes through the persistent launch (its f = 8 instance keeps the
+    tree walk's pending list): three skewed problems of different sizes, against
+    the single-index kernel and the oracle."""
+    import torch
+    probs = [W.make("skew8d", n=n, m=m, seed=s) for n, m, s in ((60_000, 700, 31), (150_000, 300, 32), (20_000, 900, 33))]
+    for stop in (ghn.GHN_STOP_EXACT, ghn.GHN_STOP_PAPER):
+        idxs, items, outs, ws, batch = _batch_setup(ghn, probs, stop)
+        assert all(ix.info.lookup == TREE for ix in idxs)
+        ghn.ghn_predict_batched(batch)
+        torch.cuda.synchronize()
+        for p, ix, (oi, op, od) in zip(probs, idxs, outs):
+            got = dict(idx=oi.cpu().numpy(), pred=op.cpu().numpy(), d2=od.cpu().numpy())
+            _assert_same(got, _run(ghn, ix, p.queries, p.k, stop), "batched f=8 vs single")
+            if stop == ghn.GHN_STOP_EXACT:
+                rows = np.arange(min(p.m, 300))
+                bi, bd, bp = oracle.bruteforce(p.points, p.targets, p.task, p.queries[rows], p.k)
+                _assert_same({k: v[rows] for k, v in got.items()}, dict(idx=bi, d2=bd, pred=bp),
+                             "batched f=8 vs oracle")
         ghn.ghn_batch_destroy(batch)
 
 
