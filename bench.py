@@ -387,6 +387,8 @@ def main():
                     help="no GPU work: write profiles/traffic.json from rocprofv3 --pmc output for --workload "
                          "(a comma list)")
     args = ap.parse_args()
+    if args.forms is None:
+        args.forms = "fp32,bf16" + (",persistent" if args.workload == "skew8d" else "")
     if args.write_traffic:
         write_traffic(args.write_traffic, args.workload.split(","))
         return
@@ -415,8 +417,6 @@ def main():
         paper_study(args, ghn, W, torch)
         return
     prob = W.make(args.workload)
-    if args.forms is None:
-        args.forms = "fp32,bf16" + (",persistent" if args.workload == "skew8d" else "")
     stop = ghn.GHN_STOP_EXACT if args.stop == "exact" else ghn.GHN_STOP_PAPER
     dev = torch.device("cuda:0")
     if prob.dtype == "bf16":
