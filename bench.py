@@ -68,7 +68,7 @@ def measured_traffic(workload: str, form: str):
     return entry.get("bytes_per_launch")
 
 
-def write_traffic(pmc_dir: str, workloads) -> None:
+def write_traffic(pmc_dir: str, workloads, out_file: str = TRAFFIC_FILE) -> dict:
     """Turn rocprofv3 --pmc runs into HBM bytes per launch (profiles/traffic.json).
 
     Expects <pmc_dir>/<tag>/pmc_counter_collection.csv for the tags fetch_copy,
@@ -98,9 +98,10 @@ def write_traffic(pmc_dir: str, workloads) -> None:
                 "kernel": kname, "dispatches": len(fv), "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
                 "bytes_per_launch": fk * 1024.0 * fetch_scale + wk * 1024.0 * write_scale,
                 "source_sha256_16": source_hash(kname)}
-    with open(TRAFFIC_FILE, "w") as fh:
+    with open(out_file, "w") as fh:
         json.dump(out, fh, indent=1, sort_keys=True)
     print(json.dumps(out, indent=1, sort_keys=True))
+    return out
 
 
 def cpu_baseline(prob, target_s: float = 15.0):
