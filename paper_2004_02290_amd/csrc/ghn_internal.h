@@ -134,15 +134,52 @@ __device__ __forceinline__ float wave_min_nonneg(float v) {
     return __int_as_float(wave_min_nonneg_i32(__float_as_int(v)));
 }
 
-// Inclusive prefix sum over the wave.
+// DPP lane patterns (gfx9 encodings).  row_shl:n / row_shr:n read lane i + n / i - n
+// of the same 16-lane row, row_ror:n lane (i - n) mod 16, quad_perm a permutation
+// inside each group of four, row_bcast:15 / :31 lane 15 of the previous row / lane 31.
+constexpr int DPP_QUAD_XOR1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;  // quad_perm [2,3,0,1]
+constexpr int DPP_ROW_SHL4 = 0x104;
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118;
+constexpr int DPP_ROW_ROR8 = 0x128;
+constexpr int DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143;
+
+// Inclusive prefix sum over the wave: a Hillis-Steele scan inside each row with
+// row shifts, then each row adds the totals of the rows before it (row broadcasts
+// of lane 15 into rows 1 and 3, then of lane 31 into rows 2 and 3).  Lanes with
+// no source lane, and rows outside the row mask, add 0.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, WAVE);
-        if (lane >= d) v += t;
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_SHR1, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_SHR2, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_SHR4, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_SHR8, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_BCAST15, 0xa, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_BCAST31, 0xc, 0xf, false);
+    return (uint32_t)x;
+}
+
+// Value of `v` held by lane (lane ^ S), S a power of two below 64: DPP inside a row
+// (S <= 8), a swizzle inside each 32-lane half (S = 16), a permute across halves.
+template <int S>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
+    const int x = (int)v;
+    if constexpr (S == 1) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(x, x, DPP_QUAD_XOR1, 0xf, 0xf, false);
+    } else if constexpr (S == 2) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(x, x, DPP_QUAD_XOR2, 0xf, 0xf, false);
+    } else if constexpr (S == 4) {
+        const int fwd = __builtin_amdgcn_update_dpp(x, x, DPP_ROW_SHL4, 0xf, 0xf, false);
+        const int back = __builtin_amdgcn_update_dpp(x, x, DPP_ROW_SHR4, 0xf, 0xf, false);
+        return (uint32_t)((lane_id() & 4) ? back : fwd);
+    } else if constexpr (S == 8) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(x, x, DPP_ROW_ROR8, 0xf, 0xf, false);
+    } else if constexpr (S == 16) {
+        return (uint32_t)__builtin_amdgcn_ds_swizzle(x, 0x401f);  // bitmask mode: and 0x1f, xor 0x10
+    } else {
+        static_assert(S == 32, "lane distance must be a power of two below 64");
+        return (uint32_t)__shfl_xor(x, 32, WAVE);
     }
-    return v;
 }
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {

@@ -265,16 +265,50 @@ __device__ __forceinline__ uint32_t lb_key(double lb) {
     return __float_as_uint(f) & ~127u;
 }
 
+// One compare-exchange step of a bitonic sort: merge blocks of SIZE lanes at lane
+// distance S; a lane keeps the smaller key when its position in the pair (lane & S)
+// and the block's direction (lane & SIZE) agree.
+template <int SIZE, int S>
+__device__ __forceinline__ uint32_t bitonic_step(uint32_t key, int lane) {
+    const uint32_t other = xor_lane<S>(key);
+    const bool up = (lane & SIZE) == 0;
+    const bool low = (lane & S) == 0;
+    return low == up ? min(key, other) : max(key, other);
+}
+
 // Ascending bitonic sort of one 32-bit key per lane over blocks of `width`
-// lanes (a power of two <= 64; lanes past the data hold 0xffffffff).
+// lanes (a power of two, 2 <= width <= 64; lanes past the data hold 0xffffffff).
 __device__ __forceinline__ uint32_t wave_sort_asc(uint32_t key, int lane, int width) {
-    for (int size = 2; size <= width; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            const uint32_t other = (uint32_t)__shfl_xor((int)key, stride, WAVE);
-            const bool up = (lane & size) == 0;
-            const bool low = (lane & stride) == 0;
-            key = low == up ? min(key, other) : max(key, other);
-        }
+    key = bitonic_step<2, 1>(key, lane);
+    if (width >= 4) {
+        key = bitonic_step<4, 2>(key, lane);
+        key = bitonic_step<4, 1>(key, lane);
+    }
+    if (width >= 8) {
+        key = bitonic_step<8, 4>(key, lane);
+        key = bitonic_step<8, 2>(key, lane);
+        key = bitonic_step<8, 1>(key, lane);
+    }
+    if (width >= 16) {
+        key = bitonic_step<16, 8>(key, lane);
+        key = bitonic_step<16, 4>(key, lane);
+        key = bitonic_step<16, 2>(key, lane);
+        key = bitonic_step<16, 1>(key, lane);
+    }
+    if (width >= 32) {
+        key = bitonic_step<32, 16>(key, lane);
+        key = bitonic_step<32, 8>(key, lane);
+        key = bitonic_step<32, 4>(key, lane);
+        key = bitonic_step<32, 2>(key, lane);
+        key = bitonic_step<32, 1>(key, lane);
+    }
+    if (width >= 64) {
+        key = bitonic_step<64, 32>(key, lane);
+        key = bitonic_step<64, 16>(key, lane);
+        key = bitonic_step<64, 8>(key, lane);
+        key = bitonic_step<64, 4>(key, lane);
+        key = bitonic_step<64, 2>(key, lane);
+        key = bitonic_step<64, 1>(key, lane);
     }
     return key;
 }

@@ -19,6 +19,18 @@
 
 namespace ghn {
 
+// ceil(2^32 / w) for 2 <= w <= 64, the multiplier of the row decode (layer boxes up
+// to 64 cells wide take it from this table instead of dividing).
+struct RowMagic {
+    uint32_t m[WAVE + 1];
+};
+constexpr RowMagic make_row_magic() {
+    RowMagic t{};
+    for (uint32_t w = 2; w <= WAVE; ++w) t.m[w] = 0xffffffffu / w + 1u;
+    return t;
+}
+static __constant__ RowMagic kRowMagic = make_row_magic();
+
 template <int FT, int STOP>
 __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& io, int64_t qi,
                                            uint32_t* s_begin, uint32_t* s_pre, uint32_t* s_key) {
@@ -64,7 +76,8 @@ __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& i
             for (int j = 0; j < (FT > 1 ? FT - 1 : (FT == 1 ? 0 : F_MAX - 1)); ++j) {
                 if (FT == 0 && j >= L) break;
                 wmax = max(wmax, w[j]);
-                mag[FT > 1 ? j : 0] = w[j] > 1 ? (uint32_t)(0xffffffffu / (uint32_t)w[j]) + 1u : 0u;
+                const uint32_t wj = (uint32_t)w[j];
+                mag[FT > 1 ? j : 0] = wj <= 1 ? 0u : (wj <= WAVE ? kRowMagic.m[wj] : 0xffffffffu / wj + 1u);
             }
             const bool small = FT > 0 && rows * (int64_t)wmax < (int64_t(1) << 32);
             for (int64_t rb = 0; rb < rows; rb += WAVE) {
@@ -144,7 +157,7 @@ __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& i
                         }
                     }
                 }
-                st.probes += wave_sum_u32(probes_l);
+                st.probes += 2 * (__popcll(ballot(probes_l >= 2)) + __popcll(ballot(probes_l >= 4)));
                 score_runs<FT>(ix, Q.q, f, k, b0, n0, key0, b1, n1, key1, prune, s_begin, s_pre, s_key, st);
             }
         }
