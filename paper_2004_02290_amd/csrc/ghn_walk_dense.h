@@ -83,7 +83,20 @@ __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& i
             for (int64_t rb = 0; rb < rows; rb += WAVE) {
                 const int64_t r = rb + lane;
                 uint32_t b0 = 0, n0 = 0, b1 = 0, n1 = 0, key0 = 0, key1 = 0, probes_l = 0;
-                if (r < rows) {
+                if (l == 0) {
+                    // layer 0 is the central cell alone (l0 = 0: it lies inside the box)
+                    if (lane == 0) {
+                        uint32_t lin = 0;
+#pragma unroll
+                        for (int j = 0; j < (FT > 0 ? FT : F_MAX); ++j) {
+                            if (FT == 0 && j >= f) break;
+                            lin += (uint32_t)(Q.c[j] - ix.cmin[j]) * ix.stride[j];
+                        }
+                        b0 = ix.cell_start[lin];
+                        n0 = ix.cell_start[lin + 1] - b0;
+                        probes_l = 2;
+                    }
+                } else if (r < rows) {
                     // decode row r: ids of dimensions 0..L-1, the last of them fastest
                     int32_t maxoff = 0;
                     uint32_t lin = 0;
