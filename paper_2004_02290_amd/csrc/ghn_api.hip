@@ -25,6 +25,7 @@ struct ghn_batch {
     int64_t total;
     int32_t f;
     int32_t stop;
+    bool any_tree;  // some item's index uses the cell tree
 };
 
 namespace {
@@ -103,6 +104,7 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
     std::vector<BatchItem> h((size_t)n_items);
     int64_t total = 0;
     int32_t f = -1;
+    bool any_tree = false;
     for (int32_t i = 0; i < n_items; ++i) {
         const ghn_batch_item& it = items[i];
         if (!it.index) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: item %d has no index", i);
@@ -132,6 +134,7 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
         b.first = total;
         b.m = it.m;
         total += it.m;
+        if (it.m > 0 && it.index->view.lookup != LOOKUP_DENSE) any_tree = true;
     }
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipGetLastError();
@@ -146,6 +149,7 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
     b->total = total;
     b->f = f;
     b->stop = o.stop;
+    b->any_tree = any_tree;
     *out = b;
     return GHN_OK;
 }
@@ -154,7 +158,7 @@ ghn_status ghn_predict_batched(const ghn_batch* batch, void* stream) {
     if (!batch) return fail(GHN_E_INVALID_ARG, "ghn_predict_batched: batch is NULL");
     if (batch->total == 0) return GHN_OK;
     hipError_t e = ghn::launch_predict_batched(batch->items_dev, batch->n_items, batch->total, batch->f, batch->stop,
-                                               batch->counter_dev, (hipStream_t)stream);
+                                               batch->any_tree, batch->counter_dev, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "ghn_predict_batched: launch");
     return GHN_OK;
 }

@@ -250,7 +250,7 @@ struct BatchItem {
     int64_t first;
     int64_t m;
 };
-hipError_t launch_predict_batched(const BatchItem* items, int n_items, int64_t total, int f, int stop,
+hipError_t launch_predict_batched(const BatchItem* items, int n_items, int64_t total, int f, int stop, bool any_tree,
                                   uint64_t* counter, hipStream_t s);
 
 // Per-dimension range of the finite coordinates of n points (synchronises s).

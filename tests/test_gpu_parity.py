@@ -502,6 +502,34 @@ def test_batched_tree_f8(ghn):
         ghn.ghn_batch_destroy(batch)
 
 
+def test_batched_mixed_lookups(ghn):
+    """A batch of 3-D indexes where one uses the cell tree and the others the dense
+    table (the launch then takes the instance that walks both)."""
+    import torch
+    probs = [W.uniform_problem(n=n, m=m, f=3, k=k, seed=s, width=0.05) for n, m, k, s in
+             ((20_000, 400, 5, 61), (8_000, 300, 12, 62), (30_000, 500, 1, 63))]
+    idxs, items, outs = [], [], []
+    for i, p in enumerate(probs):
+        ix = _index(ghn, p, lookup=TREE if i == 1 else 0)
+        oi = torch.full((p.m, p.k), -7, dtype=torch.int64, device="cuda")
+        op = torch.full((p.m,), -7, dtype=torch.int32, device="cuda")
+        od = torch.zeros((p.m, p.k), dtype=torch.float64, device="cuda")
+        q = _dev(p.queries)
+        idxs.append((ix, q))
+        items.append((ix.handle, q, p.k, oi, op, od))
+        outs.append((oi, op, od))
+    assert [ix.info.lookup for ix, _ in idxs] == [0, TREE, 0]
+    for stop in (ghn.GHN_STOP_EXACT, ghn.GHN_STOP_PAPER):
+        ws = torch.empty(ghn.ghn_batch_workspace_bytes(len(items)), dtype=torch.uint8, device="cuda")
+        batch = ghn.ghn_batch_prepare(items, ws, stop=stop)
+        ghn.ghn_predict_batched(batch)
+        torch.cuda.synchronize()
+        ghn.ghn_batch_destroy(batch)
+        for p, (ix, _), (oi, op, od) in zip(probs, idxs, outs):
+            got = dict(idx=oi.cpu().numpy(), pred=op.cpu().numpy(), d2=od.cpu().numpy())
+            _assert_same(got, _run(ghn, ix, p.queries, p.k, stop), "mixed batch vs single")
+
+
 def test_batched_graph_replay(ghn):
     import torch
     probs = _multi(problems=12, n_hi=20_000, m_hi=2_000, seed=9)
