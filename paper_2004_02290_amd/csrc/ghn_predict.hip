@@ -8,10 +8,10 @@ namespace {
 constexpr int PT = 256;  // threads per block = 4 waves = 4 queries
 constexpr int WPB = PT / WAVE;
 
-// Up to 4 dimensions the walk fits 64 VGPRs (a few spill to scratch at f = 4), which
-// lets 8 waves share a SIMD instead of 6; the extra waves hide more of the walk's
-// latency (measured: 8 % faster on the 4-D clusters).  Wider instances keep the
-// compiler's own choice.
+// Up to 4 dimensions the walk fits 64 VGPRs without scratch spills, which lets 8
+// waves share a SIMD instead of 6; the extra waves hide more of the walk's latency
+// (measured: 8 % faster on the 4-D clusters).  Wider instances keep the compiler's
+// own choice.
 template <int FT> constexpr int dense_waves_per_eu() { return FT >= 1 && FT <= 4 ? 8 : 1; }
 
 template <int FT, int STOP>

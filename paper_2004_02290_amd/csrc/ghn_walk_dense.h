@@ -130,14 +130,16 @@ __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& i
                             // shell row: every cell of the run [c-l, c+l] inside the box
                             int32_t ta = lo_l, tb = hi_l;
                             if (prune && st.tau < 1.0e300) {
-                                // conservative: tau (1 + 2^-39) >= tau / LB_SHRINK, and the
+                                // conservative: fl(tau + tau 2^-39) >= tau / LB_SHRINK, and the
                                 // reciprocal's rounding is far inside the +1 / -2 slack
-                                const double room = __dmul_rn(st.tau, 1.0 + 0x1p-39) - lb;
+                                const double room = __dadd_rn(st.tau, ldexp(st.tau, -39)) - lb;
                                 const double G = sqrt(room > 0.0 ? room : 0.0);
+                                // compared as integers (ids are within +-2^29, the bounds are
+                                // clamped to +-2^30 first)
                                 const double ub = floor((Q.v[L] + G) * aLinv) + 1.0;
                                 const double lb_t = ceil((Q.v[L] - G) * aLinv) - 2.0;
-                                if (ub < (double)tb) tb = (int32_t)ub;
-                                if (lb_t > (double)ta) ta = (int32_t)lb_t;
+                                tb = min(tb, (int32_t)fmin(fmax(ub, -0x1p30), 0x1p30));
+                                ta = max(ta, (int32_t)fmin(fmax(lb_t, -0x1p30), 0x1p30));
                             }
                             if (ta <= tb) {
                                 const uint32_t s0 = ix.cell_start[lin + (uint32_t)(ta - ix.cmin[L])];
@@ -153,7 +155,11 @@ __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& i
                         } else {
                             // interior row: only the end cells c-l and c+l belong to layer l
                             for (int e = 0; e < 2; ++e) {
-                                const int32_t t = e == 0 ? cL - l : cL + l;
+                                int32_t t = e == 0 ? cL - l : cL + l;
+                                // an empty asm keeps the end cell's bound inside the row loop: the
+                                // compiler would otherwise hoist both bounds, and at 64 VGPRs they
+                                // spill to scratch on every layer
+                                asm volatile("" : "+v"(t));
                                 if (t < lo_l || t > hi_l) continue;
                                 double lbe = 0.0;
                                 if (prune) {
