@@ -5,7 +5,8 @@
 // groups of at most 16 that share a cell (or, under the EXACT rule, a block of
 // 2^s cells per dimension).  One wave walks one group: layer l of the group is
 // the set of occupied cells at Chebyshev distance l from the group's box of
-// central cells, found with the cell tree.  Every query's own layers 0..l lie
+// central cells, found with the cell tree (or, for dense-table indexes up to 4
+// dimensions, as rows of the table).  Every query's own layers 0..l lie
 // inside the group's layers 0..l, so each query's stop rule is applied exactly
 // as in the per-query walk.  Under the PAPER rule the group is a single cell,
 // so group layers are the queries' layers.
@@ -599,9 +600,122 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
         for (; any_live && !G.brute; ++l) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) upd[i] = false;
-            if (lane == 0) S.stack[0] = ((uint64_t)ix.tree_levels << 40) | ((uint64_t)ix.tree_count[ix.tree_levels] << 32);
-            int sp = 1;
-            wave_lds_sync();
+            int sp = 0;
+            // (instances up to 4 dimensions; wider ones, at their register limit, walk the
+            // tree, which every index also holds)
+            if (FT >= 1 && FT <= 4 && ix.lookup == LOOKUP_DENSE) {
+                // Dense table: layer l of the group is enumerated as in the per-query
+                // dense walk, around the box of central cells instead of one cell.  Rows
+                // of ids over dimensions 0..f-2 span the box grown by l (clipped to the
+                // occupied box); a row at Chebyshev distance l from the group box adds its
+                // whole run along the last dimension, a nearer row only the two cells at
+                // distance l (pass e = 0 the run or the low cell, e = 1 the high cell).
+                const int L = f - 1;
+                int32_t blo[FS], bw[FS];
+                int64_t rows = 1;
+                bool empty = false;
+                for (int j = 0; j < f; ++j) {
+                    const int32_t a0 = max(S.glo[j] - l, ix.cmin[j]);
+                    const int32_t b0 = min(S.ghi[j] + l, ix.cmax[j]);
+                    blo[j] = a0;
+                    bw[j] = b0 - a0 + 1;
+                    if (b0 < a0) empty = true;
+                    if (j < L) rows *= (b0 >= a0 ? (int64_t)(b0 - a0 + 1) : 0);
+                }
+                for (int64_t row0 = 0; !empty && row0 < rows; row0 += WAVE) {
+                    for (int e = 0; e < 2; ++e) {
+                        double mt = -1.0;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) if (!done[i]) mt = fmax(mt, tau[i]);
+                        for (int d = 16; d < WAVE; d <<= 1) mt = fmax(mt, __shfl_xor(mt, d, WAVE));
+                        const int64_t r = row0 + lane;
+                        bool keepc = false;
+                        int32_t ids[FS];
+                        int32_t ta = 1, tb = 0;
+                        uint32_t lin = 0;
+                        double lb = 0.0;
+                        if (r < rows) {
+                            int64_t rem = r;
+                            int32_t maxoff = 0;
+                            for (int j = L - 1; j >= 0; --j) {
+                                const int32_t o = blo[j] + (int32_t)(rem % bw[j]);
+                                rem /= bw[j];
+                                ids[j] = o;
+                                maxoff = max(maxoff, max(S.glo[j] - o, o - S.ghi[j]));
+                                lin += (uint32_t)(o - ix.cmin[j]) * ix.stride[j];
+                            }
+                            if (maxoff == l) {
+                                if (e == 0) { ta = blo[L]; tb = blo[L] + bw[L] - 1; }
+                            } else {
+                                const int32_t tt = e == 0 ? S.glo[L] - l : S.ghi[L] + l;
+                                if (tt >= blo[L] && tt <= blo[L] + bw[L] - 1) ta = tb = tt;
+                            }
+                            if (ta <= tb) {
+                                ids[L] = ta;
+                                // distance from the box of query coordinates to the run's region
+                                for (int j = 0; j < f; ++j) {
+                                    const int32_t a = ids[j], b = j == L ? tb : ids[j];
+                                    const double aj = S.ad[j], oj = S.od[j];
+                                    const double below = __dadd_rn(__dadd_rn(__dmul_rn((double)a, aj), oj), -(double)S.qhi[j]);
+                                    const double above = __dadd_rn((double)S.qlo[j], -__dadd_rn(__dmul_rn((double)(b + 1), aj), oj));
+                                    double gap = below > above ? below : above;
+                                    gap = gap > 0.0 ? gap : 0.0;
+                                    lb = __dadd_rn(lb, __dmul_rn(gap, gap));
+                                }
+                                keepc = !prune || !(lb * LB_SHRINK > mt);
+                            }
+                        }
+                        // the per-query FP32 test of the tree path below, on the run's region
+                        if (FT > 0 && FT <= 8 && prune && cnt > 1 && ballot(keepc)) {
+                            float clo[FS], chi[FS];
+                            if (keepc) {
+                                for (int j = 0; j < f; ++j) {
+                                    const double aj = S.ad[j], oj = S.od[j];
+                                    const int32_t a = ids[j], b = j == L ? tb : ids[j];
+                                    clo[j] = f32_below(__dadd_rn(__dmul_rn((double)a, aj), oj));
+                                    chi[j] = f32_above(__dadd_rn(__dmul_rn((double)(b + 1), aj), oj));
+                                }
+                            }
+                            bool need = false;
+                            for (int qr = 0; qr < cnt; ++qr) {
+                                const float tq = S.tq[qr];
+                                if (!(tq >= 0.0f)) continue;
+                                float lbq = 0.0f;
+                                for (int j = 0; j < f; ++j) {
+                                    const float q = S.q[qr][j];
+                                    const float gp = fmaxf(fmaxf(clo[j] - q, q - chi[j]), 0.0f);
+                                    lbq = __builtin_fmaf(gp, gp, lbq);
+                                }
+                                need = need || lbq * (1.0f - 0x1p-18f) <= tq;
+                            }
+                            keepc = keepc && need;
+                        }
+                        uint32_t rb = 0, rn = 0;
+                        if (keepc) {
+                            rb = ix.cell_start[lin + (uint32_t)(ta - ix.cmin[L])];
+                            rn = ix.cell_start[lin + (uint32_t)(tb - ix.cmin[L]) + 1] - rb;
+                        }
+                        probes += 2 * __popcll(ballot(keepc));
+                        const uint32_t incl = wave_incl_scan(rn);
+                        const uint32_t npts = readlane_i32((int)incl, WAVE - 1);
+                        if (npts == 0) continue;
+                        const uint32_t nrun_incl = wave_incl_scan(rn > 0 ? 1u : 0u);
+                        const uint32_t nrun = readlane_i32((int)nrun_incl, WAVE - 1);
+                        if (rn > 0) {
+                            S.run_begin[nrun_incl - 1] = rb;
+                            S.run_pre[nrun_incl - 1] = incl - rn;
+                        }
+                        if (lane == 0) S.run_pre[nrun] = npts;  // sentinel
+                        wave_lds_sync();
+                        score_tiles(npts, nrun, false);
+                        wave_lds_sync();
+                    }
+                }
+            } else {
+                if (lane == 0) S.stack[0] = ((uint64_t)ix.tree_levels << 40) | ((uint64_t)ix.tree_count[ix.tree_levels] << 32);
+                sp = 1;
+                wave_lds_sync();
+            }
             while (sp > 0) {
                 --sp;
                 const uint64_t e = S.stack[sp];
