@@ -378,6 +378,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="time the forms only: no autotuning and no per-half runs (for profiler runs, so the "
                          "walk kernels' dispatches are all of the timed configuration)")
+    ap.add_argument("--lookup", choices=("auto", "dense", "tree", "hash"), default="auto",
+                    help="cell lookup to build (default: the build's choice, or the autotuned one)")
     ap.add_argument("--cell-width", type=float, default=None,
                     help="cell width to build with (default: the workload's calibrated width, or the autotuned one)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -431,6 +433,8 @@ def main():
     m, k = prob.m, prob.k
     f = prob.f
     width = prob.cell_width if args.cell_width is None else args.cell_width
+    lookup = {"auto": None, "dense": ghn.GHN_LOOKUP_DENSE, "tree": ghn.GHN_LOOKUP_TREE,
+              "hash": ghn.GHN_LOOKUP_HASH}[args.lookup]
     tuned = None
     sort32, levels16 = args.sort, args.group_levels
     if args.autotune == "on" or (args.autotune == "auto" and args.workload == "skew8d" and args.cell_width is None
@@ -446,7 +450,12 @@ def main():
         torch.cuda.synchronize()
         tune_ms = (time.perf_counter() - t0) * 1e3
         width = float(best["cell_width"])
-        at_w = [t for t in trials if t["cell_width"] == best["cell_width"] and t["ms"] >= 0]
+        if best["lookup"] == ghn.GHN_LOOKUP_HASH:
+            lookup = ghn.GHN_LOOKUP_HASH
+        # FP32 trials of the lookup that will be built (the bf16 trials walk the tree either way)
+        at_w = [t for t in trials if t["cell_width"] == best["cell_width"] and t["ms"] >= 0
+                and (t["prec"] != ghn.GHN_PREC_FP32
+                     or (t["lookup"] == ghn.GHN_LOOKUP_HASH) == (lookup == ghn.GHN_LOOKUP_HASH))]
         b32 = min((t for t in at_w if t["prec"] == ghn.GHN_PREC_FP32), key=lambda t: t["ms"], default=None)
         b16 = min((t for t in at_w if t["prec"] == ghn.GHN_PREC_BF16_MFMA), key=lambda t: t["ms"], default=None)
         if b32 is not None:
@@ -462,7 +471,7 @@ def main():
               file=sys.stderr, flush=True)
 
     t0 = time.perf_counter()
-    ix = ghn.Index(pts, tgt, prob.task, width)
+    ix = ghn.Index(pts, tgt, prob.task, width, lookup=lookup)
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - t0) * 1e3
     out_idx = torch.empty((m, k), dtype=torch.int64, device=dev)
@@ -521,7 +530,7 @@ def main():
             qps=m / (ms * 1e-3), ms_per_step=ms, kernel_ms=kern_ms, per=per, work=w,
             roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, "fp32"),
-                      "kernel": "k_predict_%s" % ("dense" if ix.info.lookup == 0 else "tree")},
+                      "kernel": "k_predict_%s" % ("tree" if ix.info.lookup == 1 else "dense")},
             alg={"bytes_per_step": alg_bytes})
     if "bf16" in args.forms:
         nws = ghn.ghn_predict_workspace_bytes(ix.handle, m, k, stop, ghn.GHN_PREC_BF16_MFMA, 0, levels16)
@@ -609,7 +618,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": describe(prob, args.stop.upper()), "n": prob.n, "f": f, "m": m, "k": k,
                    "cell_width": width, "stop": args.stop, "form": best,
-                   "lookup": "dense" if ix.info.lookup == 0 else "tree"},
+                   "lookup": {0: "dense", 1: "tree", 2: "hash"}[ix.info.lookup]},
         "roofline": B["roofline"],
         "forms": {name: {"qps": v["qps"], "ms_per_step": v["ms_per_step"], "kernel_ms": v["kernel_ms"],
                          "step_ms_p10_p50_p90": [float(np.percentile(v["per"], 10)), float(np.median(v["per"])),

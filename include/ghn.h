@@ -94,7 +94,7 @@ typedef struct {
     int32_t f;               /* features */
     int32_t dtype;           /* ghn_dtype */
     int32_t task;            /* ghn_task */
-    int32_t lookup;          /* GHN_LOOKUP_DENSE or GHN_LOOKUP_TREE */
+    int32_t lookup;          /* GHN_LOOKUP_DENSE, GHN_LOOKUP_TREE or GHN_LOOKUP_HASH */
     int64_t num_cells;       /* non-empty cells (never more than n, Section III-C) */
     int64_t box_cells;       /* cells in the bounding box of the occupied cells */
     int64_t max_occupancy;   /* points in the fullest cell */
@@ -129,11 +129,22 @@ ghn_status ghn_build(const void* points, int64_t n, int32_t f, int32_t dtype, co
  * GHN_LOOKUP_TREE: only the occupied cells, in Morton order, under a 64-ary
  *   tree of bounding boxes; for many dimensions, where the box (and the number
  *   of cells per layer, Eq. 2) grows exponentially.
+ * GHN_LOOKUP_HASH: only the occupied cells, in row-major order of a 64-bit
+ *   key over the box (the cell's "unique identifier", Section III-A), in an
+ *   open-addressing hash table (linear probing, load at most 1/2).  A layer is
+ *   enumerated as generated cell ids (rows of the layer box with runs along the
+ *   last dimension) and every generated cell is looked up, so a layer costs
+ *   about its cell count (Eq. 2) in probes: for low dimensions when the box is
+ *   too large for the dense table.  The key must fit 62 bits (the box holds at
+ *   most 2^62 cells), else GHN_E_KEY_OVERFLOW.  Only on request: AUTO never
+ *   picks it.  Grouped bf16 walks and batches walk a hash index with its tree
+ *   (every index also holds the occupied-cell tree).
  * GHN_LOOKUP_AUTO: dense when the box holds at most max(16 n, 2^24) cells,
  *   otherwise the tree. */
 #define GHN_LOOKUP_AUTO (-1)
 #define GHN_LOOKUP_DENSE 0
 #define GHN_LOOKUP_TREE 1
+#define GHN_LOOKUP_HASH 2
 
 typedef struct {
     int32_t lookup; /* GHN_LOOKUP_* */
@@ -269,7 +280,9 @@ void ghn_batch_destroy(ghn_batch* batch);
  * Times ghn_predict on a sample of queries for every candidate setting and
  * returns the fastest: the scalar cell width (each candidate builds an index),
  * the screen (FP32 per query, in input order or in spatial order; grouped bf16
- * with 2^s-cell groups, s = 0, 1, 2) and the lookup chosen by the build.  Under
+ * with 2^s-cell groups, s = 0 .. 3) and the lookup: the one the build chooses,
+ * and, where that is the tree in at most 6 dimensions, also the hash lookup
+ * (FP32 settings; build the index with the returned lookup).  Under
  * GHN_STOP_EXACT every width gives the same (brute-force) neighbours, so widths
  * are tuned: `widths` (HOST) lists the candidates, or NULL for six widths
  * 2^-3 .. 2^2 times the width that puts 8 points in a cell of the points'
@@ -280,7 +293,7 @@ void ghn_batch_destroy(ghn_batch* batch);
  * Errors: as ghn_build and ghn_predict; GHN_E_UNSUPPORTED if no candidate builds. */
 typedef struct {
     float cell_width;
-    int32_t lookup;        /* GHN_LOOKUP_DENSE or GHN_LOOKUP_TREE */
+    int32_t lookup;        /* GHN_LOOKUP_DENSE, GHN_LOOKUP_TREE or GHN_LOOKUP_HASH */
     int32_t prec;          /* ghn_prec */
     int32_t group_levels;  /* bf16: ghn_predict_opts.group_levels */
     uint32_t flags;        /* GHN_FLAG_* to pass to ghn_predict */

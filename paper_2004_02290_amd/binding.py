@@ -31,7 +31,7 @@ GHN_PREC_FP32, GHN_PREC_BF16_MFMA = 0, 1
 GHN_FLAG_NO_PRUNE, GHN_FLAG_NO_SORT, GHN_FLAG_MEDIAN = 1, 2, 4
 GHN_K_MAX, GHN_F_MAX = 64, 32
 
-GHN_LOOKUP_AUTO, GHN_LOOKUP_DENSE, GHN_LOOKUP_TREE = -1, 0, 1
+GHN_LOOKUP_AUTO, GHN_LOOKUP_DENSE, GHN_LOOKUP_TREE, GHN_LOOKUP_HASH = -1, 0, 1, 2
 
 P_ = ctypes.c_void_p
 

@@ -241,7 +241,36 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
                 ++nt;
                 if (ms >= 0.0 && (!have_best || ms < best->ms)) { *best = tr; have_best = true; }
             }
+            const bool tree = ix->info.lookup == GHN_LOOKUP_TREE;
             ghn_destroy(ix);
+            // a grid too fine for the dense table in few dimensions: also the hash lookup
+            // (FP32 walk; the grouped screen walks the tree either way)
+            const ghn_build_opts ho = {GHN_LOOKUP_HASH};
+            if (tree && f <= 6 && ghn_build_ex(points, n, f, dtype, targets, task, &w, 1, nullptr, &ho, stream, &ix) == GHN_OK) {
+                for (const Setting& st : settings) {
+                    if (st.prec != GHN_PREC_FP32) continue;
+                    ghn_predict_opts o = {stop, st.prec, st.flags, nullptr, nullptr, nullptr, nullptr, st.levels, nullptr, nullptr};
+                    double ms = -1.0;
+                    if (ghn_predict(ix, queries, m, k, &o, oi, nullptr, op, ws, ws_bytes, stream) == GHN_OK &&
+                        hipStreamSynchronize(s) == hipSuccess) {
+                        float best_ms = 1e30f;
+                        for (int rep = 0; rep < 3; ++rep) {
+                            float t = 0.0f;
+                            (void)hipEventRecord(e0, s);
+                            (void)ghn_predict(ix, queries, m, k, &o, oi, nullptr, op, ws, ws_bytes, stream);
+                            (void)hipEventRecord(e1, s);
+                            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess) break;
+                            best_ms = t < best_ms ? t : best_ms;
+                        }
+                        if (best_ms < 1e29f) ms = best_ms;
+                    }
+                    const ghn_tune_trial tr = {w, GHN_LOOKUP_HASH, st.prec, st.levels, st.flags, ms};
+                    if (trials && nt < max_trials) trials[nt] = tr;
+                    ++nt;
+                    if (ms >= 0.0 && (!have_best || ms < best->ms)) { *best = tr; have_best = true; }
+                }
+                ghn_destroy(ix);
+            }
         }
         if (!have_best) result = fail(GHN_E_UNSUPPORTED, "ghn_autotune: no candidate setting could be built and run");
     }
@@ -295,7 +324,8 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
     if (((uintptr_t)points % (dtype == GHN_BF16 ? 2 : 4)) || ((uintptr_t)targets % 4))
         return fail(GHN_E_INVALID_ARG, "ghn_build: misaligned points or targets");
     const int32_t want_lookup = bopts ? bopts->lookup : GHN_LOOKUP_AUTO;
-    if (want_lookup != GHN_LOOKUP_AUTO && want_lookup != GHN_LOOKUP_DENSE && want_lookup != GHN_LOOKUP_TREE)
+    if (want_lookup != GHN_LOOKUP_AUTO && want_lookup != GHN_LOOKUP_DENSE && want_lookup != GHN_LOOKUP_TREE &&
+        want_lookup != GHN_LOOKUP_HASH)
         return fail(GHN_E_INVALID_ARG, "ghn_build: bad lookup %d", want_lookup);
     float a[F_MAX], o[F_MAX];
     for (int j = 0; j < f; ++j) {
@@ -333,6 +363,8 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
     iv.n = n; iv.f = f; iv.dtype = dtype; iv.task = task; iv.lookup = LOOKUP_DENSE;
     int64_t box = 1;
     bool too_big = false;
+    uint64_t hbox = 1;  // the same product for the hash keys, up to 2^62
+    bool hash_too_big = false;
     for (int j = f - 1; j >= 0; --j) {
         iv.a[j] = a[j];
         iv.ainv[j] = 1.0 / (double)a[j];
@@ -343,17 +375,26 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
         const int64_t wj = (int64_t)iv.cmax[j] - iv.cmin[j] + 1;
         if (box > (int64_t(1) << 40) / wj) too_big = true;
         else box *= wj;
+        iv.hstride[j] = hbox;
+        if (hbox > (uint64_t(1) << 62) / (uint64_t)wj) hash_too_big = true;
+        else hbox *= (uint64_t)wj;
     }
     const bool dense_ok = !too_big && box <= dense_limit(n);
     const int32_t lookup = want_lookup == GHN_LOOKUP_AUTO ? (dense_ok ? GHN_LOOKUP_DENSE : GHN_LOOKUP_TREE) : want_lookup;
     if (lookup == GHN_LOOKUP_DENSE && !dense_ok)
         return fail(GHN_E_UNSUPPORTED, "ghn_build: the occupied box holds more than %lld cells, too many for the dense "
                     "table (use the tree lookup or a larger cell width)", (long long)dense_limit(n));
+    if (lookup == GHN_LOOKUP_HASH && hash_too_big)
+        return fail(GHN_E_KEY_OVERFLOW, "ghn_build: the occupied box holds more than 2^62 cells, too many for the "
+                    "hash keys (use the tree lookup or a larger cell width)");
     iv.lookup = lookup;
     int nbits = 0;
     if (lookup == GHN_LOOKUP_DENSE) {
         iv.box_cells = box;
         while (nbits < 64 && (uint64_t(1) << nbits) < (uint64_t)box) ++nbits;
+    } else if (lookup == GHN_LOOKUP_HASH) {
+        iv.box_cells = (int64_t)hbox;
+        while (nbits < 64 && (uint64_t(1) << nbits) < hbox) ++nbits;
     } else {
         iv.box_cells = too_big ? -1 : box;
         for (int j = 0; j < f; ++j) {
@@ -377,8 +418,8 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
         return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the index");
     const uint64_t* skeys = nullptr;
     const uint32_t* perm = nullptr;
-    if (lookup == GHN_LOOKUP_DENSE || nbits <= 64) {
-        e = lookup == GHN_LOOKUP_DENSE ? launch_dense_keys(points, n, f, dtype, iv, keys, vals, s)
+    if (lookup == GHN_LOOKUP_DENSE || lookup == GHN_LOOKUP_HASH || nbits <= 64) {
+        e = lookup != GHN_LOOKUP_TREE ? launch_dense_keys(points, n, f, dtype, iv, keys, vals, s)
                                        : launch_morton_keys(points, n, dtype, iv, nbits, 0, nullptr, keys, vals, s);
         if (e != hipSuccess) return hip_fail(e, "ghn_build: keys");
         bool in_alt = false;
@@ -422,7 +463,7 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
     iv.srec = srec;
     iv.sxn = sxn;
 
-    // 4. occupied cells (both lookups): heads of equal-key runs, their ranks, first
+    // 4. occupied cells (every lookup): heads of equal-key runs, their ranks, first
     //    points and ids, then the bounding-box levels above them
     uint32_t *heads, *rank;
     void* stemp;
@@ -475,8 +516,21 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
     iv.node_lo = nlo;
     iv.node_hi = nhi;
     size_t table_bytes = (size_t)(ncell + 1) * 4 + (size_t)ncell * f * 4 + (size_t)total * f * 8;
-    // 5. dense table over the whole box
+    // 5. dense table over the whole box, or the hash table of the occupied cells
     iv.cell_start = cf;
+    if (lookup == GHN_LOOKUP_HASH) {
+        uint64_t cap = 64;
+        while (cap < 2 * (uint64_t)ncell) cap <<= 1;
+        uint64_t* hk;
+        uint32_t* hv;
+        if (keep.alloc((void**)&hk, (size_t)cap * 8) || keep.alloc((void**)&hv, (size_t)cap * 4))
+            return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the hash table");
+        if ((e = launch_hash_build(skeys, cf, ncell, hk, hv, cap - 1, s)) != hipSuccess) return hip_fail(e, "ghn_build: hash table");
+        iv.hkeys = hk;
+        iv.hvals = hv;
+        iv.hmask = cap - 1;
+        table_bytes += (size_t)cap * 12;
+    }
     if (lookup == GHN_LOOKUP_DENSE) {
         uint32_t* cs;
         if (keep.alloc((void**)&cs, (size_t)(box + 1) * 4)) return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the table");
@@ -652,7 +706,7 @@ static ghn_status predict_common(const ghn_index* index, const float* queries, i
     }
     if (o.walk_event_begin && (e = hipEventRecord((hipEvent_t)o.walk_event_begin, s)) != hipSuccess)
         return hip_fail(e, "ghn_predict: walk_event_begin");
-    e = index->view.lookup == LOOKUP_DENSE ? launch_predict_dense(pa, s) : launch_predict_tree(pa, s);
+    e = index->view.lookup == LOOKUP_TREE ? launch_predict_tree(pa, s) : launch_predict_dense(pa, s);
     if (e != hipSuccess) return hip_fail(e, "ghn_predict: launch");
     if (o.walk_event_end && (e = hipEventRecord((hipEvent_t)o.walk_event_end, s)) != hipSuccess)
         return hip_fail(e, "ghn_predict: walk_event_end");

@@ -57,7 +57,7 @@ void k_predict_batched(const BatchItem* __restrict__ items, int n_items, int64_t
             const IndexView& ix = *it.ix;
             const int64_t qi = w - it.first;
             if (!TREE && ix.lookup != LOOKUP_DENSE) continue;  // not launched so (the host checks the items)
-            if (ix.lookup == LOOKUP_DENSE) walk_dense<FT, STOP>(ix, it.io, qi, s_begin[wv], s_pre[wv], s_key[wv]);
+            if (ix.lookup == LOOKUP_DENSE) walk_dense<FT, STOP, false>(ix, it.io, qi, s_begin[wv], s_pre[wv], s_key[wv]);
             // the tree walk's pending list only where it costs no occupancy: the f = 8
             // instance already runs at two waves per SIMD; the others hold the dense walk
             // at three or four, which the extra state would lower

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(BT) void k_dense_keys(const void* pts, int64_t n, i
         for (int j = 0; j < f; ++j) {
             float x = load_coord(pts, i * f + j, dtype);
             int64_t c = exact_floor_div(__dadd_rn((double)x, -(double)iv.o[j]), (double)iv.a[j]);
-            key += (uint64_t)(c - iv.cmin[j]) * (uint64_t)iv.stride[j];
+            key += (uint64_t)(c - iv.cmin[j]) * (iv.lookup == LOOKUP_HASH ? iv.hstride[j] : (uint64_t)iv.stride[j]);
         }
         keys[i] = key;
         vals[i] = (uint32_t)i;
@@ -282,6 +282,32 @@ __global__ __launch_bounds__(BT) void k_dense_cell_start(const uint64_t* __restr
     }
 }
 
+// Hash table of the occupied cells: every slot free, then each cell claims the
+// first free slot of its probe sequence (keys are distinct, and the table has
+// more slots than cells, so every insertion ends).
+__global__ __launch_bounds__(BT) void k_hash_clear(uint64_t* __restrict__ hkeys, int64_t cap) {
+    for (int64_t i = blockIdx.x * (int64_t)BT + threadIdx.x; i < cap; i += (int64_t)gridDim.x * BT)
+        hkeys[i] = HASH_EMPTY;
+}
+
+__global__ __launch_bounds__(BT) void k_hash_insert(const uint64_t* __restrict__ skeys,
+                                                    const uint32_t* __restrict__ cell_first, int64_t ncell,
+                                                    uint64_t* hkeys, uint32_t* __restrict__ hvals, uint64_t mask) {
+    for (int64_t c = blockIdx.x * (int64_t)BT + threadIdx.x; c < ncell; c += (int64_t)gridDim.x * BT) {
+        const uint64_t key = skeys[cell_first[c]];
+        uint64_t h = hash_slot(key, mask);
+        for (uint64_t i = 0; i <= mask; ++i) {
+            const unsigned long long prev = atomicCAS((unsigned long long*)&hkeys[h], (unsigned long long)HASH_EMPTY,
+                                                      (unsigned long long)key);
+            if (prev == HASH_EMPTY) {
+                hvals[h] = (uint32_t)c;
+                break;
+            }
+            h = (h + 1) & mask;
+        }
+    }
+}
+
 // stats[0] += non-empty cells, stats[1] = max(points in one cell).
 __global__ __launch_bounds__(BT) void k_dense_cell_stats(const uint32_t* __restrict__ cs, int64_t box_cells,
                                                          int64_t* stats) {
@@ -381,6 +407,15 @@ hipError_t launch_widen_points(const void* pts, int64_t count, int32_t dtype, fl
 
 hipError_t launch_screen_records(const IndexView& iv, uint16_t* rec, float* xn, hipStream_t s) {
     hipLaunchKernelGGL(k_screen_records, dim3(grid_for(iv.n, BT)), dim3(BT), 0, s, iv, rec, xn);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_build(const uint64_t* sorted_keys, const uint32_t* cell_first, int64_t ncell, uint64_t* hkeys,
+                             uint32_t* hvals, uint64_t mask, hipStream_t s) {
+    const int64_t cap = (int64_t)mask + 1;
+    hipLaunchKernelGGL(k_hash_clear, dim3(grid_for(cap, BT)), dim3(BT), 0, s, hkeys, cap);
+    hipLaunchKernelGGL(k_hash_insert, dim3(grid_for(ncell, BT)), dim3(BT), 0, s, sorted_keys, cell_first, ncell, hkeys,
+                       hvals, mask);
     return hipGetLastError();
 }
 

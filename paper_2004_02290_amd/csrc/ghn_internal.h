@@ -19,7 +19,8 @@ constexpr int64_t COORD_LIMIT = int64_t(1) << 27;
 // 2^29 in magnitude, where the exact floor below is verified.
 constexpr int64_t CLAMP = int64_t(1) << 28;
 
-enum Lookup : int32_t { LOOKUP_DENSE = 0, LOOKUP_TREE = 1 };
+enum Lookup : int32_t { LOOKUP_DENSE = 0, LOOKUP_TREE = 1, LOOKUP_HASH = 2 };
+constexpr uint64_t HASH_EMPTY = ~0ull;  // free slot of the cell hash (keys are < 2^62)
 constexpr int TREE_LEVELS_MAX = 6;  // levels of the bounding-box tree, cells included
 
 // Device-side view of an index, passed by value to kernels.
@@ -50,6 +51,12 @@ struct IndexView {
     int32_t cmin[F_MAX];
     int32_t cmax[F_MAX];
     uint32_t stride[F_MAX];     // dense-box linear index stride per dimension (last = 1)
+    // hash lookup: 64-bit row-major strides over the box, and the open-addressing
+    // table of occupied cells (key -> cell index, linear probing from hash_slot)
+    uint64_t hstride[F_MAX];
+    const uint64_t* hkeys;      // hcap keys, HASH_EMPTY where free
+    const uint32_t* hvals;      // hcap cell indexes
+    uint64_t hmask;             // hcap - 1 (hcap a power of two >= 2 num_cells)
     // bf16 screen records (grouped matrix-core screen): per point in cell order,
     // x' = fl32(x - c0) split as hi = bf16(x'), lo = bf16(x' - hi), stored as
     // [hi(sp), lo(sp)] with the dimensions past f zero, and xn = |x'|^2 in FP32
@@ -58,6 +65,32 @@ struct IndexView {
     int32_t sp;                 // padded dimension: 8, 16 or 32
     float c0[F_MAX];            // screen centre (centre of the occupied box)
 };
+
+// First slot of a cell key in the hash table: the SplitMix64 finalizer (Steele,
+// Lea and Flood, 2014) spreads row-major keys, whose low bits are the last
+// dimension's id, over the whole table.
+__host__ __device__ __forceinline__ uint64_t hash_slot(uint64_t key, uint64_t mask) {
+    key ^= key >> 30;
+    key *= 0xbf58476d1ce4e5b9ull;
+    key ^= key >> 27;
+    key *= 0x94d049bb133111ebull;
+    key ^= key >> 31;
+    return key & mask;
+}
+
+// Cell index of a key, or -1 if the cell is empty.  The table is at most half
+// full, so a free slot ends every probe sequence; `reads` counts the slots read.
+__device__ __forceinline__ int64_t hash_find(const IndexView& ix, uint64_t key, uint32_t& reads) {
+    uint64_t h = hash_slot(key, ix.hmask);
+    for (uint64_t i = 0; i <= ix.hmask; ++i) {
+        const uint64_t k = ix.hkeys[h];
+        ++reads;
+        if (k == key) return (int64_t)ix.hvals[h];
+        if (k == HASH_EMPTY) return -1;
+        h = (h + 1) & ix.hmask;
+    }
+    return -1;
+}
 
 // ---------------------------------------------------------------------------------------
 // Exact floor of v / a (a > 0 finite, v finite): the largest integer t with t * a <= v.
@@ -192,6 +225,8 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 // Host-side launchers (defined in the .hip files).
 hipError_t launch_cells_minmax(const void* pts, int64_t n, int32_t f, int32_t dtype, const float* a,
                                const float* o, int32_t* d_minmax, int32_t* d_flags, hipStream_t s);
+hipError_t launch_hash_build(const uint64_t* sorted_keys, const uint32_t* cell_first, int64_t ncell, uint64_t* hkeys,
+                             uint32_t* hvals, uint64_t mask, hipStream_t s);
 hipError_t launch_dense_keys(const void* pts, int64_t n, int32_t f, int32_t dtype, const IndexView& iv,
                              uint64_t* keys, uint32_t* vals, hipStream_t s);
 size_t radix_sort_temp_bytes(int64_t n);

@@ -12,10 +12,12 @@ constexpr int WPB = PT / WAVE;
 // waves share a SIMD instead of 6; the extra waves hide more of the walk's latency
 // (measured: 8 % faster on the 4-D clusters).  Wider instances keep the compiler's
 // own choice.
-template <int FT> constexpr int dense_waves_per_eu() { return FT >= 1 && FT <= 4 ? 8 : 1; }
+// (The hash-lookup instances keep the compiler's choice.)
+template <int FT, bool HASH> constexpr int dense_waves_per_eu() { return !HASH && FT >= 1 && FT <= 4 ? 8 : 1; }
 
-template <int FT, int STOP>
-__global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(dense_waves_per_eu<FT>()))) void k_predict_dense(PredictArgs A) {
+template <int FT, int STOP, bool HASH>
+__global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(dense_waves_per_eu<FT, HASH>())))
+void k_predict_dense(PredictArgs A) {
     __shared__ uint32_t s_begin[WPB][RUN_CAP];
     __shared__ uint32_t s_pre[WPB][RUN_CAP];
     __shared__ uint32_t s_key[WPB][RUN_CAP];
@@ -23,7 +25,7 @@ __global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(dense_waves_
     const int64_t slot = wave_slot(A, WPB);
     if (slot >= A.m) return;
     const int64_t qi = A.order ? (int64_t)A.order[slot] : slot;
-    walk_dense<FT, STOP>(A.ix, A.io, qi, s_begin[wv], s_pre[wv], s_key[wv]);
+    walk_dense<FT, STOP, HASH>(A.ix, A.io, qi, s_begin[wv], s_pre[wv], s_key[wv]);
 }
 
 // Sort key of a query: Morton interleave of its central cell id clamped to the
@@ -63,13 +65,19 @@ __global__ __launch_bounds__(256) void k_query_keys(const float* __restrict__ qs
     }
 }
 
+template <int FT, bool HASH>
+void launch_stop(const PredictArgs& a, dim3 grid, dim3 block, hipStream_t s) {
+    if (a.stop == GHN_STOP_PAPER)
+        hipLaunchKernelGGL((k_predict_dense<FT, GHN_STOP_PAPER, HASH>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((k_predict_dense<FT, GHN_STOP_EXACT, HASH>), grid, block, 0, s, a);
+}
+
 template <int FT>
 hipError_t launch_ft(const PredictArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)((a.m + WPB - 1) / WPB)), block(PT);
-    if (a.stop == GHN_STOP_PAPER)
-        hipLaunchKernelGGL((k_predict_dense<FT, GHN_STOP_PAPER>), grid, block, 0, s, a);
-    else
-        hipLaunchKernelGGL((k_predict_dense<FT, GHN_STOP_EXACT>), grid, block, 0, s, a);
+    if (a.ix.lookup == LOOKUP_HASH) launch_stop<FT, true>(a, grid, block, s);
+    else launch_stop<FT, false>(a, grid, block, s);
     return hipGetLastError();
 }
 

@@ -15,6 +15,8 @@
 // nor the PAPER rule's "buffer changed in this layer" signal can change.
 #pragma once
 
+#include <type_traits>
+
 #include "ghn_walk.h"
 
 namespace ghn {
@@ -31,9 +33,39 @@ constexpr RowMagic make_row_magic() {
 }
 static __constant__ RowMagic kRowMagic = make_row_magic();
 
-template <int FT, int STOP>
+// Hash lookup: the points of the occupied cells t0..t1 (ids along the last
+// dimension) of the row whose key without the last dimension is `lin`.  Keys are
+// row-major with the last dimension fastest, so these cells' points are one
+// contiguous run, from the first occupied cell of the range to the last.
+__device__ __forceinline__ void hash_run(const IndexView& ix, uint64_t lin, int32_t t0, int32_t t1, int32_t cmin_l,
+                                         uint32_t& b, uint32_t& n, uint32_t& reads) {
+    b = 0;
+    n = 0;
+    int64_t first = -1;
+    int32_t t = t0;
+    for (; t <= t1; ++t) {
+        first = hash_find(ix, lin + (uint64_t)(t - cmin_l), reads);
+        if (first >= 0) break;
+    }
+    if (first < 0) return;
+    int64_t last = first;
+    for (int32_t u = t1; u > t; --u) {
+        const int64_t c = hash_find(ix, lin + (uint64_t)(u - cmin_l), reads);
+        if (c >= 0) {
+            last = c;
+            break;
+        }
+    }
+    b = ix.cell_first[first];
+    n = ix.cell_first[last + 1] - b;
+}
+
+// HASH: the cells come from the hash table (GHN_LOOKUP_HASH) instead of the dense
+// offset table; the enumeration, bounds and scoring are the same.
+template <int FT, int STOP, bool HASH>
 __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& io, int64_t qi,
                                            uint32_t* s_begin, uint32_t* s_pre, uint32_t* s_key) {
+    using Lin = typename std::conditional<HASH, uint64_t, uint32_t>::type;  // row key without the last dimension
     const int lane = lane_id();
     const int f = FT > 0 ? FT : ix.f;
     const int k = io.k;
@@ -86,20 +118,28 @@ __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& i
                 if (l == 0) {
                     // layer 0 is the central cell alone (l0 = 0: it lies inside the box)
                     if (lane == 0) {
-                        uint32_t lin = 0;
+                        Lin lin = 0;
 #pragma unroll
                         for (int j = 0; j < (FT > 0 ? FT : F_MAX); ++j) {
                             if (FT == 0 && j >= f) break;
-                            lin += (uint32_t)(Q.c[j] - ix.cmin[j]) * ix.stride[j];
+                            lin += (Lin)(Q.c[j] - ix.cmin[j]) * (HASH ? (Lin)ix.hstride[j] : (Lin)ix.stride[j]);
                         }
-                        b0 = ix.cell_start[lin];
-                        n0 = ix.cell_start[lin + 1] - b0;
-                        probes_l = 2;
+                        if constexpr (HASH) {
+                            const int64_t c = hash_find(ix, lin, probes_l);
+                            if (c >= 0) {
+                                b0 = ix.cell_first[c];
+                                n0 = ix.cell_first[c + 1] - b0;
+                            }
+                        } else {
+                            b0 = ix.cell_start[lin];
+                            n0 = ix.cell_start[lin + 1] - b0;
+                            probes_l = 2;
+                        }
                     }
                 } else if (r < rows) {
                     // decode row r: ids of dimensions 0..L-1, the last of them fastest
                     int32_t maxoff = 0;
-                    uint32_t lin = 0;
+                    Lin lin = 0;
                     double lb = 0.0;
                     uint64_t rem64 = (uint64_t)r;
                     uint32_t rem32 = (uint32_t)r;
@@ -118,7 +158,7 @@ __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& i
                         }
                         const int32_t oj = lo[j] + digit;
                         maxoff = max(maxoff, oj > Q.c[j] ? oj - Q.c[j] : Q.c[j] - oj);
-                        lin += (uint32_t)(oj - ix.cmin[j]) * ix.stride[j];
+                        lin += (Lin)(oj - ix.cmin[j]) * (HASH ? (Lin)ix.hstride[j] : (Lin)ix.stride[j]);
                         const double g = gap_to_cells(Q.v[j], oj, oj, (double)ix.a[j]);
                         lb = __dadd_rn(lb, __dmul_rn(g, g));
                     }
@@ -142,11 +182,15 @@ __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& i
                                 ta = max(ta, (int32_t)fmin(fmax(lb_t, -0x1p30), 0x1p30));
                             }
                             if (ta <= tb) {
-                                const uint32_t s0 = ix.cell_start[lin + (uint32_t)(ta - ix.cmin[L])];
-                                const uint32_t s1 = ix.cell_start[lin + (uint32_t)(tb - ix.cmin[L]) + 1];
-                                b0 = s0;
-                                n0 = s1 - s0;
-                                probes_l += 2;
+                                if constexpr (HASH) {
+                                    hash_run(ix, lin, ta, tb, ix.cmin[L], b0, n0, probes_l);
+                                } else {
+                                    const uint32_t s0 = ix.cell_start[lin + (uint32_t)(ta - ix.cmin[L])];
+                                    const uint32_t s1 = ix.cell_start[lin + (uint32_t)(tb - ix.cmin[L]) + 1];
+                                    b0 = s0;
+                                    n0 = s1 - s0;
+                                    probes_l += 2;
+                                }
                                 if (prune) {
                                     const double g = gap_to_cells(Q.v[L], ta, tb, aL);
                                     key0 = lb_key(__dadd_rn(lb, __dmul_rn(g, g)) * LB_SHRINK);
@@ -167,16 +211,22 @@ __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& i
                                     lbe = __dadd_rn(lb, __dmul_rn(g, g)) * LB_SHRINK;
                                     if (lbe > st.tau) continue;
                                 }
-                                const uint32_t s0 = ix.cell_start[lin + (uint32_t)(t - ix.cmin[L])];
-                                const uint32_t s1 = ix.cell_start[lin + (uint32_t)(t - ix.cmin[L]) + 1];
-                                probes_l += 2;
-                                if (e == 0) { b0 = s0; n0 = s1 - s0; key0 = lb_key(lbe); }
-                                else { b1 = s0; n1 = s1 - s0; key1 = lb_key(lbe); }
+                                uint32_t s0, sn;
+                                if constexpr (HASH) {
+                                    hash_run(ix, lin, t, t, ix.cmin[L], s0, sn, probes_l);
+                                } else {
+                                    s0 = ix.cell_start[lin + (uint32_t)(t - ix.cmin[L])];
+                                    sn = ix.cell_start[lin + (uint32_t)(t - ix.cmin[L]) + 1] - s0;
+                                    probes_l += 2;
+                                }
+                                if (e == 0) { b0 = s0; n0 = sn; key0 = lb_key(lbe); }
+                                else { b1 = s0; n1 = sn; key1 = lb_key(lbe); }
                             }
                         }
                     }
                 }
-                st.probes += 2 * (__popcll(ballot(probes_l >= 2)) + __popcll(ballot(probes_l >= 4)));
+                if constexpr (HASH) st.probes += wave_sum_u32(probes_l);
+                else st.probes += 2 * (__popcll(ballot(probes_l >= 2)) + __popcll(ballot(probes_l >= 4)));
                 score_runs<FT>(ix, Q.q, f, k, b0, n0, key0, b1, n1, key1, prune, s_begin, s_pre, s_key, st);
             }
         }

@@ -359,6 +359,99 @@ def test_tree_walk_many_layers_and_pending_overflow(ghn):
         g.close()
 
 
+# ---------------------------------------------------------------------------------- hash lookup
+HASH = 2
+
+
+@pytest.mark.parametrize("f", [1, 2, 3, 4, 5, 8])
+def test_hash_lookup_uniform(ghn, f):
+    width = {1: 0.003, 2: 0.05, 3: 0.1, 4: 0.2, 5: 0.3, 8: 0.5}[f]
+    prob = W.uniform_problem(n=6000, m=301, f=f, k=9, seed=70 + f, width=width, q_lo=-0.3, q_hi=1.3)
+    ix, _ = _check_exact(ghn, prob, lookup=HASH)
+    assert ix.info.lookup == HASH
+    _check_paper(ghn, prob, lookup=HASH)
+
+
+def test_hash_lookup_edge_cases(ghn):
+    lat = W.lattice_problem(n=3000, m=300, f=3, k=12, seed=17)
+    _check_exact(ghn, lat, lookup=HASH)
+    _check_paper(ghn, lat, lookup=HASH)
+    far = W.uniform_problem(n=5000, m=120, f=3, k=5, seed=15, width=0.1)
+    far.queries[:40] *= 1e3
+    far.queries[40:80] -= 37.0
+    _check_exact(ghn, far, lookup=HASH)
+    _check_paper(ghn, far, lookup=HASH)
+    one = W.uniform_problem(n=1, m=20, f=2, k=1, seed=13, width=0.5, q_lo=-5, q_hi=5)
+    _check_exact(ghn, one, lookup=HASH)
+    _check_paper(ghn, one, lookup=HASH)
+    widths = np.array([0.31, 0.07, 0.19], np.float32)
+    origin = np.array([-0.123, 0.05, 1.7], np.float32)
+    wo = W.uniform_problem(n=8000, m=200, f=3, k=9, seed=121, lo=-2.0, hi=2.0, q_lo=-3.0, q_hi=3.0)
+    _check_exact(ghn, wo, widths=widths, origin=origin, lookup=HASH)
+    _check_paper(ghn, wo, widths=widths, origin=origin, lookup=HASH)
+
+
+def test_hash_equals_dense_and_tree(ghn):
+    """Same neighbours, stop layers and candidate counts as the dense table (the walk
+    enumerates the same runs); the same results as the tree."""
+    prob = W.make("clusters4d", n=40_000, m=2_000)
+    for stop in (ghn.GHN_STOP_EXACT, ghn.GHN_STOP_PAPER):
+        a = _run(ghn, _index(ghn, prob, lookup=0), prob.queries, prob.k, stop)
+        b = _run(ghn, _index(ghn, prob, lookup=HASH), prob.queries, prob.k, stop)
+        c = _run(ghn, _index(ghn, prob, lookup=TREE), prob.queries, prob.k, stop)
+        _assert_same(b, a, "hash vs dense", check_layers=True)
+        assert np.array_equal(a["cands"], b["cands"])
+        _assert_same(b, c, "hash vs tree", check_layers=True)
+
+
+def test_hash_fine_grid_against_oracle(ghn):
+    """A grid too fine for the dense table (about 0.1 points per cell): several
+    layers per query, every generated cell looked up."""
+    prob = W.make("clusters4d", n=200_000, m=400)
+    width = 0.012
+    ix = _index(ghn, prob, widths=width, lookup=HASH)
+    assert ix.info.lookup == HASH and ix.info.box_cells > 16 * prob.n
+    g = oracle.Grid(prob.points, prob.targets, prob.task, width)
+    for stop, ostop in ((ghn.GHN_STOP_EXACT, oracle.STOP_EXACT), (ghn.GHN_STOP_PAPER, oracle.STOP_PAPER)):
+        got = _run(ghn, ix, prob.queries, prob.k, stop)
+        _assert_same(got, g.predict(prob.queries, prob.k, ostop), "fine hash grid, stop %d" % stop, check_layers=True)
+        assert got["stop_layer"].max() >= 2
+    g.close()
+
+
+def test_hash_index_in_batches_bf16_and_save_load(ghn):
+    import torch
+    prob = W.uniform_problem(n=20_000, m=500, f=3, k=7, seed=91, width=0.04)
+    ix = _index(ghn, prob, lookup=HASH)
+    want = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_EXACT)
+    # grouped bf16 screen (walks the index's tree)
+    _assert_same(_run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_EXACT, prec=MFMA), want, "hash index, bf16")
+    # persistent launch (tree walk for hash items)
+    oi = torch.full((prob.m, prob.k), -7, dtype=torch.int64, device="cuda")
+    op = torch.full((prob.m,), -7, dtype=torch.int32, device="cuda")
+    od = torch.zeros((prob.m, prob.k), dtype=torch.float64, device="cuda")
+    q = _dev(prob.queries)
+    ws = torch.empty(ghn.ghn_batch_workspace_bytes(1), dtype=torch.uint8, device="cuda")
+    batch = ghn.ghn_batch_prepare([(ix.handle, q, prob.k, oi, op, od)], ws)
+    ghn.ghn_predict_batched(batch)
+    torch.cuda.synchronize()
+    ghn.ghn_batch_destroy(batch)
+    _assert_same(dict(idx=oi.cpu().numpy(), pred=op.cpu().numpy(), d2=od.cpu().numpy()), want, "hash index, batch")
+    # save / load keeps the lookup
+    ix2 = ghn.Index.load(ix.save())
+    assert ix2.info.lookup == HASH
+    _assert_same(_run(ghn, ix2, prob.queries, prob.k, ghn.GHN_STOP_EXACT), want, "hash index, reloaded")
+
+
+def test_hash_key_overflow_refused(ghn):
+    # cell ids up to 1e8 (inside the +-2^27 id range) in 3 dimensions: a box of about
+    # 1e24 cells, beyond the 2^62 of the hash keys
+    pts = np.random.default_rng(3).random((500, 3)).astype(np.float32)
+    with pytest.raises(ghn.GHNError) as e:
+        ghn.Index(_dev(pts), _dev(np.zeros(500, np.int32)), 0, 1e-8, lookup=HASH)
+    assert e.value.code == -5 and "hash" in str(e.value)
+
+
 def test_skew8d_regression_small(ghn):
     prob = W.make("skew8d", n=100_000, m=1_000)
     ix, _ = _check_exact(ghn, prob)
@@ -588,11 +681,15 @@ def test_autotune_exact_and_paper(ghn, tmp_path):
     cache = str(tmp_path / "tune.json")
     best = autotune.tune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_EXACT, cache_path=cache)
     assert best["ms"] > 0 and best["cell_width"] > 0
-    assert len(best["trials"]) == 6 * 6  # widths x (2 FP32 settings + bf16 at 4 grouping levels)
+    # widths x (2 FP32 settings + bf16 at 4 grouping levels), plus the 2 FP32 settings on
+    # the hash lookup for every width whose build chose the tree (4 dimensions)
+    tree_widths = {t["cell_width"] for t in best["trials"] if t["lookup"] == TREE}
+    assert len(best["trials"]) == 6 * 6 + 2 * len(tree_widths)
+    assert sum(t["lookup"] == HASH for t in best["trials"]) == 2 * len(tree_widths)
     again = autotune.tune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_EXACT, cache_path=cache)
     assert again["cell_width"] == best["cell_width"]  # served from the cache
     # the tuned setting still returns the brute-force neighbours
-    ix = ghn.Index(pts, tgt, prob.task, best["cell_width"])
+    ix = ghn.Index(pts, tgt, prob.task, best["cell_width"], lookup=best["lookup"])
     got = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_EXACT, prec=best["prec"], flags=best["flags"],
                group_levels=best["group_levels"])
     bi, bd, bp = oracle.bruteforce(prob.points, prob.targets, prob.task, prob.queries, prob.k)
