@@ -107,19 +107,27 @@ def test_skew8d_full_size(ghn, width_scale):
     ix.close()
 
 
-def test_bf16_16d_full_size(ghn):
-    """4M bf16 points in 16 dimensions, 500k queries, k = 32: the FP32 tree walk and
-    the grouped bf16 screen at its default grouping, on sampled rows."""
+@pytest.mark.parametrize("width_scale", [1.0, 2.0])
+def test_bf16_16d_full_size(ghn, width_scale):
+    """4M bf16 points in 16 dimensions, 500k queries, k = 32, at the calibrated width and
+    the twice coarser one the autotuner picks: the FP32 tree walk (input and Morton
+    order) and the grouped bf16 screen (default grouping and 2^2-cell groups), on
+    sampled rows."""
     prob = W.make("bf16_16d")
-    ix = ghn.Index(_pts(prob), _dev(prob.targets), prob.task, prob.cell_width)
+    width = float(np.float32(prob.cell_width * width_scale))
+    ix = ghn.Index(_pts(prob), _dev(prob.targets), prob.task, width)
     rows = _sample(prob.m, 200, 12)
-    g = oracle.Grid(prob.points_f32(), prob.targets, prob.task, prob.cell_width)
+    g = oracle.Grid(prob.points_f32(), prob.targets, prob.task, width)
     want = g.predict(prob.queries[rows], prob.k, oracle.STOP_EXACT)
     g.close()
     bw = _brute(prob, rows)
-    _check(ghn, prob, ix, rows, bw, "bf16_16d FP32", layers_from=want["stop_layer"], prec=FP32,
+    what = "bf16_16d w=%.6g" % width
+    _check(ghn, prob, ix, rows, bw, what + " FP32", layers_from=want["stop_layer"], prec=FP32,
            flags=ghn.GHN_FLAG_NO_SORT)
-    _check(ghn, prob, ix, rows, bw, "bf16_16d bf16", layers_from=want["stop_layer"], prec=BF16)
+    _check(ghn, prob, ix, rows, bw, what + " FP32 sorted", layers_from=want["stop_layer"], prec=FP32)
+    _check(ghn, prob, ix, rows, bw, what + " bf16", layers_from=want["stop_layer"], prec=BF16)
+    _check(ghn, prob, ix, rows, bw, what + " bf16 levels 2", layers_from=want["stop_layer"], prec=BF16,
+           group_levels=2)
     ix.close()
 
 
