@@ -206,7 +206,7 @@ size_t ghn_predict_workspace_bytes(const ghn_index* index, int64_t m, int32_t k,
  *             the sort needs the workspace.
  * Asynchronous on `stream`; allocates nothing and launches only kernels (no
  * memset, copy or host synchronisation), so a call can be captured in a graph
- * and replayed.  m = 0 is a no-op.  A query
+ * and replayed.  m = 0 is a no-op; m must be below 2^32.  A query
  * with a non-finite coordinate gets ids -1, distances NaN and prediction -1
  * (classification) or NaN (regression).
  * Errors: GHN_E_INVALID_ARG, GHN_E_K_GT_N, GHN_E_WORKSPACE, GHN_E_UNSUPPORTED,

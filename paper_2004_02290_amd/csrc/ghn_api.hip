@@ -657,6 +657,7 @@ static ghn_status predict_common(const ghn_index* index, const float* queries, i
     if ((o.flags & GHN_FLAG_MEDIAN) && index->info.task != GHN_REGRESS)
         return fail(GHN_E_INVALID_ARG, "ghn_predict: GHN_FLAG_MEDIAN needs a regression index");
     if (m == 0) return GHN_OK;
+    if (m >= (int64_t(1) << 32)) return fail(GHN_E_INVALID_ARG, "ghn_predict: m=%lld too large for one call (< 2^32)", (long long)m);
     if (!queries || !out_idx || !out_pred) return fail(GHN_E_INVALID_ARG, "ghn_predict: queries, out_idx and out_pred must not be NULL");
     if (((uintptr_t)queries % 4) || ((uintptr_t)out_idx % 8) || ((uintptr_t)out_pred % 4) || ((uintptr_t)out_d2 % 8))
         return fail(GHN_E_INVALID_ARG, "ghn_predict: misaligned array");
@@ -688,7 +689,6 @@ static ghn_status predict_common(const ghn_index* index, const float* queries, i
         if (!ws || ws_bytes < need)
             return fail(GHN_E_WORKSPACE, "ghn_predict: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
         if ((uintptr_t)ws % 256) return fail(GHN_E_INVALID_ARG, "ghn_predict: workspace must be 256-byte aligned");
-        if (m >= (int64_t(1) << 32)) return fail(GHN_E_INVALID_ARG, "ghn_predict: m=%lld too large for one call", (long long)m);
         const int levels = brute ? 32 : o.stop == GHN_STOP_PAPER ? 0 : (o.group_levels >= 0 ? o.group_levels : (index->info.f >= 12 ? 3 : 1));
         int bits = 0;
         e = run_grouped(pa, levels, ws, s, &bits, (hipEvent_t)o.walk_event_begin, (hipEvent_t)o.walk_event_end, brute);
