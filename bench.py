@@ -283,6 +283,16 @@ def bench_multi(args, ghn, W, torch):
                 ghn.ghn_predict(ix.handle, q, p.k, oi, op, None, stop, ghn.GHN_PREC_BF16_MFMA, 0, ws=w)
         ms, per = timeit(per_item16)
         forms["bf16_per_index"] = dict(ms=ms, per=per)
+        # the same grouped launches, all captured in one graph and replayed as one launch
+        g16 = torch.cuda.CUDAGraph()
+        side16 = torch.cuda.Stream()
+        side16.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side16):
+            with torch.cuda.graph(g16, stream=side16):
+                per_item16()
+        torch.cuda.current_stream().wait_stream(side16)
+        ms, per = timeit(g16.replay)
+        forms["bf16_per_index_graph"] = dict(ms=ms, per=per)
     best = min(forms, key=lambda n: forms[n]["ms"])
     B = forms[best]
     achieved = alg_bytes / (B["ms"] * 1e-3) / 1e9

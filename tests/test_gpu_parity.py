@@ -648,6 +648,49 @@ def test_batched_graph_replay(ghn):
     ghn.ghn_batch_destroy(batch)
 
 
+def test_many_indexes_bf16_in_one_graph(ghn):
+    """The grouped bf16 predicts of many indexes captured in one graph: every replay
+    (with eager work in between) equals the eager calls."""
+    import torch
+    probs = _multi(problems=10, n_hi=30_000, m_hi=3_000, seed=19)
+    runs = []
+    for p in probs:
+        ix = _index(ghn, p)
+        q = _dev(p.queries)
+        oi = torch.empty((p.m, p.k), dtype=torch.int64, device="cuda")
+        op = torch.empty(p.m, dtype=torch.int32, device="cuda")
+        nb = ghn.ghn_predict_workspace_bytes(ix.handle, p.m, p.k, ghn.GHN_STOP_EXACT, MFMA, 0)
+        ws = torch.empty(max(nb, 1), dtype=torch.uint8, device="cuda")
+        runs.append((p, ix, q, oi, op, ws))
+
+    def all_predicts():
+        for p, ix, q, oi, op, ws in runs:
+            ghn.ghn_predict(ix.handle, q, p.k, oi, op, None, ghn.GHN_STOP_EXACT, MFMA, 0, ws=ws)
+
+    all_predicts()
+    torch.cuda.synchronize()
+    want = [(oi.clone(), op.clone()) for _, _, _, oi, op, _ in runs]
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            all_predicts()
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        for _, _, _, oi, op, ws in runs:
+            oi.fill_(-1); op.fill_(-1); ws.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (_, _, _, oi, op, _), (wi, wp) in zip(runs, want):
+            assert torch.equal(oi, wi) and torch.equal(op, wp), rep
+    for (p, _, _, _, _, _), (wi, wp) in zip(runs, want):
+        rows = np.arange(min(p.m, 100))
+        bi, bd, bp = oracle.bruteforce(p.points, p.targets, p.task, p.queries[rows], p.k)
+        assert np.array_equal(wi.cpu().numpy()[rows], bi) and np.array_equal(wp.cpu().numpy()[rows], bp)
+
+
 def test_batch_errors(ghn):
     import torch
     probs = _multi(problems=2, n_hi=5_000, m_hi=100, seed=1)
