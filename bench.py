@@ -275,12 +275,14 @@ def bench_multi(args, ghn, W, torch):
         ms, per = timeit(g.replay)
         forms["fp32_batched_graph"] = dict(ms=ms, per=per)
     if "bf16" in args.forms:
-        wss = [torch.empty(max(ghn.ghn_predict_workspace_bytes(ix.handle, p.m, p.k, stop, ghn.GHN_PREC_BF16_MFMA), 1),
+        wss = [torch.empty(max(ghn.ghn_predict_workspace_bytes(ix.handle, p.m, p.k, stop, ghn.GHN_PREC_BF16_MFMA, 0,
+                                                               args.group_levels), 1),
                            dtype=torch.uint8, device=dev) for p, ix in zip(probs, idxs)]
 
         def per_item16():
             for p, ix, q, (oi, op), w in zip(probs, idxs, qs, outs, wss):
-                ghn.ghn_predict(ix.handle, q, p.k, oi, op, None, stop, ghn.GHN_PREC_BF16_MFMA, 0, ws=w)
+                ghn.ghn_predict(ix.handle, q, p.k, oi, op, None, stop, ghn.GHN_PREC_BF16_MFMA, 0, ws=w,
+                                group_levels=args.group_levels)
         ms, per = timeit(per_item16)
         forms["bf16_per_index"] = dict(ms=ms, per=per)
         # the same grouped launches, all captured in one graph and replayed as one launch
