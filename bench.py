@@ -376,8 +376,8 @@ def query_parts(prob, qs, ix, ghn, torch, stop, sort32, levels16, reps=3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="clusters4d")
     ap.add_argument("--stop", default="exact", choices=["exact", "paper"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -494,21 +494,23 @@ def main():
     out_pred = torch.empty(m, dtype=torch.int32 if prob.task == 0 else torch.float32, device=dev)
 
     def timed(step):
-        """Warm up, then time `steps` calls; each call also gets a (begin, end) event pair
-        that the library records around its walk kernel on the same stream."""
+        """Warm up, then time `steps` back-to-back calls between two events; each call also
+        gets a (begin, end) event pair that the library records around its walk kernel on
+        the same stream.  Per-step times are the spacings of the walk-begin events."""
         for _ in range(args.warmup):
             step(None)
         torch.cuda.synchronize()
         mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-        ev0, ev1, wb, we = mk(), mk(), mk(), mk()
+        wb, we = mk(), mk()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
+        start.record()
         for i in range(args.steps):
-            ev0[i].record()
             step((wb[i], we[i]))
-            ev1[i].record()
+        end.record()
         torch.cuda.synchronize()
-        per = np.array([ev0[i].elapsed_time(ev1[i]) for i in range(args.steps)])
-        ms = float(ev0[0].elapsed_time(ev1[-1])) / args.steps
+        ms = float(start.elapsed_time(end)) / args.steps
+        per = np.array([wb[i].elapsed_time(wb[i + 1]) for i in range(args.steps - 1)] + [wb[-1].elapsed_time(end)])
         kern = np.array([wb[i].elapsed_time(we[i]) for i in range(args.steps)])
         return ms, float(kern.mean()), per
 
