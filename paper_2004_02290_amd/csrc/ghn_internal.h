@@ -137,11 +137,22 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
     return __longlong_as_double(int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo)));
 }
 
-// Value of `v` held by lane (lane - 1); lane 0 gets its own value.  DPP wave_shr:1
-// (a VALU lane shift across the whole wave64, no LDS round trip).
+// `v` with the value of lane `l` (wave-uniform) replaced by `x`: one v_writelane.
+// The compiler has the intrinsic but no builtin for it, so it is bound by name.
+extern "C" __device__ int ghn_amdgcn_writelane(int x, int l, int v) __asm("llvm.amdgcn.writelane.i32");
+__device__ __forceinline__ int writelane_i32(int v, int x, int l) { return ghn_amdgcn_writelane(x, l, v); }
+__device__ __forceinline__ double writelane_f64(double v, double x, int l) {
+    const uint64_t bv = (uint64_t)__double_as_longlong(v), bx = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)ghn_amdgcn_writelane((int)(uint32_t)bx, l, (int)(uint32_t)bv);
+    const uint32_t hi = (uint32_t)ghn_amdgcn_writelane((int)(uint32_t)(bx >> 32), l, (int)(uint32_t)(bv >> 32));
+    return __longlong_as_double((int64_t)(((uint64_t)hi << 32) | lo));
+}
+
+// Value of `v` held by lane (lane - 1); lane 0 gets 0.  DPP wave_shr:1 (a VALU lane
+// shift across the whole wave64, no LDS round trip).
 constexpr int DPP_WAVE_SHR1 = 0x138;
 __device__ __forceinline__ int shfl_up1_i32(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, DPP_WAVE_SHR1, 0xf, 0xf, false);
+    return __builtin_amdgcn_mov_dpp(v, DPP_WAVE_SHR1, 0xf, 0xf, true);
 }
 __device__ __forceinline__ double shfl_up1_f64(double v) {
     int64_t b = __double_as_longlong(v);

@@ -194,6 +194,18 @@ __device__ __forceinline__ void fetch_chunk(const IndexView& ix, int f, bool val
     }
 }
 
+// (d, i) before (t, ti) in the exact (distance, row id) order; bitwise, so it
+// compiles to compares without branches.
+__device__ __forceinline__ bool before(double d, int i, double t, int ti) {
+    return (d < t) | ((d == t) & (i < ti));
+}
+
+// The lanes for which before(d, i, t, ti) holds: the three compares are balloted
+// one by one and combined as masks, so no per-lane boolean is built for the ballot.
+__device__ __forceinline__ uint64_t ballot_before(double d, int i, double t, int ti) {
+    return ballot(d < t) | (ballot(d == t) & ballot(i < ti));
+}
+
 // Screen a chunk in FP32; candidates that may enter the buffer get their FP64
 // distance and are inserted one at a time (exact (distance, id) comparison).
 template <int FT>
@@ -207,46 +219,50 @@ __device__ __forceinline__ void score_chunk(const float* q, int f, int k, const 
     st.rerank += __popcll(mask);
     double d64 = 0.0;
     if (adm) d64 = dist64<FT>(q, c.x, f);
+    // Only candidates that beat the current k-th entry in the exact (distance, id)
+    // order can enter; the mask is narrowed to them now and after every insertion
+    // into a full buffer, so each candidate left in it is inserted.
+    if (st.count == k) mask &= ballot_before(d64, c.id, st.tau, st.tau_i);
+    if (mask == 0) return;
+    st.updated = true;
+    const uint64_t kmask = ballot(lane < k);
     while (mask) {
-        // nearest admitted candidate first: the buffer then fills with near points
-        // and later candidates fail the (shrinking) threshold without an insertion
         int src;
-        if (st.count == k || __popcll(mask) <= 2) {
-            src = __ffsll((unsigned long long)mask) - 1;
-        } else {
+        if (st.count < k && st.count + __popcll(mask) > k) {
+            // more candidates than free slots: nearest first, so the buffer fills
+            // with near points and the rest drop out of the mask without an insertion
             const float mine = ((mask >> lane) & 1) ? d32 : __int_as_float(0x7f800000);
             const float mn = wave_min_nonneg(mine);
             src = __ffsll((unsigned long long)(ballot(mine == mn) & mask)) - 1;
+        } else {
+            src = __ffsll((unsigned long long)mask) - 1;
         }
         mask &= ~(1ull << src);
         const double cd = readlane_f64(d64, src);
         const int ci = readlane_i32(c.id, src);
-        if (!(cd < st.tau || (cd == st.tau && ci < st.tau_i))) continue;
-        // The new k-th entry is the old (k-1)-th unless the candidate lands last.
-        double kd = cd;
-        int ki = ci;
-        if (k > 1) { kd = readlane_f64(st.bd, k - 2); ki = readlane_i32(st.bi, k - 2); }
-        // Insert (cd, ci): slots holding a larger entry shift up by one lane.  The
-        // distances are >= 0, so their IEEE bit patterns order like the values.
-        const uint64_t cb = (uint64_t)__double_as_longlong(cd);
-        const uint64_t bb = (uint64_t)__double_as_longlong(st.bd);
-        const bool gt = lane < k && (bb > cb || (bb == cb && st.bi > ci));
-        const int pos = k - __popcll(ballot(gt));
+        // Insert (cd, ci): the entries after it move up one lane (the k-th leaves the
+        // buffer; free slots hold +inf), then its lane is written.  It beats the k-th
+        // entry, so it lands in a lane below k.
+        const bool gt = (lane < k) & before(cd, ci, st.bd, st.bi);
+        const int pos = k - __popcll(ballot_before(cd, ci, st.bd, st.bi) & kmask);
         const double ud = shfl_up1_f64(st.bd);
         const int ui = shfl_up1_i32(st.bi);
-        if (gt) {
-            st.bd = lane == pos ? cd : ud;
-            st.bi = lane == pos ? ci : ui;
+        st.bd = gt ? ud : st.bd;
+        st.bi = gt ? ui : st.bi;
+        st.bd = writelane_f64(st.bd, cd, pos);
+        st.bi = writelane_i32(st.bi, ci, pos);
+        if (st.count < k) ++st.count;
+        if (st.count == k && mask) {
+            // the candidates that no longer beat the new k-th entry drop out
+            const double t = readlane_f64(st.bd, k - 1);
+            const int ti = readlane_i32(st.bi, k - 1);
+            mask &= ballot_before(d64, c.id, t, ti);
         }
-        st.updated = true;
-        if (st.count < k) st.count += 1;
-        if (st.count == k) {
-            const bool last = pos == k - 1;
-            st.tau = last ? cd : kd;
-            st.tau_i = last ? ci : ki;
-            st.t32 = admit_threshold(st.tau);
-            mask &= ballot(c.valid && d32 <= st.t32);
-        }
+    }
+    if (st.count == k) {
+        st.tau = readlane_f64(st.bd, k - 1);
+        st.tau_i = readlane_i32(st.bi, k - 1);
+        st.t32 = admit_threshold(st.tau);
     }
 }
 
