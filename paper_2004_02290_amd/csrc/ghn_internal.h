@@ -141,6 +141,9 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
 // The compiler has the intrinsic but no builtin for it, so it is bound by name.
 extern "C" __device__ int ghn_amdgcn_writelane(int x, int l, int v) __asm("llvm.amdgcn.writelane.i32");
 __device__ __forceinline__ int writelane_i32(int v, int x, int l) { return ghn_amdgcn_writelane(x, l, v); }
+__device__ __forceinline__ float writelane_f32(float v, float x, int l) {
+    return __int_as_float(ghn_amdgcn_writelane(__float_as_int(x), l, __float_as_int(v)));
+}
 __device__ __forceinline__ double writelane_f64(double v, double x, int l) {
     const uint64_t bv = (uint64_t)__double_as_longlong(v), bx = (uint64_t)__double_as_longlong(x);
     const uint32_t lo = (uint32_t)ghn_amdgcn_writelane((int)(uint32_t)bx, l, (int)(uint32_t)bv);
@@ -162,15 +165,20 @@ __device__ __forceinline__ double shfl_up1_f64(double v) {
 }
 
 // Minimum over the wave of a non-negative int (uniform result): DPP row_shr
-// min-scans inside each 16-lane row, then the four row minima.
+// min-scans inside each 16-lane row, then row broadcasts (the pattern of the
+// prefix sum below).
 __device__ __forceinline__ int wave_min_nonneg_i32(int m) {
-    m = min(m, __builtin_amdgcn_update_dpp(m, m, 0x111, 0xf, 0xf, false));  // row_shr:1
-    m = min(m, __builtin_amdgcn_update_dpp(m, m, 0x112, 0xf, 0xf, false));  // row_shr:2
-    m = min(m, __builtin_amdgcn_update_dpp(m, m, 0x114, 0xf, 0xf, false));  // row_shr:4
-    m = min(m, __builtin_amdgcn_update_dpp(m, m, 0x118, 0xf, 0xf, false));  // row_shr:8
-    const int r0 = __builtin_amdgcn_readlane(m, 15), r1 = __builtin_amdgcn_readlane(m, 31);
-    const int r2 = __builtin_amdgcn_readlane(m, 47), r3 = __builtin_amdgcn_readlane(m, 63);
-    return min(min(r0, r1), min(r2, r3));
+    // lanes with no source lane read INT32_MAX, the identity of min, so each step
+    // folds into one DPP min
+    m = min(m, __builtin_amdgcn_update_dpp(INT32_MAX, m, 0x111, 0xf, 0xf, false));  // row_shr:1
+    m = min(m, __builtin_amdgcn_update_dpp(INT32_MAX, m, 0x112, 0xf, 0xf, false));  // row_shr:2
+    m = min(m, __builtin_amdgcn_update_dpp(INT32_MAX, m, 0x114, 0xf, 0xf, false));  // row_shr:4
+    m = min(m, __builtin_amdgcn_update_dpp(INT32_MAX, m, 0x118, 0xf, 0xf, false));  // row_shr:8
+    // row minima into the later rows: lane 15 into rows 1 and 3, then lane 31 into
+    // rows 2 and 3; lane 63 ends with the minimum of the wave
+    m = min(m, __builtin_amdgcn_update_dpp(INT32_MAX, m, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    m = min(m, __builtin_amdgcn_update_dpp(INT32_MAX, m, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return __builtin_amdgcn_readlane(m, 63);
 }
 
 // The same for a non-negative float (its bit pattern orders like the value).

@@ -113,6 +113,18 @@ __device__ __forceinline__ void init_state(WaveState& st) {
     st.rerank = 0;
 }
 
+// Cell id of coordinate v (Eq. 1) clamped to [lo, hi]: the exact floor of
+// exact_floor_div_r, clamped while still an integer-valued double (lo and hi are
+// exact in FP64), so no 64-bit integer arithmetic is needed.  A NaN clamps to lo.
+__device__ __forceinline__ int32_t clamped_cell_id(double v, double a, double ainv, int32_t lo, int32_t hi) {
+    double t = floor(v * ainv);
+    if (fabs(t) < 536870912.0) {
+        if (__dmul_rn(t, a) > v) t -= 1.0;
+        else if (__dmul_rn(t + 1.0, a) <= v) t += 1.0;
+    }
+    return (int32_t)fmin(fmax(t, (double)lo), (double)hi);
+}
+
 // Query set-up: coordinates, central cell (Eq. 1, clamped to CLAMP cells outside
 // the occupied box), first layer that reaches the box, layer that covers it.
 template <int FT>
@@ -135,10 +147,8 @@ __device__ __forceinline__ void setup_query(const IndexView& ix, const float* qu
         Q.q[j] = queries[qi * f + j];
         Q.finite = Q.finite && isfinite(Q.q[j]);
         Q.v[j] = __dadd_rn((double)Q.q[j], -(double)ix.o[j]);
-        int64_t cj = Q.finite ? exact_floor_div_r(Q.v[j], (double)ix.a[j], ix.ainv[j]) : 0;
-        cj = max(cj, (int64_t)ix.cmin[j] - CLAMP);
-        cj = min(cj, (int64_t)ix.cmax[j] + CLAMP);
-        const int32_t c32 = (int32_t)cj;
+        const int32_t c32 = clamped_cell_id(Q.v[j], (double)ix.a[j], ix.ainv[j], ix.cmin[j] - (int32_t)CLAMP,
+                                            ix.cmax[j] + (int32_t)CLAMP);
         Q.c[j] = c32;
         Q.l0 = max(Q.l0, max(ix.cmin[j] - c32, c32 - ix.cmax[j]));
         Q.lcover = max(Q.lcover, max(c32 - ix.cmin[j], ix.cmax[j] - c32));
@@ -206,6 +216,20 @@ __device__ __forceinline__ uint64_t ballot_before(double d, int i, double t, int
     return ballot(d < t) | (ballot(d == t) & ballot(i < ti));
 }
 
+// Insert (cd, ci) into the sorted buffer: the entries after it move up one lane
+// (the k-th leaves the buffer; free slots hold +inf), then its lane is written.
+// The caller guarantees that it beats the k-th entry, so it lands below lane k.
+__device__ __forceinline__ void insert_entry(WaveState& st, uint64_t kmask, int k, int lane, double cd, int ci) {
+    const bool gt = (lane < k) & before(cd, ci, st.bd, st.bi);
+    const int pos = k - __popcll(ballot_before(cd, ci, st.bd, st.bi) & kmask);
+    const double ud = shfl_up1_f64(st.bd);
+    const int ui = shfl_up1_i32(st.bi);
+    st.bd = gt ? ud : st.bd;
+    st.bi = gt ? ui : st.bi;
+    st.bd = writelane_f64(st.bd, cd, pos);
+    st.bi = writelane_i32(st.bi, ci, pos);
+}
+
 // Screen a chunk in FP32; candidates that may enter the buffer get their FP64
 // distance and are inserted one at a time (exact (distance, id) comparison).
 template <int FT>
@@ -226,38 +250,33 @@ __device__ __forceinline__ void score_chunk(const float* q, int f, int k, const 
     if (mask == 0) return;
     st.updated = true;
     const uint64_t kmask = ballot(lane < k);
+    if (st.count < k) {
+        // Free slots first.  With more candidates than free slots the nearest go
+        // first, so the buffer fills with near points and the rest drop out of the
+        // mask without an insertion.  (count + candidates left stays constant here.)
+        const bool nearest = st.count + __popcll(mask) > k;
+        float mine = ((mask >> lane) & 1) ? d32 : __int_as_float(0x7f800000);
+        while (mask && st.count < k) {
+            int src;
+            if (nearest) {
+                const float mn = wave_min_nonneg(mine);
+                src = __ffsll((unsigned long long)(ballot(mine == mn) & mask)) - 1;
+                mine = writelane_f32(mine, __int_as_float(0x7f800000), src);
+            } else {
+                src = __ffsll((unsigned long long)mask) - 1;
+            }
+            mask &= ~(1ull << src);
+            insert_entry(st, kmask, k, lane, readlane_f64(d64, src), readlane_i32(c.id, src));
+            ++st.count;
+        }
+        if (mask) mask &= ballot_before(d64, c.id, readlane_f64(st.bd, k - 1), readlane_i32(st.bi, k - 1));
+    }
     while (mask) {
-        int src;
-        if (st.count < k && st.count + __popcll(mask) > k) {
-            // more candidates than free slots: nearest first, so the buffer fills
-            // with near points and the rest drop out of the mask without an insertion
-            const float mine = ((mask >> lane) & 1) ? d32 : __int_as_float(0x7f800000);
-            const float mn = wave_min_nonneg(mine);
-            src = __ffsll((unsigned long long)(ballot(mine == mn) & mask)) - 1;
-        } else {
-            src = __ffsll((unsigned long long)mask) - 1;
-        }
+        const int src = __ffsll((unsigned long long)mask) - 1;
         mask &= ~(1ull << src);
-        const double cd = readlane_f64(d64, src);
-        const int ci = readlane_i32(c.id, src);
-        // Insert (cd, ci): the entries after it move up one lane (the k-th leaves the
-        // buffer; free slots hold +inf), then its lane is written.  It beats the k-th
-        // entry, so it lands in a lane below k.
-        const bool gt = (lane < k) & before(cd, ci, st.bd, st.bi);
-        const int pos = k - __popcll(ballot_before(cd, ci, st.bd, st.bi) & kmask);
-        const double ud = shfl_up1_f64(st.bd);
-        const int ui = shfl_up1_i32(st.bi);
-        st.bd = gt ? ud : st.bd;
-        st.bi = gt ? ui : st.bi;
-        st.bd = writelane_f64(st.bd, cd, pos);
-        st.bi = writelane_i32(st.bi, ci, pos);
-        if (st.count < k) ++st.count;
-        if (st.count == k && mask) {
-            // the candidates that no longer beat the new k-th entry drop out
-            const double t = readlane_f64(st.bd, k - 1);
-            const int ti = readlane_i32(st.bi, k - 1);
-            mask &= ballot_before(d64, c.id, t, ti);
-        }
+        insert_entry(st, kmask, k, lane, readlane_f64(d64, src), readlane_i32(c.id, src));
+        // the candidates that no longer beat the new k-th entry drop out
+        if (mask) mask &= ballot_before(d64, c.id, readlane_f64(st.bd, k - 1), readlane_i32(st.bi, k - 1));
     }
     if (st.count == k) {
         st.tau = readlane_f64(st.bd, k - 1);
