@@ -435,19 +435,20 @@ __device__ __forceinline__ bool stop_after_layer(const IndexView& ix, const Quer
     if (l >= Q.lcover) return true;  // every occupied cell has been visited
     if (st.count != k) return false;
     if (STOP == GHN_STOP_PAPER) return !st.updated;
-    double r2 = __longlong_as_double(0x7ff0000000000000LL);
+    // r_l: the query's distance to the nearest face of the layer box.  Rounding a
+    // square is monotonic on [0, inf), so squaring the smallest face distance gives
+    // the smallest of the squared ones.
+    double g = __longlong_as_double(0x7ff0000000000000LL);
 #pragma unroll
     for (int j = 0; j < (FT > 0 ? FT : F_MAX); ++j) {
         if (FT == 0 && j >= f) break;
         const double a = ix.a[j];
         const double glo = __dadd_rn(Q.v[j], -__dmul_rn((double)(Q.c[j] - l), a));
         const double ghi = __dadd_rn(__dmul_rn((double)(Q.c[j] + l + 1), a), -Q.v[j]);
-        double g = glo < ghi ? glo : ghi;
-        if (g < 0.0) g = 0.0;
-        const double g2 = __dmul_rn(g, g);
-        if (g2 < r2) r2 = g2;
+        g = fmin(g, fmin(glo, ghi));
     }
-    return st.tau < __dmul_rn(r2, EXACT_SHRINK);
+    g = fmax(g, 0.0);
+    return st.tau < __dmul_rn(__dmul_rn(g, g), EXACT_SHRINK);
 }
 
 // Neighbours in (distance, id) order, then the majority vote (ties -> smallest
