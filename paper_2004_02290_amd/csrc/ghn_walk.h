@@ -371,6 +371,7 @@ __device__ __forceinline__ void score_runs(const IndexView& ix, const float* q, 
     uint32_t sidx = seg_incl - nseg_l, pofs = pts_incl - npts_l;
     const bool sorted = order && nseg > 1 && nseg <= WAVE;
     float lbk = __int_as_float(0x7f800000);  // sorted: this lane's run bound (lanes < nseg)
+    uint32_t spre = 0xffffffffu;              // sorted: this lane's run offset (lanes < nseg)
     if (sorted) {
         if (n0 > 0) { s_begin[sidx] = b0; s_pre[sidx] = n0; s_key[sidx] = key0 | sidx; ++sidx; }
         if (n1 > 0) { s_begin[sidx] = b1; s_pre[sidx] = n1; s_key[sidx] = key1 | sidx; }
@@ -387,7 +388,11 @@ __device__ __forceinline__ void score_runs(const IndexView& ix, const float* q, 
         }
         const uint32_t incl = wave_incl_scan(rn);
         wave_lds_sync();
-        if ((uint32_t)lane < nseg) { s_begin[lane] = rb; s_pre[lane] = incl - rn; }
+        if ((uint32_t)lane < nseg) {
+            spre = incl - rn;
+            s_begin[lane] = rb;
+            s_pre[lane] = spre;
+        }
     } else {
         if (n0 > 0) { s_begin[sidx] = b0; s_pre[sidx] = pofs; ++sidx; pofs += n0; }
         if (n1 > 0) { s_begin[sidx] = b1; s_pre[sidx] = pofs; }
@@ -395,29 +400,39 @@ __device__ __forceinline__ void score_runs(const IndexView& ix, const float* q, 
     if (lane == 0) s_pre[nseg] = npts;  // sentinel
     wave_lds_sync();
     // Chunk [base, base + 64): `seg` is the run holding `base`; the runs that start
-    // inside the chunk are few, so each lane finds its run with one uniform pass.
+    // inside the chunk are few, so each lane finds its run with one uniform pass
+    // over them.  Sorted lists hold the run offsets in lanes (strictly increasing,
+    // runs are non-empty), unsorted ones only in LDS.
     uint32_t seg = 0;
     uint32_t limit = npts;
     for (uint32_t base = 0; base < limit; base += WAVE) {
-        if (sorted) {
-            const uint64_t far = ballot((double)lbk > st.tau);
-            if (far) {
-                const uint32_t cut = (uint32_t)(__ffsll((unsigned long long)far) - 1);
-                limit = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_pre[cut]);
-                if (base >= limit) break;
-            }
-        }
         const uint32_t p = base + lane;
         const uint32_t end = base + WAVE;
         uint32_t my = seg;
-        uint32_t s = seg + 1;
-        uint32_t pre_s = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_pre[s]);
-        while (pre_s < end && s < nseg) {
-            if (p >= pre_s) my = s;
-            ++s;
-            pre_s = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_pre[s]);
+        if (sorted) {
+            const uint64_t far = ballot((double)lbk > st.tau);
+            if (far) {
+                // lanes past the list hold an infinite bound, so the first far lane is
+                // at most nseg: the end of the list
+                const int cut = __ffsll((unsigned long long)far) - 1;
+                limit = cut < (int)nseg ? (uint32_t)readlane_i32((int)spre, cut) : npts;
+                if (base >= limit) break;
+            }
+            for (uint64_t in = ballot(spre > base) & ballot(spre < end); in; in &= in - 1) {
+                const int r = __ffsll((unsigned long long)in) - 1;
+                if (p >= (uint32_t)readlane_i32((int)spre, r)) my = (uint32_t)r;
+            }
+            seg = (uint32_t)__popcll(ballot(spre <= end)) - 1;  // the run holding `end`
+        } else {
+            uint32_t s = seg + 1;
+            uint32_t pre_s = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_pre[s]);
+            while (pre_s < end && s < nseg) {
+                if (p >= pre_s) my = s;
+                ++s;
+                pre_s = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_pre[s]);
+            }
+            seg = (pre_s == end && s < nseg) ? s : s - 1;
         }
-        seg = (pre_s == end && s < nseg) ? s : s - 1;
         const bool valid = p < limit;
         const uint32_t pidx = valid ? s_begin[my] + (p - s_pre[my]) : 0u;
         Chunk<FT> cur;
