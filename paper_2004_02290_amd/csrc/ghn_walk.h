@@ -235,9 +235,11 @@ __device__ __forceinline__ void insert_entry(WaveState& st, uint64_t kmask, int 
 template <int FT>
 __device__ __forceinline__ void score_chunk(const float* q, int f, int k, const Chunk<FT>& c, WaveState& st) {
     const int lane = lane_id();
-    float d32 = __int_as_float(0x7f800000);
+    // lanes without a candidate get NaN, which fails the admission compare (a real
+    // candidate's FP32 distance is never NaN: the coordinates are finite)
+    float d32 = __int_as_float(0x7fc00000);
     if (c.valid) d32 = dist32<FT>(q, c.x, f);
-    const bool adm = c.valid && d32 <= st.t32;
+    const bool adm = d32 <= st.t32;
     uint64_t mask = ballot(adm);
     if (mask == 0) return;
     st.rerank += __popcll(mask);
@@ -437,7 +439,7 @@ __device__ __forceinline__ void score_runs(const IndexView& ix, const float* q, 
         const uint32_t pidx = valid ? s_begin[my] + (p - s_pre[my]) : 0u;
         Chunk<FT> cur;
         fetch_chunk<FT>(ix, f, valid, pidx, cur);
-        st.cands += __popcll(ballot(valid));
+        st.cands += (int32_t)min((uint32_t)WAVE, limit - base);  // the lanes with p < limit
         score_chunk<FT>(q, f, k, cur, st);
     }
     wave_lds_sync();
