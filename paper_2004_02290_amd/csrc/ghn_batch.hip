@@ -23,8 +23,10 @@ __global__ void k_reset_counter(uint64_t* counter) {
 
 // A batch whose indexes all use the dense table runs an instance without the tree
 // walk, which needs fewer registers: up to 4 dimensions it is held to 96 VGPRs so
-// that 5 waves share a SIMD instead of 4 (a few values spill to scratch; measured
-// 7 % faster on 256 3-D problems than the instance that can also walk trees).
+// that 5 waves share a SIMD instead of 4 (at f = 4 a few values spill to scratch;
+// measured 7 % faster on 256 3-D problems than the instance that can also walk
+// trees).  More waves do not pay: at 72 or 64 VGPRs the 3-D instance spills 92 to
+// 116 bytes per lane.
 template <int FT, bool TREE>
 constexpr int batched_waves_per_eu() { return !TREE && FT >= 1 && FT <= 4 ? 5 : 1; }
 
