@@ -15,17 +15,37 @@ constexpr int WPB = PT / WAVE;
 // (The hash-lookup instances keep the compiler's choice.)
 template <int FT, bool HASH> constexpr int dense_waves_per_eu() { return !HASH && FT >= 1 && FT <= 4 ? 8 : 1; }
 
+// The query set-up (central cell, FP64 coordinates, first and covering layers) is
+// the same on every lane of a wave, so the block's first wave does it for all the
+// block's queries at once, one lane each, and hands it over through LDS: one set-up
+// pass per block instead of one per wave.
 template <int FT, int STOP, bool HASH>
 __global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(dense_waves_per_eu<FT, HASH>())))
 void k_predict_dense(PredictArgs A) {
     __shared__ uint32_t s_begin[WPB][RUN_CAP];
     __shared__ uint32_t s_pre[WPB][RUN_CAP];
     __shared__ uint32_t s_key[WPB][RUN_CAP];
+    constexpr bool SHARED_SETUP = FT > 0 && !HASH;  // (the hash instances keep their registers for the lookups)
+    __shared__ Query<FT> s_query[SHARED_SETUP ? WPB : 1];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int64_t slot = wave_slot(A, WPB);
+    if constexpr (SHARED_SETUP) {
+        const int lane = lane_id();
+        if (wv == 0 && lane < WPB) {
+            const int64_t s_l = slot - wv + lane;  // the slot of wave `lane` of this block
+            if (s_l < A.m) {
+                const int64_t q_l = A.order ? (int64_t)A.order[s_l] : s_l;
+                Query<FT> Q;
+                setup_query<FT>(A.ix, A.io.queries, q_l, FT, Q);
+                s_query[lane] = Q;
+            }
+        }
+        __syncthreads();
+    }
     if (slot >= A.m) return;
     const int64_t qi = A.order ? (int64_t)A.order[slot] : slot;
-    walk_dense<FT, STOP, HASH>(A.ix, A.io, qi, s_begin[wv], s_pre[wv], s_key[wv]);
+    walk_dense<FT, STOP, HASH>(A.ix, A.io, qi, s_begin[wv], s_pre[wv], s_key[wv],
+                               SHARED_SETUP ? &s_query[wv] : nullptr);
 }
 
 // Sort key of a query: Morton interleave of its central cell id clamped to the

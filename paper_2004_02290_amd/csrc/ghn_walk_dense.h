@@ -62,9 +62,11 @@ __device__ __forceinline__ void hash_run(const IndexView& ix, uint64_t lin, int3
 
 // HASH: the cells come from the hash table (GHN_LOOKUP_HASH) instead of the dense
 // offset table; the enumeration, bounds and scoring are the same.
+// `preset`: the query's set-up already done (by another lane of the block), or null.
 template <int FT, int STOP, bool HASH>
 __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& io, int64_t qi,
-                                           uint32_t* s_begin, uint32_t* s_pre, uint32_t* s_key) {
+                                           uint32_t* s_begin, uint32_t* s_pre, uint32_t* s_key,
+                                           const Query<FT>* preset = nullptr) {
     using Lin = typename std::conditional<HASH, uint64_t, uint32_t>::type;  // row key without the last dimension
     const int lane = lane_id();
     const int f = FT > 0 ? FT : ix.f;
@@ -72,7 +74,8 @@ __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& i
     const bool prune = !(io.flags & GHN_FLAG_NO_PRUNE);
 
     Query<FT> Q;
-    setup_query<FT>(ix, io.queries, qi, f, Q);
+    if (preset) Q = *preset;
+    else setup_query<FT>(ix, io.queries, qi, f, Q);
     if (!Q.finite) {
         write_invalid(ix, io, qi);
         return;
