@@ -116,8 +116,13 @@ __global__ __launch_bounds__(BT) void k_tree_level(const int32_t* __restrict__ c
 }
 
 
+// At f = 16 the walk is held to 168 VGPRs, three waves per SIMD; left to itself
+// the compiler takes 190 and two.
+template <int FT> constexpr int tree_waves_per_eu() { return FT == 16 ? 3 : 1; }
+
 template <int FT, int STOP>
-__global__ __launch_bounds__(PT) void k_predict_tree(PredictArgs A) {
+__global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(tree_waves_per_eu<FT>())))
+void k_predict_tree(PredictArgs A) {
     __shared__ uint32_t s_begin[WPB][RUN_CAP];
     __shared__ uint32_t s_pre[WPB][RUN_CAP];
     __shared__ uint64_t s_stack[WPB][TREE_STACK_CAP];
