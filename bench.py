@@ -350,7 +350,7 @@ def query_parts(prob, qs, ix, ghn, torch, stop, sort32, levels16, reps=3):
         op = torch.empty(mq, dtype=torch.int32 if prob.task == 0 else torch.float32, device=qs.device)
         part = {"queries": mq}
         for form, prec, flags, levels in (("fp32_plain", ghn.GHN_PREC_FP32, 0 if sort32 else ghn.GHN_FLAG_NO_SORT, -1),
-                                          ("bf16_batched", ghn.GHN_PREC_BF16_MFMA, 0, levels16)):
+                                          ("bf16_grouped", ghn.GHN_PREC_BF16_MFMA, 0, levels16)):
             nws = ghn.ghn_predict_workspace_bytes(ix.handle, mq, k, stop, prec, flags, levels)
             ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=qs.device)
             st = ix.predict(q, k, stop=stop, prec=prec, flags=flags, with_d2=False, with_stats=True,
@@ -562,7 +562,7 @@ def main():
         ms, kern_ms, per = timed(step16)
         flops = 2.0 * f * w["cands"]  # algorithmic: 2 f per screened (query, candidate) pair
         achieved = flops / (kern_ms * 1e-3) / 1e12
-        forms["bf16_batched"] = dict(
+        forms["bf16_grouped"] = dict(
             qps=m / (ms * 1e-3), ms_per_step=ms, kernel_ms=kern_ms, per=per, work=w,
             roofline={"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                       "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": measured_traffic(args.workload, "bf16"),
@@ -571,7 +571,7 @@ def main():
         # the screen's distance error against FP64, on a query sample against points spread over the index
         ns = min(m, 2048)
         ea, er = ghn.ghn_screen_error(ix.handle, qs[:ns], sample=8192)
-        forms["bf16_batched"]["screen_error"] = {
+        forms["bf16_grouped"]["screen_error"] = {
             "max_abs": float(ea.max().item()), "max_rel": float(er.max().item()), "mean_rel": float(er.mean().item()),
             "bound_rel": 2.0 ** -13.8, "admission_margin_rel": 2.0 ** -12,
             "sample": "first %d queries x %d points spread over the index; rel = |s - d| / (|q'|^2 + |x'|^2)"

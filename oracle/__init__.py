@@ -29,7 +29,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with g++ (FP64, no FMA contraction, OpenMP over queries)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp%d" % os.getpid()
-        cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+        cmd = ["g++", "-std=c++17", "-O3", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                "-shared", "-fPIC", SRC, "-o", tmp]
         subprocess.check_call(cmd)
         os.replace(tmp, LIB)

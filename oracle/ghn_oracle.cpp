@@ -9,7 +9,8 @@
 // What it computes, and where the paper says so:
 //   * cell coordinate of a point (Eq. 1, Section III-A): per dimension the
 //     integer division of the point by the cell measurement; read as the exact
-//     floor of the real quotient (x - o) / a, with x - o evaluated in FP64.
+//     floor of the real quotient (x - o) / a, with x - o evaluated in FP64,
+//     saturated to +-2^40 (only far query coordinates reach that).
 //   * cell sampling (Algorithm 1): a hash table from cell id to the list of its
 //     points; empty cells are never stored (Section III-A).
 //   * exploration (Section III-B, Algorithm 2): start at the query's central
@@ -52,17 +53,24 @@ namespace {
 enum { TASK_CLASSIFY = 0, TASK_REGRESS = 1, TASK_REGRESS_MEDIAN = 2 };
 enum { STOP_EXACT = 0, STOP_PAPER = 1 };
 
-// Exact floor of v / a for a > 0, v finite, via fmod (exact in IEEE arithmetic):
-// v = t*a + r with |r| < a and r carrying the sign of v, so t = (v - r) / a is an
-// integer computed exactly while |t| * a stays inside FP64's 53 bits, and the
-// floor is t - 1 when r < 0.
+// Cell ids are saturated to [-CELL_LIMIT, CELL_LIMIT]: a query coordinate can lie
+// arbitrarily far outside the data, and no finite id range holds every quotient of
+// two floats.  Below the limit the id is the exact floor.
+const int64_t CELL_LIMIT = int64_t(1) << 40;
+
+// Exact floor of v / a for a > 0 finite and v finite, via fmod in x87 extended
+// precision (64-bit significand): r = fmodl(v, a) is exact and v = t*a + r with
+// |r| < a and r carrying the sign of v.  While |t| <= 2^40 the product t*a needs
+// at most 40 + 24 bits (a is a float32 width), so v - r = t*a is exact, and so is
+// the division by a; the floor is t - 1 when r < 0.  Beyond 2^40 the (then
+// rounded) quotient only decides the saturation.
 int64_t floor_div(double v, double a) {
-    double r = std::fmod(v, a);
-    double t = (v - r) / a;
-    if (r < 0.0) t -= 1.0;
-    const double lim = 4.0e18;
-    if (t > lim) t = lim;
-    if (t < -lim) t = -lim;
+    const long double lv = v, la = a;
+    const long double r = fmodl(lv, la);
+    long double t = (lv - r) / la;
+    if (r < 0) t -= 1;
+    if (t > (long double)CELL_LIMIT) return CELL_LIMIT;
+    if (t < -(long double)CELL_LIMIT) return -CELL_LIMIT;
     return (int64_t)t;
 }
 
@@ -233,7 +241,10 @@ std::vector<Cand> walk(const Grid& g, const float* q, int k, int stop, WalkStats
             }
             done = buf.back().first < r2 * (1.0 - 0x1p-44);
         }
-        if (done) { s.stop_layer = (int32_t)l; break; }
+        if (done) {  // the stop layer is reported as int32, saturated
+            s.stop_layer = l < (int64_t)INT32_MAX ? (int32_t)l : INT32_MAX;
+            break;
+        }
     }
     if (st) *st = s;
     return buf;

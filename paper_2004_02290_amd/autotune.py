@@ -1,13 +1,17 @@
 """Autotuning driver: runs ghn_autotune on a query sample and caches the choice.
 
-The cache is a JSON file keyed by (n, f, dtype, k, stop rule, a coarse data
-signature: per-dimension coordinate range of a point sample); it stores the
-chosen cell width, screen, grouping and flags.  Under the EXACT stop rule the
-choice never changes the neighbours returned (every width gives brute-force
-results); under the PAPER rule only execution settings are tuned.
+The cache is a JSON file keyed by the problem: n, f, dtype, task, k, stop rule,
+the candidate widths asked for, and a data signature (a hash of a strided
+sample of the points, plus the per-dimension coordinate range of that sample).
+It stores the chosen cell width, lookup, screen, grouping and flags.  Under the
+EXACT stop rule the choice never changes the neighbours returned (every width
+gives brute-force results); under the PAPER rule the width is part of the
+method, so only execution settings are tuned, and a cached entry is used only
+if its width is the one requested.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 from typing import Optional
@@ -18,25 +22,35 @@ import torch
 from . import binding as ghn
 
 
-def signature(points: torch.Tensor, k: int, stop: int) -> str:
+def signature(points: torch.Tensor, task: int, k: int, stop: int, widths=None) -> str:
     n, f = points.shape
-    sample = points[:: max(1, n // 4096)].float()
-    lo = sample.min(dim=0).values.cpu().numpy()
-    hi = sample.max(dim=0).values.cpu().numpy()
-    rng = ",".join("%.3g:%.3g" % (a, b) for a, b in zip(lo, hi))
-    return "n=%d f=%d dtype=%s k=%d stop=%d range=%s" % (n, f, str(points.dtype), k, stop, rng)
+    sample = points[:: max(1, n // 4096)].contiguous()
+    raw = sample.view(torch.int16) if sample.dtype == torch.bfloat16 else sample
+    digest = hashlib.sha1(raw.cpu().numpy().tobytes()).hexdigest()[:16]
+    s32 = sample.float()
+    lo = s32.min(dim=0).values.cpu().numpy()
+    hi = s32.max(dim=0).values.cpu().numpy()
+    rng = ",".join("%.9g:%.9g" % (a, b) for a, b in zip(lo, hi))
+    wk = "auto" if widths is None else ",".join("%.9g" % float(w) for w in np.atleast_1d(widths))
+    return "n=%d f=%d dtype=%s task=%d k=%d stop=%d widths=%s data=%s range=%s" % (
+        n, f, str(points.dtype), task, k, stop, wk, digest, rng)
 
 
 def tune(points: torch.Tensor, targets: torch.Tensor, task: int, query_sample: torch.Tensor, k: int,
          stop: int = ghn.GHN_STOP_EXACT, widths=None, cache_path: Optional[str] = None):
     """Return the best setting (dict with cell_width, lookup, prec, group_levels, flags, ms)."""
-    key = signature(points, k, stop)
+    key = signature(points, task, k, stop, widths)
     cache = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as fh:
             cache = json.load(fh)
-        if key in cache:
-            return cache[key]
+        hit = cache.get(key)
+        if hit is not None:
+            # under PAPER the width decides the neighbours: never trust a cached width
+            # other than the requested one
+            if stop != ghn.GHN_STOP_PAPER or (
+                    widths is not None and np.float32(hit["cell_width"]) == np.float32(np.atleast_1d(widths)[0])):
+                return hit
     best, trials = ghn.ghn_autotune(points, targets, task, query_sample, k, stop, widths)
     best = {name: (float(v) if isinstance(v, (float, np.floating)) else int(v)) for name, v in best.items()}
     best["trials"] = trials

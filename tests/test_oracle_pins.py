@@ -93,6 +93,46 @@ def test_cells_partition_points():
             assert c[i, j] * a <= x < (c[i, j] + 1) * a
 
 
+CELL_LIMIT = 2 ** 40  # cell ids saturate here (far query coordinates)
+
+
+def test_cell_floor_far_and_saturated():
+    # Ids far beyond 2^29 (queries far outside the data) are still exact floors; past
+    # 2^40 they saturate.  Fraction gives the exact quotient.
+    rng = np.random.default_rng(13)
+    widths = np.array([0.1, 0.3, 1.7, 2.5e-3, 3.0, 0.021281155], np.float32)
+    for a in widths:
+        t = np.exp(rng.uniform(np.log(2.0 ** 28), np.log(2.0 ** 42), 600)) * rng.choice([-1.0, 1.0], 600)
+        x = (np.floor(t) * np.float64(a)).astype(np.float32)  # near exact multiples
+        x[::3] = np.nextafter(x[::3], np.float32(np.inf))
+        x[1::3] = np.nextafter(x[1::3], np.float32(-np.inf))
+        x = np.concatenate([x, np.array([3.0e38, -3.0e38, 1.0e20, -1.0e20], np.float32)])
+        got = oracle.cells(x.reshape(-1, 1), a)[:, 0]
+        for xi, gi in zip(x, got):
+            want = max(-CELL_LIMIT, min(CELL_LIMIT, _exact_cell(xi, a)))
+            assert gi == want, (float(xi), float(a))
+    # an origin in front of a far coordinate
+    o = np.float32(-12345.678)
+    x = np.array([4.5e9, -4.5e9, 7.77e11], np.float32)
+    got = oracle.cells(x.reshape(-1, 1), 0.1, np.array([o]))[:, 0]
+    assert list(got) == [max(-CELL_LIMIT, min(CELL_LIMIT, _exact_cell(xi, 0.1, o))) for xi in x]
+
+
+def test_count_cells_matches_exact_cell_sets():
+    # count_cells (used to calibrate widths) against an independent count of the
+    # distinct exact-rational cell tuples, and against the grid's own table.
+    rng = np.random.default_rng(14)
+    for f, n, a in ((1, 500, 0.05), (2, 800, 0.1), (3, 600, 0.21), (5, 300, 0.7)):
+        pts = rng.normal(0, 1, (n, f)).astype(np.float32)
+        pts[: n // 4] = np.round(pts[: n // 4] / np.float32(a)) * np.float32(a)  # on cell faces
+        want = len({tuple(_exact_cell(pts[i, j], a) for j in range(f)) for i in range(n)})
+        assert oracle.count_cells(pts, a) == want
+        g = oracle.Grid(pts, np.zeros(n, np.int32), oracle.CLASSIFY, a)
+        assert g.num_cells == want
+        ids, counts = g.cells()
+        assert counts.sum() == n and len(ids) == want
+
+
 # ----------------------------------------------------------------------------- Eq. 2 / Eq. 3
 @pytest.mark.parametrize("f,L", [(1, 6), (2, 4), (3, 3), (4, 3), (5, 2), (8, 1)])
 def test_ring_sizes_match_eq2_eq3(f, L):
@@ -188,6 +228,52 @@ def test_bruteforce_exact_rationals_random_f32():
         for t in range(k):
             s += float(tgt[order[t]])
         assert pred[qi] == np.float32(s / k)
+
+
+def _d2_sequential(q, X):
+    """The defined distance: FP64 differences, squares and sums in order j = 0..f-1,
+    each rounded (numpy never fuses a multiply with an add)."""
+    d = q.astype(np.float64)[None, :] - X.astype(np.float64)
+    s = np.zeros(X.shape[0])
+    for j in range(X.shape[1]):
+        s = s + d[:, j] * d[:, j]
+    return s
+
+
+def _d2_fused(q, X):
+    """Alternative a careless oracle could compute: every step a fused multiply-add
+    (one rounding of s + d*d, modelled with exact rationals)."""
+    out = np.empty(X.shape[0])
+    for i, x in enumerate(X):
+        s = 0.0
+        for j in range(X.shape[1]):
+            d = float(np.float64(q[j]) - np.float64(x[j]))
+            s = float(Fraction(s) + Fraction(d) * Fraction(d))
+        out[i] = s
+    return out
+
+
+def test_bruteforce_distance_bits_are_the_sequential_fp64_sum():
+    # Bit for bit: the oracle's d2 is the sequential FP64 sum without FMA.  The inputs
+    # mix magnitudes so that a fused or reordered sum differs in the last bit on many
+    # pairs; both alternatives are checked to differ, so the pin has teeth.
+    rng = np.random.default_rng(15)
+    n, m, f = 300, 6, 8
+    scale = np.float32(2.0) ** rng.integers(-12, 4, (1, f)).astype(np.float32)
+    pts = (rng.normal(0, 1, (n, f)).astype(np.float32) * scale).astype(np.float32)
+    qs = (rng.normal(0, 1, (m, f)).astype(np.float32) * scale).astype(np.float32)
+    idx, d2, _ = oracle.bruteforce(pts, np.zeros(n, np.int32), oracle.CLASSIFY, qs, n)
+    fused_differs = reordered_differs = 0
+    for qi in range(m):
+        got = np.empty(n)
+        got[idx[qi]] = d2[qi]
+        want = _d2_sequential(qs[qi], pts)
+        assert np.array_equal(got.view(np.int64), want.view(np.int64)), qi
+        fused_differs += int((_d2_fused(qs[qi], pts) != want).sum())
+        reordered_differs += int((_d2_sequential(qs[qi][::-1], pts[:, ::-1]) != want).sum())
+        # the order is the (d2, id) order of these exact values
+        assert list(idx[qi]) == sorted(range(n), key=lambda i: (want[i], i))
+    assert fused_differs > 10 and reordered_differs > 10
 
 
 def test_bruteforce_rejects_k_out_of_range():
