@@ -31,7 +31,13 @@
  *     with every difference, square and sum rounded to FP64 in that order (no
  *     fused multiply-add).  Ties in d go to the smaller row index.
  *   - Cell ids are the exact floor of (x_j - o_j) / a_j, where x_j - o_j is
- *     rounded to FP64 first (exact whenever o = 0, the grid of Eq. 1).
+ *     rounded to FP64 first (exact whenever o = 0, the grid of Eq. 1).  Query
+ *     cell ids are exact up to 2^40 in magnitude and saturate at +-2^40 beyond;
+ *     reported stop layers saturate at INT32_MAX.  A query more than 2^28 cells
+ *     outside the occupied box of some dimension is walked with the same layers
+ *     (same cells, same order, same layer numbers); under GHN_STOP_EXACT its walk
+ *     may run to a later layer than the ring bound of its true layer box would
+ *     allow (its neighbours are still exact).
  */
 #ifndef GHN_H
 #define GHN_H

@@ -27,8 +27,12 @@ __global__ void k_reset_counter(uint64_t* counter) {
 // measured 7 % faster on 256 3-D problems than the instance that can also walk
 // trees).  More waves do not pay: at 72 or 64 VGPRs the 3-D instance spills 92 to
 // 116 bytes per lane.
+// The other instances are held to the occupancy their walk reaches on its own, so that
+// the rare set-up of a query far outside the box (setup_far) cannot lower it.
 template <int FT, bool TREE>
-constexpr int batched_waves_per_eu() { return !TREE && FT >= 1 && FT <= 4 ? 5 : 1; }
+constexpr int batched_waves_per_eu() {
+    return FT < 1 ? 1 : (!TREE ? (FT <= 4 ? 5 : 3) : (FT == 1 ? 7 : (FT == 2 ? 5 : (FT <= 4 ? 4 : 3))));
+}
 
 template <int FT, int STOP, bool TREE>
 __global__ __launch_bounds__(BPT) __attribute__((amdgpu_waves_per_eu(batched_waves_per_eu<FT, TREE>())))

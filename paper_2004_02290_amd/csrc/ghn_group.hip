@@ -191,6 +191,7 @@ struct alignas(16) GroupLds {
     float qlo[FS], qhi[FS];
     double ad[FS], od[FS];  // cell width and origin (FP64), read inside the walk
     double qd[GQ][FS];      // the queries in FP64 (exact), for the re-rank
+    int64_t shift;          // true layer - walk layer (0 unless the query is far outside the box)
     float tq[GQ];           // per query: FP32 threshold >= its k-th distance (+inf while the
                             // buffer is not full), -1 once done or when invalid
     uint32_t qp[QCAP];      // queue of admitted pairs: point position in cell order
@@ -332,6 +333,27 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                 cc[j] = (int32_t)c;
                 if (act) S.qc[lane][j] = cc[j];
             }
+            // central cells in the walk frame (walk_frame in ghn_internal.h; the EXACT
+            // bound below is then the frame's, see stop_after_layer): the clamped ids
+            // are the frame unless a query lies CLAMP or more cells outside the box.
+            // Such a query walks alone (k_form_groups), and its ids are redone here one
+            // dimension per lane.
+            int32_t far0 = 0;
+            if (lane == 0 && fin)
+                for (int j = 0; j < f; ++j) far0 = max(far0, max(ix.cmin[j] - cc[j], cc[j] - ix.cmax[j]));
+            far0 = readlane_i32(far0, 0);
+            int64_t gshift = 0;
+            if (cnt == 1 && far0 == (int32_t)CLAMP) {
+                const int64_t q0 = (int64_t)A.order[gd.x];
+                gshift = far_shift(ix, A.io.queries, q0, f);
+                const int32_t cl = far_frame_id(ix, A.io.queries, q0, f);
+                if (lane < f) S.qc[0][lane] = cl;
+                for (int j = 0; j < f; ++j) {
+                    const int32_t c0 = readlane_i32(cl, j);
+                    if (lane == 0) cc[j] = c0;
+                }
+            }
+            if (lane == 0) S.shift = gshift;
             // group box of central cells and box of query coordinates (finite queries)
             for (int j = 0; j < f; ++j) {
                 int32_t lo = fin ? cc[j] : INT32_MAX, hi = fin ? cc[j] : INT32_MIN;
@@ -845,7 +867,7 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                 }
                 if (stop) {
                     done[i] = true;
-                    stopl[i] = (int32_t)l;
+                    stopl[i] = true_layer(l, S.shift);
                     thr[i] = -inf;
                     bnd[i] = -inf;
                     if (t == 0) S.tq[r] = -1.0f;

@@ -14,9 +14,11 @@ constexpr int F_MAX = GHN_F_MAX;
 constexpr int K_MAX = GHN_K_MAX;
 // Training-point cell ids must lie in (-COORD_LIMIT, COORD_LIMIT).
 constexpr int64_t COORD_LIMIT = int64_t(1) << 27;
-// A query cell id further than CLAMP cells outside the occupied range of its
-// dimension is moved to distance CLAMP.  Cell ids within that range stay below
-// 2^29 in magnitude, where the exact floor below is verified.
+// Query cell ids are exact up to CELL_SAT in magnitude and saturated beyond (a
+// query coordinate can lie arbitrarily far outside the data).
+constexpr double CELL_SAT = 0x1p40;
+// A query whose central cell lies more than CLAMP cells outside the occupied box is
+// walked in a shifted frame (walk_frame below) whose cell ids stay below 2^29.
 constexpr int64_t CLAMP = int64_t(1) << 28;
 
 enum Lookup : int32_t { LOOKUP_DENSE = 0, LOOKUP_TREE = 1, LOOKUP_HASH = 2 };
@@ -96,16 +98,53 @@ __device__ __forceinline__ int64_t hash_find(const IndexView& ix, uint64_t key, 
 // Exact floor of v / a (a > 0 finite, v finite): the largest integer t with t * a <= v.
 // The FP64 quotient is rounded, so the candidate is checked against exact products; for
 // |t| < 2^29 and an FP32 width, t * a is exact in FP64.
-// The same with the quotient estimated as v * (1 / a): the estimate is within one of
-// the floor, and the exact product checks correct it.
-__device__ __forceinline__ int64_t exact_floor_div_r(double v, double a, double ainv) {
+// t * a > v, exactly, for an integer-valued t, an FP32 width a > 0 and a finite v with
+// t within two of v / a.  p + e = t * a exactly (e is the FMA residual).  When e = 0
+// the sign of the rounded p - v is exact; when e != 0, |t| > 2^29, so p and v lie
+// within a factor of two and p - v is exact (Sterbenz).
+__device__ __forceinline__ bool prod_gt(double t, double a, double v) {
+    const double p = __dmul_rn(t, a);
+    const double e = __builtin_fma(t, a, -p);
+    const double d = __dadd_rn(p, -v);
+    return d > -e;
+}
+
+// Cell id of a query coordinate (Eq. 1): the exact floor of v / a, saturated to
+// [-CELL_SAT, CELL_SAT], as an integer-valued double.  v * (1 / a) is within 2^-11 of
+// v / a while |v / a| <= 2^41, so the floor of the estimate is off by at most one and
+// the exact product tests correct it; beyond, only the saturation matters.  A NaN
+// gives -CELL_SAT.
+__device__ __forceinline__ double cell_floor_sat(double v, double a, double ainv) {
     double t = floor(v * ainv);
-    if (!(fabs(t) < 4.0e18)) return t > 0 ? int64_t(4000000000000000000LL) : -int64_t(4000000000000000000LL);
-    if (fabs(t) < 536870912.0) {
-        if (__dmul_rn(t, a) > v) t -= 1.0;
-        else if (__dmul_rn(t + 1.0, a) <= v) t += 1.0;
+    if (fabs(t) <= 0x1p41) {
+        if (prod_gt(t, a, v)) t -= 1.0;
+        else if (!prod_gt(t + 1.0, a, v)) t += 1.0;
     }
-    return int64_t(t);
+    return fmin(fmax(t, -CELL_SAT), CELL_SAT);
+}
+
+// Walk frame of a query far outside the occupied box.  With t the true central cell,
+// D_j its distance to [cmin_j, cmax_j] in dimension j and l0 = max_j D_j, the layer of
+// a box cell x is L(x) = max_j |x_j - t_j| (Section III-B).  If l0 > CLAMP, let
+// s = l0 - CLAMP: a dimension with D_j >= s moves s cells toward the box (its
+// distances to every box cell drop by s), and any other dimension is clamped into
+// the box.  Box spans are below 2^28 = CLAMP, so the other dimensions' distances stay
+// below l0 <= L(x) before and below CLAMP <= L(x) - s after, and the frame layer of
+// every box cell is exactly L(x) - s: the layers hold the same cells in the same
+// order.  Frame ids lie within CLAMP of the box.
+__device__ __forceinline__ double cell_outside(double t, int32_t lo, int32_t hi) {
+    return fmax(fmax((double)lo - t, t - (double)hi), 0.0);
+}
+__device__ __forceinline__ double frame_shift(double l0) { return l0 > (double)CLAMP ? l0 - (double)CLAMP : 0.0; }
+__device__ __forceinline__ int32_t frame_id(double t, int32_t lo, int32_t hi, double shift) {
+    if (shift == 0.0) return (int32_t)t;
+    if (cell_outside(t, lo, hi) >= shift) return (int32_t)(t < (double)lo ? t + shift : t - shift);
+    return (int32_t)fmin(fmax(t, (double)lo), (double)hi);
+}
+// A true layer (frame layer + shift) as reported: saturated to int32.
+__device__ __forceinline__ int32_t true_layer(int32_t l, int64_t shift) {
+    const int64_t t = (int64_t)l + shift;
+    return t < (int64_t)INT32_MAX ? (int32_t)t : INT32_MAX;
 }
 
 __device__ __forceinline__ int64_t exact_floor_div(double v, double a) {

@@ -10,10 +10,13 @@ constexpr int WPB = PT / WAVE;
 
 // Up to 4 dimensions the walk fits 64 VGPRs without scratch spills, which lets 8
 // waves share a SIMD instead of 6; the extra waves hide more of the walk's latency
-// (measured: 8 % faster on the 4-D clusters).  Wider instances keep the compiler's
-// own choice.
-// (The hash-lookup instances keep the compiler's choice.)
-template <int FT, bool HASH> constexpr int dense_waves_per_eu() { return !HASH && FT >= 1 && FT <= 4 ? 8 : 1; }
+// (measured: 8 % faster on the 4-D clusters).  The other instances are held to the
+// occupancy their walk loop reaches on its own, so that the rare set-up of a query
+// far outside the box (setup_far) cannot lower it.
+template <int FT, bool HASH> constexpr int dense_waves_per_eu() {
+    return FT < 1 ? 1 : (!HASH ? (FT <= 4 ? 8 : (FT == 5 ? 6 : (FT == 6 ? 5 : 4)))
+                                : (FT <= 2 ? 7 : (FT <= 4 ? 6 : (FT <= 6 ? 5 : 4))));
+}
 
 // The query set-up (central cell, FP64 coordinates, first and covering layers) is
 // the same on every lane of a wave, so the block's first wave does it for all the

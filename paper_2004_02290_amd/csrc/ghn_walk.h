@@ -113,9 +113,24 @@ __device__ __forceinline__ void init_state(WaveState& st) {
     st.rerank = 0;
 }
 
-// Cell id of coordinate v (Eq. 1) clamped to [lo, hi]: the exact floor of
-// exact_floor_div_r, clamped while still an integer-valued double (lo and hi are
-// exact in FP64), so no 64-bit integer arithmetic is needed.  A NaN clamps to lo.
+// Query set-up: coordinates, central cell (Eq. 1) in the walk frame (walk_frame in
+// ghn_internal.h: the true cell unless it lies more than CLAMP cells outside the
+// occupied box), first layer that reaches the box and layer that covers it, both in
+// the frame; the true layer is the frame layer + shift.  setup_query alone clamps the
+// ids to CLAMP cells outside the box, which is the frame unless l0 comes out as
+// CLAMP; the walk then calls setup_far.
+template <int FT>
+struct Query {
+    float q[FT > 0 ? FT : F_MAX];
+    double v[FT > 0 ? FT : F_MAX];   // q - origin, FP64
+    int32_t c[FT > 0 ? FT : F_MAX];  // central cell id in the walk frame (|c| < 2^29)
+    int32_t l0, lcover;              // a shifted frame has l0 = CLAMP and layers >= CLAMP
+    bool finite;
+};
+
+// Cell id of coordinate v clamped to [lo, hi] (lo and hi within 2^29 of 0): the floor
+// of the quotient estimate, corrected with exact products (exact for |t| < 2^29),
+// clamped while still an integer-valued double.  A NaN clamps to lo.
 __device__ __forceinline__ int32_t clamped_cell_id(double v, double a, double ainv, int32_t lo, int32_t hi) {
     double t = floor(v * ainv);
     if (fabs(t) < 536870912.0) {
@@ -125,16 +140,60 @@ __device__ __forceinline__ int32_t clamped_cell_id(double v, double a, double ai
     return (int32_t)fmin(fmax(t, (double)lo), (double)hi);
 }
 
-// Query set-up: coordinates, central cell (Eq. 1, clamped to CLAMP cells outside
-// the occupied box), first layer that reaches the box, layer that covers it.
+// Lane j < f: the exact central cell id of query qi in dimension j (cell_floor_sat)
+// and its distance to the occupied box; other lanes 0.  The far-query paths below
+// work one dimension per lane from the query in memory, so they add almost nothing
+// to the registers a walk holds.
+__device__ __forceinline__ void far_dim(const IndexView& ix, const float* queries, int64_t qi, int f, double& t,
+                                        double& d) {
+    const int j = lane_id();
+    t = 0.0;
+    d = 0.0;
+    if (j < f) {
+        const double v = __dadd_rn((double)queries[qi * f + j], -(double)ix.o[j]);
+        t = cell_floor_sat(v, (double)ix.a[j], ix.ainv[j]);
+        d = cell_outside(t, ix.cmin[j], ix.cmax[j]);
+    }
+}
+
+__device__ __forceinline__ double wave_max_f64(double x) {
+#pragma unroll
+    for (int m = 1; m < WAVE; m <<= 1) x = fmax(x, __shfl_xor(x, m, WAVE));
+    return x;
+}
+
+// True layer - frame layer of a finite query (walk_frame).
+__device__ __forceinline__ int64_t far_shift(const IndexView& ix, const float* queries, int64_t qi, int f) {
+    double t, d;
+    far_dim(ix, queries, qi, f, t, d);
+    return (int64_t)frame_shift(wave_max_f64(d));
+}
+
+// Lane j < f: the frame id of dimension j of a finite query (walk_frame).
+__device__ __forceinline__ int32_t far_frame_id(const IndexView& ix, const float* queries, int64_t qi, int f) {
+    double t, d;
+    far_dim(ix, queries, qi, f, t, d);
+    const double sh = frame_shift(wave_max_f64(d));
+    const int j = lane_id();
+    return j < f ? frame_id(t, ix.cmin[j], ix.cmax[j], sh) : 0;
+}
+
+// The frame of a set-up query whose l0 is CLAMP (it may lie further out): ids
+// recomputed exactly and moved by walk_frame's rule.  Wave-uniform call.
 template <int FT>
-struct Query {
-    float q[FT > 0 ? FT : F_MAX];
-    double v[FT > 0 ? FT : F_MAX];   // q - origin, FP64
-    int32_t c[FT > 0 ? FT : F_MAX];  // central cell id (|c| < 2^29 after clamping)
-    int32_t l0, lcover;
-    bool finite;
-};
+__device__ __forceinline__ void setup_far(const IndexView& ix, const float* queries, int64_t qi, int f, Query<FT>& Q) {
+    const int32_t cl = far_frame_id(ix, queries, qi, f);
+    Q.l0 = 0;
+    Q.lcover = 0;
+#pragma unroll
+    for (int i = 0; i < (FT > 0 ? FT : F_MAX); ++i) {
+        if (FT == 0 && i >= f) break;
+        const int32_t c32 = readlane_i32(cl, i);
+        Q.c[i] = c32;
+        Q.l0 = max(Q.l0, max(ix.cmin[i] - c32, c32 - ix.cmax[i]));
+        Q.lcover = max(Q.lcover, max(c32 - ix.cmin[i], ix.cmax[i] - c32));
+    }
+}
 
 template <int FT>
 __device__ __forceinline__ void setup_query(const IndexView& ix, const float* queries, int64_t qi, int f, Query<FT>& Q) {
@@ -147,6 +206,7 @@ __device__ __forceinline__ void setup_query(const IndexView& ix, const float* qu
         Q.q[j] = queries[qi * f + j];
         Q.finite = Q.finite && isfinite(Q.q[j]);
         Q.v[j] = __dadd_rn((double)Q.q[j], -(double)ix.o[j]);
+        // the frame id unless the query lies CLAMP or more cells outside the box
         const int32_t c32 = clamped_cell_id(Q.v[j], (double)ix.a[j], ix.ainv[j], ix.cmin[j] - (int32_t)CLAMP,
                                             ix.cmax[j] + (int32_t)CLAMP);
         Q.c[j] = c32;
@@ -445,7 +505,10 @@ __device__ __forceinline__ void score_runs(const IndexView& ix, const float* q, 
     wave_lds_sync();
 }
 
-// Stop rules, checked after every complete layer l.
+// Stop rules, checked after every complete layer l of the walk frame.  In a shifted
+// frame the EXACT bound is that of the frame's layer box, which lies inside the true
+// layer box in every dimension: the bound is smaller (often 0) and the walk stops no
+// earlier than with the true box, so the neighbours stay exact.
 template <int FT, int STOP>
 __device__ __forceinline__ bool stop_after_layer(const IndexView& ix, const Query<FT>& Q, int f, int k, int32_t l,
                                                  const WaveState& st) {

@@ -62,24 +62,15 @@ __device__ __forceinline__ void hash_run(const IndexView& ix, uint64_t lin, int3
 
 // HASH: the cells come from the hash table (GHN_LOOKUP_HASH) instead of the dense
 // offset table; the enumeration, bounds and scoring are the same.
-// `preset`: the query's set-up already done (by another lane of the block), or null.
 template <int FT, int STOP, bool HASH>
-__device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& io, int64_t qi,
-                                           uint32_t* s_begin, uint32_t* s_pre, uint32_t* s_key,
-                                           const Query<FT>* preset = nullptr) {
+__device__ __forceinline__ void walk_dense_layers(const IndexView& ix, const QueryIO& io, int64_t qi,
+                                                  uint32_t* s_begin, uint32_t* s_pre, uint32_t* s_key,
+                                                  const Query<FT>& Q) {
     using Lin = typename std::conditional<HASH, uint64_t, uint32_t>::type;  // row key without the last dimension
     const int lane = lane_id();
     const int f = FT > 0 ? FT : ix.f;
     const int k = io.k;
     const bool prune = !(io.flags & GHN_FLAG_NO_PRUNE);
-
-    Query<FT> Q;
-    if (preset) Q = *preset;
-    else setup_query<FT>(ix, io.queries, qi, f, Q);
-    if (!Q.finite) {
-        write_invalid(ix, io, qi);
-        return;
-    }
     WaveState st;
     init_state(st);
 
@@ -235,7 +226,24 @@ __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& i
         }
         if (stop_after_layer<FT, STOP>(ix, Q, f, k, l, st)) break;
     }
-    finish_query(ix, io, qi, l, st);
+    // only a shifted frame (far query) reaches layer CLAMP or more before its walk ends
+    finish_query(ix, io, qi, l >= (int32_t)CLAMP ? true_layer(l, far_shift(ix, io.queries, qi, f)) : l, st);
+}
+
+// `preset`: the query's set-up already done (by another lane of the block), or null.
+template <int FT, int STOP, bool HASH>
+__device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& io, int64_t qi,
+                                           uint32_t* s_begin, uint32_t* s_pre, uint32_t* s_key,
+                                           const Query<FT>* preset = nullptr) {
+    Query<FT> Q;
+    if (preset) Q = *preset;
+    else setup_query<FT>(ix, io.queries, qi, FT > 0 ? FT : ix.f, Q);
+    if (!Q.finite) {
+        write_invalid(ix, io, qi);
+        return;
+    }
+    if (Q.l0 == (int32_t)CLAMP) setup_far<FT>(ix, io.queries, qi, FT > 0 ? FT : ix.f, Q);
+    walk_dense_layers<FT, STOP, HASH>(ix, io, qi, s_begin, s_pre, s_key, Q);
 }
 
 }  // namespace ghn

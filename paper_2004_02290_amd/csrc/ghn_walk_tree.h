@@ -50,19 +50,13 @@ __device__ __forceinline__ uint64_t pending_block(uint64_t p) {
 }
 
 template <int FT, int STOP, bool FRONTIER>
-__device__ __forceinline__ void walk_tree(const IndexView& ix, const QueryIO& io, int64_t qi,
-                                          uint32_t* s_begin, uint32_t* s_pre, uint64_t* stack, uint64_t* pend) {
+__device__ __forceinline__ void walk_tree_layers(const IndexView& ix, const QueryIO& io, int64_t qi,
+                                                 uint32_t* s_begin, uint32_t* s_pre, uint64_t* stack, uint64_t* pend,
+                                                 const Query<FT>& Q) {
     const int lane = lane_id();
     const int f = FT > 0 ? FT : ix.f;
     const int k = io.k;
     const bool prune = !(io.flags & GHN_FLAG_NO_PRUNE);
-
-    Query<FT> Q;
-    setup_query<FT>(ix, io.queries, qi, f, Q);
-    if (!Q.finite) {
-        write_invalid(ix, io, qi);
-        return;
-    }
     WaveState st;
     init_state(st);
     const int top = ix.tree_levels;  // level of the root entries (0 = the cells themselves)
@@ -177,7 +171,21 @@ __device__ __forceinline__ void walk_tree(const IndexView& ix, const QueryIO& io
         if (overflow) frontier = false;  // blocks were lost: later layers start from the root
         if (stop_after_layer<FT, STOP>(ix, Q, f, k, l, st)) break;
     }
-    finish_query(ix, io, qi, l, st);
+    // only a shifted frame (far query) reaches layer CLAMP or more before its walk ends
+    finish_query(ix, io, qi, l >= (int32_t)CLAMP ? true_layer(l, far_shift(ix, io.queries, qi, f)) : l, st);
+}
+
+template <int FT, int STOP, bool FRONTIER>
+__device__ __forceinline__ void walk_tree(const IndexView& ix, const QueryIO& io, int64_t qi,
+                                          uint32_t* s_begin, uint32_t* s_pre, uint64_t* stack, uint64_t* pend) {
+    Query<FT> Q;
+    setup_query<FT>(ix, io.queries, qi, FT > 0 ? FT : ix.f, Q);
+    if (!Q.finite) {
+        write_invalid(ix, io, qi);
+        return;
+    }
+    if (Q.l0 == (int32_t)CLAMP) setup_far<FT>(ix, io.queries, qi, FT > 0 ? FT : ix.f, Q);
+    walk_tree_layers<FT, STOP, FRONTIER>(ix, io, qi, s_begin, s_pre, stack, pend, Q);
 }
 
 }  // namespace ghn

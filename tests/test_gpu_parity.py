@@ -742,3 +742,65 @@ def test_autotune_exact_and_paper(ghn, tmp_path):
     with pytest.raises(ghn.GHNError) as e:
         ghn.ghn_autotune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_PAPER)
     assert e.value.code == -1
+
+
+# ---------------------------------------------------------------------------------- far queries
+def _far_problem(f, seed, n=3000, m=96, width=0.1, k=5):
+    """Uniform points on [0, 1)^f (cell ids 0..9) and queries far outside in two or more
+    dimensions at different distances: 2^29 .. 2^31 cells out (the walk then runs in a
+    shifted frame), around 2^28 cells out (the frame's edge) and beyond 2^40 cells (ids
+    saturate).  The first rows stay ordinary queries."""
+    prob = W.uniform_problem(n=n, m=m, f=f, k=k, seed=seed, width=width)
+    rng = np.random.default_rng(seed)
+    q = prob.queries.astype(np.float64)
+    cells = [2.0 ** 28 - 3, 2.0 ** 28, 2.0 ** 28 + 5, 2.0 ** 29, 3.1e8, 2.0 ** 30, 1.7e9, 2.0 ** 31, 2.0 ** 41,
+             2.0 ** 45]
+    for r in range(8, m):
+        dims = rng.choice(f, size=min(f, int(rng.integers(2, f + 1))), replace=False)
+        for j in dims:
+            c = cells[int(rng.integers(0, len(cells)))] * (1.0 + 0.01 * rng.random())
+            q[r, j] = (-c if rng.random() < 0.5 else c + 10.0) * width
+    # two rows with every far dimension at the same distance
+    q[8, :2] = -(2.0 ** 30) * width
+    q[9, :] = (2.0 ** 29) * width
+    prob.queries = q.astype(np.float32)
+    return prob
+
+
+@pytest.mark.parametrize("f", [2, 3, 4])
+def test_far_queries_shifted_frame(ghn, f):
+    prob = _far_problem(f, seed=40 + f)
+    _check_exact(ghn, prob)
+    got = _check_paper(ghn, prob)
+    assert (got["stop_layer"][8:] > 2 ** 28).all()
+
+
+@pytest.mark.parametrize("lookup", [TREE, HASH])
+def test_far_queries_shifted_frame_other_lookups(ghn, lookup):
+    prob = _far_problem(3, seed=50 + lookup)
+    _check_exact(ghn, prob, lookup=lookup)
+    _check_paper(ghn, prob, lookup=lookup)
+
+
+def test_far_queries_shifted_frame_mfma(ghn):
+    prob = _far_problem(3, seed=60)
+    _check_mfma(ghn, prob)
+
+
+def test_far_queries_shifted_frame_batched(ghn):
+    import torch
+    probs = [_far_problem(3, seed=70 + i, n=1000 + 700 * i, m=40 + 9 * i) for i in range(4)]
+    for stop in (ghn.GHN_STOP_EXACT, ghn.GHN_STOP_PAPER):
+        idxs, items, outs, ws, batch = _batch_setup(ghn, probs, stop)
+        ghn.ghn_predict_batched(batch)
+        torch.cuda.synchronize()
+        for p, ix, (oi, op, od) in zip(probs, idxs, outs):
+            got = dict(idx=oi.cpu().numpy(), pred=op.cpu().numpy(), d2=od.cpu().numpy())
+            if stop == ghn.GHN_STOP_EXACT:
+                bi, bd, bp = oracle.bruteforce(p.points, p.targets, p.task, p.queries, p.k)
+                want = dict(idx=bi, d2=bd, pred=bp)
+            else:
+                w = oracle.Grid(p.points, p.targets, p.task, p.cell_width).predict(p.queries, p.k, oracle.STOP_PAPER)
+                want = dict(idx=w["idx"], d2=w["d2"], pred=w["pred"])
+            _assert_same(got, want, "batched far queries stop=%d" % stop)
+        ghn.ghn_batch_destroy(batch)
