@@ -93,7 +93,8 @@ typedef enum { GHN_PREC_FP32 = 0, GHN_PREC_BF16_MFMA = 1 } ghn_prec;
                                 target in IEEE total order, or for even k the FP64 mean of the two
                                 middle targets rounded to FP32 */
 
-typedef struct ghn_index ghn_index; /* opaque HOST handle; owns its device memory */
+typedef struct ghn_index ghn_index; /* opaque HOST handle; owns its device memory, except an
+                                       index built into caller storage (ghn_build_into) */
 
 typedef struct {
     int64_t n;               /* training points */
@@ -164,10 +165,45 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
                         int32_t task, const float* cell_width, int32_t n_width, const float* origin,
                         const ghn_build_opts* opts, void* stream, ghn_index** out);
 
+/* ---- the build into caller-owned device memory ---------------------------------------
+ * The same build (Eq. 1, Algorithm 1) with every byte of device memory supplied by
+ * the caller, e.g. as torch tensors: `index_storage` receives the index (points in
+ * cell order, targets, cell list and lookup; the handle points into it, so the
+ * storage must outlive the handle and is never freed by the library), `ws` holds
+ * the build's temporaries (free again when the call returns).  Both are DEVICE
+ * buffers aligned to 256 bytes.  Nothing is allocated on the device.
+ *
+ * ghn_build_workspace_bytes: bytes of `ws` for n points (any data).
+ * ghn_index_bytes: bytes of `index_storage` enough for any n points of f features
+ *   with any lookup; the dense table is counted at its largest size (max(16 n, 2^24)
+ *   cells), so it is at least 64 MiB.
+ * ghn_index_bytes_for: bytes of `index_storage` for these points and widths with the
+ *   lookup the build will choose (the dense table at its actual size; the cell
+ *   list, tree and hash table bounded by num_cells <= n).  It runs the cell-range
+ *   pass of the build in `ws` (ghn_build_workspace_bytes(n, f) bytes) and
+ *   synchronises `stream`.  targets are not read.
+ * ghn_build_into: arguments as ghn_build_ex, plus the two buffers.  Synchronises
+ *   `stream` (as ghn_build).  Errors: ghn_build's, and GHN_E_WORKSPACE when a
+ *   buffer is missing or smaller than stated above.  ghn_index_get_info reports
+ *   the bytes of the storage in use as device_bytes.  ghn_destroy frees only the
+ *   host handle.  ghn_insert refuses such an index (GHN_E_UNSUPPORTED): build the
+ *   enlarged index with ghn_build_into. */
+size_t ghn_build_workspace_bytes(int64_t n, int32_t f);
+size_t ghn_index_bytes(int64_t n, int32_t f, int32_t dtype, int32_t task);
+ghn_status ghn_index_bytes_for(const void* points, int64_t n, int32_t f, int32_t dtype, int32_t task,
+                               const float* cell_width, int32_t n_width, const float* origin,
+                               const ghn_build_opts* opts, void* ws, size_t ws_bytes, void* stream,
+                               size_t* out_bytes);
+ghn_status ghn_build_into(const void* points, int64_t n, int32_t f, int32_t dtype, const void* targets,
+                          int32_t task, const float* cell_width, int32_t n_width, const float* origin,
+                          const ghn_build_opts* opts, void* index_storage, size_t index_bytes, void* ws,
+                          size_t ws_bytes, void* stream, ghn_index** out);
+
 /* Describe a built index.  `out` is HOST memory. */
 ghn_status ghn_index_get_info(const ghn_index* index, ghn_index_info* out);
 
-/* Release the index and its device memory.  NULL is ignored. */
+/* Release the index and its device memory (only the handle for an index built
+ * into caller storage).  NULL is ignored. */
 void ghn_destroy(ghn_index* index);
 
 typedef struct {

@@ -39,7 +39,8 @@ EXPORTED = ["ghn_build", "ghn_build_ex", "ghn_index_get_info", "ghn_destroy", "g
             "ghn_query_order_workspace_bytes", "ghn_query_order", "ghn_batch_workspace_bytes", "ghn_batch_prepare",
             "ghn_predict_batched", "ghn_batch_destroy", "ghn_autotune", "ghn_cell_measure", "ghn_bruteforce",
             "ghn_index_save_bytes", "ghn_index_save", "ghn_index_load", "ghn_insert", "ghn_screen_error",
-            "ghn_last_error"]
+            "ghn_build_workspace_bytes", "ghn_index_bytes", "ghn_index_bytes_for",
+            "ghn_build_into", "ghn_last_error"]
 
 
 class GHNError(RuntimeError):
@@ -90,6 +91,14 @@ def _load() -> ctypes.CDLL:
     L.ghn_build.restype = ctypes.c_int
     L.ghn_build_ex.argtypes = [P, I64, I32, I32, P, I32, P, I32, P, P, P, ctypes.POINTER(P)]
     L.ghn_build_ex.restype = ctypes.c_int
+    L.ghn_build_workspace_bytes.argtypes = [I64, I32]
+    L.ghn_build_workspace_bytes.restype = SZ
+    L.ghn_index_bytes.argtypes = [I64, I32, I32, I32]
+    L.ghn_index_bytes.restype = SZ
+    L.ghn_index_bytes_for.argtypes = [P, I64, I32, I32, I32, P, I32, P, P, P, SZ, P, ctypes.POINTER(SZ)]
+    L.ghn_index_bytes_for.restype = ctypes.c_int
+    L.ghn_build_into.argtypes = [P, I64, I32, I32, P, I32, P, I32, P, P, P, SZ, P, SZ, P, ctypes.POINTER(P)]
+    L.ghn_build_into.restype = ctypes.c_int
     L.ghn_index_get_info.argtypes = [P, ctypes.POINTER(ghn_index_info)]
     L.ghn_index_get_info.restype = ctypes.c_int
     L.ghn_destroy.argtypes = [P]
@@ -179,15 +188,20 @@ def ghn_build_ex(points: torch.Tensor, targets: torch.Tensor, task: int,
                  cell_width: Union[float, Sequence[float]], origin: Optional[Sequence[float]] = None,
                  lookup: Optional[int] = None, stream=None) -> ctypes.c_void_p:
     """ghn_build_ex: as ghn_build, with the cell lookup structure chosen (GHN_LOOKUP_*)."""
-    if points.dim() != 2:
-        raise ValueError("points must be n x f")
+    dtype = _points_dtype(points)
     n, f = points.shape
-    dtype = GHN_BF16 if points.dtype == torch.bfloat16 else GHN_F32
-    if dtype == GHN_F32 and points.dtype != torch.float32:
-        raise ValueError("points must be float32 or bfloat16")
     want = torch.int32 if task == GHN_CLASSIFY else torch.float32
     if targets.dtype != want or targets.numel() != n:
         raise ValueError("targets must be %s with n entries" % want)
+    w, nw, o = _widths(cell_width, origin)
+    h = ctypes.c_void_p()
+    opts = None if lookup is None else ctypes.byref(ghn_build_opts(int(lookup)))
+    _check(_lib.ghn_build_ex(_ptr(points), n, f, dtype, _ptr(targets), task, w, nw, o, opts, _stream(stream),
+                             ctypes.byref(h)))
+    return h
+
+
+def _widths(cell_width, origin):
     w = (ctypes.c_float * GHN_F_MAX)()
     ws = [float(cell_width)] if isinstance(cell_width, (int, float)) else [float(x) for x in cell_width]
     for i, x in enumerate(ws):
@@ -197,10 +211,52 @@ def ghn_build_ex(points: torch.Tensor, targets: torch.Tensor, task: int,
         o = (ctypes.c_float * GHN_F_MAX)()
         for i, x in enumerate(origin):
             o[i] = float(x)
-    h = ctypes.c_void_p()
+    return w, len(ws), o
+
+
+def _points_dtype(points: torch.Tensor) -> int:
+    if points.dim() != 2:
+        raise ValueError("points must be n x f")
+    if points.dtype not in (torch.float32, torch.bfloat16):
+        raise ValueError("points must be float32 or bfloat16")
+    return GHN_BF16 if points.dtype == torch.bfloat16 else GHN_F32
+
+
+def ghn_build_workspace_bytes(n: int, f: int) -> int:
+    return int(_lib.ghn_build_workspace_bytes(n, f))
+
+
+def ghn_index_bytes(n: int, f: int, dtype: int = GHN_F32, task: int = GHN_CLASSIFY) -> int:
+    return int(_lib.ghn_index_bytes(n, f, dtype, task))
+
+
+def ghn_index_bytes_for(points: torch.Tensor, task: int, cell_width, ws: torch.Tensor, origin=None,
+                        lookup: Optional[int] = None, stream=None) -> int:
+    """ghn_index_bytes_for: index storage bytes for these points and widths (runs the cell-range pass in ws)."""
+    dtype = _points_dtype(points)
+    n, f = points.shape
+    w, nw, o = _widths(cell_width, origin)
     opts = None if lookup is None else ctypes.byref(ghn_build_opts(int(lookup)))
-    _check(_lib.ghn_build_ex(_ptr(points), n, f, dtype, _ptr(targets), task, w, len(ws), o, opts, _stream(stream),
-                             ctypes.byref(h)))
+    out = ctypes.c_size_t(0)
+    _check(_lib.ghn_index_bytes_for(_ptr(points), n, f, dtype, task, w, nw, o, opts, _ptr(ws),
+                                    ws.numel() * ws.element_size(), _stream(stream), ctypes.byref(out)))
+    return int(out.value)
+
+
+def ghn_build_into(points: torch.Tensor, targets: torch.Tensor, task: int, cell_width, storage: torch.Tensor,
+                   ws: torch.Tensor, origin=None, lookup: Optional[int] = None, stream=None) -> ctypes.c_void_p:
+    """ghn_build_into: the build with the index in `storage` and temporaries in `ws` (uint8 GPU tensors)."""
+    dtype = _points_dtype(points)
+    n, f = points.shape
+    want = torch.int32 if task == GHN_CLASSIFY else torch.float32
+    if targets.dtype != want or targets.numel() != n:
+        raise ValueError("targets must be %s with n entries" % want)
+    w, nw, o = _widths(cell_width, origin)
+    opts = None if lookup is None else ctypes.byref(ghn_build_opts(int(lookup)))
+    h = ctypes.c_void_p()
+    _check(_lib.ghn_build_into(_ptr(points), n, f, dtype, _ptr(targets), task, w, nw, o, opts, _ptr(storage),
+                               storage.numel() * storage.element_size(), _ptr(ws), ws.numel() * ws.element_size(),
+                               _stream(stream), ctypes.byref(h)))
     return h
 
 
@@ -368,9 +424,19 @@ class Index:
     """Owner of a built index (build on construction, free on close / garbage collection)."""
 
     def __init__(self, points: torch.Tensor, targets: torch.Tensor, task: int,
-                 cell_width: Union[float, Sequence[float]], origin=None, lookup: Optional[int] = None, stream=None):
+                 cell_width: Union[float, Sequence[float]], origin=None, lookup: Optional[int] = None, stream=None,
+                 torch_storage: bool = False):
+        """torch_storage: the index lives in a torch tensor (ghn_build_into) instead of library memory."""
         self.task = task
-        self.handle = ghn_build_ex(points, targets, task, cell_width, origin, lookup, stream)
+        self.storage = None
+        if torch_storage:
+            n, f = points.shape
+            ws = torch.empty(ghn_build_workspace_bytes(n, f), dtype=torch.uint8, device=points.device)
+            nbytes = ghn_index_bytes_for(points, task, cell_width, ws, origin, lookup, stream)
+            self.storage = torch.empty(nbytes, dtype=torch.uint8, device=points.device)
+            self.handle = ghn_build_into(points, targets, task, cell_width, self.storage, ws, origin, lookup, stream)
+        else:
+            self.handle = ghn_build_ex(points, targets, task, cell_width, origin, lookup, stream)
         self.info = ghn_index_get_info(self.handle)
 
     def predict(self, queries: torch.Tensor, k: int, stop=GHN_STOP_EXACT, prec=GHN_PREC_FP32, flags=0,

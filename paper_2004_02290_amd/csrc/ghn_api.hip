@@ -47,14 +47,30 @@ ghn_status hip_fail(hipError_t e, const char* what) {
     return fail(GHN_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Device allocations released together unless kept.
+// Device memory of a build: hipMalloc'd blocks released together unless kept, or
+// (carve) 256-byte aligned pieces of a caller's buffer, which is never freed here.
 struct DevPool {
     std::vector<void*> ptrs;
+    char* base = nullptr;  // carve mode: the caller's buffer
+    size_t cap = 0, used = 0;
+    const char* what = nullptr;  // carve mode: name of the buffer, for errors
+    DevPool() = default;
+    DevPool(void* buffer, size_t bytes, const char* name) : base((char*)buffer), cap(bytes), what(name) {}
+    DevPool(const DevPool&) = delete;
+    DevPool& operator=(const DevPool&) = delete;
     ~DevPool() {
         for (void* p : ptrs) (void)hipFree(p);
     }
+    bool carving() const { return base != nullptr; }
     hipError_t alloc(void** p, size_t bytes) {
         *p = nullptr;
+        if (carving()) {
+            const size_t at = (used + 255) & ~(size_t)255;
+            if (at > cap || cap - at < bytes) return hipErrorOutOfMemory;
+            *p = base + at;
+            used = at + bytes;
+            return hipSuccess;
+        }
         hipError_t e = hipMalloc(p, bytes ? bytes : 1);
         if (e == hipSuccess) ptrs.push_back(*p);
         return e;
@@ -64,6 +80,48 @@ struct DevPool {
         ptrs.clear();
     }
 };
+
+// Status of a failed DevPool::alloc: out of device memory, or a caller's buffer too small.
+ghn_status no_memory(const DevPool& pool, const char* fn, const char* purpose) {
+    if (pool.carving())
+        return fail(GHN_E_WORKSPACE, "%s: the %s (%zu bytes) is too small for the %s", fn, pool.what, pool.cap, purpose);
+    return fail(GHN_E_NOMEM, "%s: out of device memory for the %s", fn, purpose);
+}
+
+constexpr size_t ALIGN_SLACK = 256;  // per piece carved from a caller's buffer
+inline size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Padded dimension of the bf16 screen records.
+inline int screen_pad(int f) { return f <= 8 ? 8 : (f <= 16 ? 16 : 32); }
+
+// Device bytes of an index of n points in f dimensions with the given lookup: exact
+// for the points, targets and screen records, an upper bound (num_cells <= n) for the
+// cell list, the tree and the hash table; `box` = cells of the dense table's box.
+size_t index_bytes_bound(int64_t n, int f, int lookup, int64_t box) {
+    const size_t un = (size_t)n;
+    size_t b = 0;
+    b += up256(un * f * 4) + up256(un * 4) + up256(un * 4);           // points, row ids, targets
+    b += up256(un * 2 * screen_pad(f) * 2) + up256(un * 4);           // screen records and norms
+    b += up256((un + 1) * 4) + up256(un * f * 4);                     // cell list: first points, ids
+    const size_t nodes = un / (ghn::WAVE - 1) + ghn::TREE_LEVELS_MAX + 1;
+    b += 2 * up256(nodes * f * 4);                                     // tree node boxes
+    if (lookup == GHN_LOOKUP_HASH) {
+        size_t cap = 64;
+        while (cap < 2 * un) cap <<= 1;
+        b += up256(cap * 8) + up256(cap * 4);
+    }
+    if (lookup == GHN_LOOKUP_DENSE) b += up256(((size_t)box + 1) * 4);
+    b += up256(sizeof(ghn::IndexView));
+    return b + 16 * ALIGN_SLACK;
+}
+
+// Build temporaries (bytes of the caller workspace of ghn_build_into).
+struct BuildSmall { float a[ghn::F_MAX]; float o[ghn::F_MAX]; int32_t minmax[2 * ghn::F_MAX]; int32_t flags[2]; int64_t stats[2]; };
+size_t build_ws_bytes(int64_t n) {
+    const size_t un = (size_t)n;
+    return up256(sizeof(BuildSmall)) + 2 * up256(un * 8) + 2 * up256(un * 4) + up256(ghn::radix_sort_temp_bytes(n)) +
+           2 * up256(un * 4) + up256(ghn::exclusive_scan_temp_bytes(n)) + 16 * ALIGN_SLACK;
+}
 
 size_t sort_ws_bytes(int64_t m);  // workspace of the spatial query sort (defined below)
 
@@ -308,13 +366,21 @@ ghn_status ghn_build(const void* points, int64_t n, int32_t f, int32_t dtype, co
     return ghn_build_ex(points, n, f, dtype, targets, task, cell_width, n_width, origin, nullptr, stream, out);
 }
 
-ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype, const void* targets, int32_t task,
-                        const float* cell_width, int32_t n_width, const float* origin, const ghn_build_opts* bopts,
-                        void* stream, ghn_index** out) {
+}  // extern "C"
+
+namespace {
+
+// The build (Eq. 1, Algorithm 1).  Temporaries come from `tmp`, the index's memory
+// from `keep` (hipMalloc'd, or carved from caller buffers).  With `size_only` set,
+// only the cell range is computed and *size_only receives the index's device bytes
+// (index_bytes_bound for the lookup the build would use); nothing is kept.
+ghn_status build_impl(const void* points, int64_t n, int32_t f, int32_t dtype, const void* targets, int32_t task,
+                      const float* cell_width, int32_t n_width, const float* origin, const ghn_build_opts* bopts,
+                      void* stream, DevPool& tmp, DevPool& keep, size_t* size_only, ghn_index** out) {
     using namespace ghn;
-    if (!out) return fail(GHN_E_INVALID_ARG, "ghn_build: out is NULL");
-    *out = nullptr;
-    if (!points || !targets) return fail(GHN_E_INVALID_ARG, "ghn_build: points and targets must not be NULL");
+    if (!out && !size_only) return fail(GHN_E_INVALID_ARG, "ghn_build: out is NULL");
+    if (out) *out = nullptr;
+    if (!points || (!targets && !size_only)) return fail(GHN_E_INVALID_ARG, "ghn_build: points and targets must not be NULL");
     if (n < 1 || n >= (int64_t(1) << 31)) return fail(GHN_E_INVALID_ARG, "ghn_build: n=%lld outside [1, 2^31)", (long long)n);
     if (f < 1 || f > F_MAX) return fail(GHN_E_INVALID_ARG, "ghn_build: f=%d outside [1, %d]", f, F_MAX);
     if (dtype != GHN_F32 && dtype != GHN_BF16) return fail(GHN_E_INVALID_ARG, "ghn_build: bad dtype %d", dtype);
@@ -339,16 +405,15 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "ghn_build: pending HIP error");
 
-    DevPool tmp, keep;
     // 1. cell id range and data checks
-    struct Small { float a[F_MAX]; float o[F_MAX]; int32_t minmax[2 * F_MAX]; int32_t flags[2]; int64_t stats[2]; };
+    typedef BuildSmall Small;
     Small h;
     std::memset(&h, 0, sizeof h);
     std::memcpy(h.a, a, sizeof a);
     std::memcpy(h.o, o, sizeof o);
     for (int j = 0; j < F_MAX; ++j) { h.minmax[j] = INT32_MAX; h.minmax[F_MAX + j] = INT32_MIN; }
     Small* d_small = nullptr;
-    if ((e = tmp.alloc((void**)&d_small, sizeof(Small))) != hipSuccess) return fail(GHN_E_NOMEM, "ghn_build: hipMalloc failed");
+    if ((e = tmp.alloc((void**)&d_small, sizeof(Small))) != hipSuccess) return no_memory(tmp, "ghn_build", "cell range");
     if ((e = hipMemcpyAsync(d_small, &h, sizeof h, hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e, "ghn_build: upload");
     if ((e = launch_cells_minmax(points, n, f, dtype, d_small->a, d_small->o, d_small->minmax, d_small->flags, s)) != hipSuccess)
         return hip_fail(e, "ghn_build: cell range kernel");
@@ -388,6 +453,14 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
         return fail(GHN_E_KEY_OVERFLOW, "ghn_build: the occupied box holds more than 2^62 cells, too many for the "
                     "hash keys (use the tree lookup or a larger cell width)");
     iv.lookup = lookup;
+    const size_t need = index_bytes_bound(n, f, lookup, box);
+    if (size_only) {
+        *size_only = need;
+        return GHN_OK;
+    }
+    if (keep.carving() && keep.cap < need)
+        return fail(GHN_E_WORKSPACE, "ghn_build: index storage of %zu bytes needed (ghn_index_bytes_for), %zu given",
+                    need, keep.cap);
     int nbits = 0;
     if (lookup == GHN_LOOKUP_DENSE) {
         iv.box_cells = box;
@@ -409,13 +482,13 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
     void* rtemp;
     if (tmp.alloc((void**)&keys, n * 8) || tmp.alloc((void**)&keys2, n * 8) || tmp.alloc((void**)&vals, n * 4) ||
         tmp.alloc((void**)&vals2, n * 4) || tmp.alloc(&rtemp, radix_sort_temp_bytes(n)))
-        return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the sort");
+        return no_memory(tmp, "ghn_build", "sort");
     float* spts;
     int32_t* sid;
     void* tg;
     if (keep.alloc((void**)&spts, (size_t)n * f * 4) || keep.alloc((void**)&sid, (size_t)n * 4) ||
         keep.alloc(&tg, (size_t)n * 4))
-        return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the index");
+        return no_memory(keep, "ghn_build", "index");
     const uint64_t* skeys = nullptr;
     const uint32_t* perm = nullptr;
     if (lookup == GHN_LOOKUP_DENSE || lookup == GHN_LOOKUP_HASH || nbits <= 64) {
@@ -451,14 +524,14 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
     iv.spts = spts; iv.sid = sid; iv.targets = tg;
 
     // bf16 screen records, centred on the occupied box
-    iv.sp = f <= 8 ? 8 : (f <= 16 ? 16 : 32);
+    iv.sp = screen_pad(f);
     for (int j = 0; j < F_MAX; ++j) iv.c0[j] = 0.0f;
     for (int j = 0; j < f; ++j)
         iv.c0[j] = (float)((double)o[j] + ((double)iv.cmin[j] + (double)iv.cmax[j] + 1.0) * 0.5 * (double)a[j]);
     uint16_t* srec;
     float* sxn;
     if (keep.alloc((void**)&srec, (size_t)n * 2 * iv.sp * 2) || keep.alloc((void**)&sxn, (size_t)n * 4))
-        return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the screen records");
+        return no_memory(keep, "ghn_build", "screen records");
     if ((e = launch_screen_records(iv, srec, sxn, s)) != hipSuccess) return hip_fail(e, "ghn_build: screen records");
     iv.srec = srec;
     iv.sxn = sxn;
@@ -469,7 +542,7 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
     void* stemp;
     if (tmp.alloc((void**)&heads, n * 4) || tmp.alloc((void**)&rank, n * 4) ||
         tmp.alloc(&stemp, exclusive_scan_temp_bytes(n)))
-        return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the cell list");
+        return no_memory(tmp, "ghn_build", "cell list");
     e = skeys ? launch_cell_heads(skeys, n, heads, s) : launch_cell_heads_ids(iv, n, heads, s);
     if (e != hipSuccess) return hip_fail(e, "ghn_build: heads");
     if ((e = exclusive_scan_u32(heads, rank, n, stemp, s)) != hipSuccess) return hip_fail(e, "ghn_build: scan");
@@ -482,7 +555,7 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
     uint32_t* cf;
     int32_t* coord;
     if (keep.alloc((void**)&cf, (size_t)(ncell + 1) * 4) || keep.alloc((void**)&coord, (size_t)ncell * f * 4))
-        return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the cell list");
+        return no_memory(keep, "ghn_build", "cell list");
     if ((e = launch_cell_list(heads, rank, n, iv, cf, coord, s)) != hipSuccess) return hip_fail(e, "ghn_build: cell list");
     const uint32_t n32 = (uint32_t)n;
     if ((e = hipMemcpyAsync(cf + ncell, &n32, 4, hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e, "ghn_build: cell end");
@@ -500,7 +573,7 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
     }
     int32_t *nlo = nullptr, *nhi = nullptr;
     if (total > 0 && (keep.alloc((void**)&nlo, (size_t)total * f * 4) || keep.alloc((void**)&nhi, (size_t)total * f * 4)))
-        return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the tree");
+        return no_memory(keep, "ghn_build", "tree");
     for (int L = 1; L <= top; ++L) {
         const int32_t* clo = L == 1 ? coord : nlo + off[L - 1] * f;
         const int32_t* chi = L == 1 ? coord : nhi + off[L - 1] * f;
@@ -524,7 +597,7 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
         uint64_t* hk;
         uint32_t* hv;
         if (keep.alloc((void**)&hk, (size_t)cap * 8) || keep.alloc((void**)&hv, (size_t)cap * 4))
-            return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the hash table");
+            return no_memory(keep, "ghn_build", "hash table");
         if ((e = launch_hash_build(skeys, cf, ncell, hk, hv, cap - 1, s)) != hipSuccess) return hip_fail(e, "ghn_build: hash table");
         iv.hkeys = hk;
         iv.hvals = hv;
@@ -533,7 +606,7 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
     }
     if (lookup == GHN_LOOKUP_DENSE) {
         uint32_t* cs;
-        if (keep.alloc((void**)&cs, (size_t)(box + 1) * 4)) return fail(GHN_E_NOMEM, "ghn_build: out of device memory for the table");
+        if (keep.alloc((void**)&cs, (size_t)(box + 1) * 4)) return no_memory(keep, "ghn_build", "table");
         if ((e = launch_dense_cell_start(skeys, n, box, cs, s)) != hipSuccess) return hip_fail(e, "ghn_build: table");
         iv.cell_start = cs;
         table_bytes += (size_t)(box + 1) * 4;
@@ -542,7 +615,7 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "ghn_build: sync");
 
     ghn::IndexView* ivd;
-    if (keep.alloc((void**)&ivd, sizeof(IndexView))) return fail(GHN_E_NOMEM, "ghn_build: out of device memory");
+    if (keep.alloc((void**)&ivd, sizeof(IndexView))) return no_memory(keep, "ghn_build", "index view");
     if ((e = hipMemcpyAsync(ivd, &iv, sizeof iv, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
         return hip_fail(e, "ghn_build: index view upload");
@@ -564,9 +637,73 @@ ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype,
                            (size_t)n * 2 * iv.sp * 2 + (size_t)n * 4;
     keep.release(ix->allocs);
     ix->want_lookup = want_lookup;
+    ix->info.device_bytes = keep.carving() ? keep.used : ix->info.device_bytes;
     *out = ix;
     return GHN_OK;
 }
+
+// Checks of ghn_build_into's caller buffers.
+ghn_status check_buffer(const char* fn, const char* name, const void* p, size_t bytes, size_t need) {
+    if (!p || bytes < need)
+        return fail(GHN_E_WORKSPACE, "%s: %s of %zu bytes needed, %zu given", fn, name, need, p ? bytes : (size_t)0);
+    if ((uintptr_t)p % 256) return fail(GHN_E_INVALID_ARG, "%s: %s must be 256-byte aligned", fn, name);
+    return GHN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ghn_status ghn_build_ex(const void* points, int64_t n, int32_t f, int32_t dtype, const void* targets, int32_t task,
+                        const float* cell_width, int32_t n_width, const float* origin, const ghn_build_opts* bopts,
+                        void* stream, ghn_index** out) {
+    DevPool tmp, keep;
+    return build_impl(points, n, f, dtype, targets, task, cell_width, n_width, origin, bopts, stream, tmp, keep,
+                      nullptr, out);
+}
+
+size_t ghn_build_workspace_bytes(int64_t n, int32_t f) {
+    (void)f;
+    return n < 1 ? 0 : build_ws_bytes(n);
+}
+
+size_t ghn_index_bytes(int64_t n, int32_t f, int32_t dtype, int32_t task) {
+    (void)dtype; (void)task;
+    if (n < 1 || f < 1 || f > ghn::F_MAX) return 0;
+    const size_t dense = index_bytes_bound(n, f, GHN_LOOKUP_DENSE, dense_limit(n));
+    const size_t hash = index_bytes_bound(n, f, GHN_LOOKUP_HASH, 0);
+    return dense > hash ? dense : hash;
+}
+
+ghn_status ghn_index_bytes_for(const void* points, int64_t n, int32_t f, int32_t dtype, int32_t task,
+                               const float* cell_width, int32_t n_width, const float* origin,
+                               const ghn_build_opts* opts, void* ws, size_t ws_bytes, void* stream,
+                               size_t* out_bytes) {
+    if (!out_bytes) return fail(GHN_E_INVALID_ARG, "ghn_index_bytes_for: out_bytes is NULL");
+    *out_bytes = 0;
+    if (n < 1) return fail(GHN_E_INVALID_ARG, "ghn_index_bytes_for: n=%lld < 1", (long long)n);
+    ghn_status st = check_buffer("ghn_index_bytes_for", "workspace", ws, ws_bytes, up256(sizeof(BuildSmall)));
+    if (st != GHN_OK) return st;
+    DevPool tmp(ws, ws_bytes, "workspace"), keep(nullptr, 0, "index storage");
+    return build_impl(points, n, f, dtype, nullptr, task, cell_width, n_width, origin, opts, stream, tmp, keep,
+                      out_bytes, nullptr);
+}
+
+ghn_status ghn_build_into(const void* points, int64_t n, int32_t f, int32_t dtype, const void* targets, int32_t task,
+                          const float* cell_width, int32_t n_width, const float* origin, const ghn_build_opts* opts,
+                          void* index_storage, size_t index_bytes, void* ws, size_t ws_bytes, void* stream,
+                          ghn_index** out) {
+    if (!out) return fail(GHN_E_INVALID_ARG, "ghn_build_into: out is NULL");
+    *out = nullptr;
+    if (n < 1 || n >= (int64_t(1) << 31)) return fail(GHN_E_INVALID_ARG, "ghn_build_into: n=%lld outside [1, 2^31)", (long long)n);
+    ghn_status st = check_buffer("ghn_build_into", "workspace", ws, ws_bytes, build_ws_bytes(n));
+    if (st != GHN_OK) return st;
+    if ((st = check_buffer("ghn_build_into", "index storage", index_storage, index_bytes, 1)) != GHN_OK) return st;
+    DevPool tmp(ws, ws_bytes, "workspace"), keep(index_storage, index_bytes, "index storage");
+    return build_impl(points, n, f, dtype, targets, task, cell_width, n_width, origin, opts, stream, tmp, keep,
+                      nullptr, out);
+}
+
 
 ghn_status ghn_index_get_info(const ghn_index* index, ghn_index_info* out) {
     if (!index || !out) return fail(GHN_E_INVALID_ARG, "ghn_index_get_info: NULL argument");
@@ -725,6 +862,7 @@ ghn_status ghn_bruteforce(const ghn_index* index, const float* queries, int64_t 
     return predict_common(index, queries, m, k, opts, out_idx, out_d2, out_pred, ws, ws_bytes, stream, true);
 }
 
+
 ghn_status ghn_screen_error(const ghn_index* index, const float* queries, int64_t m, int64_t sample,
                             float* out_abs, float* out_rel, void* stream) {
     using namespace ghn;
@@ -850,6 +988,9 @@ ghn_status ghn_insert(ghn_index* index, const void* points, int64_t n_new, int32
     if (!index) return fail(GHN_E_INVALID_ARG, "ghn_insert: index is NULL");
     if (n_new < 0) return fail(GHN_E_INVALID_ARG, "ghn_insert: n_new < 0");
     if (n_new == 0) return GHN_OK;
+    if (index->allocs.empty())
+        return fail(GHN_E_UNSUPPORTED, "ghn_insert: the index lives in caller storage; build the enlarged index with "
+                    "ghn_build_into");
     if (!points || !targets) return fail(GHN_E_INVALID_ARG, "ghn_insert: points and targets must not be NULL");
     if (dtype != GHN_F32 && dtype != GHN_BF16) return fail(GHN_E_INVALID_ARG, "ghn_insert: bad dtype %d", dtype);
     if (((uintptr_t)points % (dtype == GHN_BF16 ? 2 : 4)) || ((uintptr_t)targets % 4))
