@@ -257,6 +257,27 @@ ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, 
                        const ghn_predict_opts* opts, int64_t* out_idx, double* out_d2, void* out_pred,
                        void* ws, size_t ws_bytes, void* stream);
 
+/* ghn_predict for callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * arguments, kernels and results as ghn_predict, with the workspace taken from
+ * an array the library holds on each GPU (GHN_NOALLOC_WS_BYTES bytes, a static
+ * device array that every GPU the library runs on keeps until the process ends)
+ * instead of a caller workspace.  The caller still passes inputs and outputs.
+ * A call whose workspace (ghn_predict_workspace_bytes) exceeds the array fails
+ * with GHN_E_WORKSPACE before anything is launched: above about 1.85 million
+ * queries for the bf16 screen, 2.76 million for the FP32 screen's spatial sort
+ * (the FP32 screen with GHN_FLAG_NO_SORT or a given order needs none).  No hipMalloc,
+ * hipFree or other allocation happens.  The first call on a GPU looks up that
+ * GPU's array (the device current at the call is used).  Every call on a GPU
+ * shares that GPU's array and its contents from the last call (nothing in it
+ * needs to start at zero: the kernels write what they read): calls that overlap
+ * on one GPU (several streams or threads) race, so the caller must serialise
+ * them.  Errors: those of ghn_predict. */
+#define GHN_NOALLOC_WS_BYTES ((size_t)64 << 20)
+ghn_status ghn_predict_noalloc(const ghn_index* index, const float* queries, int64_t m, int32_t k,
+                               const ghn_predict_opts* opts, int64_t* out_idx, double* out_d2, void* out_pred,
+                               void* stream);
+
 /* Exhaustive KNN (the plain definition, Section I; the paper's comparison
  * method in Table 2) on the same index: every training point is screened for
  * every query with the bf16 matrix-core screen and the exact FP64 re-rank of

@@ -39,8 +39,9 @@ EXPORTED = ["ghn_build", "ghn_build_ex", "ghn_index_get_info", "ghn_destroy", "g
             "ghn_query_order_workspace_bytes", "ghn_query_order", "ghn_batch_workspace_bytes", "ghn_batch_prepare",
             "ghn_predict_batched", "ghn_batch_destroy", "ghn_autotune", "ghn_cell_measure", "ghn_bruteforce",
             "ghn_index_save_bytes", "ghn_index_save", "ghn_index_load", "ghn_insert", "ghn_screen_error",
-            "ghn_build_workspace_bytes", "ghn_index_bytes", "ghn_index_bytes_for",
+            "ghn_predict_noalloc", "ghn_build_workspace_bytes", "ghn_index_bytes", "ghn_index_bytes_for",
             "ghn_build_into", "ghn_last_error"]
+GHN_NOALLOC_WS_BYTES = 64 << 20
 
 
 class GHNError(RuntimeError):
@@ -123,6 +124,8 @@ def _load() -> ctypes.CDLL:
     L.ghn_autotune.argtypes = [P, I64, I32, I32, P, I32, P, I64, I32, I32, P, I32, ctypes.POINTER(ghn_tune_trial),
                                ctypes.POINTER(ghn_tune_trial), I32, ctypes.POINTER(I32), P]
     L.ghn_autotune.restype = ctypes.c_int
+    L.ghn_predict_noalloc.argtypes = [P, P, I64, I32, ctypes.POINTER(ghn_predict_opts), P, P, P, P]
+    L.ghn_predict_noalloc.restype = ctypes.c_int
     L.ghn_bruteforce.argtypes = [P, P, I64, I32, ctypes.POINTER(ghn_predict_opts), P, P, P, P, SZ, P]
     L.ghn_bruteforce.restype = ctypes.c_int
     L.ghn_index_save_bytes.argtypes = [P]
@@ -308,6 +311,16 @@ def ghn_predict(handle, queries: torch.Tensor, k: int, out_idx: torch.Tensor, ou
     ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
     _check(_lib.ghn_predict(handle, _ptr(queries), m, k, ctypes.byref(o), _ptr(out_idx), _ptr(out_d2),
                             _ptr(out_pred), _ptr(ws), ws_bytes, _stream(stream)))
+
+
+def ghn_predict_noalloc(handle, queries: torch.Tensor, k: int, out_idx: torch.Tensor, out_pred: torch.Tensor,
+                        out_d2: Optional[torch.Tensor] = None, stop=GHN_STOP_EXACT, prec=GHN_PREC_FP32, flags=0,
+                        out_stop_layer: Optional[torch.Tensor] = None, group_levels: int = -1, stream=None) -> None:
+    """ghn_predict_noalloc: ghn_predict with the library's own per-GPU workspace array (no allocation)."""
+    m = queries.shape[0]
+    o = _opts(stop, prec, flags, out_stop_layer, group_levels=group_levels)
+    _check(_lib.ghn_predict_noalloc(handle, _ptr(queries), m, k, ctypes.byref(o), _ptr(out_idx), _ptr(out_d2),
+                                    _ptr(out_pred), _stream(stream)))
 
 
 def ghn_bruteforce(handle, queries: torch.Tensor, k: int, out_idx: torch.Tensor, out_pred: torch.Tensor,

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -862,6 +863,58 @@ ghn_status ghn_bruteforce(const ghn_index* index, const float* queries, int64_t 
     return predict_common(index, queries, m, k, opts, out_idx, out_d2, out_pred, ws, ws_bytes, stream, true);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Workspace of ghn_predict_noalloc.  In host code `scratch` only names the symbol;
+// its address on each GPU comes from hipGetSymbolAddress, looked up once per device
+// (with that device current) and kept in g_scratch_ptr.
+__device__ __align__(256) unsigned char scratch[GHN_NOALLOC_WS_BYTES];
+constexpr int SCRATCH_DEVICES = 256;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_DEVICES] = {};
+
+ghn_status scratch_address(void** out) {
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "ghn_predict_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= SCRATCH_DEVICES) return fail(GHN_E_UNSUPPORTED, "ghn_predict_noalloc: device %d", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess)
+            return hip_fail(e, "ghn_predict_noalloc: address of the workspace array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GHN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ghn_status ghn_predict_noalloc(const ghn_index* index, const float* queries, int64_t m, int32_t k,
+                               const ghn_predict_opts* opts, int64_t* out_idx, double* out_d2, void* out_pred,
+                               void* stream) {
+    if (!index) return fail(GHN_E_INVALID_ARG, "ghn_predict_noalloc: index is NULL");
+    if (m < 0 || m >= (int64_t(1) << 32))
+        return fail(GHN_E_INVALID_ARG, "ghn_predict_noalloc: m=%lld outside [0, 2^32)", (long long)m);
+    const size_t need = ghn_predict_workspace_bytes(index, m, k, opts);
+    if (need > GHN_NOALLOC_WS_BYTES)
+        return fail(GHN_E_WORKSPACE, "ghn_predict_noalloc: m=%lld needs %zu bytes of workspace, more than the %zu "
+                    "bytes the library holds (use ghn_predict with a caller workspace)", (long long)m, need,
+                    (size_t)GHN_NOALLOC_WS_BYTES);
+    void* ws = nullptr;
+    if (need > 0) {
+        const ghn_status st = scratch_address(&ws);
+        if (st != GHN_OK) return st;
+    }
+    return predict_common(index, queries, m, k, opts, out_idx, out_d2, out_pred, ws, ws ? GHN_NOALLOC_WS_BYTES : 0,
+                          stream, false);
+}
 
 ghn_status ghn_screen_error(const ghn_index* index, const float* queries, int64_t m, int64_t sample,
                             float* out_abs, float* out_rel, void* stream) {
