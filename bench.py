@@ -72,6 +72,35 @@ def measured_traffic(workload: str, form: str):
     return entry.get("bytes_per_launch")
 
 
+# Algorithmic bytes of the gather/probe walk per query: 4f per candidate point gathered, 16 per
+# index entry read, 4f for the query and 12k for the outputs (ids and distances); C_q and P_q
+# are the kernels' own counts.  The extended count adds the 4-byte row id of every candidate
+# and the prediction.
+BYTES_FORMULA = "4f C_q + 16 P_q + 4f + 12k per query (C_q candidates, P_q index entries read)"
+
+
+def walk_bytes(m, f, k, cands, probes):
+    return m * 4 * f + cands * 4 * f + probes * 16 + m * 12 * k
+
+
+def walk_bytes_extended(m, f, k, cands, probes):
+    return m * 4 * f + cands * (4 * f + 4) + probes * 4 + m * k * 4 + m * k * 8 + m * 4
+
+
+def hbm_roofline(alg_bytes, ext_bytes, kern_ms, traffic, kernel):
+    """Roofline of a gather/probe kernel: `achieved` = algorithmic bytes / kernel time; the
+    counter-measured HBM rate (FETCH_SIZE + WRITE_SIZE, which count L2 misses including those
+    the Infinity Cache serves) and the extended byte count are reported beside it."""
+    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    r = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+         "traffic": traffic, "kernel": kernel, "bytes_per_launch": alg_bytes, "bytes_formula": BYTES_FORMULA,
+         "achieved_extended": ext_bytes / (kern_ms * 1e-3) / 1e9}
+    if traffic is not None:
+        r["measured_GBs"] = traffic / (kern_ms * 1e-3) / 1e9
+        r["traffic_over_algorithmic"] = traffic / alg_bytes
+    return r
+
+
 def write_traffic(pmc_dir: str, workloads, out_file: str = TRAFFIC_FILE) -> dict:
     """Turn rocprofv3 --pmc runs into HBM bytes per launch (profiles/traffic.json).
 
@@ -232,13 +261,15 @@ def bench_multi(args, ghn, W, torch):
     f = 3
     # work counts (untimed)
     cands = probes = 0
+    alg_bytes = ext_bytes = 0
     for p, ix, q in zip(probs, idxs, qs):
         st = ix.predict(q, p.k, stop=stop, with_d2=False, with_stats=True)
-        cands += int(st["cands"].sum().item())
-        probes += int(st["probes"].sum().item())
+        c, pr = int(st["cands"].sum().item()), int(st["probes"].sum().item())
+        cands += c
+        probes += pr
+        alg_bytes += walk_bytes(p.m, f, p.k, c, pr)
+        ext_bytes += walk_bytes_extended(p.m, f, p.k, c, pr)
     torch.cuda.synchronize()
-    out_bytes = sum(p.m * p.k * 8 + p.m * 4 + p.m * p.k * 4 for p in probs)
-    alg_bytes = M * 4 * f + cands * (4 * f + 4) + probes * 4 + out_bytes
 
     def timeit(step):
         for _ in range(args.warmup):
@@ -295,9 +326,26 @@ def bench_multi(args, ghn, W, torch):
         torch.cuda.current_stream().wait_stream(side16)
         ms, per = timeit(g16.replay)
         forms["bf16_per_index_graph"] = dict(ms=ms, per=per)
+        # all items' query groups in one grouped persistent launch (one sort of every
+        # query by (item, cell), then one walk kernel), and its graph replay
+        items16 = [(ix.handle, q, p.k, oi, op, None) for p, ix, q, (oi, op) in zip(probs, idxs, qs, outs)]
+        ws16 = torch.empty(ghn.ghn_batch_workspace_bytes_for(items16, stop, ghn.GHN_PREC_BF16_MFMA, 0,
+                                                             args.group_levels), dtype=torch.uint8, device=dev)
+        batch16 = ghn.ghn_batch_prepare(items16, ws16, stop=stop, prec=ghn.GHN_PREC_BF16_MFMA,
+                                        group_levels=args.group_levels)
+        ms, per = timeit(lambda: ghn.ghn_predict_batched(batch16))
+        forms["bf16_batched"] = dict(ms=ms, per=per)
+        gb = torch.cuda.CUDAGraph()
+        sideb = torch.cuda.Stream()
+        sideb.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(sideb):
+            with torch.cuda.graph(gb, stream=sideb):
+                ghn.ghn_predict_batched(batch16)
+        torch.cuda.current_stream().wait_stream(sideb)
+        ms, per = timeit(gb.replay)
+        forms["bf16_batched_graph"] = dict(ms=ms, per=per)
     best = min(forms, key=lambda n: forms[n]["ms"])
     B = forms[best]
-    achieved = alg_bytes / (B["ms"] * 1e-3) / 1e9
     line = {
         "metric": METRIC, "value": M / (B["ms"] * 1e-3), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": B["ms"], "higher_is_better": True, "scaling": "weak",
@@ -306,9 +354,8 @@ def bench_multi(args, ghn, W, torch):
                                "sum m = %d queries, k in {1,5,10,20}, majority vote, %s stop" % (
                                    len(probs), sum(p.n for p in probs), M, args.stop.upper()),
                    "problems": len(probs), "sum_n": sum(p.n for p in probs), "sum_m": M, "form": best},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_predict_batched" if "batched" in best else "per-index kernels"},
+        "roofline": hbm_roofline(alg_bytes, ext_bytes, B["ms"], None,
+                                 "k_predict_batched" if "batched" in best else "per-index kernels"),
         "forms": {n: {"qps": M / (v["ms"] * 1e-3), "ms_per_step": v["ms"],
                       "step_ms_p10_p50_p90": [float(np.percentile(v["per"], 10)), float(np.median(v["per"])),
                                               float(np.percentile(v["per"], 90))]} for n, v in forms.items()},
@@ -542,13 +589,12 @@ def main():
                                 walk_events=evs)
 
         ms, kern_ms, per = timed(step32)
-        alg_bytes = (m * 4 * f + w["cands"] * (4 * f + 4) + w["probes"] * 4 + m * k * 4 + m * k * 8 + m * 4)
-        achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+        alg_bytes = walk_bytes(m, f, k, w["cands"], w["probes"])
         forms["fp32_plain"] = dict(
             qps=m / (ms * 1e-3), ms_per_step=ms, kernel_ms=kern_ms, per=per, work=w,
-            roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, "fp32"),
-                      "kernel": "k_predict_%s" % ("tree" if ix.info.lookup == 1 else "dense")},
+            roofline=hbm_roofline(alg_bytes, walk_bytes_extended(m, f, k, w["cands"], w["probes"]), kern_ms,
+                                  measured_traffic(args.workload, "fp32"),
+                                  "k_predict_%s" % ("tree" if ix.info.lookup == 1 else "dense")),
             alg={"bytes_per_step": alg_bytes})
     if "bf16" in args.forms:
         nws = ghn.ghn_predict_workspace_bytes(ix.handle, m, k, stop, ghn.GHN_PREC_BF16_MFMA, 0, levels16)
@@ -593,12 +639,11 @@ def main():
 
         ms, kern_ms, per = timed(stepp)
         ghn.ghn_batch_destroy(batch)
-        alg_bytes = (m * 4 * f + w["cands"] * (4 * f + 4) + w["probes"] * 4 + m * k * 4 + m * k * 8 + m * 4)
-        achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+        alg_bytes = walk_bytes(m, f, k, w["cands"], w["probes"])
         forms["fp32_persistent"] = dict(
             qps=m / (ms * 1e-3), ms_per_step=ms, kernel_ms=kern_ms, per=per, work=w,
-            roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_predict_batched"},
+            roofline=hbm_roofline(alg_bytes, walk_bytes_extended(m, f, k, w["cands"], w["probes"]), kern_ms,
+                                  None, "k_predict_batched"),
             alg={"bytes_per_step": alg_bytes, "timed": "counter reset + persistent kernel"})
     if "brute" in args.forms:
         # exhaustive KNN (the paper's comparison method) on the same GPU and index data

@@ -312,8 +312,14 @@ ghn_status ghn_query_order(const ghn_index* index, const float* queries, int64_t
  * caller's device workspace (synchronising `stream`) and returns a HOST handle;
  * ghn_predict_batched then only launches kernels that read device memory, so
  * the call can be captured into a graph (hipStreamBeginCapture) and replayed.
- * Results equal those of ghn_predict on each item with the same options (FP32
- * screen; the bf16 screen is per index).  All items must share f. */
+ * Results equal those of ghn_predict on each item with the same options.  All
+ * items must share f.
+ * With the FP32 screen the waves take single queries; with GHN_PREC_BF16_MFMA
+ * all items' queries are sorted together by (item, Morton code of the central
+ * cell) and cut into groups (one item, one cell or, under GHN_STOP_EXACT, one
+ * block of 2^group_levels cells per dimension), and one persistent launch walks
+ * every group of every item with the grouped matrix-core screen (as ghn_predict's
+ * GHN_PREC_BF16_MFMA path). */
 typedef struct {
     const ghn_index* index;
     const float* queries;  /* m x f float32 */
@@ -326,9 +332,14 @@ typedef struct {
 
 typedef struct ghn_batch ghn_batch;
 
+/* Workspace of a batch: ghn_batch_workspace_bytes covers the FP32 screen (item
+ * descriptors and a work counter); ghn_batch_workspace_bytes_for covers the given
+ * items and options (HOST), with the bf16 screen's sort and groups of all their
+ * queries (about 36 bytes per query). */
 size_t ghn_batch_workspace_bytes(int32_t n_items);
-/* items and opts are HOST memory; opts may be NULL (EXACT, FP32).  Only the stop
- * rule and flags of opts are used; prec must be GHN_PREC_FP32.  The workspace
+size_t ghn_batch_workspace_bytes_for(const ghn_batch_item* items, int32_t n_items, const ghn_predict_opts* opts);
+/* items and opts are HOST memory; opts may be NULL (EXACT, FP32).  Of opts the stop
+ * rule, the screen (prec), the flags and group_levels are used.  The workspace
  * and every item's arrays must stay valid until the batch is destroyed.
  * Errors: GHN_E_INVALID_ARG, GHN_E_K_GT_N, GHN_E_WORKSPACE, GHN_E_UNSUPPORTED,
  * GHN_E_HIP. */

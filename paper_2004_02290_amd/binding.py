@@ -40,7 +40,7 @@ EXPORTED = ["ghn_build", "ghn_build_ex", "ghn_index_get_info", "ghn_destroy", "g
             "ghn_predict_batched", "ghn_batch_destroy", "ghn_autotune", "ghn_cell_measure", "ghn_bruteforce",
             "ghn_index_save_bytes", "ghn_index_save", "ghn_index_load", "ghn_insert", "ghn_screen_error",
             "ghn_predict_noalloc", "ghn_build_workspace_bytes", "ghn_index_bytes", "ghn_index_bytes_for",
-            "ghn_build_into", "ghn_last_error"]
+            "ghn_build_into", "ghn_batch_workspace_bytes_for", "ghn_last_error"]
 GHN_NOALLOC_WS_BYTES = 64 << 20
 
 
@@ -114,6 +114,8 @@ def _load() -> ctypes.CDLL:
     L.ghn_query_order.restype = ctypes.c_int
     L.ghn_batch_workspace_bytes.argtypes = [I32]
     L.ghn_batch_workspace_bytes.restype = SZ
+    L.ghn_batch_workspace_bytes_for.argtypes = [ctypes.POINTER(ghn_batch_item), I32, ctypes.POINTER(ghn_predict_opts)]
+    L.ghn_batch_workspace_bytes_for.restype = SZ
     L.ghn_batch_prepare.argtypes = [ctypes.POINTER(ghn_batch_item), I32, ctypes.POINTER(ghn_predict_opts), P, SZ, P,
                                     ctypes.POINTER(P)]
     L.ghn_batch_prepare.restype = ctypes.c_int
@@ -349,13 +351,25 @@ def ghn_batch_workspace_bytes(n_items: int) -> int:
     return int(_lib.ghn_batch_workspace_bytes(n_items))
 
 
-def ghn_batch_prepare(items, ws: torch.Tensor, stop=GHN_STOP_EXACT, flags=0, stream=None) -> ctypes.c_void_p:
-    """ghn_batch_prepare: items = [(handle, queries, k, out_idx, out_pred, out_d2 or None), ...]."""
+def _batch_items(items):
     arr = (ghn_batch_item * len(items))()
     for i, (h, q, k, oi, op, od) in enumerate(items):
         arr[i] = ghn_batch_item(h.value if isinstance(h, ctypes.c_void_p) else h, _ptr(q), q.shape[0], int(k),
                                 _ptr(oi), _ptr(od), _ptr(op))
-    o = _opts(stop, GHN_PREC_FP32, flags)
+    return arr
+
+
+def ghn_batch_workspace_bytes_for(items, stop=GHN_STOP_EXACT, prec=GHN_PREC_FP32, flags=0, group_levels=-1) -> int:
+    """ghn_batch_workspace_bytes_for: workspace of a batch of these items (as ghn_batch_prepare's)."""
+    o = _opts(stop, prec, flags, group_levels=group_levels)
+    return int(_lib.ghn_batch_workspace_bytes_for(_batch_items(items), len(items), ctypes.byref(o)))
+
+
+def ghn_batch_prepare(items, ws: torch.Tensor, stop=GHN_STOP_EXACT, flags=0, stream=None, prec=GHN_PREC_FP32,
+                      group_levels=-1) -> ctypes.c_void_p:
+    """ghn_batch_prepare: items = [(handle, queries, k, out_idx, out_pred, out_d2 or None), ...]."""
+    arr = _batch_items(items)
+    o = _opts(stop, prec, flags, group_levels=group_levels)
     out = ctypes.c_void_p()
     _check(_lib.ghn_batch_prepare(arr, len(items), ctypes.byref(o), _ptr(ws), ws.numel() * ws.element_size(),
                                   _stream(stream), ctypes.byref(out)))

@@ -27,6 +27,12 @@ struct ghn_batch {
     int32_t f;
     int32_t stop;
     bool any_tree;  // some item's index uses the cell tree
+    // bf16 screen: one grouped launch over all items' query groups
+    int32_t prec;
+    int32_t kmax;
+    int32_t kb;         // key bits below the item index
+    int32_t key_bits;   // bits of the sort key
+    void* group_ws;     // group_ws_bytes(total) bytes of the caller's workspace
 };
 
 namespace {
@@ -145,6 +151,15 @@ size_t ghn_batch_workspace_bytes(int32_t n_items) {
     return (((size_t)n_items * sizeof(ghn::BatchItem) + 255) & ~(size_t)255) + 256;
 }
 
+size_t ghn_batch_workspace_bytes_for(const ghn_batch_item* items, int32_t n_items, const ghn_predict_opts* opts) {
+    if (n_items <= 0 || !items) return 0;
+    const size_t base = ghn_batch_workspace_bytes(n_items);
+    if (!opts || opts->prec != GHN_PREC_BF16_MFMA) return base;
+    int64_t total = 0;
+    for (int32_t i = 0; i < n_items; ++i) total += items[i].m > 0 ? items[i].m : 0;
+    return base + (total > 0 ? ghn::group_ws_bytes(total) : 0);
+}
+
 ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const ghn_predict_opts* opts, void* ws,
                              size_t ws_bytes, void* stream, ghn_batch** out) {
     using namespace ghn;
@@ -154,9 +169,12 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
     ghn_predict_opts o = {GHN_STOP_EXACT, GHN_PREC_FP32, 0u, nullptr, nullptr, nullptr, nullptr, -1, nullptr, nullptr};
     if (opts) o = *opts;
     if (o.stop != GHN_STOP_EXACT && o.stop != GHN_STOP_PAPER) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: bad stop rule %d", o.stop);
-    if (o.prec != GHN_PREC_FP32) return fail(GHN_E_UNSUPPORTED, "ghn_batch_prepare: batches use the FP32 screen");
+    if (o.prec != GHN_PREC_FP32 && o.prec != GHN_PREC_BF16_MFMA) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: bad precision %d", o.prec);
+    if (o.group_levels < -1 || o.group_levels > 16) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: group_levels=%d outside [-1, 16]", o.group_levels);
     if (o.flags & ~(GHN_FLAG_NO_PRUNE | GHN_FLAG_NO_SORT | GHN_FLAG_MEDIAN)) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: unknown flags 0x%x", o.flags);
-    const size_t need = ghn_batch_workspace_bytes(n_items);
+    const size_t base = ghn_batch_workspace_bytes(n_items);
+    ghn_predict_opts oo = o;
+    const size_t need = ghn_batch_workspace_bytes_for(items, n_items, &oo);
     if (!ws || ws_bytes < need)
         return fail(GHN_E_WORKSPACE, "ghn_batch_prepare: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
     if ((uintptr_t)ws % 256) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: workspace must be 256-byte aligned");
@@ -195,6 +213,44 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
         total += it.m;
         if (it.m > 0 && it.index->view.lookup != LOOKUP_DENSE) any_tree = true;
     }
+    // bf16: the sort key of every item's queries (item index above kb bits, then the
+    // item's Morton code of the central cell, aligned) and its group shift
+    int32_t kmax = 1, kb = 0, key_bits = 1;
+    if (o.prec == GHN_PREC_BF16_MFMA) {
+        int item_bits = 0;
+        while ((int64_t(1) << item_bits) < (int64_t)n_items) ++item_bits;
+        std::vector<int> cbits((size_t)n_items), scode((size_t)n_items), tot((size_t)n_items);
+        const int levels = o.stop == GHN_STOP_PAPER ? 0 : (o.group_levels >= 0 ? o.group_levels : (f >= 12 ? 3 : 1));
+        int maxc = 0;
+        for (int32_t i = 0; i < n_items; ++i) {
+            const IndexView& v = items[i].index->view;
+            int bits[F_MAX], total = 0, maxb = 0;
+            for (int j = 0; j < f; ++j) {
+                const uint32_t span = (uint32_t)(v.cmax[j] - v.cmin[j]);
+                bits[j] = span ? 32 - __builtin_clz(span) : 0;
+                total += bits[j];
+                maxb = maxb > bits[j] ? maxb : bits[j];
+            }
+            int sh = 0;
+            for (int b = 0; b < levels && b < maxb; ++b)
+                for (int j = 0; j < f; ++j) sh += bits[j] > b ? 1 : 0;
+            cbits[(size_t)i] = total > 64 ? 64 : total;
+            scode[(size_t)i] = total > 64 ? (sh > total - 64 ? sh - (total - 64) : 0) : sh;
+            tot[(size_t)i] = total;
+            if (items[i].m > 0 && cbits[(size_t)i] > maxc) maxc = cbits[(size_t)i];
+            if (items[i].k > kmax) kmax = items[i].k;
+        }
+        kb = 64 - item_bits < maxc ? 64 - item_bits : maxc;
+        key_bits = item_bits + kb > 0 ? item_bits + kb : 1;
+        for (int32_t i = 0; i < n_items; ++i) {
+            BatchItem& b = h[(size_t)i];
+            b.kshift = kb - cbits[(size_t)i];
+            b.gshift = b.kshift >= 0 ? scode[(size_t)i] + b.kshift
+                                     : (scode[(size_t)i] + b.kshift > 0 ? scode[(size_t)i] + b.kshift : 0);
+            b.trunc = o.stop == GHN_STOP_PAPER && (tot[(size_t)i] > cbits[(size_t)i] || b.kshift < 0) ? 1 : 0;
+            b.pad = 0;
+        }
+    }
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "ghn_batch_prepare: pending HIP error");
@@ -203,12 +259,17 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
         return hip_fail(e, "ghn_batch_prepare: upload");
     ghn_batch* b = new ghn_batch();
     b->items_dev = (BatchItem*)ws;
-    b->counter_dev = (uint64_t*)((char*)ws + need - 256);
+    b->counter_dev = (uint64_t*)((char*)ws + base - 256);
     b->n_items = n_items;
     b->total = total;
     b->f = f;
     b->stop = o.stop;
     b->any_tree = any_tree;
+    b->prec = o.prec;
+    b->kmax = kmax;
+    b->kb = kb;
+    b->key_bits = key_bits;
+    b->group_ws = (char*)ws + base;
     *out = b;
     return GHN_OK;
 }
@@ -216,6 +277,13 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
 ghn_status ghn_predict_batched(const ghn_batch* batch, void* stream) {
     if (!batch) return fail(GHN_E_INVALID_ARG, "ghn_predict_batched: batch is NULL");
     if (batch->total == 0) return GHN_OK;
+    if (batch->prec == GHN_PREC_BF16_MFMA) {
+        const hipError_t e = ghn::run_grouped_batched(batch->items_dev, batch->n_items, batch->total, batch->f,
+                                                      batch->kmax, batch->stop, batch->kb, batch->key_bits,
+                                                      batch->group_ws, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "ghn_predict_batched: grouped launch");
+        return GHN_OK;
+    }
     hipError_t e = ghn::launch_predict_batched(batch->items_dev, batch->n_items, batch->total, batch->f, batch->stop,
                                                batch->any_tree, batch->counter_dev, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "ghn_predict_batched: launch");

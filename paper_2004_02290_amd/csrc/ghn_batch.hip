@@ -53,13 +53,7 @@ void k_predict_batched(const BatchItem* __restrict__ items, int n_items, int64_t
         for (int c = 0; c < CHUNK; ++c) {
             const int64_t w = (int64_t)w0 + c;
             if (w >= total) break;
-            int lo = 0, hi = n_items;  // last item whose first position is <= w
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (items[mid].first <= w) lo = mid;
-                else hi = mid;
-            }
-            const BatchItem& it = items[lo];
+            const BatchItem& it = items[batch_item_of(items, n_items, w)];
             const IndexView& ix = *it.ix;
             const int64_t qi = w - it.first;
             if (!TREE && ix.lookup != LOOKUP_DENSE) continue;  // not launched so (the host checks the items)

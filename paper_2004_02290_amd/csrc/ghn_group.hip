@@ -37,6 +37,8 @@
 // 16-lane DPP row g holds queries 4g .. 4g+3.  Each query's size-k buffer lives
 // in registers of its row (entry e = 16 j + t in register j of lane t), so the
 // four rows insert in parallel with row-local DPP shifts.
+#include <cstring>
+
 #include "ghn_walk.h"
 
 namespace ghn {
@@ -87,12 +89,10 @@ __device__ __forceinline__ float admit_group(double tau) {
     return f32_round_up(tau * (1.0 + 0x1p-30)) + 0x1p-125f;
 }
 
-// Sort key and flags of every query: Morton code of its central cell clamped to
-// the occupied box; flag bit 0 = a coordinate is not finite, bit 1 = the central
-// cell lies outside the box (such queries walk alone).
-__global__ __launch_bounds__(256) void k_group_keys(const float* __restrict__ qs, int64_t m, IndexView ix,
-                                                    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                    uint32_t* __restrict__ qflags) {
+// Sort key and flags of a query: the top 64 bits of the Morton code of its central
+// cell clamped to the occupied box; flag bit 0 = a coordinate is not finite, bit 1 =
+// the central cell lies outside the box (such queries walk alone).
+__device__ __forceinline__ uint64_t query_group_code(const IndexView& ix, const float* q, uint32_t& fl) {
     const int f = ix.f;
     int bits[F_MAX];
     int maxb = 0, total = 0;
@@ -103,29 +103,54 @@ __global__ __launch_bounds__(256) void k_group_keys(const float* __restrict__ qs
         total += bits[j];
     }
     const int drop = total > 64 ? total - 64 : 0;
+    uint32_t u[F_MAX];
+    fl = 0;
+    for (int j = 0; j < f; ++j) {
+        const float x = q[j];
+        int64_t c = 0;
+        if (isfinite(x)) c = exact_floor_div(__dadd_rn((double)x, -(double)ix.o[j]), (double)ix.a[j]);
+        else fl |= 1u;
+        if (c < ix.cmin[j] || c > ix.cmax[j]) fl |= 2u;
+        c = min(max(c, (int64_t)ix.cmin[j]), (int64_t)ix.cmax[j]);
+        u[j] = (uint32_t)(c - ix.cmin[j]);
+    }
+    uint64_t code = 0;
+    int pos = total;
+    for (int b = maxb - 1; b >= 0; --b)
+        for (int j = 0; j < f; ++j)
+            if (b < bits[j]) {
+                --pos;
+                if (pos >= drop) code = (code << 1) | ((u[j] >> b) & 1u);
+            }
+    return code;
+}
+
+__global__ __launch_bounds__(256) void k_group_keys(const float* __restrict__ qs, int64_t m, IndexView ix,
+                                                    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                    uint32_t* __restrict__ qflags) {
     for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
-        uint32_t u[F_MAX];
-        uint32_t fl = 0;
-        for (int j = 0; j < f; ++j) {
-            const float x = qs[i * f + j];
-            int64_t c = 0;
-            if (isfinite(x)) c = exact_floor_div(__dadd_rn((double)x, -(double)ix.o[j]), (double)ix.a[j]);
-            else fl |= 1u;
-            if (c < ix.cmin[j] || c > ix.cmax[j]) fl |= 2u;
-            c = min(max(c, (int64_t)ix.cmin[j]), (int64_t)ix.cmax[j]);
-            u[j] = (uint32_t)(c - ix.cmin[j]);
-        }
-        uint64_t code = 0;  // the top 64 bits of the code
-        int pos = total;
-        for (int b = maxb - 1; b >= 0; --b)
-            for (int j = 0; j < f; ++j)
-                if (b < bits[j]) {
-                    --pos;
-                    if (pos >= drop) code = (code << 1) | ((u[j] >> b) & 1u);
-                }
-        keys[i] = code;
+        uint32_t fl;
+        keys[i] = query_group_code(ix, qs + i * ix.f, fl);
         vals[i] = (uint32_t)i;
         qflags[i] = fl;
+    }
+}
+
+// The same over all queries of a batch (global positions): the item's index above
+// kb key bits, its code moved by the item's kshift below.
+__global__ __launch_bounds__(256) void k_batch_group_keys(const BatchItem* __restrict__ items, int n_items,
+                                                          int64_t total, int kb, uint64_t* __restrict__ keys,
+                                                          uint32_t* __restrict__ vals, uint32_t* __restrict__ qflags) {
+    for (int64_t w = blockIdx.x * 256ll + threadIdx.x; w < total; w += (int64_t)gridDim.x * 256) {
+        const int it = batch_item_of(items, n_items, w);
+        const BatchItem& B = items[it];
+        const IndexView& ix = *B.ix;
+        uint32_t fl;
+        const uint64_t code = query_group_code(ix, B.io.queries + (w - B.first) * ix.f, fl);
+        const uint64_t kc = B.kshift >= 0 ? code << B.kshift : code >> (-B.kshift);
+        keys[w] = kb < 64 ? ((uint64_t)it << kb) | kc : kc;
+        vals[w] = (uint32_t)w;
+        qflags[w] = fl;
     }
 }
 
@@ -169,12 +194,41 @@ __global__ __launch_bounds__(256) void k_form_groups(const uint64_t* __restrict_
     }
 }
 
+// Group starts of a batch: also where the item changes; the key shift and the PAPER
+// rule's exact cell check are the item's.
+__device__ __forceinline__ bool batch_group_start(const uint64_t* keys, const uint32_t* vals, const uint32_t* qflags,
+                                                  int64_t i, const BatchItem* items, int kb) {
+    if (i == 0 || (i % GQ) == 0) return true;
+    if (qflags[vals[i]] || qflags[vals[i - 1]]) return true;
+    const int it = kb < 64 ? (int)(keys[i] >> kb) : 0;
+    if (kb < 64 && it != (int)(keys[i - 1] >> kb)) return true;
+    const BatchItem& B = items[it];
+    if (B.gshift < 64 && (keys[i] >> B.gshift) != (keys[i - 1] >> B.gshift)) return true;
+    return B.trunc && !same_cell(B.io.queries, *B.ix, (uint32_t)(vals[i] - B.first), (uint32_t)(vals[i - 1] - B.first));
+}
+
+__global__ __launch_bounds__(256) void k_batch_form_groups(const uint64_t* __restrict__ keys,
+                                                           const uint32_t* __restrict__ vals,
+                                                           const uint32_t* __restrict__ qflags, int64_t total,
+                                                           const BatchItem* __restrict__ items, int kb,
+                                                           uint2* __restrict__ groups, uint32_t* ngroups) {
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        if (!batch_group_start(keys, vals, qflags, i, items, kb)) continue;
+        int64_t j = i + 1;
+        while (j < total && !batch_group_start(keys, vals, qflags, j, items, kb)) ++j;
+        const uint32_t g = atomicAdd(ngroups, 1u);
+        groups[g] = make_uint2((uint32_t)i, (uint32_t)(j - i));
+    }
+}
+
 struct GroupArgs {
     int32_t brute;          // exhaustive KNN: no grid walk, every point screened
-    PredictArgs p;          // p.order = queries in sorted order
+    PredictArgs p;          // p.order = queries in sorted order (global positions in a batch)
     const uint2* groups;
     const uint32_t* counters;  // [0] = number of groups
     uint32_t* work;            // next group to take
+    const BatchItem* items;    // batch: the items (device), in order of first positions
+    int32_t n_items;
 };
 
 template <int FT>
@@ -282,22 +336,20 @@ __device__ __forceinline__ floatx4 screen_block(const IndexView& ix, const bf16x
     return acc;
 }
 
-template <int FT, int SP, int KR>
+// BATCH: the groups come from many indexes (a batch); each group belongs to one item,
+// found from its first query's global position, and is walked with that item's index,
+// queries, k and outputs.  KR covers the largest k of the batch.
+template <int FT, int SP, int KR, bool BATCH>
 __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
     __shared__ GroupLds<FT> lds_all[GWPB];
     constexpr int FS = GroupLds<FT>::FS;
     using SC = Screen<SP>;
     constexpr int NKB = SC::NKB;
     constexpr int NCH = SC::NCH;
-    const PredictArgs& A = G.p;
-    const IndexView& ix = A.ix;
     const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     GroupLds<FT>& S = lds_all[wv];
-    const int f = FT > 0 ? FT : ix.f;
-    const int k = A.io.k;
     const int g = lane >> 4, t = lane & 15;
-    const bool prune = !(A.io.flags & GHN_FLAG_NO_PRUNE);
     const uint32_t ngroups = G.counters[0];
     const float inf = __int_as_float(0x7f800000);
 
@@ -308,16 +360,25 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
         if (gid >= ngroups) break;
         const uint2 gd = G.groups[gid];
         const int cnt = (int)gd.y;
+        // the group's index, queries and outputs; query positions are global in a batch
+        const BatchItem* item = nullptr;
+        if constexpr (BATCH) item = &G.items[batch_item_of(G.items, G.n_items, (int64_t)G.p.order[gd.x])];
+        const IndexView& ix = BATCH ? *item->ix : G.p.ix;
+        const QueryIO& io = BATCH ? item->io : G.p.io;
+        const int64_t qbase = BATCH ? item->first : 0;
+        const int f = FT > 0 ? FT : ix.f;
+        const int k = io.k;
+        const bool prune = !(io.flags & GHN_FLAG_NO_PRUNE);
 
         // ---- group set-up: lane r < cnt loads query r
         bool fin = false;
         {
             const bool act = lane < cnt;
-            const int64_t qi = act ? (int64_t)A.order[gd.x + lane] : 0;
+            const int64_t qi = act ? (int64_t)G.p.order[gd.x + lane] - qbase : 0;
             fin = act;
             int32_t cc[FS];
             for (int j = 0; j < f; ++j) {
-                const float x = act ? A.io.queries[qi * f + j] : 0.0f;
+                const float x = act ? io.queries[qi * f + j] : 0.0f;
                 fin = fin && isfinite(x);
                 cc[j] = 0;
                 if (act) { S.q[lane][j] = x; S.qd[lane][j] = (double)x; }
@@ -344,9 +405,9 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
             far0 = readlane_i32(far0, 0);
             int64_t gshift = 0;
             if (cnt == 1 && far0 == (int32_t)CLAMP) {
-                const int64_t q0 = (int64_t)A.order[gd.x];
-                gshift = far_shift(ix, A.io.queries, q0, f);
-                const int32_t cl = far_frame_id(ix, A.io.queries, q0, f);
+                const int64_t q0 = (int64_t)G.p.order[gd.x] - qbase;
+                gshift = far_shift(ix, io.queries, q0, f);
+                const int32_t cl = far_frame_id(ix, io.queries, q0, f);
                 if (lane < f) S.qc[0][lane] = cl;
                 for (int j = 0; j < f; ++j) {
                     const int32_t c0 = readlane_i32(cl, j);
@@ -847,7 +908,7 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                 const bool full = taui[i] != INT32_MAX;
                 bool stop = l >= lcover;
                 if (!stop && full) {
-                    if (A.stop == GHN_STOP_PAPER) {
+                    if (G.p.stop == GHN_STOP_PAPER) {
                         stop = !upd[i];
                     } else {
                         double r2 = __longlong_as_double(0x7ff0000000000000LL);
@@ -883,23 +944,23 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
         for (int i = 0; i < 4; ++i) {
             const int r = 4 * g + i;
             const bool act = r < cnt;
-            const int64_t qi = act ? (int64_t)A.order[gd.x + r] : 0;
+            const int64_t qi = act ? (int64_t)G.p.order[gd.x + r] - qbase : 0;
             const bool live = act && ((fin_mask >> r) & 1);
             if (act && !live) {
                 for (int j = 0; j < KR; ++j) {
                     const int ee = 16 * j + t;
                     if (ee < k) {
-                        A.io.out_idx[qi * k + ee] = -1;
-                        if (A.io.out_d2) A.io.out_d2[qi * k + ee] = __longlong_as_double(0x7ff8000000000000LL);
+                        io.out_idx[qi * k + ee] = -1;
+                        if (io.out_d2) io.out_d2[qi * k + ee] = __longlong_as_double(0x7ff8000000000000LL);
                     }
                 }
                 if (t == 0) {
-                    if (ix.task == GHN_CLASSIFY) ((int32_t*)A.io.out_pred)[qi] = -1;
-                    else ((float*)A.io.out_pred)[qi] = __int_as_float(0x7fc00000);
-                    if (A.io.out_stop_layer) A.io.out_stop_layer[qi] = -1;
-                    if (A.io.out_cands) A.io.out_cands[qi] = 0;
-                    if (A.io.out_probes) A.io.out_probes[qi] = 0;
-                    if (A.io.out_rerank) A.io.out_rerank[qi] = 0;
+                    if (ix.task == GHN_CLASSIFY) ((int32_t*)io.out_pred)[qi] = -1;
+                    else ((float*)io.out_pred)[qi] = __int_as_float(0x7fc00000);
+                    if (io.out_stop_layer) io.out_stop_layer[qi] = -1;
+                    if (io.out_cands) io.out_cands[qi] = 0;
+                    if (io.out_probes) io.out_probes[qi] = 0;
+                    if (io.out_rerank) io.out_rerank[qi] = 0;
                 }
             }
             if (live) {
@@ -907,8 +968,8 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                 for (int j = 0; j < KR; ++j) {
                     const int ee = 16 * j + t;
                     if (ee < k) {
-                        A.io.out_idx[qi * k + ee] = bi[i][j];
-                        if (A.io.out_d2) A.io.out_d2[qi * k + ee] = bd[i][j];
+                        io.out_idx[qi * k + ee] = bi[i][j];
+                        if (io.out_d2) io.out_d2[qi * k + ee] = bd[i][j];
                         S.lab[g][ee] = (uint32_t)bi[i][j] < (uint64_t)ix.n ? ((const int32_t*)ix.targets)[bi[i][j]] : 0;
                     }
                 }
@@ -930,8 +991,8 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                         const int ob = __shfl_xor(best, d, 16), on = __shfl_xor(best_n, d, 16);
                         if (on > best_n || (on == best_n && ob < best)) { best = ob; best_n = on; }
                     }
-                    if (t == 0) ((int32_t*)A.io.out_pred)[qi] = best;
-                } else if (A.io.flags & GHN_FLAG_MEDIAN) {
+                    if (t == 0) ((int32_t*)io.out_pred)[qi] = best;
+                } else if (io.flags & GHN_FLAG_MEDIAN) {
                     // the targets at sorted positions (k - 1) / 2 and k / 2 (IEEE total order): each
                     // entry's rank is counted against the row's k targets
                     const int p1 = (k - 1) >> 1, p2 = k >> 1;
@@ -952,18 +1013,18 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                     wave_lds_sync();
                     if (t == 0) {
                         const float a = __int_as_float(S.med[g][0]), b = __int_as_float(S.med[g][1]);
-                        ((float*)A.io.out_pred)[qi] = (k & 1) ? a : (float)(__dadd_rn((double)a, (double)b) / 2.0);
+                        ((float*)io.out_pred)[qi] = (k & 1) ? a : (float)(__dadd_rn((double)a, (double)b) / 2.0);
                     }
                 } else if (t == 0) {
                     double s = 0.0;
                     for (int e2 = 0; e2 < k; ++e2) s = __dadd_rn(s, (double)__int_as_float(S.lab[g][e2]));
-                    ((float*)A.io.out_pred)[qi] = (float)(s / (double)k);
+                    ((float*)io.out_pred)[qi] = (float)(s / (double)k);
                 }
                 if (t == 0) {
-                    if (A.io.out_stop_layer) A.io.out_stop_layer[qi] = stopl[i];
-                    if (A.io.out_cands) A.io.out_cands[qi] = cands[i];
-                    if (A.io.out_probes) A.io.out_probes[qi] = probes;
-                    if (A.io.out_rerank) A.io.out_rerank[qi] = rer[i];
+                    if (io.out_stop_layer) io.out_stop_layer[qi] = stopl[i];
+                    if (io.out_cands) io.out_cands[qi] = cands[i];
+                    if (io.out_probes) io.out_probes[qi] = probes;
+                    if (io.out_rerank) io.out_rerank[qi] = rer[i];
                 }
             }
             wave_lds_sync();
@@ -1090,21 +1151,34 @@ hipError_t launch_err(const IndexView& ix, const float* qs, int64_t m, uint32_t 
     return hipGetLastError();
 }
 
-template <int FT, int SP>
-hipError_t launch_k(const GroupArgs& a, int blocks, hipStream_t s) {
-    if (a.p.io.k <= 16) hipLaunchKernelGGL((k_predict_group<FT, SP, 1>), dim3(blocks), dim3(GT), 0, s, a);
-    else if (a.p.io.k <= 32) hipLaunchKernelGGL((k_predict_group<FT, SP, 2>), dim3(blocks), dim3(GT), 0, s, a);
-    else hipLaunchKernelGGL((k_predict_group<FT, SP, 4>), dim3(blocks), dim3(GT), 0, s, a);
+template <int FT, int SP, bool BATCH>
+hipError_t launch_k(const GroupArgs& a, int kmax, int blocks, hipStream_t s) {
+    if (kmax <= 16) hipLaunchKernelGGL((k_predict_group<FT, SP, 1, BATCH>), dim3(blocks), dim3(GT), 0, s, a);
+    else if (kmax <= 32) hipLaunchKernelGGL((k_predict_group<FT, SP, 2, BATCH>), dim3(blocks), dim3(GT), 0, s, a);
+    else hipLaunchKernelGGL((k_predict_group<FT, SP, 4, BATCH>), dim3(blocks), dim3(GT), 0, s, a);
     return hipGetLastError();
 }
 
-template <int FT>
-hipError_t launch_ft(const GroupArgs& a, int blocks, hipStream_t s) {
+// sp: the padded screen dimension (every index of a batch has f, so the same sp)
+template <int FT, bool BATCH>
+hipError_t launch_ft(const GroupArgs& a, int sp, int kmax, int blocks, hipStream_t s) {
     constexpr int SP = FT <= 8 ? 8 : (FT <= 16 ? 16 : 32);
-    if (FT > 0) return launch_k<FT, SP>(a, blocks, s);
-    if (a.p.ix.sp == 8) return launch_k<0, 8>(a, blocks, s);
-    if (a.p.ix.sp == 16) return launch_k<0, 16>(a, blocks, s);
-    return launch_k<0, 32>(a, blocks, s);
+    if (FT > 0) return launch_k<FT, SP, BATCH>(a, kmax, blocks, s);
+    if (sp == 8) return launch_k<0, 8, BATCH>(a, kmax, blocks, s);
+    if (sp == 16) return launch_k<0, 16, BATCH>(a, kmax, blocks, s);
+    return launch_k<0, 32, BATCH>(a, kmax, blocks, s);
+}
+
+template <bool BATCH>
+hipError_t launch_group_walk(const GroupArgs& ga, int f, int sp, int kmax, int blocks, hipStream_t s) {
+    switch (f) {
+        case 2: return launch_ft<2, BATCH>(ga, sp, kmax, blocks, s);
+        case 3: return launch_ft<3, BATCH>(ga, sp, kmax, blocks, s);
+        case 4: return launch_ft<4, BATCH>(ga, sp, kmax, blocks, s);
+        case 8: return launch_ft<8, BATCH>(ga, sp, kmax, blocks, s);
+        case 16: return launch_ft<16, BATCH>(ga, sp, kmax, blocks, s);
+        default: return launch_ft<0, BATCH>(ga, sp, kmax, blocks, s);
+    }
 }
 
 }  // namespace
@@ -1163,19 +1237,56 @@ hipError_t run_grouped(const PredictArgs& pa, int keep_shift_levels, void* ws, h
     ga.groups = groups;
     ga.counters = counters;
     ga.work = counters + 1;
+    ga.items = nullptr;
+    ga.n_items = 0;
     int64_t blocks = (m + GQ * GWPB - 1) / (GQ * GWPB);
     if (blocks > 2048) blocks = 2048;
     if (ev_begin && (e = hipEventRecord(ev_begin, s)) != hipSuccess) return e;
-    switch (ix.f) {
-        case 2: e = launch_ft<2>(ga, (int)blocks, s); break;
-        case 3: e = launch_ft<3>(ga, (int)blocks, s); break;
-        case 4: e = launch_ft<4>(ga, (int)blocks, s); break;
-        case 8: e = launch_ft<8>(ga, (int)blocks, s); break;
-        case 16: e = launch_ft<16>(ga, (int)blocks, s); break;
-        default: e = launch_ft<0>(ga, (int)blocks, s); break;
-    }
+    e = launch_group_walk<false>(ga, ix.f, ix.sp, pa.io.k, (int)blocks, s);
     if (e == hipSuccess && ev_end) e = hipEventRecord(ev_end, s);
     return e;
+}
+
+hipError_t run_grouped_batched(const BatchItem* items, int n_items, int64_t total, int f, int kmax, int stop, int kb,
+                               int key_bits, void* ws, hipStream_t s) {
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const int64_t m = total;
+    char* p = (char*)ws;
+    uint64_t* k0 = (uint64_t*)p; p += up(m * 8);
+    uint64_t* k1 = (uint64_t*)p; p += up(m * 8);
+    uint32_t* v0 = (uint32_t*)p; p += up(m * 4);
+    uint32_t* v1 = (uint32_t*)p; p += up(m * 4);
+    uint32_t* qflags = (uint32_t*)p; p += up(m * 4);
+    uint2* groups = (uint2*)p; p += up(m * 8);
+    uint32_t* counters = (uint32_t*)p; p += up(64);
+    void* rtemp = p;
+    int64_t g = (m + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counters, 2);
+    hipLaunchKernelGGL(k_batch_group_keys, dim3((unsigned)g), dim3(256), 0, s, items, n_items, m, kb, k0, v0, qflags);
+    bool alt = false;
+    hipError_t e = radix_sort_pairs(k0, v0, k1, v1, m, key_bits, rtemp, &alt, s);
+    if (e != hipSuccess) return e;
+    const uint64_t* sk = alt ? k1 : k0;
+    const uint32_t* sv = alt ? v1 : v0;
+    hipLaunchKernelGGL(k_batch_form_groups, dim3((unsigned)g), dim3(256), 0, s, sk, sv, qflags, m, items, kb, groups,
+                       counters);
+    GroupArgs ga;
+    std::memset(&ga, 0, sizeof ga);
+    ga.brute = 0;
+    ga.p.m = m;
+    ga.p.stop = stop;
+    ga.p.order = sv;
+    ga.groups = groups;
+    ga.counters = counters;
+    ga.work = counters + 1;
+    ga.items = items;
+    ga.n_items = n_items;
+    int64_t blocks = (m + GQ * GWPB - 1) / (GQ * GWPB);
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    const int sp = f <= 8 ? 8 : (f <= 16 ? 16 : 32);
+    return launch_group_walk<true>(ga, f, sp, kmax, (int)blocks, s);
 }
 
 hipError_t launch_screen_error(const IndexView& ix, const float* qs, int64_t m, uint32_t nsamp, float* out_abs,

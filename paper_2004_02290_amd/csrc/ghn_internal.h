@@ -342,9 +342,34 @@ struct BatchItem {
     QueryIO io;
     int64_t first;
     int64_t m;
+    // grouped (bf16) batches: the item's query sort key is (item << kb) | its Morton code
+    // moved by kshift bits (left if >= 0); groups split where the key >> gshift changes;
+    // trunc: the key lost code bits, so the PAPER rule also compares exact cell ids
+    int32_t kshift;
+    int32_t gshift;
+    int32_t trunc;
+    int32_t pad;
 };
+
+// The item owning global query position w: the last item whose first position is <= w
+// (items are in order of first positions; empty items share their successor's).
+__device__ __forceinline__ int batch_item_of(const BatchItem* items, int n_items, int64_t w) {
+    int lo = 0, hi = n_items;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (items[mid].first <= w) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 hipError_t launch_predict_batched(const BatchItem* items, int n_items, int64_t total, int f, int stop, bool any_tree,
                                   uint64_t* counter, hipStream_t s);
+// Grouped (bf16 screen) walk of a whole batch in one persistent launch, after one sort
+// of all its queries by (item, cell) and the grouping; `ws` holds group_ws_bytes(total).
+// kb: key bits below the item index; kmax: largest k.
+hipError_t run_grouped_batched(const BatchItem* items, int n_items, int64_t total, int f, int kmax, int stop, int kb,
+                               int key_bits, void* ws, hipStream_t s);
 
 // Per-dimension range of the finite coordinates of n points (synchronises s).
 hipError_t coord_range(const void* pts, int64_t n, int32_t f, int32_t dtype, float* lo, float* hi, hipStream_t s);

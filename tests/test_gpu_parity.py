@@ -566,10 +566,7 @@ def test_batched_matches_single_and_oracle(ghn):
             single = _run(ghn, ix, p.queries, p.k, stop)
             got = dict(idx=oi.cpu().numpy(), pred=op.cpu().numpy(), d2=od.cpu().numpy())
             _assert_same(got, single, "batched vs single")
-            if stop == ghn.GHN_STOP_EXACT:
-                rows = np.arange(min(p.m, 200))
-                bi, bd, bp = oracle.bruteforce(p.points, p.targets, p.task, p.queries[rows], p.k)
-                _assert_same({k: v[rows] for k, v in got.items()}, dict(idx=bi, d2=bd, pred=bp), "batched vs oracle")
+            _assert_same(got, _oracle_want(p, stop), "batched vs oracle stop=%d" % stop)
         ghn.ghn_batch_destroy(batch)
 
 
@@ -593,6 +590,110 @@ def test_batched_tree_f8(ghn):
                 _assert_same({k: v[rows] for k, v in got.items()}, dict(idx=bi, d2=bd, pred=bp),
                              "batched f=8 vs oracle")
         ghn.ghn_batch_destroy(batch)
+
+
+def _oracle_want(p, stop, median=False):
+    """The oracle's answer for problem p: brute force (EXACT) or the grid walk (PAPER)."""
+    task = oracle.REGRESS_MEDIAN if median else p.task
+    pf = p.points_f32()
+    if stop == 0:
+        bi, bd, bp = oracle.bruteforce(pf, p.targets, task, p.queries, p.k)
+        return dict(idx=bi, d2=bd, pred=bp)
+    w = oracle.Grid(pf, p.targets, task, p.cell_width).predict(p.queries, p.k, oracle.STOP_PAPER)
+    return dict(idx=w["idx"], d2=w["d2"], pred=w["pred"])
+
+
+def _batch_run(ghn, probs, idxs, stop, prec, levels=-1, flags=0):
+    """One batch over (problem, index) pairs; returns the host outputs per problem."""
+    import torch
+    items, outs = [], []
+    for p, ix in zip(probs, idxs):
+        q = _dev(p.queries)
+        oi = torch.full((p.m, p.k), -7, dtype=torch.int64, device="cuda")
+        op = torch.full((p.m,), -7, dtype=torch.int32 if p.task == W.CLASSIFY else torch.float32, device="cuda")
+        od = torch.zeros((p.m, p.k), dtype=torch.float64, device="cuda")
+        items.append((ix.handle, q, p.k, oi, op, od))
+        outs.append((oi, op, od))
+    nb = ghn.ghn_batch_workspace_bytes_for(items, stop, prec, flags, levels)
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device="cuda")
+    batch = ghn.ghn_batch_prepare(items, ws, stop=stop, flags=flags, prec=prec, group_levels=levels)
+    ghn.ghn_predict_batched(batch)
+    torch.cuda.synchronize()
+    ghn.ghn_batch_destroy(batch)
+    return [dict(idx=oi.cpu().numpy(), pred=op.cpu().numpy(), d2=od.cpu().numpy()) for oi, op, od in outs]
+
+
+def test_batched_bf16_matches_oracle(ghn):
+    """The bf16 screen over all items in one grouped persistent launch: every query of
+    every problem against the oracle, both rules, several group sizes."""
+    probs = _multi()
+    idxs = [_index(ghn, p) for p in probs]
+    for stop, levels in ((ghn.GHN_STOP_EXACT, -1), (ghn.GHN_STOP_EXACT, 0), (ghn.GHN_STOP_EXACT, 3),
+                         (ghn.GHN_STOP_PAPER, -1)):
+        got = _batch_run(ghn, probs, idxs, stop, MFMA, levels)
+        for i, (p, g) in enumerate(zip(probs, got)):
+            _assert_same(g, _oracle_want(p, stop), "bf16 batch item %d stop=%d levels=%d" % (i, stop, levels))
+
+
+def test_batched_bf16_mixed_lookups_large_k_and_empty_item(ghn):
+    probs = [W.uniform_problem(n=n, m=m, f=3, k=k, seed=s, width=0.05) for n, m, k, s in
+             ((20_000, 400, 5, 161), (8_000, 300, 40, 162), (30_000, 0, 3, 163), (12_000, 350, 64, 164),
+              (5_000, 200, 1, 165))]
+    lookups = [0, TREE, 0, HASH, 0]
+    idxs = [_index(ghn, p, lookup=lk) for p, lk in zip(probs, lookups)]
+    assert [ix.info.lookup for ix in idxs] == lookups
+    for stop in (ghn.GHN_STOP_EXACT, ghn.GHN_STOP_PAPER):
+        got = _batch_run(ghn, probs, idxs, stop, MFMA)
+        for i, (p, g) in enumerate(zip(probs, got)):
+            if p.m:
+                _assert_same(g, _oracle_want(p, stop), "mixed bf16 batch item %d stop=%d" % (i, stop))
+
+
+def test_batched_bf16_regression_median(ghn):
+    probs = [W.uniform_problem(n=n, m=m, f=3, k=k, seed=s, width=0.05, task=W.REGRESS) for n, m, k, s in
+             ((15_000, 300, 6, 171), (9_000, 250, 11, 172), (4_000, 100, 20, 173))]
+    idxs = [_index(ghn, p) for p in probs]
+    for median in (False, True):
+        got = _batch_run(ghn, probs, idxs, ghn.GHN_STOP_EXACT, MFMA, flags=ghn.GHN_FLAG_MEDIAN if median else 0)
+        for i, (p, g) in enumerate(zip(probs, got)):
+            _assert_same(g, _oracle_want(p, 0, median), "bf16 batch regression item %d median=%d" % (i, median))
+
+
+def test_batched_bf16_graph_replay(ghn):
+    import torch
+    probs = _multi(problems=12, n_hi=20_000, m_hi=2_000, seed=29)
+    items, outs = [], []
+    idxs = [_index(ghn, p) for p in probs]
+    for p, ix in zip(probs, idxs):
+        oi = torch.empty((p.m, p.k), dtype=torch.int64, device="cuda")
+        op = torch.empty(p.m, dtype=torch.int32, device="cuda")
+        od = torch.empty((p.m, p.k), dtype=torch.float64, device="cuda")
+        items.append((ix.handle, _dev(p.queries), p.k, oi, op, od))
+        outs.append((oi, op, od))
+    ws = torch.empty(ghn.ghn_batch_workspace_bytes_for(items, prec=MFMA), dtype=torch.uint8, device="cuda")
+    batch = ghn.ghn_batch_prepare(items, ws, prec=MFMA)
+    ghn.ghn_predict_batched(batch)
+    torch.cuda.synchronize()
+    want = [(oi.clone(), op.clone(), od.clone()) for oi, op, od in outs]
+    for p, (wi, wp, wd) in zip(probs, want):
+        _assert_same(dict(idx=wi.cpu().numpy(), pred=wp.cpu().numpy(), d2=wd.cpu().numpy()), _oracle_want(p, 0),
+                     "bf16 batch before capture")
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            ghn.ghn_predict_batched(batch)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        for oi, op, od in outs:      # eager work between replays
+            oi.fill_(-1); op.fill_(-1); od.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (oi, op, od), (wi, wp, wd) in zip(outs, want):
+            assert torch.equal(oi, wi) and torch.equal(op, wp) and torch.equal(od, wd), rep
+    ghn.ghn_batch_destroy(batch)
 
 
 def test_batched_mixed_lookups(ghn):
@@ -621,6 +722,7 @@ def test_batched_mixed_lookups(ghn):
         for p, (ix, _), (oi, op, od) in zip(probs, idxs, outs):
             got = dict(idx=oi.cpu().numpy(), pred=op.cpu().numpy(), d2=od.cpu().numpy())
             _assert_same(got, _run(ghn, ix, p.queries, p.k, stop), "mixed batch vs single")
+            _assert_same(got, _oracle_want(p, stop), "mixed batch vs oracle")
 
 
 def test_batched_graph_replay(ghn):
@@ -785,6 +887,14 @@ def test_far_queries_shifted_frame_other_lookups(ghn, lookup):
 def test_far_queries_shifted_frame_mfma(ghn):
     prob = _far_problem(3, seed=60)
     _check_mfma(ghn, prob)
+
+
+def test_far_queries_shifted_frame_batched_bf16(ghn):
+    probs = [_far_problem(3, seed=80 + i, n=1000 + 700 * i, m=40 + 9 * i) for i in range(4)]
+    idxs = [_index(ghn, p) for p in probs]
+    for stop in (ghn.GHN_STOP_EXACT, ghn.GHN_STOP_PAPER):
+        for i, (p, g) in enumerate(zip(probs, _batch_run(ghn, probs, idxs, stop, MFMA))):
+            _assert_same(g, _oracle_want(p, stop), "bf16 batch far queries item %d stop=%d" % (i, stop))
 
 
 def test_far_queries_shifted_frame_batched(ghn):
