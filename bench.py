@@ -292,7 +292,13 @@ def bench_multi(args, ghn, W, torch):
         ms, per = timeit(per_item)
         forms["fp32_per_index"] = dict(ms=ms, per=per)
         items = [(ix.handle, q, p.k, oi, op, None) for p, ix, q, (oi, op) in zip(probs, idxs, qs, outs)]
-        ws = torch.empty(ghn.ghn_batch_workspace_bytes(len(items)), dtype=torch.uint8, device=dev)
+        # input order (items one after another) and spatial order (sorted by item and cell)
+        wsi = torch.empty(ghn.ghn_batch_workspace_bytes_for(items, stop, ghn.GHN_PREC_FP32, ghn.GHN_FLAG_NO_SORT),
+                          dtype=torch.uint8, device=dev)
+        batch_in = ghn.ghn_batch_prepare(items, wsi, stop=stop, flags=ghn.GHN_FLAG_NO_SORT)
+        ms, per = timeit(lambda: ghn.ghn_predict_batched(batch_in))
+        forms["fp32_batched_input_order"] = dict(ms=ms, per=per)
+        ws = torch.empty(ghn.ghn_batch_workspace_bytes_for(items, stop), dtype=torch.uint8, device=dev)
         batch = ghn.ghn_batch_prepare(items, ws, stop=stop)
         ms, per = timeit(lambda: ghn.ghn_predict_batched(batch))
         forms["fp32_batched"] = dict(ms=ms, per=per)
@@ -624,11 +630,15 @@ def main():
                       % (ns, min(8192, prob.n))}
 
     if "persistent" in args.forms:
-        # the same FP32 walk, queries in input order, through the batched persistent launch
-        # (waves take queries from an atomic counter until none are left)
-        w = stats(ghn.GHN_PREC_FP32, ghn.GHN_FLAG_NO_SORT)
-        bws = torch.empty(max(ghn.ghn_batch_workspace_bytes(1), 1), dtype=torch.uint8, device=dev)
-        batch = ghn.ghn_batch_prepare([(ix.handle, qs, k, out_idx, out_pred, None)], bws, stop)
+        # the same FP32 walk through the batched persistent launch (waves take queries from
+        # 8 per-XCD ranges of atomic counters until none are left), in the spatial order
+        # the FP32 form uses (the launch then sorts the queries first)
+        pflags = 0 if sort32 else ghn.GHN_FLAG_NO_SORT
+        w = stats(ghn.GHN_PREC_FP32, pflags)
+        pitems = [(ix.handle, qs, k, out_idx, out_pred, None)]
+        bws = torch.empty(max(ghn.ghn_batch_workspace_bytes_for(pitems, stop, ghn.GHN_PREC_FP32, pflags), 1),
+                          dtype=torch.uint8, device=dev)
+        batch = ghn.ghn_batch_prepare(pitems, bws, stop, flags=pflags)
 
         def stepp(evs):
             if evs:
@@ -644,7 +654,8 @@ def main():
             qps=m / (ms * 1e-3), ms_per_step=ms, kernel_ms=kern_ms, per=per, work=w,
             roofline=hbm_roofline(alg_bytes, walk_bytes_extended(m, f, k, w["cands"], w["probes"]), kern_ms,
                                   None, "k_predict_batched"),
-            alg={"bytes_per_step": alg_bytes, "timed": "counter reset + persistent kernel"})
+            alg={"bytes_per_step": alg_bytes, "timed": "counter reset (+ query sort) + persistent kernel",
+                 "spatial_order": bool(sort32)})
     if "brute" in args.forms:
         # exhaustive KNN (the paper's comparison method) on the same GPU and index data
         nws = ghn.ghn_predict_workspace_bytes(ix.handle, m, k, stop, ghn.GHN_PREC_BF16_MFMA, 0)

@@ -314,7 +314,12 @@ ghn_status ghn_query_order(const ghn_index* index, const float* queries, int64_t
  * the call can be captured into a graph (hipStreamBeginCapture) and replayed.
  * Results equal those of ghn_predict on each item with the same options.  All
  * items must share f.
- * With the FP32 screen the waves take single queries; with GHN_PREC_BF16_MFMA
+ * With the FP32 screen the waves take single queries, from 8 ranges of the
+ * batch's queries (one per XCD, stealing from the others once empty), in spatial
+ * order (all items' queries sorted by (item, Morton code of the central cell))
+ * unless GHN_FLAG_NO_SORT is set or the batch holds fewer than 4096 queries; the
+ * environment variable GHN_BATCH_BLOCKS, read by ghn_batch_prepare, fixes the
+ * launch's grid size (results do not depend on it).  With GHN_PREC_BF16_MFMA
  * all items' queries are sorted together by (item, Morton code of the central
  * cell) and cut into groups (one item, one cell or, under GHN_STOP_EXACT, one
  * block of 2^group_levels cells per dimension), and one persistent launch walks
@@ -332,10 +337,11 @@ typedef struct {
 
 typedef struct ghn_batch ghn_batch;
 
-/* Workspace of a batch: ghn_batch_workspace_bytes covers the FP32 screen (item
- * descriptors and a work counter); ghn_batch_workspace_bytes_for covers the given
- * items and options (HOST), with the bf16 screen's sort and groups of all their
- * queries (about 36 bytes per query). */
+/* Workspace of a batch: ghn_batch_workspace_bytes covers the FP32 screen without
+ * the spatial order (item descriptors and the work counters);
+ * ghn_batch_workspace_bytes_for covers the given items and options (HOST),
+ * including the sort (and for the bf16 screen the groups) of all their queries,
+ * about 36 bytes per query. */
 size_t ghn_batch_workspace_bytes(int32_t n_items);
 size_t ghn_batch_workspace_bytes_for(const ghn_batch_item* items, int32_t n_items, const ghn_predict_opts* opts);
 /* items and opts are HOST memory; opts may be NULL (EXACT, FP32).  Of opts the stop

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -33,6 +34,8 @@ struct ghn_batch {
     int32_t kb;         // key bits below the item index
     int32_t key_bits;   // bits of the sort key
     void* group_ws;     // group_ws_bytes(total) bytes of the caller's workspace
+    bool sorted;        // FP32 screen: walk the queries in spatial order (sorted by the key)
+    int32_t blocks;     // grid size of the FP32 launch (0 = by the query count)
 };
 
 namespace {
@@ -132,6 +135,8 @@ size_t build_ws_bytes(int64_t n) {
 
 size_t sort_ws_bytes(int64_t m);  // workspace of the spatial query sort (defined below)
 
+constexpr size_t BATCH_COUNTER_BYTES = 1024;  // the FP32 batch's 8 work counters, 128 bytes apart
+
 // Dense tables larger than this many cells are not built (linear cell indices stay 32-bit).
 int64_t dense_limit(int64_t n) {
     int64_t lim = 16 * n;
@@ -148,15 +153,22 @@ const char* ghn_last_error(void) { return g_err.c_str(); }
 
 size_t ghn_batch_workspace_bytes(int32_t n_items) {
     if (n_items <= 0) return 0;
-    return (((size_t)n_items * sizeof(ghn::BatchItem) + 255) & ~(size_t)255) + 256;
+    return (((size_t)n_items * sizeof(ghn::BatchItem) + 255) & ~(size_t)255) + BATCH_COUNTER_BYTES;
 }
+
+namespace {
+// FP32 batches walk their queries in spatial order unless GHN_FLAG_NO_SORT is set or
+// they hold fewer than SORT_MIN_QUERIES queries.
+bool batch_sorts(int64_t total, uint32_t flags) { return total >= ghn::SORT_MIN_QUERIES && !(flags & GHN_FLAG_NO_SORT); }
+}  // namespace
 
 size_t ghn_batch_workspace_bytes_for(const ghn_batch_item* items, int32_t n_items, const ghn_predict_opts* opts) {
     if (n_items <= 0 || !items) return 0;
     const size_t base = ghn_batch_workspace_bytes(n_items);
-    if (!opts || opts->prec != GHN_PREC_BF16_MFMA) return base;
     int64_t total = 0;
     for (int32_t i = 0; i < n_items; ++i) total += items[i].m > 0 ? items[i].m : 0;
+    const bool bf16 = opts && opts->prec == GHN_PREC_BF16_MFMA;
+    if (!bf16 && !batch_sorts(total, opts ? opts->flags : 0u)) return base;
     return base + (total > 0 ? ghn::group_ws_bytes(total) : 0);
 }
 
@@ -213,10 +225,11 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
         total += it.m;
         if (it.m > 0 && it.index->view.lookup != LOOKUP_DENSE) any_tree = true;
     }
-    // bf16: the sort key of every item's queries (item index above kb bits, then the
-    // item's Morton code of the central cell, aligned) and its group shift
+    // the sort key of every item's queries (item index above kb bits, then the item's
+    // Morton code of the central cell, aligned) and its group shift (bf16 groups)
     int32_t kmax = 1, kb = 0, key_bits = 1;
-    if (o.prec == GHN_PREC_BF16_MFMA) {
+    const bool sorted = o.prec == GHN_PREC_FP32 && batch_sorts(total, o.flags);
+    if (o.prec == GHN_PREC_BF16_MFMA || sorted) {
         int item_bits = 0;
         while ((int64_t(1) << item_bits) < (int64_t)n_items) ++item_bits;
         std::vector<int> cbits((size_t)n_items), scode((size_t)n_items), tot((size_t)n_items);
@@ -259,7 +272,7 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
         return hip_fail(e, "ghn_batch_prepare: upload");
     ghn_batch* b = new ghn_batch();
     b->items_dev = (BatchItem*)ws;
-    b->counter_dev = (uint64_t*)((char*)ws + base - 256);
+    b->counter_dev = (uint64_t*)((char*)ws + base - BATCH_COUNTER_BYTES);
     b->n_items = n_items;
     b->total = total;
     b->f = f;
@@ -270,6 +283,9 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
     b->kb = kb;
     b->key_bits = key_bits;
     b->group_ws = (char*)ws + base;
+    b->sorted = sorted;
+    b->blocks = 0;
+    if (const char* env = std::getenv("GHN_BATCH_BLOCKS")) b->blocks = std::atoi(env) > 0 ? std::atoi(env) : 0;
     *out = b;
     return GHN_OK;
 }
@@ -284,8 +300,14 @@ ghn_status ghn_predict_batched(const ghn_batch* batch, void* stream) {
         if (e != hipSuccess) return hip_fail(e, "ghn_predict_batched: grouped launch");
         return GHN_OK;
     }
-    hipError_t e = ghn::launch_predict_batched(batch->items_dev, batch->n_items, batch->total, batch->f, batch->stop,
-                                               batch->any_tree, batch->counter_dev, (hipStream_t)stream);
+    const uint32_t* order = nullptr;
+    hipError_t e = hipSuccess;
+    if (batch->sorted && (e = ghn::batch_query_order(batch->items_dev, batch->n_items, batch->total, batch->kb,
+                                                    batch->key_bits, batch->group_ws, (hipStream_t)stream,
+                                                    &order)) != hipSuccess)
+        return hip_fail(e, "ghn_predict_batched: query order");
+    e = ghn::launch_predict_batched(batch->items_dev, batch->n_items, batch->total, batch->f, batch->stop,
+                                    batch->any_tree, order, batch->blocks, batch->counter_dev, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "ghn_predict_batched: launch");
     return GHN_OK;
 }

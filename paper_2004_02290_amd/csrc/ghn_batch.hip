@@ -1,12 +1,18 @@
 // Many independent indexes answered in one persistent launch.
 //
 // The queries of all batch items form one index space: item i owns global query
-// positions [first_i, first_i + m_i).  Waves take chunks of positions from one
-// atomic counter (work stealing, so items of very different cost balance), find
-// the item of each position by a binary search over the items' first positions,
-// and walk that query with the item's own index (dense or tree lookup) exactly
-// as the single-index kernels do.  The launch reads only device memory, so it
-// can be captured in a graph and replayed.
+// positions [first_i, first_i + m_i).  The space is cut into 8 equal ranges, one per
+// XCD (blocks are dealt round-robin over the XCDs, so block b runs on XCD b % 8):
+// the waves of an XCD take chunks of its range from that range's atomic counter, and
+// steal from the next ranges once it is empty, so items of very different cost
+// balance while each XCD's L2 mostly serves its own range.  The counters sit 128
+// bytes apart: in one cache line their atomics serialised (measured on the 256 3-D
+// problems: one counter 4.76 ms, 8 counters in one line 5.80 ms, 8 counters 128 bytes
+// apart 3.97 ms).  With a spatial order
+// (queries sorted by (item, Morton code of the central cell)) the ranges are regions
+// of space.  Each position is walked with its item's own index (dense or tree
+// lookup) exactly as the single-index kernels do.  The launch reads only device
+// memory, so it can be captured in a graph and replayed.
 #include "ghn_walk_dense.h"
 #include "ghn_walk_tree.h"
 
@@ -17,8 +23,10 @@ constexpr int BPT = 256;
 constexpr int BWPB = BPT / WAVE;
 constexpr int CHUNK = 4;  // queries taken per atomic
 
+constexpr int COUNTER_STRIDE = 16;  // the 8 work counters sit 128 bytes apart
+
 __global__ void k_reset_counter(uint64_t* counter) {
-    if (threadIdx.x == 0) *counter = 0;
+    if (threadIdx.x < NUM_XCD) counter[threadIdx.x * COUNTER_STRIDE] = 0;
 }
 
 // A batch whose indexes all use the dense table runs an instance without the tree
@@ -36,7 +44,8 @@ constexpr int batched_waves_per_eu() {
 
 template <int FT, int STOP, bool TREE>
 __global__ __launch_bounds__(BPT) __attribute__((amdgpu_waves_per_eu(batched_waves_per_eu<FT, TREE>())))
-void k_predict_batched(const BatchItem* __restrict__ items, int n_items, int64_t total, uint64_t* counter) {
+void k_predict_batched(const BatchItem* __restrict__ items, int n_items, int64_t total,
+                       const uint32_t* __restrict__ order, uint64_t* counter) {
     __shared__ uint32_t s_begin[BWPB][RUN_CAP];
     __shared__ uint32_t s_pre[BWPB][RUN_CAP];
     __shared__ uint32_t s_key[BWPB][RUN_CAP];
@@ -44,62 +53,70 @@ void k_predict_batched(const BatchItem* __restrict__ items, int n_items, int64_t
     __shared__ uint64_t s_pend[BWPB][TREE && FT == 8 ? TREE_PEND_CAP : 1];
     const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    for (;;) {
-        uint64_t w0 = 0;
-        if (lane == 0) w0 = atomicAdd((unsigned long long*)counter, (unsigned long long)CHUNK);
-        w0 = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(w0 >> 32)) << 32) |
-             (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)w0);
-        if ((int64_t)w0 >= total) break;
-        for (int c = 0; c < CHUNK; ++c) {
-            const int64_t w = (int64_t)w0 + c;
-            if (w >= total) break;
-            const BatchItem& it = items[batch_item_of(items, n_items, w)];
-            const IndexView& ix = *it.ix;
-            const int64_t qi = w - it.first;
-            if (!TREE && ix.lookup != LOOKUP_DENSE) continue;  // not launched so (the host checks the items)
-            if (ix.lookup == LOOKUP_DENSE) walk_dense<FT, STOP, false>(ix, it.io, qi, s_begin[wv], s_pre[wv], s_key[wv]);
-            // the tree walk's pending list only where it costs no occupancy: the f = 8
-            // instance already runs at two waves per SIMD; the others hold the dense walk
-            // at three or four, which the extra state would lower
-            else if constexpr (TREE) walk_tree<FT, STOP, FT == 8>(ix, it.io, qi, s_begin[wv], s_pre[wv], s_stack[wv], s_pend[wv]);
+    const int home = (int)(blockIdx.x % NUM_XCD);
+    for (int r = 0; r < NUM_XCD; ++r) {
+        const int x = (home + r) % NUM_XCD;
+        const int64_t lo = total * x / NUM_XCD, hi = total * (x + 1) / NUM_XCD;
+        for (;;) {
+            uint64_t c0 = 0;
+            if (lane == 0) c0 = atomicAdd((unsigned long long*)&counter[x * COUNTER_STRIDE], (unsigned long long)CHUNK);
+            c0 = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(c0 >> 32)) << 32) |
+                 (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)c0);
+            const int64_t w0 = lo + (int64_t)c0;
+            if (w0 >= hi) break;
+            for (int c = 0; c < CHUNK; ++c) {
+                const int64_t w = w0 + c;
+                if (w >= hi) break;
+                const int64_t pos = order ? (int64_t)order[w] : w;
+                const BatchItem& it = items[batch_item_of(items, n_items, pos)];
+                const IndexView& ix = *it.ix;
+                const int64_t qi = pos - it.first;
+                if (!TREE && ix.lookup != LOOKUP_DENSE) continue;  // not launched so (the host checks the items)
+                if (ix.lookup == LOOKUP_DENSE) walk_dense<FT, STOP, false>(ix, it.io, qi, s_begin[wv], s_pre[wv], s_key[wv]);
+                // the tree walk's pending list only where it costs no occupancy: the f = 8
+                // instance already runs at two waves per SIMD; the others hold the dense walk
+                // at three or four, which the extra state would lower
+                else if constexpr (TREE) walk_tree<FT, STOP, FT == 8>(ix, it.io, qi, s_begin[wv], s_pre[wv], s_stack[wv], s_pend[wv]);
+            }
         }
     }
 }
 
 template <int FT, bool TREE>
-void launch_stop(const BatchItem* items, int n_items, int64_t total, uint64_t* counter, int stop, int blocks,
-                 hipStream_t s) {
+void launch_stop(const BatchItem* items, int n_items, int64_t total, const uint32_t* order, uint64_t* counter,
+                 int stop, int blocks, hipStream_t s) {
     if (stop == GHN_STOP_PAPER)
         hipLaunchKernelGGL((k_predict_batched<FT, GHN_STOP_PAPER, TREE>), dim3(blocks), dim3(BPT), 0, s, items, n_items,
-                           total, counter);
+                           total, order, counter);
     else
         hipLaunchKernelGGL((k_predict_batched<FT, GHN_STOP_EXACT, TREE>), dim3(blocks), dim3(BPT), 0, s, items, n_items,
-                           total, counter);
+                           total, order, counter);
 }
 
 template <int FT>
-hipError_t launch_ft(const BatchItem* items, int n_items, int64_t total, uint64_t* counter, int stop, bool any_tree,
-                     int blocks, hipStream_t s) {
-    if (any_tree) launch_stop<FT, true>(items, n_items, total, counter, stop, blocks, s);
-    else launch_stop<FT, false>(items, n_items, total, counter, stop, blocks, s);
+hipError_t launch_ft(const BatchItem* items, int n_items, int64_t total, const uint32_t* order, uint64_t* counter,
+                     int stop, bool any_tree, int blocks, hipStream_t s) {
+    if (any_tree) launch_stop<FT, true>(items, n_items, total, order, counter, stop, blocks, s);
+    else launch_stop<FT, false>(items, n_items, total, order, counter, stop, blocks, s);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_predict_batched(const BatchItem* items, int n_items, int64_t total, int f, int stop, bool any_tree,
-                                  uint64_t* counter, hipStream_t s) {
+                                  const uint32_t* order, int blocks_override, uint64_t* counter, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
     int64_t blocks = (total + BWPB * CHUNK - 1) / (BWPB * CHUNK);
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
+    if (blocks_override > 0) blocks = blocks_override;
     switch (f) {
-        case 1: return launch_ft<1>(items, n_items, total, counter, stop, any_tree, (int)blocks, s);
-        case 2: return launch_ft<2>(items, n_items, total, counter, stop, any_tree, (int)blocks, s);
-        case 3: return launch_ft<3>(items, n_items, total, counter, stop, any_tree, (int)blocks, s);
-        case 4: return launch_ft<4>(items, n_items, total, counter, stop, any_tree, (int)blocks, s);
-        case 8: return launch_ft<8>(items, n_items, total, counter, stop, any_tree, (int)blocks, s);
-        default: return launch_ft<0>(items, n_items, total, counter, stop, any_tree, (int)blocks, s);
+        case 1: return launch_ft<1>(items, n_items, total, order, counter, stop, any_tree, (int)blocks, s);
+        case 2: return launch_ft<2>(items, n_items, total, order, counter, stop, any_tree, (int)blocks, s);
+        case 3: return launch_ft<3>(items, n_items, total, order, counter, stop, any_tree, (int)blocks, s);
+        case 4: return launch_ft<4>(items, n_items, total, order, counter, stop, any_tree, (int)blocks, s);
+        case 8: return launch_ft<8>(items, n_items, total, order, counter, stop, any_tree, (int)blocks, s);
+        default: return launch_ft<0>(items, n_items, total, order, counter, stop, any_tree, (int)blocks, s);
     }
 }
 

@@ -1247,6 +1247,27 @@ hipError_t run_grouped(const PredictArgs& pa, int keep_shift_levels, void* ws, h
     return e;
 }
 
+hipError_t batch_query_order(const BatchItem* items, int n_items, int64_t total, int kb, int key_bits, void* ws,
+                             hipStream_t s, const uint32_t** order) {
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const int64_t m = total;
+    char* p = (char*)ws;
+    uint64_t* k0 = (uint64_t*)p; p += up(m * 8);
+    uint64_t* k1 = (uint64_t*)p; p += up(m * 8);
+    uint32_t* v0 = (uint32_t*)p; p += up(m * 4);
+    uint32_t* v1 = (uint32_t*)p; p += up(m * 4);
+    uint32_t* qflags = (uint32_t*)p; p += up(m * 4);
+    p += up(m * 8) + up(64);  // (groups and counters of the grouped form)
+    void* rtemp = p;
+    int64_t g = (m + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_batch_group_keys, dim3((unsigned)g), dim3(256), 0, s, items, n_items, m, kb, k0, v0, qflags);
+    bool alt = false;
+    const hipError_t e = radix_sort_pairs(k0, v0, k1, v1, m, key_bits, rtemp, &alt, s);
+    *order = alt ? v1 : v0;
+    return e;
+}
+
 hipError_t run_grouped_batched(const BatchItem* items, int n_items, int64_t total, int f, int kmax, int stop, int kb,
                                int key_bits, void* ws, hipStream_t s) {
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };

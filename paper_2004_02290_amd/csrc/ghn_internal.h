@@ -363,8 +363,14 @@ __device__ __forceinline__ int batch_item_of(const BatchItem* items, int n_items
     return lo;
 }
 
+// order: optional walk order of the global positions (a permutation); counter: 8
+// work counters (one per XCD range); blocks_override > 0 fixes the grid size.
 hipError_t launch_predict_batched(const BatchItem* items, int n_items, int64_t total, int f, int stop, bool any_tree,
-                                  uint64_t* counter, hipStream_t s);
+                                  const uint32_t* order, int blocks_override, uint64_t* counter, hipStream_t s);
+// The batch's queries sorted by (item, Morton code of the central cell): *order
+// receives the sorted global positions, in `ws` (group_ws_bytes(total) bytes).
+hipError_t batch_query_order(const BatchItem* items, int n_items, int64_t total, int kb, int key_bits, void* ws,
+                             hipStream_t s, const uint32_t** order);
 // Grouped (bf16 screen) walk of a whole batch in one persistent launch, after one sort
 // of all its queries by (item, cell) and the grouping; `ws` holds group_ws_bytes(total).
 // kb: key bits below the item index; kmax: largest k.

@@ -96,9 +96,10 @@ def test_skew8d_full_size(ghn, width_scale):
     oi = torch.empty((prob.m, prob.k), dtype=torch.int64, device="cuda")
     op = torch.empty(prob.m, dtype=torch.float32, device="cuda")
     od = torch.empty((prob.m, prob.k), dtype=torch.float64, device="cuda")
-    ws = torch.empty(ghn.ghn_batch_workspace_bytes(1), dtype=torch.uint8, device="cuda")
     q = _dev(prob.queries)  # the batch descriptor points at it until the launch has run
-    batch = ghn.ghn_batch_prepare([(ix.handle, q, prob.k, oi, op, od)], ws, EXACT)
+    items = [(ix.handle, q, prob.k, oi, op, od)]
+    ws = torch.empty(ghn.ghn_batch_workspace_bytes_for(items), dtype=torch.uint8, device="cuda")
+    batch = ghn.ghn_batch_prepare(items, ws, EXACT)
     ghn.ghn_predict_batched(batch)
     torch.cuda.synchronize()
     ghn.ghn_batch_destroy(batch)
@@ -145,7 +146,7 @@ def test_multi3d_full_size_batched(ghn):
         idxs.append(ix)
         items.append((ix.handle, _dev(p.queries), p.k, oi, op, od))
         outs.append((oi, op, od))
-    ws = torch.empty(ghn.ghn_batch_workspace_bytes(len(items)), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(ghn.ghn_batch_workspace_bytes_for(items), dtype=torch.uint8, device="cuda")
     batch = ghn.ghn_batch_prepare(items, ws, EXACT)
     ghn.ghn_predict_batched(batch)
     torch.cuda.synchronize()

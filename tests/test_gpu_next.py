@@ -180,8 +180,9 @@ def test_median_batched_and_errors(ghn):
     q = _dev(prob.queries)
     oi = torch.empty((prob.m, prob.k), dtype=torch.int64, device="cuda")
     op = torch.empty(prob.m, dtype=torch.float32, device="cuda")
-    ws = torch.empty(ghn.ghn_batch_workspace_bytes(1), dtype=torch.uint8, device="cuda")
-    b = ghn.ghn_batch_prepare([(ix.handle, q, prob.k, oi, op, None)], ws, flags=ghn.GHN_FLAG_MEDIAN)
+    items = [(ix.handle, q, prob.k, oi, op, None)]
+    ws = torch.empty(ghn.ghn_batch_workspace_bytes_for(items, flags=ghn.GHN_FLAG_MEDIAN), dtype=torch.uint8, device="cuda")
+    b = ghn.ghn_batch_prepare(items, ws, flags=ghn.GHN_FLAG_MEDIAN)
     ghn.ghn_predict_batched(b)
     torch.cuda.synchronize()
     ghn.ghn_batch_destroy(b)

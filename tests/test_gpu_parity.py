@@ -431,8 +431,9 @@ def test_hash_index_in_batches_bf16_and_save_load(ghn):
     op = torch.full((prob.m,), -7, dtype=torch.int32, device="cuda")
     od = torch.zeros((prob.m, prob.k), dtype=torch.float64, device="cuda")
     q = _dev(prob.queries)
-    ws = torch.empty(ghn.ghn_batch_workspace_bytes(1), dtype=torch.uint8, device="cuda")
-    batch = ghn.ghn_batch_prepare([(ix.handle, q, prob.k, oi, op, od)], ws)
+    items = [(ix.handle, q, prob.k, oi, op, od)]
+    ws = torch.empty(ghn.ghn_batch_workspace_bytes_for(items), dtype=torch.uint8, device="cuda")
+    batch = ghn.ghn_batch_prepare(items, ws)
     ghn.ghn_predict_batched(batch)
     torch.cuda.synchronize()
     ghn.ghn_batch_destroy(batch)
@@ -550,7 +551,7 @@ def _batch_setup(ghn, probs, stop):
         idxs.append(ix)
         items.append((ix.handle, q, p.k, oi, op, od))
         outs.append((oi, op, od))
-    ws = torch.empty(ghn.ghn_batch_workspace_bytes(len(items)), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(ghn.ghn_batch_workspace_bytes_for(items), dtype=torch.uint8, device="cuda")
     batch = ghn.ghn_batch_prepare(items, ws, stop=stop)
     return idxs, items, outs, ws, batch
 
@@ -714,7 +715,7 @@ def test_batched_mixed_lookups(ghn):
         outs.append((oi, op, od))
     assert [ix.info.lookup for ix, _ in idxs] == [0, TREE, 0]
     for stop in (ghn.GHN_STOP_EXACT, ghn.GHN_STOP_PAPER):
-        ws = torch.empty(ghn.ghn_batch_workspace_bytes(len(items)), dtype=torch.uint8, device="cuda")
+        ws = torch.empty(ghn.ghn_batch_workspace_bytes_for(items), dtype=torch.uint8, device="cuda")
         batch = ghn.ghn_batch_prepare(items, ws, stop=stop)
         ghn.ghn_predict_batched(batch)
         torch.cuda.synchronize()
@@ -811,7 +812,7 @@ def test_batch_errors(ghn):
     p4 = W.uniform_problem(n=500, m=10, f=4, k=3, seed=2, width=0.2)
     ix4 = _index(ghn, p4)
     mixed = list(items) + [(ix4.handle, _dev(p4.queries), 3, oi, op, od)]
-    ws2 = torch.empty(ghn.ghn_batch_workspace_bytes(len(mixed)), dtype=torch.uint8, device="cuda")
+    ws2 = torch.empty(ghn.ghn_batch_workspace_bytes_for(mixed), dtype=torch.uint8, device="cuda")
     with pytest.raises(ghn.GHNError) as e:
         ghn.ghn_batch_prepare(mixed, ws2)
     assert e.value.code == -1
@@ -914,3 +915,27 @@ def test_far_queries_shifted_frame_batched(ghn):
                 want = dict(idx=w["idx"], d2=w["d2"], pred=w["pred"])
             _assert_same(got, want, "batched far queries stop=%d" % stop)
         ghn.ghn_batch_destroy(batch)
+
+
+def test_batched_independent_of_grid_and_order(ghn):
+    """The persistent FP32 launch gives the same answers whatever its grid size (one
+    block, a few, the default) and walk order (spatial or input order), for both rules;
+    its answers are the oracle's."""
+    import os
+    probs = _multi(problems=16, n_hi=40_000, m_hi=3_000, seed=41)
+    assert sum(p.m for p in probs) >= 4096  # large enough for the spatial order
+    idxs = [_index(ghn, p) for p in probs]
+    for stop in (ghn.GHN_STOP_EXACT, ghn.GHN_STOP_PAPER):
+        want = [_oracle_want(p, stop) for p in probs]
+        for blocks, flags in ((None, 0), ("1", 0), ("3", 0), ("5", ghn.GHN_FLAG_NO_SORT)):
+            old = os.environ.pop("GHN_BATCH_BLOCKS", None)
+            if blocks is not None:
+                os.environ["GHN_BATCH_BLOCKS"] = blocks
+            try:
+                got = _batch_run(ghn, probs, idxs, stop, ghn.GHN_PREC_FP32, flags=flags)
+            finally:
+                os.environ.pop("GHN_BATCH_BLOCKS", None)
+                if old is not None:
+                    os.environ["GHN_BATCH_BLOCKS"] = old
+            for i, (g, w) in enumerate(zip(got, want)):
+                _assert_same(g, w, "batch item %d stop=%d blocks=%s flags=%d" % (i, stop, blocks, flags))

@@ -70,8 +70,9 @@ def test_build_into_torch_storage_matches_oracle(ghn, name, kw, lookup):
     oi = torch.empty((prob.m, prob.k), dtype=torch.int64, device="cuda")
     op = torch.empty(prob.m, dtype=torch.int32 if prob.task == W.CLASSIFY else torch.float32, device="cuda")
     od = torch.empty((prob.m, prob.k), dtype=torch.float64, device="cuda")
-    bws = torch.empty(ghn.ghn_batch_workspace_bytes(1), dtype=torch.uint8, device="cuda")
-    batch = ghn.ghn_batch_prepare([(ix.handle, q, prob.k, oi, op, od)], bws)
+    items = [(ix.handle, q, prob.k, oi, op, od)]
+    bws = torch.empty(ghn.ghn_batch_workspace_bytes_for(items), dtype=torch.uint8, device="cuda")
+    batch = ghn.ghn_batch_prepare(items, bws)
     ghn.ghn_predict_batched(batch)
     torch.cuda.synchronize()
     _same(dict(idx=oi.cpu().numpy(), d2=od.cpu().numpy(), pred=op.cpu().numpy()), dict(idx=bi, d2=bd, pred=bp),
