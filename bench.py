@@ -389,7 +389,7 @@ def bench_multi(args, ghn, W, torch):
     print(json.dumps(line), flush=True)
 
 
-def query_parts(prob, qs, ix, ghn, torch, stop, sort32, levels16, reps=3):
+def query_parts(prob, qs, ix, ghn, torch, stop, sort32, levels16, reps=3, ring32=0, grow32=0):
     """Each half of a mixed query set (cluster / uniform background) timed on its own, both forms."""
     out = {}
     k = prob.k
@@ -402,12 +402,13 @@ def query_parts(prob, qs, ix, ghn, torch, stop, sort32, levels16, reps=3):
         oi = torch.empty((mq, k), dtype=torch.int64, device=qs.device)
         op = torch.empty(mq, dtype=torch.int32 if prob.task == 0 else torch.float32, device=qs.device)
         part = {"queries": mq}
-        for form, prec, flags, levels in (("fp32_plain", ghn.GHN_PREC_FP32, 0 if sort32 else ghn.GHN_FLAG_NO_SORT, -1),
-                                          ("bf16_grouped", ghn.GHN_PREC_BF16_MFMA, 0, levels16)):
+        for form, prec, flags, levels, ring in (
+                ("fp32_plain", ghn.GHN_PREC_FP32, (0 if sort32 else ghn.GHN_FLAG_NO_SORT) | grow32, -1, ring32),
+                ("bf16_grouped", ghn.GHN_PREC_BF16_MFMA, 0, levels16, 0)):
             nws = ghn.ghn_predict_workspace_bytes(ix.handle, mq, k, stop, prec, flags, levels)
             ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=qs.device)
             st = ix.predict(q, k, stop=stop, prec=prec, flags=flags, with_d2=False, with_stats=True,
-                            group_levels=levels)
+                            group_levels=levels, ring_step=ring)
             torch.cuda.synchronize()
             cands = float(st["cands"].double().mean().item())
             layers = float(st["stop_layer"].double().mean().item())
@@ -416,7 +417,7 @@ def query_parts(prob, qs, ix, ghn, torch, stop, sort32, levels16, reps=3):
             for _ in range(reps + 1):
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 ghn.ghn_predict(ix.handle, q, k, oi, op, None, stop, prec, flags, ws=ws, group_levels=levels,
-                                walk_events=(e0, e1))
+                                walk_events=(e0, e1), ring_step=ring)
                 torch.cuda.synchronize()
                 ms.append(e0.elapsed_time(e1))
             kern = float(np.mean(ms[1:]))
@@ -506,6 +507,7 @@ def main():
               "hash": ghn.GHN_LOOKUP_HASH}[args.lookup]
     tuned = None
     sort32, levels16 = args.sort, args.group_levels
+    ring32, grow32 = 0, 0  # FP32 form: the EXACT walk's ring schedule (autotuned)
     if args.autotune == "on" or (args.autotune == "auto" and args.workload in AUTOTUNED and args.cell_width is None
                                     and not args.no_extras):
         # widths around the calibrated one (under PAPER only execution settings are tuned);
@@ -529,13 +531,16 @@ def main():
         b16 = min((t for t in at_w if t["prec"] == ghn.GHN_PREC_BF16_MFMA), key=lambda t: t["ms"], default=None)
         if b32 is not None:
             sort32 = not (b32["flags"] & ghn.GHN_FLAG_NO_SORT)
+            ring32 = int(b32["ring_step"])
+            grow32 = int(b32["flags"]) & ghn.GHN_FLAG_RING_GROW
         if b16 is not None:
             levels16 = int(b16["group_levels"])
         tuned = {"cell_width": width, "tune_ms": tune_ms, "sample_queries": ns, "widths_tried": widths,
-                 "fp32_sort": sort32, "bf16_group_levels": levels16,
+                 "fp32_sort": sort32, "fp32_ring_step": ring32, "fp32_ring_grow": bool(grow32),
+                 "bf16_group_levels": levels16,
                  "trials": [{"w": t["cell_width"], "prec": "fp32" if t["prec"] == ghn.GHN_PREC_FP32 else "bf16",
                              "lookup": t["lookup"], "levels": t["group_levels"], "flags": t["flags"],
-                             "ms": t["ms"]} for t in trials]}
+                             "ring_step": t["ring_step"], "ms": t["ms"]} for t in trials]}
         print("autotune: width %.6g (calibrated %.6g), %.1f s" % (width, prob.cell_width, tune_ms * 1e-3),
               file=sys.stderr, flush=True)
 
@@ -567,8 +572,9 @@ def main():
         kern = np.array([wb[i].elapsed_time(we[i]) for i in range(args.steps)])
         return ms, float(kern.mean()), per
 
-    def stats(prec, flags=0, levels=-1):
-        st = ix.predict(qs, k, stop=stop, prec=prec, flags=flags, with_d2=False, with_stats=True, group_levels=levels)
+    def stats(prec, flags=0, levels=-1, ring=0):
+        st = ix.predict(qs, k, stop=stop, prec=prec, flags=flags, with_d2=False, with_stats=True, group_levels=levels,
+                        ring_step=ring)
         torch.cuda.synchronize()
         out = dict(cands=int(st["cands"].sum().item()), probes=int(st["probes"].sum().item()),
                    layers=float(st["stop_layer"].double().mean().item()),
@@ -580,19 +586,19 @@ def main():
     if "fp32" in args.forms:
         # per-query walk; with --sort a step = spatial order (Morton sort) + walk, events
         # between the two calls time the walk kernel alone on the stream both run on
-        flags = 0 if sort32 else ghn.GHN_FLAG_NO_SORT
-        w = stats(ghn.GHN_PREC_FP32, flags)
+        flags = (0 if sort32 else ghn.GHN_FLAG_NO_SORT) | grow32
+        w = stats(ghn.GHN_PREC_FP32, flags, ring=ring32)
         order = torch.empty(m, dtype=torch.int32, device=dev)
         ows = torch.empty(max(ghn.ghn_query_order_workspace_bytes(m), 1), dtype=torch.uint8, device=dev)
 
         def step32(evs):
             if sort32:
                 ghn.ghn_query_order(ix.handle, qs, order, ows)
-                ghn.ghn_predict(ix.handle, qs, k, out_idx, out_pred, None, stop, ghn.GHN_PREC_FP32, 0, order=order,
-                                walk_events=evs)
+                ghn.ghn_predict(ix.handle, qs, k, out_idx, out_pred, None, stop, ghn.GHN_PREC_FP32, grow32,
+                                order=order, walk_events=evs, ring_step=ring32)
             else:
                 ghn.ghn_predict(ix.handle, qs, k, out_idx, out_pred, None, stop, ghn.GHN_PREC_FP32, flags,
-                                walk_events=evs)
+                                walk_events=evs, ring_step=ring32)
 
         ms, kern_ms, per = timed(step32)
         alg_bytes = walk_bytes(m, f, k, w["cands"], w["probes"])
@@ -633,12 +639,12 @@ def main():
         # the same FP32 walk through the batched persistent launch (waves take queries from
         # 8 per-XCD ranges of atomic counters until none are left), in the spatial order
         # the FP32 form uses (the launch then sorts the queries first)
-        pflags = 0 if sort32 else ghn.GHN_FLAG_NO_SORT
-        w = stats(ghn.GHN_PREC_FP32, pflags)
+        pflags = (0 if sort32 else ghn.GHN_FLAG_NO_SORT) | grow32
+        w = stats(ghn.GHN_PREC_FP32, pflags, ring=ring32)
         pitems = [(ix.handle, qs, k, out_idx, out_pred, None)]
         bws = torch.empty(max(ghn.ghn_batch_workspace_bytes_for(pitems, stop, ghn.GHN_PREC_FP32, pflags), 1),
                           dtype=torch.uint8, device=dev)
-        batch = ghn.ghn_batch_prepare(pitems, bws, stop, flags=pflags)
+        batch = ghn.ghn_batch_prepare(pitems, bws, stop, flags=pflags, ring_step=ring32)
 
         def stepp(evs):
             if evs:
@@ -715,7 +721,8 @@ def main():
         line["config"]["cell_width_source"] = "autotuned"
         line["autotune"] = tuned
     if prob.query_part is not None and not args.no_extras:
-        line["query_parts"] = query_parts(prob, qs, ix, ghn, torch, stop, sort32, levels16)
+        line["query_parts"] = query_parts(prob, qs, ix, ghn, torch, stop, sort32, levels16, ring32=ring32,
+                                          grow32=grow32)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob)
         line["cpu_oracle_more"] = cpu_more(prob)

@@ -88,6 +88,10 @@ typedef enum { GHN_PREC_FP32 = 0, GHN_PREC_BF16_MFMA = 1 } ghn_prec;
 #define GHN_FLAG_NO_PRUNE 1u /* visit every cell of a layer, even those that provably
                                 cannot hold a closer point (same result, slower) */
 #define GHN_FLAG_NO_SORT 2u  /* do not reorder queries by central cell before the walk */
+#define GHN_FLAG_RING_GROW 8u /* GHN_STOP_EXACT, FP32 screen: while a query's buffer holds fewer than k
+                                entries, each step of its walk covers twice the layers of the step
+                                before (from ghn_predict_opts.ring_step, at most 64; back to it once
+                                the buffer is full); same result */
 #define GHN_FLAG_MEDIAN 4u   /* regression index: predict the median of the k targets instead of
                                 their mean (the paper names both, Sections I and IV): the middle
                                 target in IEEE total order, or for even k the FP64 mean of the two
@@ -227,6 +231,12 @@ typedef struct {
     void* walk_event_end;    /* optional hipEvent_t: recorded right after the walk kernel */
     int64_t* out_rerank;     /* optional, m int64: candidates re-scored in FP64 per query (those the
                                 FP32 or bf16 screen could not rule out: the re-rank band) */
+    int32_t ring_step;       /* GHN_STOP_EXACT, FP32 screen: the walk's ring schedule, layers visited
+                                per step before the stop test (0 or 1: one, the paper's layer by layer;
+                                at most 64).  Every step's stop test uses the EXACT bound of its last
+                                layer, so the neighbours do not depend on it; the reported stop layer
+                                is the last layer of the final step.  Must be 0 or 1 under
+                                GHN_STOP_PAPER (and without GHN_FLAG_RING_GROW) */
 } ghn_predict_opts;
 
 /* Bytes of device workspace ghn_predict needs for these arguments (the bf16
@@ -359,8 +369,10 @@ void ghn_batch_destroy(ghn_batch* batch);
 /* ---- autotuning ---------------------------------------------------------------------
  * Times ghn_predict on a sample of queries for every candidate setting and
  * returns the fastest: the scalar cell width (each candidate builds an index),
- * the screen (FP32 per query, in input order or in spatial order; grouped bf16
- * with 2^s-cell groups, s = 0 .. 3) and the lookup: the one the build chooses,
+ * the screen (FP32 per query, in input order or in spatial order, and under
+ * GHN_STOP_EXACT with the ring schedules ring_step 2, GHN_FLAG_RING_GROW from 1
+ * and from 2; grouped bf16 with 2^s-cell groups, s = 0 .. 3) and the lookup: the
+ * one the build chooses,
  * and, where that is the tree in at most 6 dimensions, also the hash lookup
  * (FP32 settings; build the index with the returned lookup).  Under
  * GHN_STOP_EXACT every width gives the same (brute-force) neighbours, so widths
@@ -377,6 +389,7 @@ typedef struct {
     int32_t prec;          /* ghn_prec */
     int32_t group_levels;  /* bf16: ghn_predict_opts.group_levels */
     uint32_t flags;        /* GHN_FLAG_* to pass to ghn_predict */
+    int32_t ring_step;     /* ghn_predict_opts.ring_step (FP32 screen, GHN_STOP_EXACT) */
     double ms;             /* time of one predict call over the sample, or -1 if the setting failed */
 } ghn_tune_trial;
 

@@ -137,6 +137,12 @@ size_t sort_ws_bytes(int64_t m);  // workspace of the spatial query sort (define
 
 constexpr size_t BATCH_COUNTER_BYTES = 1024;  // the FP32 batch's 8 work counters, 128 bytes apart
 
+// The ring schedule (ghn_predict_opts.ring_step, GHN_FLAG_RING_GROW) is for the EXACT rule.
+bool ring_ok(const ghn_predict_opts& o) {
+    if (o.ring_step < 0 || o.ring_step > 64) return false;
+    return o.stop != GHN_STOP_PAPER || (o.ring_step <= 1 && !(o.flags & GHN_FLAG_RING_GROW));
+}
+
 // Dense tables larger than this many cells are not built (linear cell indices stay 32-bit).
 int64_t dense_limit(int64_t n) {
     int64_t lim = 16 * n;
@@ -183,7 +189,8 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
     if (o.stop != GHN_STOP_EXACT && o.stop != GHN_STOP_PAPER) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: bad stop rule %d", o.stop);
     if (o.prec != GHN_PREC_FP32 && o.prec != GHN_PREC_BF16_MFMA) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: bad precision %d", o.prec);
     if (o.group_levels < -1 || o.group_levels > 16) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: group_levels=%d outside [-1, 16]", o.group_levels);
-    if (o.flags & ~(GHN_FLAG_NO_PRUNE | GHN_FLAG_NO_SORT | GHN_FLAG_MEDIAN)) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: unknown flags 0x%x", o.flags);
+    if (o.flags & ~(GHN_FLAG_NO_PRUNE | GHN_FLAG_NO_SORT | GHN_FLAG_MEDIAN | GHN_FLAG_RING_GROW)) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: unknown flags 0x%x", o.flags);
+    if (!ring_ok(o)) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: ring_step=%d (0..64, and 0 or 1 without GHN_FLAG_RING_GROW under the PAPER rule)", o.ring_step);
     const size_t base = ghn_batch_workspace_bytes(n_items);
     ghn_predict_opts oo = o;
     const size_t need = ghn_batch_workspace_bytes_for(items, n_items, &oo);
@@ -220,6 +227,7 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
         b.io.out_rerank = nullptr;
         b.io.k = it.k;
         b.io.flags = o.flags;
+        b.io.ring_step = o.ring_step;
         b.first = total;
         b.m = it.m;
         total += it.m;
@@ -344,10 +352,20 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
         const double w0 = std::exp((logvol + std::log(8.0 / (double)n)) / f);
         for (int i = -3; i <= 2; ++i) cand.push_back((float)(w0 * std::ldexp(1.0, i)));
     }
-    struct Setting { int32_t prec, levels; uint32_t flags; };
-    std::vector<Setting> settings = {{GHN_PREC_FP32, -1, GHN_FLAG_NO_SORT}, {GHN_PREC_FP32, -1, 0u}};
-    if (stop == GHN_STOP_PAPER) settings.push_back({GHN_PREC_BF16_MFMA, 0, 0u});
-    else for (int lv = 0; lv <= 3; ++lv) settings.push_back({GHN_PREC_BF16_MFMA, lv, 0u});
+    struct Setting { int32_t prec, levels; uint32_t flags; int32_t ring; };
+    std::vector<Setting> settings = {{GHN_PREC_FP32, -1, GHN_FLAG_NO_SORT, 0}, {GHN_PREC_FP32, -1, 0u, 0}};
+    if (stop == GHN_STOP_PAPER) {
+        settings.push_back({GHN_PREC_BF16_MFMA, 0, 0u, 0});
+    } else {
+        // the EXACT walk's ring schedule: 2 layers a step, doubling steps until the buffer is
+        // full, or both (input and spatial order)
+        for (uint32_t order : {(uint32_t)GHN_FLAG_NO_SORT, 0u}) {
+            settings.push_back({GHN_PREC_FP32, -1, order, 2});
+            settings.push_back({GHN_PREC_FP32, -1, order | GHN_FLAG_RING_GROW, 1});
+            settings.push_back({GHN_PREC_FP32, -1, order | GHN_FLAG_RING_GROW, 2});
+        }
+        for (int lv = 0; lv <= 3; ++lv) settings.push_back({GHN_PREC_BF16_MFMA, lv, 0u, 0});
+    }
 
     // outputs and a workspace large enough for every setting
     int64_t* oi = nullptr;
@@ -365,12 +383,13 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
         for (float w : cand) {
             ghn_index* ix = nullptr;
             if (ghn_build(points, n, f, dtype, targets, task, &w, 1, nullptr, stream, &ix) != GHN_OK) {
-                if (trials && nt < max_trials) trials[nt] = {w, -1, -1, -1, 0u, -1.0};
+                if (trials && nt < max_trials) trials[nt] = {w, -1, -1, -1, 0u, 0, -1.0};
                 ++nt;
                 continue;
             }
             for (const Setting& st : settings) {
-                ghn_predict_opts o = {stop, st.prec, st.flags, nullptr, nullptr, nullptr, nullptr, st.levels, nullptr, nullptr};
+                ghn_predict_opts o = {stop, st.prec, st.flags, nullptr, nullptr, nullptr, nullptr, st.levels, nullptr, nullptr,
+                                      nullptr, st.ring};
                 double ms = -1.0;
                 if (ghn_predict(ix, queries, m, k, &o, oi, nullptr, op, ws, ws_bytes, stream) == GHN_OK &&
                     hipStreamSynchronize(s) == hipSuccess) {
@@ -385,7 +404,7 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
                     }
                     if (best_ms < 1e29f) ms = best_ms;
                 }
-                const ghn_tune_trial tr = {w, ix->info.lookup, st.prec, st.levels, st.flags, ms};
+                const ghn_tune_trial tr = {w, ix->info.lookup, st.prec, st.levels, st.flags, st.ring, ms};
                 if (trials && nt < max_trials) trials[nt] = tr;
                 ++nt;
                 if (ms >= 0.0 && (!have_best || ms < best->ms)) { *best = tr; have_best = true; }
@@ -398,7 +417,8 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
             if (tree && f <= 6 && ghn_build_ex(points, n, f, dtype, targets, task, &w, 1, nullptr, &ho, stream, &ix) == GHN_OK) {
                 for (const Setting& st : settings) {
                     if (st.prec != GHN_PREC_FP32) continue;
-                    ghn_predict_opts o = {stop, st.prec, st.flags, nullptr, nullptr, nullptr, nullptr, st.levels, nullptr, nullptr};
+                    ghn_predict_opts o = {stop, st.prec, st.flags, nullptr, nullptr, nullptr, nullptr, st.levels, nullptr, nullptr,
+                                      nullptr, st.ring};
                     double ms = -1.0;
                     if (ghn_predict(ix, queries, m, k, &o, oi, nullptr, op, ws, ws_bytes, stream) == GHN_OK &&
                         hipStreamSynchronize(s) == hipSuccess) {
@@ -413,7 +433,7 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
                         }
                         if (best_ms < 1e29f) ms = best_ms;
                     }
-                    const ghn_tune_trial tr = {w, GHN_LOOKUP_HASH, st.prec, st.levels, st.flags, ms};
+                    const ghn_tune_trial tr = {w, GHN_LOOKUP_HASH, st.prec, st.levels, st.flags, st.ring, ms};
                     if (trials && nt < max_trials) trials[nt] = tr;
                     ++nt;
                     if (ms >= 0.0 && (!have_best || ms < best->ms)) { *best = tr; have_best = true; }
@@ -881,7 +901,8 @@ static ghn_status predict_common(const ghn_index* index, const float* queries, i
     if (opts) o = *opts;
     if (o.stop != GHN_STOP_EXACT && o.stop != GHN_STOP_PAPER) return fail(GHN_E_INVALID_ARG, "ghn_predict: bad stop rule %d", o.stop);
     if (o.prec != GHN_PREC_FP32 && o.prec != GHN_PREC_BF16_MFMA) return fail(GHN_E_INVALID_ARG, "ghn_predict: bad precision %d", o.prec);
-    if (o.flags & ~(GHN_FLAG_NO_PRUNE | GHN_FLAG_NO_SORT | GHN_FLAG_MEDIAN)) return fail(GHN_E_INVALID_ARG, "ghn_predict: unknown flags 0x%x", o.flags);
+    if (o.flags & ~(GHN_FLAG_NO_PRUNE | GHN_FLAG_NO_SORT | GHN_FLAG_MEDIAN | GHN_FLAG_RING_GROW)) return fail(GHN_E_INVALID_ARG, "ghn_predict: unknown flags 0x%x", o.flags);
+    if (!ring_ok(o)) return fail(GHN_E_INVALID_ARG, "ghn_predict: ring_step=%d (0..64, and 0 or 1 without GHN_FLAG_RING_GROW under the PAPER rule)", o.ring_step);
     if ((o.flags & GHN_FLAG_MEDIAN) && index->info.task != GHN_REGRESS)
         return fail(GHN_E_INVALID_ARG, "ghn_predict: GHN_FLAG_MEDIAN needs a regression index");
     if (m == 0) return GHN_OK;
@@ -899,6 +920,7 @@ static ghn_status predict_common(const ghn_index* index, const float* queries, i
     pa.io.k = k;
     pa.stop = o.stop;
     pa.io.flags = o.flags;
+    pa.io.ring_step = o.ring_step;
     pa.io.out_idx = out_idx;
     pa.io.out_d2 = out_d2;
     pa.io.out_pred = out_pred;

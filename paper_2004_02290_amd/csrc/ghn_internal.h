@@ -325,6 +325,8 @@ struct QueryIO {
     int64_t* out_rerank;
     int32_t k;
     uint32_t flags;
+    int32_t ring_step;   // EXACT rule: layers per step of the walk (<= 1: one)
+    int32_t pad;
 };
 
 struct PredictArgs {

@@ -77,18 +77,21 @@ __device__ __forceinline__ void walk_dense_layers(const IndexView& ix, const Que
     const int L = f - 1;  // the run dimension
     const double aL = ix.a[L];
     const double aLinv = ix.ainv[L];
-    int32_t l = Q.l0;
-    for (;; ++l) {
+    // ring schedule (EXACT rule only): each step walks the layers l .. lh at once
+    RingStep ring(io);
+    int32_t l = Q.l0, lh = Q.l0;
+    for (;; l = lh + 1) {
+        lh = STOP == GHN_STOP_PAPER ? l : ring.last_layer(l, st.count == k, Q.lcover);
         st.updated = false;
-        // Range of ids per dimension: layer box c +- l clipped to the occupied box.
+        // Range of ids per dimension: box c +- lh clipped to the occupied box.
         int32_t lo[FT > 0 ? FT : F_MAX], w[FT > 0 ? FT : F_MAX];
         int64_t rows = 1;
         bool empty = false;
 #pragma unroll
         for (int j = 0; j < (FT > 0 ? FT : F_MAX); ++j) {
             if (FT == 0 && j >= f) break;
-            const int32_t a0 = max(Q.c[j] - l, ix.cmin[j]);
-            const int32_t b0 = min(Q.c[j] + l, ix.cmax[j]);
+            const int32_t a0 = max(Q.c[j] - lh, ix.cmin[j]);
+            const int32_t b0 = min(Q.c[j] + lh, ix.cmax[j]);
             lo[j] = a0;
             w[j] = b0 - a0 + 1;
             if (b0 < a0) empty = true;
@@ -109,7 +112,7 @@ __device__ __forceinline__ void walk_dense_layers(const IndexView& ix, const Que
             for (int64_t rb = 0; rb < rows; rb += WAVE) {
                 const int64_t r = rb + lane;
                 uint32_t b0 = 0, n0 = 0, b1 = 0, n1 = 0, key0 = 0, key1 = 0, probes_l = 0;
-                if (l == 0) {
+                if (lh == 0) {
                     // layer 0 is the central cell alone (l0 = 0: it lies inside the box)
                     if (lane == 0) {
                         Lin lin = 0;
@@ -160,8 +163,8 @@ __device__ __forceinline__ void walk_dense_layers(const IndexView& ix, const Que
                     if (pass_row) {
                         const int32_t cL = Q.c[L];
                         const int32_t lo_l = lo[L], hi_l = lo[L] + w[L] - 1;
-                        if (maxoff == l) {
-                            // shell row: every cell of the run [c-l, c+l] inside the box
+                        if (maxoff >= l) {
+                            // shell row: every cell of the run [c-lh, c+lh] inside the box
                             int32_t ta = lo_l, tb = hi_l;
                             if (prune && st.tau < 1.0e300) {
                                 // conservative: fl(tau + tau 2^-39) >= tau / LB_SHRINK, and the
@@ -191,26 +194,34 @@ __device__ __forceinline__ void walk_dense_layers(const IndexView& ix, const Que
                                 }
                             }
                         } else {
-                            // interior row: only the end cells c-l and c+l belong to layer l
+                            // interior row: only the end runs [c-lh, c-l] and [c+l, c+lh] belong to
+                            // the layers l .. lh (single cells when lh = l)
                             for (int e = 0; e < 2; ++e) {
                                 int32_t t = e == 0 ? cL - l : cL + l;
                                 // an empty asm keeps the end cell's bound inside the row loop: the
                                 // compiler would otherwise hoist both bounds, and at 64 VGPRs they
                                 // spill to scratch on every layer
                                 asm volatile("" : "+v"(t));
-                                if (t < lo_l || t > hi_l) continue;
+                                int32_t ta = t, tb = t;
+                                if (STOP != GHN_STOP_PAPER && lh > l) {
+                                    ta = e == 0 ? max(cL - lh, lo_l) : t;
+                                    tb = e == 0 ? t : min(cL + lh, hi_l);
+                                }
+                                if (tb < lo_l || ta > hi_l) continue;
+                                ta = max(ta, lo_l);
+                                tb = min(tb, hi_l);
                                 double lbe = 0.0;
                                 if (prune) {
-                                    const double g = gap_to_cells(Q.v[L], t, t, aL);
+                                    const double g = gap_to_cells(Q.v[L], ta, tb, aL);
                                     lbe = __dadd_rn(lb, __dmul_rn(g, g)) * LB_SHRINK;
                                     if (lbe > st.tau) continue;
                                 }
                                 uint32_t s0, sn;
                                 if constexpr (HASH) {
-                                    hash_run(ix, lin, t, t, ix.cmin[L], s0, sn, probes_l);
+                                    hash_run(ix, lin, ta, tb, ix.cmin[L], s0, sn, probes_l);
                                 } else {
-                                    s0 = ix.cell_start[lin + (uint32_t)(t - ix.cmin[L])];
-                                    sn = ix.cell_start[lin + (uint32_t)(t - ix.cmin[L]) + 1] - s0;
+                                    s0 = ix.cell_start[lin + (uint32_t)(ta - ix.cmin[L])];
+                                    sn = ix.cell_start[lin + (uint32_t)(tb - ix.cmin[L]) + 1] - s0;
                                     probes_l += 2;
                                 }
                                 if (e == 0) { b0 = s0; n0 = sn; key0 = lb_key(lbe); }
@@ -224,10 +235,10 @@ __device__ __forceinline__ void walk_dense_layers(const IndexView& ix, const Que
                 score_runs<FT>(ix, Q.q, f, k, b0, n0, key0, b1, n1, key1, prune, s_begin, s_pre, s_key, st);
             }
         }
-        if (stop_after_layer<FT, STOP>(ix, Q, f, k, l, st)) break;
+        if (stop_after_layer<FT, STOP>(ix, Q, f, k, lh, st)) break;
     }
     // only a shifted frame (far query) reaches layer CLAMP or more before its walk ends
-    finish_query(ix, io, qi, l >= (int32_t)CLAMP ? true_layer(l, far_shift(ix, io.queries, qi, f)) : l, st);
+    finish_query(ix, io, qi, lh >= (int32_t)CLAMP ? true_layer(lh, far_shift(ix, io.queries, qi, f)) : lh, st);
 }
 
 // `preset`: the query's set-up already done (by another lane of the block), or null.

@@ -63,13 +63,16 @@ __device__ __forceinline__ void walk_tree_layers(const IndexView& ix, const Quer
 
     int npend = 0;          // pending blocks (wave-uniform)
     bool frontier = FRONTIER;  // false once the pending list overflowed or keys could saturate
-    int32_t l = Q.l0;
-    for (;; ++l) {
+    // ring schedule (EXACT rule only): each step walks the layers l .. lh at once
+    RingStep ring(io);
+    int32_t l = Q.l0, lh = Q.l0;
+    for (;; l = lh + 1) {
+        lh = STOP == GHN_STOP_PAPER ? l : ring.last_layer(l, st.count == k, Q.lcover);
         st.updated = false;
-        if (l >= PEND_KEY_MAX - 1) frontier = false;
+        if (lh >= PEND_KEY_MAX - 1) frontier = false;
         bool overflow = false;
-        bool root = !frontier || l == Q.l0;  // the root block starts the walk of this layer
-        int scan = 0;                        // pending entries below `scan` are not due in this layer
+        bool root = !frontier || l == Q.l0;  // the root block starts the walk of this step
+        int scan = 0;                        // pending entries below `scan` are not due in this step
         for (;;) {
             uint64_t e;
             if (root) {
@@ -80,7 +83,7 @@ __device__ __forceinline__ void walk_tree_layers(const IndexView& ix, const Quer
                 int found = -1;
                 while (scan < npend) {
                     const int idx = scan + lane;
-                    const bool due = idx < npend && pending_key(pend[idx]) <= l;
+                    const bool due = idx < npend && pending_key(pend[idx]) <= lh;
                     const uint64_t dm = ballot(due);
                     if (dm) {
                         found = scan + __ffsll((unsigned long long)dm) - 1;
@@ -134,8 +137,8 @@ __device__ __forceinline__ void walk_tree_layers(const IndexView& ix, const Quer
                 const bool close = active && (!prune || !(lb * LB_SHRINK > st.tau));
                 st.probes += __popcll(ballot(active));
                 if (frontier) {
-                    // nodes of later layers: the block comes back at the nearest of them
-                    const bool later = close && dmin > l;
+                    // nodes of later steps: the block comes back at the nearest of them
+                    const bool later = close && dmin > lh;
                     if (ballot(later)) {
                         const int32_t key = wave_min_nonneg_i32(later ? dmin : INT32_MAX);
                         if (npend < TREE_PEND_CAP) {
@@ -148,15 +151,15 @@ __device__ __forceinline__ void walk_tree_layers(const IndexView& ix, const Quer
                 }
                 if (level == 0) {
                     uint32_t b0 = 0, n0 = 0;
-                    if (close && dmin == l) {
+                    if (close && dmin >= l && dmin <= lh) {
                         b0 = ix.cell_first[node];
                         n0 = ix.cell_first[node + 1] - b0;
                     }
                     score_runs<FT>(ix, Q.q, f, k, b0, n0, 0u, 0u, 0u, 0u, false, s_begin, s_pre, nullptr, st);
                 } else {
-                    // frontier mode reaches a node first at its dmin; from the root, every
-                    // node whose range spans l
-                    const bool keep = close && (frontier ? dmin == l : (dmin <= l && l <= dmax));
+                    // frontier mode reaches a node first at the step holding its dmin; from the
+                    // root, every node whose range meets the step's layers
+                    const bool keep = close && (frontier ? (dmin >= l && dmin <= lh) : (dmin <= lh && l <= dmax));
                     const uint64_t km = ballot(keep);
                     if (keep) {
                         const int64_t c0 = node * WAVE;
@@ -168,11 +171,11 @@ __device__ __forceinline__ void walk_tree_layers(const IndexView& ix, const Quer
                 wave_lds_sync();
             }
         }
-        if (overflow) frontier = false;  // blocks were lost: later layers start from the root
-        if (stop_after_layer<FT, STOP>(ix, Q, f, k, l, st)) break;
+        if (overflow) frontier = false;  // blocks were lost: later steps start from the root
+        if (stop_after_layer<FT, STOP>(ix, Q, f, k, lh, st)) break;
     }
     // only a shifted frame (far query) reaches layer CLAMP or more before its walk ends
-    finish_query(ix, io, qi, l >= (int32_t)CLAMP ? true_layer(l, far_shift(ix, io.queries, qi, f)) : l, st);
+    finish_query(ix, io, qi, lh >= (int32_t)CLAMP ? true_layer(lh, far_shift(ix, io.queries, qi, f)) : lh, st);
 }
 
 template <int FT, int STOP, bool FRONTIER>

@@ -31,13 +31,28 @@ def test_every_declared_symbol_is_exported(ghn):
     assert sorted(ghn.EXPORTED) == names
 
 
-def test_struct_sizes_match_header(ghn):
-    # ghn_index_info: 8+4+4+4+4+8+8+8 + 4*32*4 + 8 bytes
-    # ghn_predict_opts: 3*4 + pad + 4*8 + 4 + pad + 3*8
-    assert ctypes.sizeof(ghn.ghn_index_info) == 48 + 4 * 32 * 4 + 8
-    assert ctypes.sizeof(ghn.ghn_predict_opts) == 80
-    assert ctypes.sizeof(ghn.ghn_batch_item) == 56  # 3 pointers/ints of 8, k + pad, 3 pointers
-    assert ctypes.sizeof(ghn.ghn_tune_trial) == 32  # 5 x 4 bytes, pad, double
+def test_struct_sizes_match_header(ghn, tmp_path):
+    """The binding's ctypes structures have the size and field offsets the C compiler
+    gives the header's structures."""
+    import subprocess
+    structs = {"ghn_index_info": ghn.ghn_index_info, "ghn_predict_opts": ghn.ghn_predict_opts,
+               "ghn_batch_item": ghn.ghn_batch_item, "ghn_tune_trial": ghn.ghn_tune_trial,
+               "ghn_build_opts": ghn.ghn_build_opts}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ghn.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (name, name))
+        for field, _ in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (name, field, name, field))
+    lines.append("return 0; }")
+    src = tmp_path / "sizes.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "sizes"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert int(got["%s.%s" % (name, field)]) == getattr(cls, field).offset, (name, field)
 
 
 def _build_raw(ghn, points=1, n=10, f=2, dtype=0, targets=2, task=0, widths=(0.5,), origin=None):

@@ -827,17 +827,19 @@ def test_autotune_exact_and_paper(ghn, tmp_path):
     cache = str(tmp_path / "tune.json")
     best = autotune.tune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_EXACT, cache_path=cache)
     assert best["ms"] > 0 and best["cell_width"] > 0
-    # widths x (2 FP32 settings + bf16 at 4 grouping levels), plus the 2 FP32 settings on
-    # the hash lookup for every width whose build chose the tree (4 dimensions)
+    # widths x (8 FP32 settings: 2 walk orders x 4 ring schedules + bf16 at 4 grouping
+    # levels), plus the 8 FP32 settings on the hash lookup for every width whose build
+    # chose the tree (4 dimensions)
     tree_widths = {t["cell_width"] for t in best["trials"] if t["lookup"] == TREE}
-    assert len(best["trials"]) == 6 * 6 + 2 * len(tree_widths)
-    assert sum(t["lookup"] == HASH for t in best["trials"]) == 2 * len(tree_widths)
+    assert len(best["trials"]) == 6 * 12 + 8 * len(tree_widths)
+    assert sum(t["lookup"] == HASH for t in best["trials"]) == 8 * len(tree_widths)
+    assert {t["ring_step"] for t in best["trials"]} == {0, 1, 2}
     again = autotune.tune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_EXACT, cache_path=cache)
     assert again["cell_width"] == best["cell_width"]  # served from the cache
     # the tuned setting still returns the brute-force neighbours
     ix = ghn.Index(pts, tgt, prob.task, best["cell_width"], lookup=best["lookup"])
     got = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_EXACT, prec=best["prec"], flags=best["flags"],
-               group_levels=best["group_levels"])
+               group_levels=best["group_levels"], ring_step=best["ring_step"])
     bi, bd, bp = oracle.bruteforce(prob.points, prob.targets, prob.task, prob.queries, prob.k)
     _assert_same(got, dict(idx=bi, d2=bd, pred=bp), "autotuned EXACT")
     pb, trials = ghn.ghn_autotune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_PAPER, widths=[prob.cell_width])
@@ -939,3 +941,57 @@ def test_batched_independent_of_grid_and_order(ghn):
                     os.environ["GHN_BATCH_BLOCKS"] = old
             for i, (g, w) in enumerate(zip(got, want)):
                 _assert_same(g, w, "batch item %d stop=%d blocks=%s flags=%d" % (i, stop, blocks, flags))
+
+
+# ---------------------------------------------------------------------------------- ring schedule
+@pytest.mark.parametrize("name,kw,lookup", [
+    ("clusters4d", dict(n=60_000, m=1_500), None),                # dense table
+    ("skew8d", dict(n=80_000, m=600, seed=5), None),              # cell tree
+    ("clusters4d", dict(n=30_000, m=800), HASH),                  # hash lookup
+])
+def test_ring_schedule_same_neighbours(ghn, name, kw, lookup):
+    """EXACT walks that visit several layers per step (and double the step while the
+    buffer is not full) return the brute-force neighbours; they stop no earlier than
+    the layer-by-layer walk."""
+    prob = W.make(name, **kw)
+    ix = _index(ghn, prob, lookup=lookup)
+    bi, bd, bp = oracle.bruteforce(prob.points_f32(), prob.targets, prob.task, prob.queries, prob.k)
+    want = dict(idx=bi, d2=bd, pred=bp)
+    base = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_EXACT)
+    for step, flags in ((2, 0), (3, 0), (8, 0), (1, ghn.GHN_FLAG_RING_GROW), (2, ghn.GHN_FLAG_RING_GROW)):
+        got = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_EXACT, ring_step=step, flags=flags)
+        _assert_same(got, want, "%s ring_step=%d flags=%d" % (name, step, flags))
+        assert (got["stop_layer"] >= base["stop_layer"]).all()
+
+
+def test_ring_schedule_batched_and_refused_under_paper(ghn):
+    probs = _multi(problems=8, n_hi=30_000, m_hi=2_000, seed=51)
+    idxs = [_index(ghn, p) for p in probs]
+    for flags in (0, ghn.GHN_FLAG_NO_SORT):
+        got = _batch_run_ring(ghn, probs, idxs, 4, ghn.GHN_FLAG_RING_GROW | flags)
+        for i, (p, g) in enumerate(zip(probs, got)):
+            _assert_same(g, _oracle_want(p, 0), "ring batch item %d" % i)
+    p = probs[0]
+    with pytest.raises(ghn.GHNError) as e:
+        _run(ghn, idxs[0], p.queries, p.k, ghn.GHN_STOP_PAPER, ring_step=2)
+    assert e.value.code == -1
+    with pytest.raises(ghn.GHNError) as e:
+        _run(ghn, idxs[0], p.queries, p.k, ghn.GHN_STOP_PAPER, flags=ghn.GHN_FLAG_RING_GROW)
+    assert e.value.code == -1
+
+
+def _batch_run_ring(ghn, probs, idxs, ring_step, flags):
+    import torch
+    items, outs = [], []
+    for p, ix in zip(probs, idxs):
+        oi = torch.full((p.m, p.k), -7, dtype=torch.int64, device="cuda")
+        op = torch.full((p.m,), -7, dtype=torch.int32, device="cuda")
+        od = torch.zeros((p.m, p.k), dtype=torch.float64, device="cuda")
+        items.append((ix.handle, _dev(p.queries), p.k, oi, op, od))
+        outs.append((oi, op, od))
+    ws = torch.empty(ghn.ghn_batch_workspace_bytes_for(items, flags=flags), dtype=torch.uint8, device="cuda")
+    batch = ghn.ghn_batch_prepare(items, ws, flags=flags, ring_step=ring_step)
+    ghn.ghn_predict_batched(batch)
+    torch.cuda.synchronize()
+    ghn.ghn_batch_destroy(batch)
+    return [dict(idx=oi.cpu().numpy(), pred=op.cpu().numpy(), d2=od.cpu().numpy()) for oi, op, od in outs]
