@@ -237,6 +237,8 @@ typedef struct {
                                 layer, so the neighbours do not depend on it; the reported stop layer
                                 is the last layer of the final step.  Must be 0 or 1 under
                                 GHN_STOP_PAPER (and without GHN_FLAG_RING_GROW) */
+    int32_t group_size;      /* bf16 screen: most queries per group, 1..16 (0 = 16, a full matrix tile of
+                                query rows; smaller groups leave rows empty but share fewer cells) */
 } ghn_predict_opts;
 
 /* Bytes of device workspace ghn_predict needs for these arguments (the bf16
@@ -371,8 +373,8 @@ void ghn_batch_destroy(ghn_batch* batch);
  * returns the fastest: the scalar cell width (each candidate builds an index),
  * the screen (FP32 per query, in input order or in spatial order, and under
  * GHN_STOP_EXACT with the ring schedules ring_step 2, GHN_FLAG_RING_GROW from 1
- * and from 2; grouped bf16 with 2^s-cell groups, s = 0 .. 3) and the lookup: the
- * one the build chooses,
+ * and from 2; grouped bf16 with 2^s-cell groups, s = 0 .. 3, of at most 16 or 8
+ * queries) and the lookup: the one the build chooses,
  * and, where that is the tree in at most 6 dimensions, also the hash lookup
  * (FP32 settings; build the index with the returned lookup).  Under
  * GHN_STOP_EXACT every width gives the same (brute-force) neighbours, so widths
@@ -390,6 +392,7 @@ typedef struct {
     int32_t group_levels;  /* bf16: ghn_predict_opts.group_levels */
     uint32_t flags;        /* GHN_FLAG_* to pass to ghn_predict */
     int32_t ring_step;     /* ghn_predict_opts.ring_step (FP32 screen, GHN_STOP_EXACT) */
+    int32_t group_size;    /* ghn_predict_opts.group_size (bf16 screen) */
     double ms;             /* time of one predict call over the sample, or -1 if the setting failed */
 } ghn_tune_trial;
 

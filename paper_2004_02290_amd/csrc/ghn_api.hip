@@ -34,6 +34,7 @@ struct ghn_batch {
     int32_t kb;         // key bits below the item index
     int32_t key_bits;   // bits of the sort key
     void* group_ws;     // group_ws_bytes(total) bytes of the caller's workspace
+    int32_t group_size; // bf16 screen: most queries per group
     bool sorted;        // FP32 screen: walk the queries in spatial order (sorted by the key)
     int32_t blocks;     // grid size of the FP32 launch (0 = by the query count)
 };
@@ -191,6 +192,7 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
     if (o.group_levels < -1 || o.group_levels > 16) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: group_levels=%d outside [-1, 16]", o.group_levels);
     if (o.flags & ~(GHN_FLAG_NO_PRUNE | GHN_FLAG_NO_SORT | GHN_FLAG_MEDIAN | GHN_FLAG_RING_GROW)) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: unknown flags 0x%x", o.flags);
     if (!ring_ok(o)) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: ring_step=%d (0..64, and 0 or 1 without GHN_FLAG_RING_GROW under the PAPER rule)", o.ring_step);
+    if (o.group_size < 0 || o.group_size > 16) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: group_size=%d outside [0, 16]", o.group_size);
     const size_t base = ghn_batch_workspace_bytes(n_items);
     ghn_predict_opts oo = o;
     const size_t need = ghn_batch_workspace_bytes_for(items, n_items, &oo);
@@ -292,6 +294,7 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
     b->key_bits = key_bits;
     b->group_ws = (char*)ws + base;
     b->sorted = sorted;
+    b->group_size = o.group_size > 0 ? o.group_size : 16;
     b->blocks = 0;
     if (const char* env = std::getenv("GHN_BATCH_BLOCKS")) b->blocks = std::atoi(env) > 0 ? std::atoi(env) : 0;
     *out = b;
@@ -304,7 +307,7 @@ ghn_status ghn_predict_batched(const ghn_batch* batch, void* stream) {
     if (batch->prec == GHN_PREC_BF16_MFMA) {
         const hipError_t e = ghn::run_grouped_batched(batch->items_dev, batch->n_items, batch->total, batch->f,
                                                       batch->kmax, batch->stop, batch->kb, batch->key_bits,
-                                                      batch->group_ws, (hipStream_t)stream);
+                                                      batch->group_size, batch->group_ws, (hipStream_t)stream);
         if (e != hipSuccess) return hip_fail(e, "ghn_predict_batched: grouped launch");
         return GHN_OK;
     }
@@ -352,19 +355,21 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
         const double w0 = std::exp((logvol + std::log(8.0 / (double)n)) / f);
         for (int i = -3; i <= 2; ++i) cand.push_back((float)(w0 * std::ldexp(1.0, i)));
     }
-    struct Setting { int32_t prec, levels; uint32_t flags; int32_t ring; };
-    std::vector<Setting> settings = {{GHN_PREC_FP32, -1, GHN_FLAG_NO_SORT, 0}, {GHN_PREC_FP32, -1, 0u, 0}};
+    struct Setting { int32_t prec, levels; uint32_t flags; int32_t ring, gsize; };
+    std::vector<Setting> settings = {{GHN_PREC_FP32, -1, GHN_FLAG_NO_SORT, 0, 0}, {GHN_PREC_FP32, -1, 0u, 0, 0}};
     if (stop == GHN_STOP_PAPER) {
-        settings.push_back({GHN_PREC_BF16_MFMA, 0, 0u, 0});
+        for (int gs : {16, 8}) settings.push_back({GHN_PREC_BF16_MFMA, 0, 0u, 0, gs});
     } else {
         // the EXACT walk's ring schedule: 2 layers a step, doubling steps until the buffer is
         // full, or both (input and spatial order)
         for (uint32_t order : {(uint32_t)GHN_FLAG_NO_SORT, 0u}) {
-            settings.push_back({GHN_PREC_FP32, -1, order, 2});
-            settings.push_back({GHN_PREC_FP32, -1, order | GHN_FLAG_RING_GROW, 1});
-            settings.push_back({GHN_PREC_FP32, -1, order | GHN_FLAG_RING_GROW, 2});
+            settings.push_back({GHN_PREC_FP32, -1, order, 2, 0});
+            settings.push_back({GHN_PREC_FP32, -1, order | GHN_FLAG_RING_GROW, 1, 0});
+            settings.push_back({GHN_PREC_FP32, -1, order | GHN_FLAG_RING_GROW, 2, 0});
         }
-        for (int lv = 0; lv <= 3; ++lv) settings.push_back({GHN_PREC_BF16_MFMA, lv, 0u, 0});
+        // bf16: groups of 2^lv cells per dimension, of at most 16 or 8 queries
+        for (int gs : {16, 8})
+            for (int lv = 0; lv <= 3; ++lv) settings.push_back({GHN_PREC_BF16_MFMA, lv, 0u, 0, gs});
     }
 
     // outputs and a workspace large enough for every setting
@@ -383,13 +388,13 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
         for (float w : cand) {
             ghn_index* ix = nullptr;
             if (ghn_build(points, n, f, dtype, targets, task, &w, 1, nullptr, stream, &ix) != GHN_OK) {
-                if (trials && nt < max_trials) trials[nt] = {w, -1, -1, -1, 0u, 0, -1.0};
+                if (trials && nt < max_trials) trials[nt] = {w, -1, -1, -1, 0u, 0, 0, -1.0};
                 ++nt;
                 continue;
             }
             for (const Setting& st : settings) {
                 ghn_predict_opts o = {stop, st.prec, st.flags, nullptr, nullptr, nullptr, nullptr, st.levels, nullptr, nullptr,
-                                      nullptr, st.ring};
+                                      nullptr, st.ring, st.gsize};
                 double ms = -1.0;
                 if (ghn_predict(ix, queries, m, k, &o, oi, nullptr, op, ws, ws_bytes, stream) == GHN_OK &&
                     hipStreamSynchronize(s) == hipSuccess) {
@@ -404,7 +409,7 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
                     }
                     if (best_ms < 1e29f) ms = best_ms;
                 }
-                const ghn_tune_trial tr = {w, ix->info.lookup, st.prec, st.levels, st.flags, st.ring, ms};
+                const ghn_tune_trial tr = {w, ix->info.lookup, st.prec, st.levels, st.flags, st.ring, st.gsize, ms};
                 if (trials && nt < max_trials) trials[nt] = tr;
                 ++nt;
                 if (ms >= 0.0 && (!have_best || ms < best->ms)) { *best = tr; have_best = true; }
@@ -418,7 +423,7 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
                 for (const Setting& st : settings) {
                     if (st.prec != GHN_PREC_FP32) continue;
                     ghn_predict_opts o = {stop, st.prec, st.flags, nullptr, nullptr, nullptr, nullptr, st.levels, nullptr, nullptr,
-                                      nullptr, st.ring};
+                                      nullptr, st.ring, st.gsize};
                     double ms = -1.0;
                     if (ghn_predict(ix, queries, m, k, &o, oi, nullptr, op, ws, ws_bytes, stream) == GHN_OK &&
                         hipStreamSynchronize(s) == hipSuccess) {
@@ -433,7 +438,7 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
                         }
                         if (best_ms < 1e29f) ms = best_ms;
                     }
-                    const ghn_tune_trial tr = {w, GHN_LOOKUP_HASH, st.prec, st.levels, st.flags, st.ring, ms};
+                    const ghn_tune_trial tr = {w, GHN_LOOKUP_HASH, st.prec, st.levels, st.flags, st.ring, st.gsize, ms};
                     if (trials && nt < max_trials) trials[nt] = tr;
                     ++nt;
                     if (ms >= 0.0 && (!have_best || ms < best->ms)) { *best = tr; have_best = true; }
@@ -903,6 +908,7 @@ static ghn_status predict_common(const ghn_index* index, const float* queries, i
     if (o.prec != GHN_PREC_FP32 && o.prec != GHN_PREC_BF16_MFMA) return fail(GHN_E_INVALID_ARG, "ghn_predict: bad precision %d", o.prec);
     if (o.flags & ~(GHN_FLAG_NO_PRUNE | GHN_FLAG_NO_SORT | GHN_FLAG_MEDIAN | GHN_FLAG_RING_GROW)) return fail(GHN_E_INVALID_ARG, "ghn_predict: unknown flags 0x%x", o.flags);
     if (!ring_ok(o)) return fail(GHN_E_INVALID_ARG, "ghn_predict: ring_step=%d (0..64, and 0 or 1 without GHN_FLAG_RING_GROW under the PAPER rule)", o.ring_step);
+    if (o.group_size < 0 || o.group_size > 16) return fail(GHN_E_INVALID_ARG, "ghn_predict: group_size=%d outside [0, 16]", o.group_size);
     if ((o.flags & GHN_FLAG_MEDIAN) && index->info.task != GHN_REGRESS)
         return fail(GHN_E_INVALID_ARG, "ghn_predict: GHN_FLAG_MEDIAN needs a regression index");
     if (m == 0) return GHN_OK;
@@ -941,7 +947,9 @@ static ghn_status predict_common(const ghn_index* index, const float* queries, i
         if ((uintptr_t)ws % 256) return fail(GHN_E_INVALID_ARG, "ghn_predict: workspace must be 256-byte aligned");
         const int levels = brute ? 32 : o.stop == GHN_STOP_PAPER ? 0 : (o.group_levels >= 0 ? o.group_levels : (index->info.f >= 12 ? 3 : 1));
         int bits = 0;
-        e = run_grouped(pa, levels, ws, s, &bits, (hipEvent_t)o.walk_event_begin, (hipEvent_t)o.walk_event_end, brute);
+        const int gsize = o.group_size > 0 ? o.group_size : 16;
+        e = run_grouped(pa, levels, gsize, ws, s, &bits, (hipEvent_t)o.walk_event_begin, (hipEvent_t)o.walk_event_end,
+                        brute);
         if (e != hipSuccess) return hip_fail(e, "ghn_predict: grouped walk");
         return GHN_OK;
     }

@@ -159,7 +159,8 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 }
 
 // Cut the sorted queries into groups: a group starts where the (shifted) key
-// changes, at a query that walks alone, or every GQ positions.
+// changes, at a query that walks alone, or every gsize positions (gsize <= GQ: the
+// matrix tile's 16 query rows, of which smaller groups leave some empty).
 // Under the PAPER rule a group must share one central cell; when the sort key is a
 // truncated code (more than 64 bits), equal keys do not imply equal cells, so the
 // cell ids are compared too (`exact`).
@@ -174,8 +175,9 @@ __device__ __forceinline__ bool same_cell(const float* qs, const IndexView& ix, 
 }
 
 __device__ __forceinline__ bool group_start(const uint64_t* keys, const uint32_t* vals, const uint32_t* qflags,
-                                            int64_t i, int shift, const float* qs, const IndexView& ix, bool exact) {
-    if (i == 0 || (i % GQ) == 0) return true;
+                                            int64_t i, int shift, const float* qs, const IndexView& ix, bool exact,
+                                            int gsize) {
+    if (i == 0 || (i % gsize) == 0) return true;
     if (qflags[vals[i]] || qflags[vals[i - 1]]) return true;
     if (shift < 64 && (keys[i] >> shift) != (keys[i - 1] >> shift)) return true;
     return exact && !same_cell(qs, ix, vals[i], vals[i - 1]);
@@ -183,12 +185,12 @@ __device__ __forceinline__ bool group_start(const uint64_t* keys, const uint32_t
 
 __global__ __launch_bounds__(256) void k_form_groups(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
                                                      const uint32_t* __restrict__ qflags, int64_t m, int shift,
-                                                     const float* __restrict__ qs, IndexView ix, int exact,
+                                                     const float* __restrict__ qs, IndexView ix, int exact, int gsize,
                                                      uint2* __restrict__ groups, uint32_t* ngroups) {
     for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
-        if (!group_start(keys, vals, qflags, i, shift, qs, ix, exact)) continue;
+        if (!group_start(keys, vals, qflags, i, shift, qs, ix, exact, gsize)) continue;
         int64_t j = i + 1;
-        while (j < m && !group_start(keys, vals, qflags, j, shift, qs, ix, exact)) ++j;
+        while (j < m && !group_start(keys, vals, qflags, j, shift, qs, ix, exact, gsize)) ++j;
         const uint32_t g = atomicAdd(ngroups, 1u);
         groups[g] = make_uint2((uint32_t)i, (uint32_t)(j - i));
     }
@@ -197,8 +199,8 @@ __global__ __launch_bounds__(256) void k_form_groups(const uint64_t* __restrict_
 // Group starts of a batch: also where the item changes; the key shift and the PAPER
 // rule's exact cell check are the item's.
 __device__ __forceinline__ bool batch_group_start(const uint64_t* keys, const uint32_t* vals, const uint32_t* qflags,
-                                                  int64_t i, const BatchItem* items, int kb) {
-    if (i == 0 || (i % GQ) == 0) return true;
+                                                  int64_t i, const BatchItem* items, int kb, int gsize) {
+    if (i == 0 || (i % gsize) == 0) return true;
     if (qflags[vals[i]] || qflags[vals[i - 1]]) return true;
     const int it = kb < 64 ? (int)(keys[i] >> kb) : 0;
     if (kb < 64 && it != (int)(keys[i - 1] >> kb)) return true;
@@ -210,12 +212,12 @@ __device__ __forceinline__ bool batch_group_start(const uint64_t* keys, const ui
 __global__ __launch_bounds__(256) void k_batch_form_groups(const uint64_t* __restrict__ keys,
                                                            const uint32_t* __restrict__ vals,
                                                            const uint32_t* __restrict__ qflags, int64_t total,
-                                                           const BatchItem* __restrict__ items, int kb,
+                                                           const BatchItem* __restrict__ items, int kb, int gsize,
                                                            uint2* __restrict__ groups, uint32_t* ngroups) {
     for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
-        if (!batch_group_start(keys, vals, qflags, i, items, kb)) continue;
+        if (!batch_group_start(keys, vals, qflags, i, items, kb, gsize)) continue;
         int64_t j = i + 1;
-        while (j < total && !batch_group_start(keys, vals, qflags, j, items, kb)) ++j;
+        while (j < total && !batch_group_start(keys, vals, qflags, j, items, kb, gsize)) ++j;
         const uint32_t g = atomicAdd(ngroups, 1u);
         groups[g] = make_uint2((uint32_t)i, (uint32_t)(j - i));
     }
@@ -1189,8 +1191,8 @@ size_t group_ws_bytes(int64_t m) {
 }
 
 // Sort + group the queries, then walk the groups.  `ws` holds group_ws_bytes(m).
-hipError_t run_grouped(const PredictArgs& pa, int keep_shift_levels, void* ws, hipStream_t s, int* morton_bits,
-                       hipEvent_t ev_begin, hipEvent_t ev_end, bool brute) {
+hipError_t run_grouped(const PredictArgs& pa, int keep_shift_levels, int gsize, void* ws, hipStream_t s,
+                       int* morton_bits, hipEvent_t ev_begin, hipEvent_t ev_end, bool brute) {
     const IndexView& ix = pa.ix;
     const int64_t m = pa.m;
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
@@ -1229,7 +1231,7 @@ hipError_t run_grouped(const PredictArgs& pa, int keep_shift_levels, void* ws, h
     const uint32_t* sv = alt ? v1 : v0;
     const int exact = pa.stop == GHN_STOP_PAPER && total > 64 ? 1 : 0;
     hipLaunchKernelGGL(k_form_groups, dim3((unsigned)g), dim3(256), 0, s, sk, sv, qflags, m, shift, pa.io.queries,
-                       ix, exact, groups, counters);
+                       ix, exact, gsize, groups, counters);
     GroupArgs ga;
     ga.brute = brute ? 1 : 0;
     ga.p = pa;
@@ -1269,7 +1271,7 @@ hipError_t batch_query_order(const BatchItem* items, int n_items, int64_t total,
 }
 
 hipError_t run_grouped_batched(const BatchItem* items, int n_items, int64_t total, int f, int kmax, int stop, int kb,
-                               int key_bits, void* ws, hipStream_t s) {
+                               int key_bits, int gsize, void* ws, hipStream_t s) {
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
     const int64_t m = total;
     char* p = (char*)ws;
@@ -1290,8 +1292,8 @@ hipError_t run_grouped_batched(const BatchItem* items, int n_items, int64_t tota
     if (e != hipSuccess) return e;
     const uint64_t* sk = alt ? k1 : k0;
     const uint32_t* sv = alt ? v1 : v0;
-    hipLaunchKernelGGL(k_batch_form_groups, dim3((unsigned)g), dim3(256), 0, s, sk, sv, qflags, m, items, kb, groups,
-                       counters);
+    hipLaunchKernelGGL(k_batch_form_groups, dim3((unsigned)g), dim3(256), 0, s, sk, sv, qflags, m, items, kb, gsize,
+                       groups, counters);
     GroupArgs ga;
     std::memset(&ga, 0, sizeof ga);
     ga.brute = 0;

@@ -471,16 +471,17 @@ def test_bf16_16d_small(ghn):
 MFMA = 1
 
 
-def _check_mfma(ghn, prob, sample=None, levels=-1, lookup=None, paper=True, seed=0):
+def _check_mfma(ghn, prob, sample=None, levels=-1, lookup=None, paper=True, seed=0, group_size=0):
     ix = _index(ghn, prob, lookup=lookup)
-    got = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_EXACT, prec=MFMA, group_levels=levels)
+    got = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_EXACT, prec=MFMA, group_levels=levels,
+               group_size=group_size)
     rows = np.arange(prob.m)
     if sample is not None and sample < prob.m:
         rows = np.sort(np.random.default_rng(seed).choice(prob.m, sample, replace=False))
     bi, bd, bp = oracle.bruteforce(prob.points_f32(), prob.targets, prob.task, prob.queries[rows], prob.k)
     _assert_same({k: v[rows] for k, v in got.items()}, dict(idx=bi, d2=bd, pred=bp), prob.name + " MFMA EXACT")
     if paper:
-        gp = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_PAPER, prec=MFMA)
+        gp = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_PAPER, prec=MFMA, group_size=group_size)
         want = oracle.Grid(prob.points_f32(), prob.targets, prob.task, prob.cell_width).predict(
             prob.queries[rows], prob.k, oracle.STOP_PAPER)
         _assert_same({k: v[rows] for k, v in gp.items()}, want, prob.name + " MFMA PAPER", check_layers=True)
@@ -495,6 +496,36 @@ def test_mfma_clusters4d_small(ghn):
     prob = W.make("clusters4d", n=60_000, m=3_001)
     for levels in (-1, 0, 2):
         _check_mfma(ghn, prob, levels=levels, paper=levels == -1)
+
+
+@pytest.mark.parametrize("group_size", [1, 4, 8])
+def test_mfma_group_sizes(ghn, group_size):
+    """Groups of at most 1, 4 or 8 queries (the tile's other query rows stay empty)."""
+    prob = W.make("clusters4d", n=40_000, m=1_500)
+    _check_mfma(ghn, prob, levels=2, group_size=group_size)
+    probs = _multi(problems=6, n_hi=20_000, m_hi=1_500, seed=61)
+    idxs = [_index(ghn, p) for p in probs]
+    for stop in (ghn.GHN_STOP_EXACT, ghn.GHN_STOP_PAPER):
+        got = _batch_run_gs(ghn, probs, idxs, stop, group_size)
+        for i, (p, g) in enumerate(zip(probs, got)):
+            _assert_same(g, _oracle_want(p, stop), "bf16 batch group_size=%d item %d" % (group_size, i))
+
+
+def _batch_run_gs(ghn, probs, idxs, stop, group_size):
+    import torch
+    items, outs = [], []
+    for p, ix in zip(probs, idxs):
+        oi = torch.full((p.m, p.k), -7, dtype=torch.int64, device="cuda")
+        op = torch.full((p.m,), -7, dtype=torch.int32, device="cuda")
+        od = torch.zeros((p.m, p.k), dtype=torch.float64, device="cuda")
+        items.append((ix.handle, _dev(p.queries), p.k, oi, op, od))
+        outs.append((oi, op, od))
+    ws = torch.empty(ghn.ghn_batch_workspace_bytes_for(items, stop, MFMA), dtype=torch.uint8, device="cuda")
+    batch = ghn.ghn_batch_prepare(items, ws, stop=stop, prec=MFMA, group_size=group_size)
+    ghn.ghn_predict_batched(batch)
+    torch.cuda.synchronize()
+    ghn.ghn_batch_destroy(batch)
+    return [dict(idx=oi.cpu().numpy(), pred=op.cpu().numpy(), d2=od.cpu().numpy()) for oi, op, od in outs]
 
 
 @pytest.mark.parametrize("k", [1, 5, 16, 17, 32, 33, 64])
@@ -828,10 +859,11 @@ def test_autotune_exact_and_paper(ghn, tmp_path):
     best = autotune.tune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_EXACT, cache_path=cache)
     assert best["ms"] > 0 and best["cell_width"] > 0
     # widths x (8 FP32 settings: 2 walk orders x 4 ring schedules + bf16 at 4 grouping
-    # levels), plus the 8 FP32 settings on the hash lookup for every width whose build
-    # chose the tree (4 dimensions)
+    # levels x 2 group sizes), plus the 8 FP32 settings on the hash lookup for every
+    # width whose build chose the tree (4 dimensions)
     tree_widths = {t["cell_width"] for t in best["trials"] if t["lookup"] == TREE}
-    assert len(best["trials"]) == 6 * 12 + 8 * len(tree_widths)
+    assert len(best["trials"]) == 6 * 16 + 8 * len(tree_widths)
+    assert {t["group_size"] for t in best["trials"] if t["prec"] == MFMA} == {8, 16}
     assert sum(t["lookup"] == HASH for t in best["trials"]) == 8 * len(tree_widths)
     assert {t["ring_step"] for t in best["trials"]} == {0, 1, 2}
     again = autotune.tune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_EXACT, cache_path=cache)
@@ -839,11 +871,11 @@ def test_autotune_exact_and_paper(ghn, tmp_path):
     # the tuned setting still returns the brute-force neighbours
     ix = ghn.Index(pts, tgt, prob.task, best["cell_width"], lookup=best["lookup"])
     got = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_EXACT, prec=best["prec"], flags=best["flags"],
-               group_levels=best["group_levels"], ring_step=best["ring_step"])
+               group_levels=best["group_levels"], ring_step=best["ring_step"], group_size=best["group_size"])
     bi, bd, bp = oracle.bruteforce(prob.points, prob.targets, prob.task, prob.queries, prob.k)
     _assert_same(got, dict(idx=bi, d2=bd, pred=bp), "autotuned EXACT")
     pb, trials = ghn.ghn_autotune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_PAPER, widths=[prob.cell_width])
-    assert abs(pb["cell_width"] - prob.cell_width) < 1e-9 and len(trials) == 3
+    assert abs(pb["cell_width"] - prob.cell_width) < 1e-9 and len(trials) == 4
     with pytest.raises(ghn.GHNError) as e:
         ghn.ghn_autotune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_PAPER)
     assert e.value.code == -1
