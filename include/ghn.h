@@ -206,6 +206,15 @@ ghn_status ghn_build_into(const void* points, int64_t n, int32_t f, int32_t dtyp
 /* Describe a built index.  `out` is HOST memory. */
 ghn_status ghn_index_get_info(const ghn_index* index, ghn_index_info* out);
 
+/* The cells of Eq. 1 as the build grouped the points (Algorithm 1): for each of the
+ * index's num_cells occupied cells, in the index's cell order, its ids (out_ids,
+ * num_cells x f int32) and point count (out_counts, num_cells int64), and for every
+ * training point, in original row order, the position of its cell in that list
+ * (out_point_cell, n int32).  DEVICE arrays; any may be NULL.  Asynchronous on
+ * `stream`.  Errors: GHN_E_INVALID_ARG, GHN_E_HIP. */
+ghn_status ghn_index_cells(const ghn_index* index, int32_t* out_ids, int64_t* out_counts, int32_t* out_point_cell,
+                           void* stream);
+
 /* Release the index and its device memory (only the handle for an index built
  * into caller storage).  NULL is ignored. */
 void ghn_destroy(ghn_index* index);

@@ -40,7 +40,7 @@ EXPORTED = ["ghn_build", "ghn_build_ex", "ghn_index_get_info", "ghn_destroy", "g
             "ghn_predict_batched", "ghn_batch_destroy", "ghn_autotune", "ghn_cell_measure", "ghn_bruteforce",
             "ghn_index_save_bytes", "ghn_index_save", "ghn_index_load", "ghn_insert", "ghn_screen_error",
             "ghn_predict_noalloc", "ghn_build_workspace_bytes", "ghn_index_bytes", "ghn_index_bytes_for",
-            "ghn_build_into", "ghn_batch_workspace_bytes_for", "ghn_last_error"]
+            "ghn_build_into", "ghn_batch_workspace_bytes_for", "ghn_index_cells", "ghn_last_error"]
 GHN_NOALLOC_WS_BYTES = 64 << 20
 
 
@@ -102,6 +102,8 @@ def _load() -> ctypes.CDLL:
     L.ghn_index_bytes_for.restype = ctypes.c_int
     L.ghn_build_into.argtypes = [P, I64, I32, I32, P, I32, P, I32, P, P, P, SZ, P, SZ, P, ctypes.POINTER(P)]
     L.ghn_build_into.restype = ctypes.c_int
+    L.ghn_index_cells.argtypes = [P, P, P, P, P]
+    L.ghn_index_cells.restype = ctypes.c_int
     L.ghn_index_get_info.argtypes = [P, ctypes.POINTER(ghn_index_info)]
     L.ghn_index_get_info.restype = ctypes.c_int
     L.ghn_destroy.argtypes = [P]
@@ -271,6 +273,16 @@ def ghn_index_get_info(handle) -> ghn_index_info:
     info = ghn_index_info()
     _check(_lib.ghn_index_get_info(handle, ctypes.byref(info)))
     return info
+
+
+def ghn_index_cells(handle, stream=None):
+    """ghn_index_cells: (ids num_cells x f int32, counts num_cells int64, point_cell n int32) GPU tensors."""
+    info = ghn_index_get_info(handle)
+    ids = torch.empty((info.num_cells, info.f), dtype=torch.int32, device="cuda")
+    counts = torch.empty(info.num_cells, dtype=torch.int64, device="cuda")
+    point_cell = torch.empty(info.n, dtype=torch.int32, device="cuda")
+    _check(_lib.ghn_index_cells(handle, _ptr(ids), _ptr(counts), _ptr(point_cell), _stream(stream)))
+    return ids, counts, point_cell
 
 
 def ghn_destroy(handle) -> None:

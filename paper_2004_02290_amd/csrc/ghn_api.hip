@@ -821,6 +821,18 @@ ghn_status ghn_build_into(const void* points, int64_t n, int32_t f, int32_t dtyp
 }
 
 
+ghn_status ghn_index_cells(const ghn_index* index, int32_t* out_ids, int64_t* out_counts, int32_t* out_point_cell,
+                           void* stream) {
+    if (!index) return fail(GHN_E_INVALID_ARG, "ghn_index_cells: index is NULL");
+    if (((uintptr_t)out_ids % 4) || ((uintptr_t)out_counts % 8) || ((uintptr_t)out_point_cell % 4))
+        return fail(GHN_E_INVALID_ARG, "ghn_index_cells: misaligned array");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "ghn_index_cells: pending HIP error");
+    if ((e = ghn::launch_index_cells(index->view, out_ids, out_counts, out_point_cell, (hipStream_t)stream)) != hipSuccess)
+        return hip_fail(e, "ghn_index_cells");
+    return GHN_OK;
+}
+
 ghn_status ghn_index_get_info(const ghn_index* index, ghn_index_info* out) {
     if (!index || !out) return fail(GHN_E_INVALID_ARG, "ghn_index_get_info: NULL argument");
     *out = index->info;

@@ -426,6 +426,29 @@ hipError_t launch_dense_cell_start(const uint64_t* sorted_keys, int64_t n, int64
     return hipGetLastError();
 }
 
+// The index's occupied cells in its cell order: ids and point counts per cell, and for
+// every training point (original row id) the position of its cell.
+__global__ void k_index_cells(const uint32_t* __restrict__ cell_first, const int32_t* __restrict__ coord,
+                              const int32_t* __restrict__ sid, int64_t ncells, int32_t f, int32_t* __restrict__ out_ids,
+                              int64_t* __restrict__ out_counts, int32_t* __restrict__ out_point_cell) {
+    for (int64_t c = blockIdx.x * (int64_t)BT + threadIdx.x; c < ncells; c += (int64_t)gridDim.x * BT) {
+        const uint32_t b = cell_first[c], e = cell_first[c + 1];
+        if (out_ids)
+            for (int j = 0; j < f; ++j) out_ids[c * f + j] = coord[c * f + j];
+        if (out_counts) out_counts[c] = (int64_t)(e - b);
+        if (out_point_cell)
+            for (uint32_t p = b; p < e; ++p) out_point_cell[sid[p]] = (int32_t)c;
+    }
+}
+
+hipError_t launch_index_cells(const IndexView& iv, int32_t* out_ids, int64_t* out_counts, int32_t* out_point_cell,
+                              hipStream_t s) {
+    if (iv.num_cells == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_index_cells, dim3(grid_for(iv.num_cells, BT, 4096)), dim3(BT), 0, s, iv.cell_first,
+                       iv.cell_coord, iv.sid, iv.num_cells, iv.f, out_ids, out_counts, out_point_cell);
+    return hipGetLastError();
+}
+
 hipError_t launch_cell_stats(const uint32_t* cell_start, int64_t ncells, int64_t* d_stats, hipStream_t s) {
     hipLaunchKernelGGL(k_dense_cell_stats, dim3(grid_for(ncells, BT, 4096)), dim3(BT), 0, s, cell_start, ncells, d_stats);
     return hipGetLastError();

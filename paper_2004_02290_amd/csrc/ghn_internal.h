@@ -300,6 +300,8 @@ hipError_t measure_cells(const void* pts, int64_t n, int32_t f, int32_t dtype, f
 hipError_t launch_dense_cell_start(const uint64_t* sorted_keys, int64_t n, int64_t box_cells,
                                    uint32_t* cell_start, hipStream_t s);
 
+hipError_t launch_index_cells(const IndexView& iv, int32_t* out_ids, int64_t* out_counts, int32_t* out_point_cell,
+                              hipStream_t s);
 // stats[0] += non-empty cells, stats[1] = max points in one cell, over `ncells` offsets.
 hipError_t launch_cell_stats(const uint32_t* cell_start, int64_t ncells, int64_t* d_stats, hipStream_t s);
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* temp, hipStream_t s);

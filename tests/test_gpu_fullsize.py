@@ -1,20 +1,37 @@
-"""Full-size parity on sampled outputs, in the launch configurations the benchmark
-times.
+"""Full-size parity, in the launch configurations the benchmark times.
 
-Each workload is generated at its full size and the GPU answers every query; a
-seeded sample of rows is then checked one by one against the oracle: brute-force
-neighbours, distances and predictions (bit-identical), and for the per-query walks
-the grid oracle's EXACT stop layers as well."""
+Each workload is generated at its full size and the GPU answers every query.  The
+oracle's answers for seeded row sets (tests/golden/fullsize.npz, written by
+tests/golden/make_fullsize.py, which calls only the oracle) are stored as one hash
+per row: brute force for the EXACT rule (neighbour ids, FP64 distances,
+prediction) and the grid walk at the calibrated width for the PAPER rule (the same
+plus the stop layer).  Every GPU form must reproduce the hashes of every sampled
+row: 10,000 clusters4d rows, 2,000 rows of each skew8d half, 2,000 bf16_16d rows,
+and every query of 32 multi3d problems (one hash per problem)."""
+import importlib.util
+import os
+
 import numpy as np
 import pytest
 
-import oracle
 from paper_2004_02290_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
 FP32, BF16 = 0, 1
 EXACT, PAPER = 0, 1
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _golden_module():
+    spec = importlib.util.spec_from_file_location("make_fullsize", os.path.join(HERE, "golden", "make_fullsize.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+G = _golden_module()
+GOLD = dict(np.load(os.path.join(HERE, "golden", "fullsize.npz")))
 
 
 @pytest.fixture(scope="module")
@@ -37,124 +54,144 @@ def _pts(prob):
     return _dev(prob.points)
 
 
-def _host(out):
+def _hashes(out, rows, layers):
+    return G.row_hashes(out["idx"][rows], out["d2"][rows], out["pred"][rows],
+                        out["stop_layer"][rows] if layers else None)
+
+
+def _compare(got, want, rows, what):
+    bad = np.flatnonzero(got != want)
+    assert bad.size == 0, "%s: %d of %d sampled rows differ from the oracle, first query %d" % (
+        what, bad.size, rows.size, rows[bad[0]])
+
+
+def _run(ix, q, prob, stop, **kw):
     import torch
+    out = ix.predict(q, prob.k, stop=stop, with_stats=True, **kw)
     torch.cuda.synchronize()
     return {k: v.cpu().numpy() for k, v in out.items()}
 
 
-def _same(got, want, what, rows, keys=("idx", "d2", "pred")):
-    for key in keys:
-        g, w = got[key][rows], want[key]
-        if not np.array_equal(g, w):
-            bad = np.flatnonzero((g != w).reshape(g.shape[0], -1).any(axis=1))
-            raise AssertionError("%s: %s differs on %d of %d sampled rows, first query %d: got %s want %s" % (
-                what, key, bad.size, rows.size, rows[bad[0]], g[bad[0]], w[bad[0]]))
+def _check_forms(ghn, name, prob, ix, forms, width_is_calibrated=True):
+    rows = GOLD[name + "/rows"]
+    q = _dev(prob.queries)
+    for stop, tag in ((EXACT, "exact"), (PAPER, "paper")):
+        if stop == PAPER and not width_is_calibrated:
+            continue  # the PAPER answers depend on the cell width
+        for label, kw in forms[stop]:
+            got = _hashes(_run(ix, q, prob, stop, **kw), rows, stop == PAPER)
+            _compare(got, GOLD["%s/%s" % (name, tag)], rows, "%s %s %s" % (name, tag, label))
 
 
-def _sample(m, count, seed):
-    return np.sort(np.random.default_rng(seed).choice(m, min(m, count), replace=False))
-
-
-def _brute(prob, rows):
-    bi, bd, bp = oracle.bruteforce(prob.points_f32(), prob.targets, prob.task, prob.queries[rows], prob.k)
-    return dict(idx=bi, d2=bd, pred=bp)
-
-
-def _check(ghn, prob, ix, rows, brute, what, layers_from=None, **kw):
-    got = _host(ix.predict(_dev(prob.queries), prob.k, with_stats=True, **kw))
-    _same(got, brute, what, rows)
-    if layers_from is not None:
-        assert np.array_equal(got["stop_layer"][rows], layers_from), what + ": stop layers"
-    return got
+def test_clusters4d_full_size(ghn):
+    prob = W.make("clusters4d")
+    assert np.float32(prob.cell_width) == GOLD["clusters4d/width"]
+    ix = ghn.Index(_pts(prob), _dev(prob.targets), prob.task, prob.cell_width)
+    forms = {EXACT: [("FP32 input order", dict(prec=FP32, flags=ghn.GHN_FLAG_NO_SORT)),
+                     ("FP32 sorted", dict(prec=FP32)),
+                     ("FP32 ring grow", dict(prec=FP32, flags=ghn.GHN_FLAG_RING_GROW, ring_step=1)),
+                     ("bf16", dict(prec=BF16)),
+                     ("bf16 levels 0 groups of 8", dict(prec=BF16, group_levels=0, group_size=8))],
+             PAPER: [("FP32 input order", dict(prec=FP32, flags=ghn.GHN_FLAG_NO_SORT)),
+                     ("bf16", dict(prec=BF16))]}
+    _check_forms(ghn, "clusters4d", prob, ix, forms)
+    ix.close()
 
 
 @pytest.mark.parametrize("width_scale", [1.0, 2.0 ** -0.5])
 def test_skew8d_full_size(ghn, width_scale):
     """10M points, 1M queries: the calibrated width and the finer one the autotuner
-    picks for the FP32 walk; FP32 in Morton order and in input order, the grouped bf16
-    screen, and the persistent launch, all on the same sampled rows."""
+    picks (EXACT answers do not depend on the width); FP32 in Morton and input order,
+    with the ring schedule, the grouped bf16 screen and the persistent launch."""
     import torch
     prob = W.make("skew8d")
-    width = np.float32(prob.cell_width * width_scale)
-    ix = ghn.Index(_pts(prob), _dev(prob.targets), prob.task, float(width))
+    assert np.float32(prob.cell_width) == GOLD["skew8d/width"]
+    width = float(np.float32(prob.cell_width * width_scale))
+    ix = ghn.Index(_pts(prob), _dev(prob.targets), prob.task, width)
     assert ix.info.lookup == 1
-    rows = _sample(prob.m, 160, 11)
-    g = oracle.Grid(prob.points_f32(), prob.targets, prob.task, float(width))
-    want = g.predict(prob.queries[rows], prob.k, oracle.STOP_EXACT)
-    g.close()
-    what = "skew8d w=%.6g" % width
-    bw = _brute(prob, rows)
-    a = _check(ghn, prob, ix, rows, bw, what + " FP32 sorted", layers_from=want["stop_layer"], prec=FP32)
-    b = _check(ghn, prob, ix, rows, bw, what + " FP32 input order", layers_from=want["stop_layer"], prec=FP32,
-               flags=ghn.GHN_FLAG_NO_SORT)
-    assert np.array_equal(a["idx"], b["idx"]) and np.array_equal(a["pred"], b["pred"])
-    for levels in (0, 1):
-        _check(ghn, prob, ix, rows, bw, what + " bf16 levels %d" % levels, layers_from=want["stop_layer"], prec=BF16,
-               group_levels=levels)
-    # persistent launch: every query, against the per-query kernel's answers
+    forms = {EXACT: [("FP32 sorted", dict(prec=FP32)),
+                     ("FP32 sorted ring grow", dict(prec=FP32, flags=ghn.GHN_FLAG_RING_GROW, ring_step=1)),
+                     ("FP32 input order ring 2", dict(prec=FP32, flags=ghn.GHN_FLAG_NO_SORT, ring_step=2)),
+                     ("bf16 levels 0", dict(prec=BF16, group_levels=0)),
+                     ("bf16 levels 1", dict(prec=BF16, group_levels=1))],
+             PAPER: [("FP32 sorted", dict(prec=FP32)), ("bf16", dict(prec=BF16))]}
+    _check_forms(ghn, "skew8d", prob, ix, forms, width_scale == 1.0)
+    # the persistent launch over every query (spatial order, ring schedule)
+    rows = GOLD["skew8d/rows"]
     oi = torch.empty((prob.m, prob.k), dtype=torch.int64, device="cuda")
     op = torch.empty(prob.m, dtype=torch.float32, device="cuda")
     od = torch.empty((prob.m, prob.k), dtype=torch.float64, device="cuda")
     q = _dev(prob.queries)  # the batch descriptor points at it until the launch has run
     items = [(ix.handle, q, prob.k, oi, op, od)]
-    ws = torch.empty(ghn.ghn_batch_workspace_bytes_for(items), dtype=torch.uint8, device="cuda")
-    batch = ghn.ghn_batch_prepare(items, ws, EXACT)
-    ghn.ghn_predict_batched(batch)
-    torch.cuda.synchronize()
-    ghn.ghn_batch_destroy(batch)
-    assert np.array_equal(oi.cpu().numpy(), b["idx"]) and np.array_equal(od.cpu().numpy(), b["d2"])
-    assert np.array_equal(op.cpu().numpy(), b["pred"])
+    for flags, ring in ((0, 0), (ghn.GHN_FLAG_RING_GROW, 1)):
+        ws = torch.empty(ghn.ghn_batch_workspace_bytes_for(items, flags=flags), dtype=torch.uint8, device="cuda")
+        batch = ghn.ghn_batch_prepare(items, ws, EXACT, flags=flags, ring_step=ring)
+        ghn.ghn_predict_batched(batch)
+        torch.cuda.synchronize()
+        ghn.ghn_batch_destroy(batch)
+        got = dict(idx=oi.cpu().numpy(), d2=od.cpu().numpy(), pred=op.cpu().numpy())
+        _compare(_hashes(got, rows, False), GOLD["skew8d/exact"], rows, "skew8d persistent flags=%d" % flags)
     ix.close()
 
 
 @pytest.mark.parametrize("width_scale", [1.0, 2.0])
 def test_bf16_16d_full_size(ghn, width_scale):
     """4M bf16 points in 16 dimensions, 500k queries, k = 32, at the calibrated width and
-    the twice coarser one the autotuner picks: the FP32 tree walk (input and Morton
-    order) and the grouped bf16 screen (default grouping and 2^2-cell groups), on
-    sampled rows."""
+    the twice coarser one the autotuner picks: the FP32 tree walk and the grouped bf16
+    screen."""
     prob = W.make("bf16_16d")
+    assert np.float32(prob.cell_width) == GOLD["bf16_16d/width"]
     width = float(np.float32(prob.cell_width * width_scale))
     ix = ghn.Index(_pts(prob), _dev(prob.targets), prob.task, width)
-    rows = _sample(prob.m, 200, 12)
-    g = oracle.Grid(prob.points_f32(), prob.targets, prob.task, width)
-    want = g.predict(prob.queries[rows], prob.k, oracle.STOP_EXACT)
-    g.close()
-    bw = _brute(prob, rows)
-    what = "bf16_16d w=%.6g" % width
-    _check(ghn, prob, ix, rows, bw, what + " FP32", layers_from=want["stop_layer"], prec=FP32,
-           flags=ghn.GHN_FLAG_NO_SORT)
-    _check(ghn, prob, ix, rows, bw, what + " FP32 sorted", layers_from=want["stop_layer"], prec=FP32)
-    _check(ghn, prob, ix, rows, bw, what + " bf16", layers_from=want["stop_layer"], prec=BF16)
-    _check(ghn, prob, ix, rows, bw, what + " bf16 levels 2", layers_from=want["stop_layer"], prec=BF16,
-           group_levels=2)
+    forms = {EXACT: [("FP32 input order", dict(prec=FP32, flags=ghn.GHN_FLAG_NO_SORT)),
+                     ("FP32 sorted ring 2 grow", dict(prec=FP32, flags=ghn.GHN_FLAG_RING_GROW, ring_step=2)),
+                     ("bf16", dict(prec=BF16)),
+                     ("bf16 levels 2", dict(prec=BF16, group_levels=2))],
+             PAPER: [("FP32 sorted", dict(prec=FP32)), ("bf16", dict(prec=BF16))]}
+    _check_forms(ghn, "bf16_16d", prob, ix, forms, width_scale == 1.0)
     ix.close()
 
 
 def test_multi3d_full_size_batched(ghn):
-    """All 256 independent 3-D problems in one persistent launch (EXACT), as the
-    benchmark times it; a few sampled queries of every problem against brute force."""
+    """All 256 independent 3-D problems in one persistent launch, as the benchmark times
+    it (FP32 in input and in spatial order, and the grouped bf16 launch); every query
+    of the 32 golden problems must match the oracle, under both rules."""
     import torch
     probs = W.make_multi3d()
+    chosen = [int(i) for i in GOLD["multi3d/problems"]]
     idxs, items, outs = [], [], []
     for p in probs:
         ix = ghn.Index(_dev(p.points), _dev(p.targets), p.task, p.cell_width)
         oi = torch.full((p.m, p.k), -7, dtype=torch.int64, device="cuda")
         op = torch.full((p.m,), -7, dtype=torch.int32, device="cuda")
         od = torch.zeros((p.m, p.k), dtype=torch.float64, device="cuda")
+        sl = torch.zeros(p.m, dtype=torch.int32, device="cuda")
         idxs.append(ix)
         items.append((ix.handle, _dev(p.queries), p.k, oi, op, od))
-        outs.append((oi, op, od))
-    ws = torch.empty(ghn.ghn_batch_workspace_bytes_for(items), dtype=torch.uint8, device="cuda")
-    batch = ghn.ghn_batch_prepare(items, ws, EXACT)
-    ghn.ghn_predict_batched(batch)
-    torch.cuda.synchronize()
-    ghn.ghn_batch_destroy(batch)
-    for i, (p, (oi, op, od)) in enumerate(zip(probs, outs)):
-        rows = _sample(p.m, 6, 100 + i)
-        bi, bd, bp = oracle.bruteforce(p.points, p.targets, p.task, p.queries[rows], p.k)
-        got = dict(idx=oi.cpu().numpy(), pred=op.cpu().numpy(), d2=od.cpu().numpy())
-        _same(got, dict(idx=bi, d2=bd, pred=bp), "multi3d problem %d (n=%d, m=%d, k=%d)" % (i, p.n, p.m, p.k), rows)
+        outs.append((oi, op, od, sl))
+    for stop, tag in ((EXACT, "exact"), (PAPER, "paper")):
+        for label, prec, flags in (("FP32 input order", FP32, ghn.GHN_FLAG_NO_SORT), ("FP32 sorted", FP32, 0),
+                                   ("bf16", BF16, 0)):
+            ws = torch.empty(ghn.ghn_batch_workspace_bytes_for(items, stop, prec, flags), dtype=torch.uint8,
+                             device="cuda")
+            batch = ghn.ghn_batch_prepare(items, ws, stop, flags=flags, prec=prec)
+            ghn.ghn_predict_batched(batch)
+            torch.cuda.synchronize()
+            ghn.ghn_batch_destroy(batch)
+            for j, i in enumerate(chosen):
+                p, ix = probs[i], idxs[i]
+                oi, op, od, _ = outs[i]
+                got = dict(idx=oi.cpu().numpy(), pred=op.cpu().numpy(), d2=od.cpu().numpy())
+                if stop == PAPER:
+                    # batches do not report stop layers: take them from the per-index walk,
+                    # whose neighbours must then equal the batch's
+                    single = {k: v.cpu().numpy() for k, v in ix.predict(_dev(p.queries), p.k, stop=PAPER,
+                                                                       with_stats=True).items()}
+                    assert np.array_equal(single["idx"], got["idx"]), "multi3d %d %s" % (i, label)
+                    got["stop_layer"] = single["stop_layer"]
+                h = G.fold(G.row_hashes(got["idx"], got["d2"], got["pred"],
+                                        got["stop_layer"] if stop == PAPER else None))
+                assert h == GOLD["multi3d/" + tag][j], "multi3d problem %d (n=%d, m=%d, k=%d) %s %s" % (
+                    i, p.n, p.m, p.k, tag, label)
     for ix in idxs:
         ix.close()
