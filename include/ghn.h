@@ -271,7 +271,8 @@ size_t ghn_predict_workspace_bytes(const ghn_index* index, int64_t m, int32_t k,
  * memset, copy or host synchronisation), so a call can be captured in a graph
  * and replayed.  m = 0 is a no-op; m must be below 2^32.  A query
  * with a non-finite coordinate gets ids -1, distances NaN and prediction -1
- * (classification) or NaN (regression).
+ * (classification) or NaN (regression), stop layer -1 (see ghn_walk_faults for
+ * the same row with stop layer -2).
  * Errors: GHN_E_INVALID_ARG, GHN_E_K_GT_N, GHN_E_WORKSPACE, GHN_E_UNSUPPORTED,
  * GHN_E_HIP. */
 ghn_status ghn_predict(const ghn_index* index, const float* queries, int64_t m, int32_t k,
@@ -465,6 +466,19 @@ ghn_status ghn_index_load(const void* buffer, size_t bytes, void* stream, ghn_in
  * unchanged.  Synchronises `stream`.  Errors: as ghn_build. */
 ghn_status ghn_insert(ghn_index* index, const void* points, int64_t n_new, int32_t dtype, const void* targets,
                       void* stream);
+
+/* Walk faults (Section III-B: a walk returns k rows of the index).  Every walk ends
+ * with k neighbours by construction; if one ever ends with fewer, or with an entry
+ * that is not a row of the index, its query gets the "no answer" row of a
+ * non-finite query (ids -1, distances NaN, prediction -1 or NaN) with stop layer
+ * -2, and the GPU raises GHN_WALK_SHORT in a fault word the library keeps on each
+ * device.  ghn_walk_faults waits for `stream`, then writes that word of the current
+ * device to *out_flags (HOST) and, if `clear` is nonzero, resets it to 0.  The word
+ * collects faults of every ghn_predict, ghn_predict_noalloc, ghn_bruteforce and
+ * batched launch on the device since it was last cleared.  Errors:
+ * GHN_E_INVALID_ARG, GHN_E_HIP. */
+#define GHN_WALK_SHORT 1u
+ghn_status ghn_walk_faults(uint32_t* out_flags, int clear, void* stream);
 
 /* Last error message of the calling thread ("" if none).  Valid until the
  * thread's next failing call. */

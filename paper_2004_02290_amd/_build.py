@@ -12,7 +12,7 @@ OBJ = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(PKG, "libghn.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["ghn_api.hip", "ghn_build.hip", "ghn_predict.hip", "ghn_tree.hip", "ghn_group.hip", "ghn_batch.hip", "ghn_tune.hip", "ghn_measure.hip"]
+SOURCES = ["ghn_api.hip", "ghn_hostenv.hip", "ghn_build.hip", "ghn_predict.hip", "ghn_tree.hip", "ghn_group.hip", "ghn_batch.hip", "ghn_tune.hip", "ghn_measure.hip"]
 
 # -ffp-contract=off: FP64 distances and bounds are evaluated exactly as written.
 # -packed-fp32-ops off: no packed FP32 instructions are generated.

@@ -29,6 +29,7 @@ GHN_CLASSIFY, GHN_REGRESS = 0, 1
 GHN_STOP_EXACT, GHN_STOP_PAPER = 0, 1
 GHN_PREC_FP32, GHN_PREC_BF16_MFMA = 0, 1
 GHN_FLAG_NO_PRUNE, GHN_FLAG_NO_SORT, GHN_FLAG_MEDIAN, GHN_FLAG_RING_GROW = 1, 2, 4, 8
+GHN_WALK_SHORT = 1
 GHN_K_MAX, GHN_F_MAX = 64, 32
 
 GHN_LOOKUP_AUTO, GHN_LOOKUP_DENSE, GHN_LOOKUP_TREE, GHN_LOOKUP_HASH = -1, 0, 1, 2
@@ -40,7 +41,8 @@ EXPORTED = ["ghn_build", "ghn_build_ex", "ghn_index_get_info", "ghn_destroy", "g
             "ghn_predict_batched", "ghn_batch_destroy", "ghn_autotune", "ghn_cell_measure", "ghn_bruteforce",
             "ghn_index_save_bytes", "ghn_index_save", "ghn_index_load", "ghn_insert", "ghn_screen_error",
             "ghn_predict_noalloc", "ghn_build_workspace_bytes", "ghn_index_bytes", "ghn_index_bytes_for",
-            "ghn_build_into", "ghn_batch_workspace_bytes_for", "ghn_index_cells", "ghn_last_error"]
+            "ghn_build_into", "ghn_batch_workspace_bytes_for", "ghn_index_cells", "ghn_walk_faults",
+            "ghn_last_error"]
 GHN_NOALLOC_WS_BYTES = 64 << 20
 
 
@@ -104,6 +106,8 @@ def _load() -> ctypes.CDLL:
     L.ghn_build_into.restype = ctypes.c_int
     L.ghn_index_cells.argtypes = [P, P, P, P, P]
     L.ghn_index_cells.restype = ctypes.c_int
+    L.ghn_walk_faults.argtypes = [ctypes.POINTER(ctypes.c_uint32), ctypes.c_int, P]
+    L.ghn_walk_faults.restype = ctypes.c_int
     L.ghn_index_get_info.argtypes = [P, ctypes.POINTER(ghn_index_info)]
     L.ghn_index_get_info.restype = ctypes.c_int
     L.ghn_destroy.argtypes = [P]
@@ -283,6 +287,14 @@ def ghn_index_cells(handle, stream=None):
     point_cell = torch.empty(info.n, dtype=torch.int32, device="cuda")
     _check(_lib.ghn_index_cells(handle, _ptr(ids), _ptr(counts), _ptr(point_cell), _stream(stream)))
     return ids, counts, point_cell
+
+
+def ghn_walk_faults(clear=False, stream=None) -> int:
+    """ghn_walk_faults: the current device's walk fault bits (GHN_WALK_SHORT), after
+    waiting for `stream`; clear resets them."""
+    v = ctypes.c_uint32(0)
+    _check(_lib.ghn_walk_faults(ctypes.byref(v), int(bool(clear)), _stream(stream)))
+    return v.value
 
 
 def ghn_destroy(handle) -> None:

@@ -51,12 +51,48 @@ ghn_status fail(ghn_status st, const char* fmt, ...) {
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     g_err = buf;
+    ghn::log_line("error %d: %s", (int)st, buf);
     return st;
 }
 
 ghn_status hip_fail(hipError_t e, const char* what) {
     return fail(GHN_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
+
+// Static device arrays of the library.  In host code such an array's name only names
+// the symbol; its address on each GPU comes from hipGetSymbolAddress, looked up once
+// per device (with that device current) and kept here.
+constexpr int SYMBOL_DEVICES = 256;
+struct SymbolCache {
+    std::mutex mu;
+    void* ptr[SYMBOL_DEVICES] = {};
+};
+
+ghn_status symbol_address(const void* symbol, SymbolCache& cache, const char* what, void** out) {
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, what);
+    if (dev < 0 || dev >= SYMBOL_DEVICES) return fail(GHN_E_UNSUPPORTED, "%s: device %d", what, dev);
+    std::lock_guard<std::mutex> lock(cache.mu);
+    if (!cache.ptr[dev]) {
+        void* p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, symbol)) != hipSuccess) return hip_fail(e, what);
+        cache.ptr[dev] = p;
+    }
+    *out = cache.ptr[dev];
+    return GHN_OK;
+}
+
+// The walk fault word of each GPU (GHN_WALK_SHORT), padded to its own 256 bytes.
+__device__ __align__(256) uint32_t walk_fault_word[64];
+SymbolCache g_fault_word;
+
+ghn_status fault_word(uint32_t** out) {
+    return symbol_address(HIP_SYMBOL(walk_fault_word), g_fault_word, "walk fault word address", (void**)out);
+}
+
+__global__ void k_clear_word(uint32_t* w) { *w = 0u; }
 
 // Device memory of a build: hipMalloc'd blocks released together unless kept, or
 // (carve) 256-byte aligned pieces of a caller's buffer, which is never freed here.
@@ -70,7 +106,7 @@ struct DevPool {
     DevPool(const DevPool&) = delete;
     DevPool& operator=(const DevPool&) = delete;
     ~DevPool() {
-        for (void* p : ptrs) (void)hipFree(p);
+        for (void* p : ptrs) ghn::device_free(p);
     }
     bool carving() const { return base != nullptr; }
     hipError_t alloc(void** p, size_t bytes) {
@@ -82,7 +118,7 @@ struct DevPool {
             used = at + bytes;
             return hipSuccess;
         }
-        hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+        hipError_t e = ghn::device_alloc(p, bytes);
         if (e == hipSuccess) ptrs.push_back(*p);
         return e;
     }
@@ -199,6 +235,8 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
     if (!ws || ws_bytes < need)
         return fail(GHN_E_WORKSPACE, "ghn_batch_prepare: workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
     if ((uintptr_t)ws % 256) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: workspace must be 256-byte aligned");
+    uint32_t* faults = nullptr;
+    if (const ghn_status fs = fault_word(&faults); fs != GHN_OK) return fs;
     std::vector<BatchItem> h((size_t)n_items);
     int64_t total = 0;
     int32_t f = -1;
@@ -230,6 +268,7 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
         b.io.k = it.k;
         b.io.flags = o.flags;
         b.io.ring_step = o.ring_step;
+        b.io.faults = faults;
         b.first = total;
         b.m = it.m;
         total += it.m;
@@ -297,12 +336,15 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
     b->group_size = o.group_size > 0 ? o.group_size : 16;
     b->blocks = 0;
     if (const char* env = std::getenv("GHN_BATCH_BLOCKS")) b->blocks = std::atoi(env) > 0 ? std::atoi(env) : 0;
+    ghn::log_line("batch_prepare items=%d queries=%lld f=%d kmax=%d stop=%d prec=%d flags=0x%x sorted=%d", n_items,
+                  (long long)total, f, kmax, o.stop, o.prec, o.flags, (int)sorted);
     *out = b;
     return GHN_OK;
 }
 
 ghn_status ghn_predict_batched(const ghn_batch* batch, void* stream) {
     if (!batch) return fail(GHN_E_INVALID_ARG, "ghn_predict_batched: batch is NULL");
+    ghn::log_line("predict_batched items=%d queries=%lld prec=%d", batch->n_items, (long long)batch->total, batch->prec);
     if (batch->total == 0) return GHN_OK;
     if (batch->prec == GHN_PREC_BF16_MFMA) {
         const hipError_t e = ghn::run_grouped_batched(batch->items_dev, batch->n_items, batch->total, batch->f,
@@ -381,8 +423,8 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
     ghn_status result = GHN_OK;
     bool have_best = false;
     int32_t nt = 0;
-    if (hipMalloc((void**)&oi, (size_t)m * k * 8) != hipSuccess || hipMalloc(&op, (size_t)m * 4) != hipSuccess ||
-        hipMalloc(&ws, ws_bytes) != hipSuccess || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (device_alloc((void**)&oi, (size_t)m * k * 8) != hipSuccess || device_alloc(&op, (size_t)m * 4) != hipSuccess ||
+        device_alloc(&ws, ws_bytes) != hipSuccess || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         result = fail(GHN_E_NOMEM, "ghn_autotune: out of device memory");
     } else {
         for (float w : cand) {
@@ -450,10 +492,14 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    if (oi) (void)hipFree(oi);
-    if (op) (void)hipFree(op);
-    if (ws) (void)hipFree(ws);
+    if (oi) ghn::device_free(oi);
+    if (op) ghn::device_free(op);
+    if (ws) ghn::device_free(ws);
     if (n_trials) *n_trials = nt;
+    if (result == GHN_OK)
+        log_line("autotune trials=%d best: width=%g lookup=%d prec=%d group_levels=%d flags=0x%x ring_step=%d "
+                 "group_size=%d ms=%.4f", nt, best->cell_width, best->lookup, best->prec, best->group_levels,
+                 best->flags, best->ring_step, best->group_size, best->ms);
     return result;
 }
 
@@ -754,6 +800,9 @@ ghn_status build_impl(const void* points, int64_t n, int32_t f, int32_t dtype, c
     keep.release(ix->allocs);
     ix->want_lookup = want_lookup;
     ix->info.device_bytes = keep.carving() ? keep.used : ix->info.device_bytes;
+    ghn::log_line("build n=%lld f=%d dtype=%d task=%d lookup=%d cells=%lld max_occupancy=%lld device_bytes=%zu%s",
+                  (long long)n, f, dtype, task, lookup, (long long)iv.num_cells, (long long)h.stats[1],
+                  ix->info.device_bytes, keep.carving() ? " (caller storage)" : "");
     *out = ix;
     return GHN_OK;
 }
@@ -841,7 +890,7 @@ ghn_status ghn_index_get_info(const ghn_index* index, ghn_index_info* out) {
 
 void ghn_destroy(ghn_index* index) {
     if (!index) return;
-    for (void* p : index->allocs) (void)hipFree(p);
+    for (void* p : index->allocs) ghn::device_free(p);
     delete index;
 }
 
@@ -946,12 +995,19 @@ static ghn_status predict_common(const ghn_index* index, const float* queries, i
     pa.io.out_cands = o.out_cands;
     pa.io.out_probes = o.out_probes;
     pa.io.out_rerank = o.out_rerank;
+    pa.io.pad = 0;
+    if (const ghn_status fs = fault_word(&pa.io.faults); fs != GHN_OK) return fs;
     pa.order = o.order;
     hipStream_t s = (hipStream_t)stream;
     if (brute) {
         o.prec = GHN_PREC_BF16_MFMA;
         pa.order = nullptr;
     }
+    if (log_enabled())
+        log_line("%s m=%lld k=%d stop=%d prec=%d flags=0x%x ring_step=%d group_levels=%d group_size=%d lookup=%d order=%s",
+                 brute ? "bruteforce" : "predict", (long long)m, k, o.stop, o.prec, o.flags, o.ring_step,
+                 o.group_levels, o.group_size, index->view.lookup,
+                 o.order ? "given" : (o.prec == GHN_PREC_FP32 && wants_sort(m, o.flags)) ? "sorted" : "input");
     if (o.prec == GHN_PREC_BF16_MFMA) {
         const size_t need = group_ws_bytes(m);
         if (!ws || ws_bytes < need)
@@ -1000,33 +1056,35 @@ ghn_status ghn_bruteforce(const ghn_index* index, const float* queries, int64_t 
 namespace {
 
 // Workspace of ghn_predict_noalloc.  In host code `scratch` only names the symbol;
-// its address on each GPU comes from hipGetSymbolAddress, looked up once per device
-// (with that device current) and kept in g_scratch_ptr.
+// its address on each GPU comes from symbol_address (hipGetSymbolAddress once per
+// device, with that device current).
 __device__ __align__(256) unsigned char scratch[GHN_NOALLOC_WS_BYTES];
-constexpr int SCRATCH_DEVICES = 256;
-std::mutex g_scratch_mu;
-void* g_scratch_ptr[SCRATCH_DEVICES] = {};
+SymbolCache g_scratch;
 
 ghn_status scratch_address(void** out) {
-    *out = nullptr;
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "ghn_predict_noalloc: hipGetDevice");
-    if (dev < 0 || dev >= SCRATCH_DEVICES) return fail(GHN_E_UNSUPPORTED, "ghn_predict_noalloc: device %d", dev);
-    std::lock_guard<std::mutex> lock(g_scratch_mu);
-    if (!g_scratch_ptr[dev]) {
-        void* p = nullptr;
-        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess)
-            return hip_fail(e, "ghn_predict_noalloc: address of the workspace array");
-        g_scratch_ptr[dev] = p;
-    }
-    *out = g_scratch_ptr[dev];
-    return GHN_OK;
+    return symbol_address(HIP_SYMBOL(scratch), g_scratch, "ghn_predict_noalloc: address of the workspace array", out);
 }
 
 }  // namespace
 
 extern "C" {
+
+ghn_status ghn_walk_faults(uint32_t* out_flags, int clear, void* stream) {
+    if (!out_flags) return fail(GHN_E_INVALID_ARG, "ghn_walk_faults: out_flags is NULL");
+    uint32_t* w = nullptr;
+    if (const ghn_status fs = fault_word(&w); fs != GHN_OK) return fs;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t v = 0;
+    hipError_t e = hipMemcpyAsync(&v, w, sizeof v, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && clear) {
+        hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(1), 0, s, w);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "ghn_walk_faults");
+    *out_flags = v;
+    return GHN_OK;
+}
 
 ghn_status ghn_predict_noalloc(const ghn_index* index, const float* queries, int64_t m, int32_t k,
                                const ghn_predict_opts* opts, int64_t* out_idx, double* out_d2, void* out_pred,
@@ -1090,7 +1148,7 @@ hipError_t original_points(const ghn_index* index, float* out, hipStream_t s) {
 
 // Replace the contents of `dst` by those of `src` (which is consumed).
 void adopt(ghn_index* dst, ghn_index* src) {
-    for (void* p : dst->allocs) (void)hipFree(p);
+    for (void* p : dst->allocs) ghn::device_free(p);
     *dst = *src;
     src->allocs.clear();
     delete src;

@@ -98,7 +98,7 @@ hipError_t launch_ft(const BatchItem* items, int n_items, int64_t total, const u
                      int stop, bool any_tree, int blocks, hipStream_t s) {
     if (any_tree) launch_stop<FT, true>(items, n_items, total, order, counter, stop, blocks, s);
     else launch_stop<FT, false>(items, n_items, total, order, counter, stop, blocks, s);
-    return hipGetLastError();
+    return launch_status();
 }
 
 }  // namespace

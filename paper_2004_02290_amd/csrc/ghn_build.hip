@@ -339,14 +339,14 @@ hipError_t launch_cells_minmax(const void* pts, int64_t n, int32_t f, int32_t dt
                                const float* o, int32_t* d_minmax, int32_t* d_flags, hipStream_t s) {
     hipLaunchKernelGGL(k_cells_minmax, dim3(grid_for(n, BT, 4096)), dim3(BT), 0, s, pts, n, f, dtype, a, o,
                        d_minmax, d_flags);
-    return hipGetLastError();
+    return launch_status();
 }
 
 hipError_t launch_dense_keys(const void* pts, int64_t n, int32_t f, int32_t dtype, const IndexView& iv,
                              uint64_t* keys, uint32_t* vals, hipStream_t s) {
     (void)f;
     hipLaunchKernelGGL(k_dense_keys, dim3(grid_for(n, BT)), dim3(BT), 0, s, pts, n, dtype, iv, keys, vals);
-    return hipGetLastError();
+    return launch_status();
 }
 
 size_t radix_sort_temp_bytes(int64_t n) {
@@ -386,28 +386,28 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void
     hipLaunchKernelGGL(k_tile_sums, dim3(nb), dim3(BT), 0, s, in, n, sums);
     hipLaunchKernelGGL(k_exclusive_scan_u32, dim3(1), dim3(SCAN_T), 0, s, sums, (int64_t)nb);
     hipLaunchKernelGGL(k_tile_scan, dim3(nb), dim3(BT), 0, s, in, out, n, sums);
-    return hipGetLastError();
+    return launch_status();
 }
 
 hipError_t launch_gather_points(const void* pts, int64_t n, int32_t f, int32_t dtype, const uint32_t* perm,
                                 float* spts, int32_t* sid, hipStream_t s) {
     hipLaunchKernelGGL(k_gather_points, dim3(grid_for(n, BT)), dim3(BT), 0, s, pts, n, f, dtype, perm, spts, sid);
-    return hipGetLastError();
+    return launch_status();
 }
 
 hipError_t launch_unsort_points(const float* spts, const int32_t* sid, int64_t n, int32_t f, float* out, hipStream_t s) {
     hipLaunchKernelGGL(k_unsort_points, dim3(grid_for(n, BT)), dim3(BT), 0, s, spts, sid, n, f, out);
-    return hipGetLastError();
+    return launch_status();
 }
 
 hipError_t launch_widen_points(const void* pts, int64_t count, int32_t dtype, float* out, hipStream_t s) {
     hipLaunchKernelGGL(k_widen_points, dim3(grid_for(count, BT)), dim3(BT), 0, s, pts, count, dtype, out);
-    return hipGetLastError();
+    return launch_status();
 }
 
 hipError_t launch_screen_records(const IndexView& iv, uint16_t* rec, float* xn, hipStream_t s) {
     hipLaunchKernelGGL(k_screen_records, dim3(grid_for(iv.n, BT)), dim3(BT), 0, s, iv, rec, xn);
-    return hipGetLastError();
+    return launch_status();
 }
 
 hipError_t launch_hash_build(const uint64_t* sorted_keys, const uint32_t* cell_first, int64_t ncell, uint64_t* hkeys,
@@ -416,14 +416,14 @@ hipError_t launch_hash_build(const uint64_t* sorted_keys, const uint32_t* cell_f
     hipLaunchKernelGGL(k_hash_clear, dim3(grid_for(cap, BT)), dim3(BT), 0, s, hkeys, cap);
     hipLaunchKernelGGL(k_hash_insert, dim3(grid_for(ncell, BT)), dim3(BT), 0, s, sorted_keys, cell_first, ncell, hkeys,
                        hvals, mask);
-    return hipGetLastError();
+    return launch_status();
 }
 
 hipError_t launch_dense_cell_start(const uint64_t* sorted_keys, int64_t n, int64_t box_cells, uint32_t* cell_start,
                                    hipStream_t s) {
     hipLaunchKernelGGL(k_dense_cell_start, dim3(grid_for(box_cells + 1, BT)), dim3(BT), 0, s, sorted_keys, n,
                        box_cells, cell_start);
-    return hipGetLastError();
+    return launch_status();
 }
 
 // The index's occupied cells in its cell order: ids and point counts per cell, and for
@@ -446,12 +446,12 @@ hipError_t launch_index_cells(const IndexView& iv, int32_t* out_ids, int64_t* ou
     if (iv.num_cells == 0) return hipSuccess;
     hipLaunchKernelGGL(k_index_cells, dim3(grid_for(iv.num_cells, BT, 4096)), dim3(BT), 0, s, iv.cell_first,
                        iv.cell_coord, iv.sid, iv.num_cells, iv.f, out_ids, out_counts, out_point_cell);
-    return hipGetLastError();
+    return launch_status();
 }
 
 hipError_t launch_cell_stats(const uint32_t* cell_start, int64_t ncells, int64_t* d_stats, hipStream_t s) {
     hipLaunchKernelGGL(k_dense_cell_stats, dim3(grid_for(ncells, BT, 4096)), dim3(BT), 0, s, cell_start, ncells, d_stats);
-    return hipGetLastError();
+    return launch_status();
 }
 
 }  // namespace ghn

@@ -947,23 +947,19 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
             const int r = 4 * g + i;
             const bool act = r < cnt;
             const int64_t qi = act ? (int64_t)G.p.order[gd.x + r] - qbase : 0;
-            const bool live = act && ((fin_mask >> r) & 1);
+            // every walk ends with k rows of the index; one that does not reports it (the
+            // buffer fills from the front, so its k-th entry is a row once it is full)
+            const bool fin_r = act && ((fin_mask >> r) & 1);
+            bool bad = false;
+#pragma unroll
+            for (int j = 0; j < KR; ++j) bad = bad || (16 * j + t < k && !entry_ok(bi[i][j], ix.n));
+            const bool short_r = ((ballot(fin_r && bad) >> (16 * g)) & 0xffffu) != 0;
+            const bool live = fin_r && !short_r;
             if (act && !live) {
-                for (int j = 0; j < KR; ++j) {
-                    const int ee = 16 * j + t;
-                    if (ee < k) {
-                        io.out_idx[qi * k + ee] = -1;
-                        if (io.out_d2) io.out_d2[qi * k + ee] = __longlong_as_double(0x7ff8000000000000LL);
-                    }
-                }
-                if (t == 0) {
-                    if (ix.task == GHN_CLASSIFY) ((int32_t*)io.out_pred)[qi] = -1;
-                    else ((float*)io.out_pred)[qi] = __int_as_float(0x7fc00000);
-                    if (io.out_stop_layer) io.out_stop_layer[qi] = -1;
-                    if (io.out_cands) io.out_cands[qi] = 0;
-                    if (io.out_probes) io.out_probes[qi] = 0;
-                    if (io.out_rerank) io.out_rerank[qi] = 0;
-                }
+                write_no_answer_row(io.out_idx, io.out_d2, io.out_pred, io.out_stop_layer, io.out_cands,
+                                    io.out_probes, io.out_rerank, ix.task == GHN_CLASSIFY, k, qi, t, 16,
+                                    short_r ? STOP_SHORT : STOP_NONFINITE);
+                if (short_r && t == 0 && io.faults) atomicOr(io.faults, GHN_WALK_SHORT);
             }
             if (live) {
 #pragma unroll
@@ -972,7 +968,7 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                     if (ee < k) {
                         io.out_idx[qi * k + ee] = bi[i][j];
                         if (io.out_d2) io.out_d2[qi * k + ee] = bd[i][j];
-                        S.lab[g][ee] = (uint32_t)bi[i][j] < (uint64_t)ix.n ? ((const int32_t*)ix.targets)[bi[i][j]] : 0;
+                        S.lab[g][ee] = ((const int32_t*)ix.targets)[bi[i][j]];
                     }
                 }
             }
@@ -1150,7 +1146,7 @@ hipError_t launch_err(const IndexView& ix, const float* qs, int64_t m, uint32_t 
     } else {
         hipLaunchKernelGGL((k_screen_error<0, 32>), dim3((unsigned)blocks), dim3(GT), 0, s, ix, qs, m, nsamp, out_abs, out_rel);
     }
-    return hipGetLastError();
+    return launch_status();
 }
 
 template <int FT, int SP, bool BATCH>
@@ -1158,7 +1154,7 @@ hipError_t launch_k(const GroupArgs& a, int kmax, int blocks, hipStream_t s) {
     if (kmax <= 16) hipLaunchKernelGGL((k_predict_group<FT, SP, 1, BATCH>), dim3(blocks), dim3(GT), 0, s, a);
     else if (kmax <= 32) hipLaunchKernelGGL((k_predict_group<FT, SP, 2, BATCH>), dim3(blocks), dim3(GT), 0, s, a);
     else hipLaunchKernelGGL((k_predict_group<FT, SP, 4, BATCH>), dim3(blocks), dim3(GT), 0, s, a);
-    return hipGetLastError();
+    return launch_status();
 }
 
 // sp: the padded screen dimension (every index of a batch has f, so the same sp)

@@ -280,6 +280,15 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 }
 
 // ---------------------------------------------------------------------------------------
+// Host-layer environment (ghn_hostenv.hip).  GHN_FAULT=alloc[:N] or launch[:N] makes the
+// N-th device allocation or launch check fail; GHN_LOG=1 logs calls and failures.
+hipError_t device_alloc(void** p, size_t bytes);  // hipMalloc of max(bytes, 1), or the injected failure
+void device_free(void* p);                        // hipFree of a device_alloc block (NULL is ignored)
+hipError_t launch_status();                       // hipGetLastError after launches, or the injected failure
+bool log_enabled();
+void log_line(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+
+// ---------------------------------------------------------------------------------------
 // Host-side launchers (defined in the .hip files).
 hipError_t launch_cells_minmax(const void* pts, int64_t n, int32_t f, int32_t dtype, const float* a,
                                const float* o, int32_t* d_minmax, int32_t* d_flags, hipStream_t s);
@@ -329,6 +338,7 @@ struct QueryIO {
     uint32_t flags;
     int32_t ring_step;   // EXACT rule: layers per step of the walk (<= 1: one)
     int32_t pad;
+    uint32_t* faults;    // the device's walk fault word (GHN_WALK_SHORT), or NULL
 };
 
 struct PredictArgs {

@@ -113,12 +113,12 @@ hipError_t measure_cells(const void* pts, int64_t n, int32_t f, int32_t dtype, f
     int* bad = nullptr;
     hipError_t e = hipSuccess;
     auto release = [&]() {
-        (void)hipFree(k0); (void)hipFree(k1); (void)hipFree(v0); (void)hipFree(v1); (void)hipFree(temp);
-        (void)hipFree(bad);
+        ghn::device_free(k0); ghn::device_free(k1); ghn::device_free(v0); ghn::device_free(v1); ghn::device_free(temp);
+        ghn::device_free(bad);
     };
-    if ((e = hipMalloc((void**)&k0, n * 8)) != hipSuccess || (e = hipMalloc((void**)&k1, n * 8)) != hipSuccess ||
-        (e = hipMalloc((void**)&v0, n * 4)) != hipSuccess || (e = hipMalloc((void**)&v1, n * 4)) != hipSuccess ||
-        (e = hipMalloc(&temp, radix_sort_temp_bytes(n))) != hipSuccess || (e = hipMalloc((void**)&bad, 4)) != hipSuccess) {
+    if ((e = device_alloc((void**)&k0, n * 8)) != hipSuccess || (e = device_alloc((void**)&k1, n * 8)) != hipSuccess ||
+        (e = device_alloc((void**)&v0, n * 4)) != hipSuccess || (e = device_alloc((void**)&v1, n * 4)) != hipSuccess ||
+        (e = device_alloc(&temp, radix_sort_temp_bytes(n))) != hipSuccess || (e = device_alloc((void**)&bad, 4)) != hipSuccess) {
         release();
         return e;
     }
@@ -129,7 +129,7 @@ hipError_t measure_cells(const void* pts, int64_t n, int32_t f, int32_t dtype, f
         if (g > 4096) g = 4096;
         if ((e = hipMemsetAsync(bad, 0, 4, s)) != hipSuccess) break;
         hipLaunchKernelGGL(k_column_keys, dim3((unsigned)g), dim3(MT), 0, s, pts, n, f, j, dtype, k0, v0, bad);
-        if ((e = hipGetLastError()) != hipSuccess) break;
+        if ((e = launch_status()) != hipSuccess) break;
         bool alt = false;
         if ((e = radix_sort_pairs(k0, v0, k1, v1, n, 32, temp, &alt, s)) != hipSuccess) break;
         if ((e = hipMemcpyAsync(keys.data(), alt ? k1 : k0, n * 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||

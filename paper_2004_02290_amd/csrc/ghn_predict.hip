@@ -101,7 +101,7 @@ hipError_t launch_ft(const PredictArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)((a.m + WPB - 1) / WPB)), block(PT);
     if (a.ix.lookup == LOOKUP_HASH) launch_stop<FT, true>(a, grid, block, s);
     else launch_stop<FT, false>(a, grid, block, s);
-    return hipGetLastError();
+    return launch_status();
 }
 
 }  // namespace
@@ -111,7 +111,7 @@ hipError_t launch_query_keys(const float* qs, int64_t m, const IndexView& ix, in
     int64_t g = (m + 255) / 256;
     if (g > 65536) g = 65536;
     hipLaunchKernelGGL(k_query_keys, dim3((unsigned)g), dim3(256), 0, s, qs, m, ix, keep_bits, keys, vals);
-    return hipGetLastError();
+    return launch_status();
 }
 
 hipError_t launch_predict_dense(const PredictArgs& a, hipStream_t s) {

@@ -144,7 +144,7 @@ hipError_t launch_ft(const PredictArgs& a, hipStream_t s) {
         hipLaunchKernelGGL((k_predict_tree<FT, GHN_STOP_PAPER>), grid, block, 0, s, a);
     else
         hipLaunchKernelGGL((k_predict_tree<FT, GHN_STOP_EXACT>), grid, block, 0, s, a);
-    return hipGetLastError();
+    return launch_status();
 }
 
 int grid_for(int64_t work, int threads, int cap = 65536) {
@@ -160,30 +160,30 @@ hipError_t launch_morton_keys(const void* pts, int64_t n, int32_t dtype, const I
                               const uint32_t* order, uint64_t* keys, uint32_t* vals, hipStream_t s) {
     hipLaunchKernelGGL(k_morton_keys, dim3(grid_for(n, BT)), dim3(BT), 0, s, pts, n, dtype, iv, nbits, word, order,
                        keys, vals);
-    return hipGetLastError();
+    return launch_status();
 }
 
 hipError_t launch_cell_heads_ids(const IndexView& iv, int64_t n, uint32_t* heads, hipStream_t s) {
     hipLaunchKernelGGL(k_cell_heads_ids, dim3(grid_for(n, BT)), dim3(BT), 0, s, iv, n, heads);
-    return hipGetLastError();
+    return launch_status();
 }
 
 hipError_t launch_cell_heads(const uint64_t* sorted_keys, int64_t n, uint32_t* heads, hipStream_t s) {
     hipLaunchKernelGGL(k_cell_heads, dim3(grid_for(n, BT)), dim3(BT), 0, s, sorted_keys, n, heads);
-    return hipGetLastError();
+    return launch_status();
 }
 
 hipError_t launch_cell_list(const uint32_t* heads, const uint32_t* rank, int64_t n, const IndexView& iv,
                             uint32_t* cell_start, int32_t* cell_coord, hipStream_t s) {
     hipLaunchKernelGGL(k_cell_list, dim3(grid_for(n, BT)), dim3(BT), 0, s, heads, rank, n, iv, cell_start, cell_coord);
-    return hipGetLastError();
+    return launch_status();
 }
 
 hipError_t launch_tree_level(const int32_t* child_lo, const int32_t* child_hi, int64_t nchild, int32_t f,
                              int32_t* node_lo, int32_t* node_hi, int64_t nnode, hipStream_t s) {
     hipLaunchKernelGGL(k_tree_level, dim3(grid_for(nnode, BT)), dim3(BT), 0, s, child_lo, child_hi, nchild, f, node_lo,
                        node_hi, nnode);
-    return hipGetLastError();
+    return launch_status();
 }
 
 hipError_t launch_predict_tree(const PredictArgs& a, hipStream_t s) {

@@ -51,7 +51,7 @@ float ord2f(uint32_t u) {
 
 hipError_t coord_range(const void* pts, int64_t n, int32_t f, int32_t dtype, float* lo, float* hi, hipStream_t s) {
     uint32_t* d = nullptr;
-    hipError_t e = hipMalloc((void**)&d, (size_t)2 * f * 4);
+    hipError_t e = device_alloc((void**)&d, (size_t)2 * f * 4);
     if (e != hipSuccess) return e;
     std::vector<uint32_t> h((size_t)2 * f);
     for (int j = 0; j < f; ++j) { h[2 * j] = 0xffffffffu; h[2 * j + 1] = 0u; }
@@ -59,11 +59,11 @@ hipError_t coord_range(const void* pts, int64_t n, int32_t f, int32_t dtype, flo
         int64_t g = (n + 255) / 256;
         if (g > 1024) g = 1024;
         hipLaunchKernelGGL(k_coord_range, dim3((unsigned)g), dim3(256), 0, s, pts, n, f, dtype, d);
-        if ((e = hipGetLastError()) == hipSuccess &&
+        if ((e = launch_status()) == hipSuccess &&
             (e = hipMemcpyAsync(h.data(), d, h.size() * 4, hipMemcpyDeviceToHost, s)) == hipSuccess)
             e = hipStreamSynchronize(s);
     }
-    (void)hipFree(d);
+    ghn::device_free(d);
     for (int j = 0; j < f; ++j) { lo[j] = ord2f(h[2 * j]); hi[j] = ord2f(h[2 * j + 1]); }
     return e;
 }

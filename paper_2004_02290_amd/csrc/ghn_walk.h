@@ -9,6 +9,7 @@
 // exactly the k best of everything scored so far.
 #pragma once
 
+#include "ghn_guard.h"
 #include "ghn_internal.h"
 
 namespace ghn {
@@ -236,22 +237,22 @@ __device__ __forceinline__ void setup_query(const IndexView& ix, const float* qu
     }
 }
 
+// The "no answer" row of query qi, written by the wave (entry e by lane e).
+__device__ __forceinline__ void write_no_answer(const IndexView& ix, const QueryIO& io, int64_t qi, int32_t stop) {
+    write_no_answer_row(io.out_idx, io.out_d2, io.out_pred, io.out_stop_layer, io.out_cands, io.out_probes,
+                        io.out_rerank, ix.task == GHN_CLASSIFY, io.k, qi, lane_id(), WAVE, stop);
+}
+
 // Outputs of a query with a non-finite coordinate.
 __device__ __forceinline__ void write_invalid(const IndexView& ix, const QueryIO& io, int64_t qi) {
-    const int lane = lane_id();
-    const int k = io.k;
-    if (lane < k) {
-        io.out_idx[qi * k + lane] = -1;
-        if (io.out_d2) io.out_d2[qi * k + lane] = __longlong_as_double(0x7ff8000000000000LL);
-    }
-    if (lane == 0) {
-        if (ix.task == GHN_CLASSIFY) ((int32_t*)io.out_pred)[qi] = -1;
-        else ((float*)io.out_pred)[qi] = __int_as_float(0x7fc00000);
-        if (io.out_stop_layer) io.out_stop_layer[qi] = -1;
-        if (io.out_cands) io.out_cands[qi] = 0;
-        if (io.out_probes) io.out_probes[qi] = 0;
-        if (io.out_rerank) io.out_rerank[qi] = 0;
-    }
+    write_no_answer(ix, io, qi, STOP_NONFINITE);
+}
+
+// A walk that ended without k rows of the index: the "no answer" row, and the
+// device's fault word records it.
+__device__ __forceinline__ void report_short_walk(const IndexView& ix, const QueryIO& io, int64_t qi) {
+    write_no_answer(ix, io, qi, STOP_SHORT);
+    if (lane_id() == 0 && io.faults) atomicOr(io.faults, GHN_WALK_SHORT);
 }
 
 // Which query this wave walks.  With a spatial query order each XCD (blocks are
@@ -558,9 +559,11 @@ __device__ __forceinline__ void finish_query(const IndexView& ix, const QueryIO&
                                              const WaveState& st) {
     const int lane = lane_id();
     const int k = io.k;
-    // every walk ends with k entries (k <= n and the box-covered stop); the guard only
-    // keeps a broken invariant from reading outside the targets
-    const bool have = lane < k && (uint32_t)st.bi < (uint64_t)ix.n;
+    if (ballot(lane < k && !entry_ok(st.bi, ix.n))) {
+        report_short_walk(ix, io, qi);
+        return;
+    }
+    const bool have = lane < k;
     if (lane < k) {
         io.out_idx[qi * k + lane] = st.bi;
         if (io.out_d2) io.out_d2[qi * k + lane] = st.bd;
