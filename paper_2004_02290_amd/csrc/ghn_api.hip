@@ -5,7 +5,6 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -59,40 +58,13 @@ ghn_status hip_fail(hipError_t e, const char* what) {
     return fail(GHN_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Static device arrays of the library.  In host code such an array's name only names
-// the symbol; its address on each GPU comes from hipGetSymbolAddress, looked up once
-// per device (with that device current) and kept here.
-constexpr int SYMBOL_DEVICES = 256;
-struct SymbolCache {
-    std::mutex mu;
-    void* ptr[SYMBOL_DEVICES] = {};
-};
-
-ghn_status symbol_address(const void* symbol, SymbolCache& cache, const char* what, void** out) {
-    *out = nullptr;
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, what);
-    if (dev < 0 || dev >= SYMBOL_DEVICES) return fail(GHN_E_UNSUPPORTED, "%s: device %d", what, dev);
-    std::lock_guard<std::mutex> lock(cache.mu);
-    if (!cache.ptr[dev]) {
-        void* p = nullptr;
-        if ((e = hipGetSymbolAddress(&p, symbol)) != hipSuccess) return hip_fail(e, what);
-        cache.ptr[dev] = p;
-    }
-    *out = cache.ptr[dev];
+// The device's walk fault word (GHN_WALK_SHORT).
+ghn_status fault_word(uint32_t** out) {
+    const hipError_t e = ghn::walk_fault_address(out);
+    if (e == hipErrorInvalidDevice) return fail(GHN_E_UNSUPPORTED, "walk fault word: device index above 255");
+    if (e != hipSuccess) return hip_fail(e, "walk fault word address");
     return GHN_OK;
 }
-
-// The walk fault word of each GPU (GHN_WALK_SHORT), padded to its own 256 bytes.
-__device__ __align__(256) uint32_t walk_fault_word[64];
-SymbolCache g_fault_word;
-
-ghn_status fault_word(uint32_t** out) {
-    return symbol_address(HIP_SYMBOL(walk_fault_word), g_fault_word, "walk fault word address", (void**)out);
-}
-
-__global__ void k_clear_word(uint32_t* w) { *w = 0u; }
 
 // Device memory of a build: hipMalloc'd blocks released together unless kept, or
 // (carve) 256-byte aligned pieces of a caller's buffer, which is never freed here.
@@ -1055,14 +1027,12 @@ ghn_status ghn_bruteforce(const ghn_index* index, const float* queries, int64_t 
 
 namespace {
 
-// Workspace of ghn_predict_noalloc.  In host code `scratch` only names the symbol;
-// its address on each GPU comes from symbol_address (hipGetSymbolAddress once per
-// device, with that device current).
-__device__ __align__(256) unsigned char scratch[GHN_NOALLOC_WS_BYTES];
-SymbolCache g_scratch;
-
+// Workspace of ghn_predict_noalloc: the device's static array (ghn_arrays.hip).
 ghn_status scratch_address(void** out) {
-    return symbol_address(HIP_SYMBOL(scratch), g_scratch, "ghn_predict_noalloc: address of the workspace array", out);
+    const hipError_t e = ghn::noalloc_workspace(out);
+    if (e == hipErrorInvalidDevice) return fail(GHN_E_UNSUPPORTED, "ghn_predict_noalloc: device index above 255");
+    if (e != hipSuccess) return hip_fail(e, "ghn_predict_noalloc: address of the workspace array");
+    return GHN_OK;
 }
 
 }  // namespace
@@ -1076,10 +1046,7 @@ ghn_status ghn_walk_faults(uint32_t* out_flags, int clear, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     uint32_t v = 0;
     hipError_t e = hipMemcpyAsync(&v, w, sizeof v, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess && clear) {
-        hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(1), 0, s, w);
-        e = hipGetLastError();
-    }
+    if (e == hipSuccess && clear) e = ghn::launch_clear_word(w, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "ghn_walk_faults");
     *out_flags = v;

@@ -288,6 +288,12 @@ hipError_t launch_status();                       // hipGetLastError after launc
 bool log_enabled();
 void log_line(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
 
+// Static device arrays (ghn_arrays.hip): this device's address of each, looked up once
+// per device with hipGetSymbolAddress (hipErrorInvalidDevice above device 255).
+hipError_t noalloc_workspace(void** out);        // GHN_NOALLOC_WS_BYTES for ghn_predict_noalloc
+hipError_t walk_fault_address(uint32_t** out);   // the walk fault word
+hipError_t launch_clear_word(uint32_t* w, hipStream_t s);
+
 // ---------------------------------------------------------------------------------------
 // Host-side launchers (defined in the .hip files).
 hipError_t launch_cells_minmax(const void* pts, int64_t n, int32_t f, int32_t dtype, const float* a,
