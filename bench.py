@@ -41,10 +41,11 @@ def describe(prob, stop_name):
 
 # Sources each walk kernel is compiled from (its traffic figure is void once they change).
 KERNEL_SOURCES = {
-    "k_predict_dense": ["ghn_predict.hip", "ghn_walk_dense.h", "ghn_walk.h", "ghn_internal.h"],
-    "k_predict_tree": ["ghn_tree.hip", "ghn_walk_tree.h", "ghn_walk.h", "ghn_internal.h"],
-    "k_predict_group": ["ghn_group.hip", "ghn_walk.h", "ghn_internal.h"],
-    "k_predict_batched": ["ghn_batch.hip", "ghn_walk_dense.h", "ghn_walk_tree.h", "ghn_walk.h", "ghn_internal.h"],
+    "k_predict_dense": ["ghn_predict.hip", "ghn_walk_dense.h", "ghn_walk.h", "ghn_guard.h", "ghn_internal.h"],
+    "k_predict_tree": ["ghn_tree.hip", "ghn_walk_tree.h", "ghn_walk.h", "ghn_guard.h", "ghn_internal.h"],
+    "k_predict_group": ["ghn_group.hip", "ghn_walk.h", "ghn_guard.h", "ghn_internal.h"],
+    "k_predict_batched": ["ghn_batch.hip", "ghn_walk_dense.h", "ghn_walk_tree.h", "ghn_walk.h", "ghn_guard.h",
+                          "ghn_internal.h"],
 }
 
 
@@ -108,6 +109,7 @@ def write_traffic(pmc_dir: str, workloads, out_file: str = TRAFFIC_FILE) -> dict
     write_copy (FETCH_SIZE / WRITE_SIZE of `bench.py --copy-calib`) and
     fetch_<workload>, write_<workload> (the same counters over a bench run).  The
     counters (KiB per dispatch) are scaled by what they read for the 1 GiB copy.
+    Entries of other workloads already in the file are kept.
     """
     import csv
 
@@ -119,10 +121,16 @@ def write_traffic(pmc_dir: str, workloads, out_file: str = TRAFFIC_FILE) -> dict
     cf, cw = values("fetch_copy", "copyBuffer"), values("write_copy", "copyBuffer")
     fetch_scale = copy_bytes / (float(np.mean(cf)) * 1024.0)
     write_scale = copy_bytes / (float(np.mean(cw)) * 1024.0)
-    out = {"copy_calibration": {"bytes": copy_bytes, "fetch_kib": float(np.mean(cf)), "write_kib": float(np.mean(cw)),
-                                "fetch_scale": fetch_scale, "write_scale": write_scale}}
+    try:
+        with open(out_file) as fh:
+            out = json.load(fh)
+    except (OSError, ValueError):
+        out = {}
+    out["copy_calibration"] = {"bytes": copy_bytes, "fetch_kib": float(np.mean(cf)), "write_kib": float(np.mean(cw)),
+                               "fetch_scale": fetch_scale, "write_scale": write_scale}
     for w in workloads:
-        for form, kname in (("fp32", "k_predict_dense"), ("fp32", "k_predict_tree"), ("bf16", "k_predict_group")):
+        for form, kname in (("fp32", "k_predict_dense"), ("fp32", "k_predict_tree"), ("bf16", "k_predict_group"),
+                            ("fp32_batched", "k_predict_batched")):
             fv, wv = values("fetch_" + w, kname), values("write_" + w, kname)
             if not fv or not wv:
                 continue
@@ -360,7 +368,9 @@ def bench_multi(args, ghn, W, torch):
                                "sum m = %d queries, k in {1,5,10,20}, majority vote, %s stop" % (
                                    len(probs), sum(p.n for p in probs), M, args.stop.upper()),
                    "problems": len(probs), "sum_n": sum(p.n for p in probs), "sum_m": M, "form": best},
-        "roofline": hbm_roofline(alg_bytes, ext_bytes, B["ms"], None,
+        "roofline": hbm_roofline(alg_bytes, ext_bytes, B["ms"],
+                                 measured_traffic("multi3d", "fp32_batched") if best.startswith("fp32_batched")
+                                 else None,
                                  "k_predict_batched" if "batched" in best else "per-index kernels"),
         "forms": {n: {"qps": M / (v["ms"] * 1e-3), "ms_per_step": v["ms"],
                       "step_ms_p10_p50_p90": [float(np.percentile(v["per"], 10)), float(np.median(v["per"])),
