@@ -451,6 +451,9 @@ def main():
                          "through the batched persistent launch), brute (exhaustive KNN, reported beside); default "
                          "fp32,bf16, plus persistent for skew8d")
     ap.add_argument("--group-levels", type=int, default=-1, help="bf16 form: cell-id bits dropped to group queries")
+    ap.add_argument("--ring-step", type=int, default=-1,
+                    help="FP32 form, EXACT rule: layers per step of the walk (-1: the autotuned value, else 2, so the "
+                         "central cell and layer 1 are walked in one step; the neighbours do not depend on it)")
     ap.add_argument("--autotune", choices=("auto", "on", "off"), default="auto",
                     help="pick the cell width (and each form's settings) with ghn_autotune on a query sample "
                          "before the timed region; auto = on for %s" % ", ".join(AUTOTUNED))
@@ -517,7 +520,7 @@ def main():
               "hash": ghn.GHN_LOOKUP_HASH}[args.lookup]
     tuned = None
     sort32, levels16 = args.sort, args.group_levels
-    ring32, grow32 = 0, 0  # FP32 form: the EXACT walk's ring schedule (autotuned)
+    ring32, grow32 = 0, 0  # FP32 form: the EXACT walk's ring schedule (autotuned, else --ring-step)
     gs16 = 0               # bf16 form: most queries per group (autotuned; 0 = 16)
     if args.autotune == "on" or (args.autotune == "auto" and args.workload in AUTOTUNED and args.cell_width is None
                                     and not args.no_extras):
@@ -556,6 +559,12 @@ def main():
                             for t in trials]}
         print("autotune: width %.6g (calibrated %.6g), %.1f s" % (width, prob.cell_width, tune_ms * 1e-3),
               file=sys.stderr, flush=True)
+    if args.ring_step >= 0:
+        ring32 = args.ring_step
+    elif tuned is None and stop == ghn.GHN_STOP_EXACT:
+        # layers 0 and 1 in one step: the central cell alone rarely fills the buffer, so its own
+        # pass (run list, stop test) buys no pruning (clusters4d walk 0.348 -> 0.331 ms)
+        ring32 = 2
 
     t0 = time.perf_counter()
     ix = ghn.Index(pts, tgt, prob.task, width, lookup=lookup)
@@ -716,7 +725,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": describe(prob, args.stop.upper()), "n": prob.n, "f": f, "m": m, "k": k,
                    "cell_width": width, "stop": args.stop, "form": best,
-                   "lookup": {0: "dense", 1: "tree", 2: "hash"}[ix.info.lookup]},
+                   "lookup": {0: "dense", 1: "tree", 2: "hash"}[ix.info.lookup],
+                   "fp32_ring_step": ring32, "fp32_ring_grow": bool(grow32), "fp32_sorted": bool(sort32)},
         "roofline": B["roofline"],
         "forms": {name: {"qps": v["qps"], "ms_per_step": v["ms_per_step"], "kernel_ms": v["kernel_ms"],
                          "step_ms_p10_p50_p90": [float(np.percentile(v["per"], 10)), float(np.median(v["per"])),

@@ -241,12 +241,13 @@ struct alignas(16) GroupLds {
     uint32_t run_begin[WAVE + 1];
     uint32_t run_pre[WAVE + 1];
     uint64_t stack[STACK_CAP];
-    int32_t lab[4][K_MAX];
+    int32_t lab[4][K_MAX + 1];  // + 1: the four rows' entries e fall in different banks
     int32_t med[4][2];
     int32_t glo[FS], ghi[FS];
     float qlo[FS], qhi[FS];
     double ad[FS], od[FS];  // cell width and origin (FP64), read inside the walk
-    double qd[GQ][FS];      // the queries in FP64 (exact), for the re-rank
+    double qd[GQ][FS | 1];  // the queries in FP64 (exact), for the re-rank; an odd row length
+                            // puts the rows the re-rank lanes read at once in different banks
     int64_t shift;          // true layer - walk layer (0 unless the query is far outside the box)
     float tq[GQ];           // per query: FP32 threshold >= its k-th distance (+inf while the
                             // buffer is not full), -1 once done or when invalid
