@@ -458,10 +458,13 @@ ghn_status ghn_index_load(const void* buffer, size_t bytes, void* stream, ghn_in
 /* Insert n_new training points (DEVICE, n_new x f, float32 or bf16 bits) and their
  * targets (DEVICE, int32 labels or float32 values as the index's task) into an
  * index: Algorithm 1 appends every point to its cell.  The new points get row
- * ids n .. n + n_new - 1.  The index is rebuilt with its cell widths, origin and
- * lookup choice (GHN_LOOKUP_AUTO may pick the other lookup if the occupied box
- * grew), so the result equals ghn_build on all points; the cost is one build of
- * n + n_new points.  The handle stays valid (its device memory is replaced:
+ * ids n .. n + n_new - 1.  A dense-table or hash index sorts only the new points
+ * and merges them into its cell order (each after the points already in its
+ * cell), then rebuilds its cell tables from that order; a tree index (Morton
+ * order), or one whose enlarged box needs the tree, is rebuilt from all points.
+ * Either way the index keeps its cell widths, origin and lookup choice
+ * (GHN_LOOKUP_AUTO may pick the other lookup if the occupied box grew) and
+ * equals ghn_build on all points.  The handle stays valid (its device memory is replaced:
  * batches prepared with it must be prepared again); on error the index is
  * unchanged.  Synchronises `stream`.  Errors: as ghn_build. */
 ghn_status ghn_insert(ghn_index* index, const void* points, int64_t n_new, int32_t dtype, const void* targets,

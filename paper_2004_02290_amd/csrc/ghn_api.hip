@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <utility>
 #include <vector>
@@ -504,13 +505,23 @@ ghn_status ghn_build(const void* points, int64_t n, int32_t f, int32_t dtype, co
 
 namespace {
 
+// Points already in cell order (an insert's merge): FP32 coordinates and row ids.
+// The build then computes their keys, which come out ascending, and skips the sort.
+struct Presorted {
+    const float* spts;
+    const int32_t* sid;
+};
+
 // The build (Eq. 1, Algorithm 1).  Temporaries come from `tmp`, the index's memory
 // from `keep` (hipMalloc'd, or carved from caller buffers).  With `size_only` set,
 // only the cell range is computed and *size_only receives the index's device bytes
-// (index_bytes_bound for the lookup the build would use); nothing is kept.
+// (index_bytes_bound for the lookup the build would use); nothing is kept.  With
+// `pre` the points come in cell order; only the dense-table and hash lookups take
+// them (the tree's Morton order differs): GHN_E_UNSUPPORTED otherwise.
 ghn_status build_impl(const void* points, int64_t n, int32_t f, int32_t dtype, const void* targets, int32_t task,
                       const float* cell_width, int32_t n_width, const float* origin, const ghn_build_opts* bopts,
-                      void* stream, DevPool& tmp, DevPool& keep, size_t* size_only, ghn_index** out) {
+                      void* stream, DevPool& tmp, DevPool& keep, size_t* size_only, ghn_index** out,
+                      const Presorted* pre = nullptr) {
     using namespace ghn;
     if (!out && !size_only) return fail(GHN_E_INVALID_ARG, "ghn_build: out is NULL");
     if (out) *out = nullptr;
@@ -549,7 +560,8 @@ ghn_status build_impl(const void* points, int64_t n, int32_t f, int32_t dtype, c
     Small* d_small = nullptr;
     if ((e = tmp.alloc((void**)&d_small, sizeof(Small))) != hipSuccess) return no_memory(tmp, "ghn_build", "cell range");
     if ((e = hipMemcpyAsync(d_small, &h, sizeof h, hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e, "ghn_build: upload");
-    if ((e = launch_cells_minmax(points, n, f, dtype, d_small->a, d_small->o, d_small->minmax, d_small->flags, s)) != hipSuccess)
+    if ((e = launch_cells_minmax(pre ? (const void*)pre->spts : points, n, f, pre ? (int32_t)GHN_F32 : dtype, d_small->a,
+                                 d_small->o, d_small->minmax, d_small->flags, s)) != hipSuccess)
         return hip_fail(e, "ghn_build: cell range kernel");
     if ((e = hipMemcpyAsync(&h, d_small, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess) return hip_fail(e, "ghn_build: readback");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "ghn_build: sync");
@@ -587,6 +599,8 @@ ghn_status build_impl(const void* points, int64_t n, int32_t f, int32_t dtype, c
         return fail(GHN_E_KEY_OVERFLOW, "ghn_build: the occupied box holds more than 2^62 cells, too many for the "
                     "hash keys (use the tree lookup or a larger cell width)");
     iv.lookup = lookup;
+    if (pre && lookup == GHN_LOOKUP_TREE)
+        return fail(GHN_E_UNSUPPORTED, "ghn_build: points in cell order need the dense table or the hash lookup");
     const size_t need = index_bytes_bound(n, f, lookup, box);
     if (size_only) {
         *size_only = need;
@@ -595,6 +609,16 @@ ghn_status build_impl(const void* points, int64_t n, int32_t f, int32_t dtype, c
     if (keep.carving() && keep.cap < need)
         return fail(GHN_E_WORKSPACE, "ghn_build: index storage of %zu bytes needed (ghn_index_bytes_for), %zu given",
                     need, keep.cap);
+    // memory the library allocates for the index is one block of that size, carved like
+    // caller storage: one allocation, and one release when the index goes
+    std::unique_ptr<DevPool> block_pool;
+    DevPool* kp = &keep;
+    if (!keep.carving()) {
+        void* block = nullptr;
+        if (keep.alloc(&block, need)) return no_memory(keep, "ghn_build", "index");
+        block_pool.reset(new DevPool(block, need, "index block"));
+        kp = block_pool.get();
+    }
     int nbits = 0;
     if (lookup == GHN_LOOKUP_DENSE) {
         iv.box_cells = box;
@@ -620,12 +644,17 @@ ghn_status build_impl(const void* points, int64_t n, int32_t f, int32_t dtype, c
     float* spts;
     int32_t* sid;
     void* tg;
-    if (keep.alloc((void**)&spts, (size_t)n * f * 4) || keep.alloc((void**)&sid, (size_t)n * 4) ||
-        keep.alloc(&tg, (size_t)n * 4))
-        return no_memory(keep, "ghn_build", "index");
+    if (kp->alloc((void**)&spts, (size_t)n * f * 4) || kp->alloc((void**)&sid, (size_t)n * 4) ||
+        kp->alloc(&tg, (size_t)n * 4))
+        return no_memory(*kp, "ghn_build", "index");
     const uint64_t* skeys = nullptr;
     const uint32_t* perm = nullptr;
-    if (lookup == GHN_LOOKUP_DENSE || lookup == GHN_LOOKUP_HASH || nbits <= 64) {
+    if (pre) {
+        // row-major keys (last dimension fastest) of points in cell order are ascending
+        if ((e = launch_dense_keys(pre->spts, n, f, GHN_F32, iv, keys, vals, s)) != hipSuccess)
+            return hip_fail(e, "ghn_build: keys");
+        skeys = keys;
+    } else if (lookup == GHN_LOOKUP_DENSE || lookup == GHN_LOOKUP_HASH || nbits <= 64) {
         e = lookup != GHN_LOOKUP_TREE ? launch_dense_keys(points, n, f, dtype, iv, keys, vals, s)
                                        : launch_morton_keys(points, n, dtype, iv, nbits, 0, nullptr, keys, vals, s);
         if (e != hipSuccess) return hip_fail(e, "ghn_build: keys");
@@ -653,7 +682,13 @@ ghn_status build_impl(const void* points, int64_t n, int32_t f, int32_t dtype, c
             std::swap(va, vb);
         }
     }
-    if ((e = launch_gather_points(points, n, f, dtype, perm, spts, sid, s)) != hipSuccess) return hip_fail(e, "ghn_build: gather");
+    if (pre) {
+        if ((e = hipMemcpyAsync(spts, pre->spts, (size_t)n * f * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(sid, pre->sid, (size_t)n * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+            return hip_fail(e, "ghn_build: points in cell order");
+    } else if ((e = launch_gather_points(points, n, f, dtype, perm, spts, sid, s)) != hipSuccess) {
+        return hip_fail(e, "ghn_build: gather");
+    }
     if ((e = hipMemcpyAsync(tg, targets, (size_t)n * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(e, "ghn_build: targets");
     iv.spts = spts; iv.sid = sid; iv.targets = tg;
 
@@ -664,8 +699,8 @@ ghn_status build_impl(const void* points, int64_t n, int32_t f, int32_t dtype, c
         iv.c0[j] = (float)((double)o[j] + ((double)iv.cmin[j] + (double)iv.cmax[j] + 1.0) * 0.5 * (double)a[j]);
     uint16_t* srec;
     float* sxn;
-    if (keep.alloc((void**)&srec, (size_t)n * 2 * iv.sp * 2) || keep.alloc((void**)&sxn, (size_t)n * 4))
-        return no_memory(keep, "ghn_build", "screen records");
+    if (kp->alloc((void**)&srec, (size_t)n * 2 * iv.sp * 2) || kp->alloc((void**)&sxn, (size_t)n * 4))
+        return no_memory(*kp, "ghn_build", "screen records");
     if ((e = launch_screen_records(iv, srec, sxn, s)) != hipSuccess) return hip_fail(e, "ghn_build: screen records");
     iv.srec = srec;
     iv.sxn = sxn;
@@ -688,8 +723,8 @@ ghn_status build_impl(const void* points, int64_t n, int32_t f, int32_t dtype, c
     const int64_t ncell = (int64_t)last[0] + last[1];
     uint32_t* cf;
     int32_t* coord;
-    if (keep.alloc((void**)&cf, (size_t)(ncell + 1) * 4) || keep.alloc((void**)&coord, (size_t)ncell * f * 4))
-        return no_memory(keep, "ghn_build", "cell list");
+    if (kp->alloc((void**)&cf, (size_t)(ncell + 1) * 4) || kp->alloc((void**)&coord, (size_t)ncell * f * 4))
+        return no_memory(*kp, "ghn_build", "cell list");
     if ((e = launch_cell_list(heads, rank, n, iv, cf, coord, s)) != hipSuccess) return hip_fail(e, "ghn_build: cell list");
     const uint32_t n32 = (uint32_t)n;
     if ((e = hipMemcpyAsync(cf + ncell, &n32, 4, hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e, "ghn_build: cell end");
@@ -706,8 +741,8 @@ ghn_status build_impl(const void* points, int64_t n, int32_t f, int32_t dtype, c
         ++top;
     }
     int32_t *nlo = nullptr, *nhi = nullptr;
-    if (total > 0 && (keep.alloc((void**)&nlo, (size_t)total * f * 4) || keep.alloc((void**)&nhi, (size_t)total * f * 4)))
-        return no_memory(keep, "ghn_build", "tree");
+    if (total > 0 && (kp->alloc((void**)&nlo, (size_t)total * f * 4) || kp->alloc((void**)&nhi, (size_t)total * f * 4)))
+        return no_memory(*kp, "ghn_build", "tree");
     for (int L = 1; L <= top; ++L) {
         const int32_t* clo = L == 1 ? coord : nlo + off[L - 1] * f;
         const int32_t* chi = L == 1 ? coord : nhi + off[L - 1] * f;
@@ -730,8 +765,8 @@ ghn_status build_impl(const void* points, int64_t n, int32_t f, int32_t dtype, c
         while (cap < 2 * (uint64_t)ncell) cap <<= 1;
         uint64_t* hk;
         uint32_t* hv;
-        if (keep.alloc((void**)&hk, (size_t)cap * 8) || keep.alloc((void**)&hv, (size_t)cap * 4))
-            return no_memory(keep, "ghn_build", "hash table");
+        if (kp->alloc((void**)&hk, (size_t)cap * 8) || kp->alloc((void**)&hv, (size_t)cap * 4))
+            return no_memory(*kp, "ghn_build", "hash table");
         if ((e = launch_hash_build(skeys, cf, ncell, hk, hv, cap - 1, s)) != hipSuccess) return hip_fail(e, "ghn_build: hash table");
         iv.hkeys = hk;
         iv.hvals = hv;
@@ -740,7 +775,7 @@ ghn_status build_impl(const void* points, int64_t n, int32_t f, int32_t dtype, c
     }
     if (lookup == GHN_LOOKUP_DENSE) {
         uint32_t* cs;
-        if (keep.alloc((void**)&cs, (size_t)(box + 1) * 4)) return no_memory(keep, "ghn_build", "table");
+        if (kp->alloc((void**)&cs, (size_t)(box + 1) * 4)) return no_memory(*kp, "ghn_build", "table");
         if ((e = launch_dense_cell_start(skeys, n, box, cs, s)) != hipSuccess) return hip_fail(e, "ghn_build: table");
         iv.cell_start = cs;
         table_bytes += (size_t)(box + 1) * 4;
@@ -749,7 +784,7 @@ ghn_status build_impl(const void* points, int64_t n, int32_t f, int32_t dtype, c
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "ghn_build: sync");
 
     ghn::IndexView* ivd;
-    if (keep.alloc((void**)&ivd, sizeof(IndexView))) return no_memory(keep, "ghn_build", "index view");
+    if (kp->alloc((void**)&ivd, sizeof(IndexView))) return no_memory(*kp, "ghn_build", "index view");
     if ((e = hipMemcpyAsync(ivd, &iv, sizeof iv, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
         return hip_fail(e, "ghn_build: index view upload");
@@ -771,7 +806,7 @@ ghn_status build_impl(const void* points, int64_t n, int32_t f, int32_t dtype, c
                            (size_t)n * 2 * iv.sp * 2 + (size_t)n * 4;
     keep.release(ix->allocs);
     ix->want_lookup = want_lookup;
-    ix->info.device_bytes = keep.carving() ? keep.used : ix->info.device_bytes;
+    ix->info.device_bytes = keep.carving() ? keep.used : need;
     ghn::log_line("build n=%lld f=%d dtype=%d task=%d lookup=%d cells=%lld max_occupancy=%lld device_bytes=%zu%s",
                   (long long)n, f, dtype, task, lookup, (long long)iv.num_cells, (long long)h.stats[1],
                   ix->info.device_bytes, keep.carving() ? " (caller storage)" : "");
@@ -1113,6 +1148,94 @@ hipError_t original_points(const ghn_index* index, float* out, hipStream_t s) {
     return ghn::launch_unsort_points(index->view.spts, index->view.sid, index->info.n, index->info.f, out, s);
 }
 
+// Insert by merge (Algorithm 1 appends each new point to its cell): only the new points
+// are sorted; they are merged into the index's cell order, and the cell structures are
+// rebuilt from the merged order.  The result equals a build of all the points.  Needs
+// an index in row-major cell order (dense table or hash) and an enlarged index that
+// takes one of those lookups with keys in 64 bits: GHN_E_UNSUPPORTED otherwise, with
+// nothing changed (the caller then rebuilds from all the points).
+ghn_status insert_merge(const ghn_index* index, const void* points, int64_t nn, int32_t dtype, const void* targets,
+                        hipStream_t s, ghn_index** fresh) {
+    using namespace ghn;
+    *fresh = nullptr;
+    const IndexView& iv = index->view;
+    if (iv.lookup == LOOKUP_TREE) return fail(GHN_E_UNSUPPORTED, "ghn_insert: the tree index is in Morton order");
+    const int64_t n = index->info.n, total = n + nn;
+    const int32_t f = index->info.f;
+    hipError_t e;
+    // one device block for the merge's temporaries and the build's (one allocation and
+    // one release instead of one per array)
+    const size_t un = (size_t)n, unn = (size_t)nn, ut = (size_t)total;
+    const size_t merge_bytes = up256(sizeof(BuildSmall)) + up256(un * 8) + up256(un * 4) + 2 * up256(unn * 8) +
+                               2 * up256(unn * 4) + up256(radix_sort_temp_bytes(nn)) + up256(unn * f * 4) +
+                               up256(ut * f * 4) + 2 * up256(ut * 4) + 16 * ALIGN_SLACK;
+    const size_t build_bytes = build_ws_bytes(total);
+    DevPool block;
+    void* base = nullptr;
+    if (block.alloc(&base, merge_bytes + build_bytes)) return no_memory(block, "ghn_insert", "merge workspace");
+    DevPool tmp(base, merge_bytes, "merge workspace");
+    // 1. cell range of the new points
+    BuildSmall h;
+    std::memset(&h, 0, sizeof h);
+    for (int j = 0; j < f; ++j) { h.a[j] = index->info.cell_width[j]; h.o[j] = index->info.origin[j]; }
+    for (int j = 0; j < F_MAX; ++j) { h.minmax[j] = INT32_MAX; h.minmax[F_MAX + j] = INT32_MIN; }
+    BuildSmall* d_small = nullptr;
+    if (tmp.alloc((void**)&d_small, sizeof h)) return no_memory(tmp, "ghn_insert", "cell range");
+    if ((e = hipMemcpyAsync(d_small, &h, sizeof h, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = launch_cells_minmax(points, nn, f, dtype, d_small->a, d_small->o, d_small->minmax, d_small->flags, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(&h, d_small, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "ghn_insert: cell range");
+    if (h.flags[0]) return fail(GHN_E_NONFINITE, "ghn_insert: a new point has a NaN or infinite coordinate");
+    if (h.flags[1]) return fail(GHN_E_KEY_OVERFLOW, "ghn_insert: a cell id is outside (-2^27, 2^27)");
+    // 2. row-major keys over the box of all the points (last dimension fastest)
+    IndexView mv = iv;
+    mv.lookup = LOOKUP_HASH;  // the keys kernel takes the 64-bit strides
+    uint64_t box = 1;
+    for (int j = f - 1; j >= 0; --j) {
+        mv.cmin[j] = std::min(iv.cmin[j], h.minmax[j]);
+        mv.cmax[j] = std::max(iv.cmax[j], h.minmax[F_MAX + j]);
+        mv.hstride[j] = box;
+        const uint64_t w = (uint64_t)((int64_t)mv.cmax[j] - mv.cmin[j] + 1);
+        if (box > (uint64_t(1) << 62) / w) return fail(GHN_E_UNSUPPORTED, "ghn_insert: keys wider than 64 bits");
+        box *= w;
+    }
+    int nbits = 0;
+    while (nbits < 64 && (uint64_t(1) << nbits) < box) ++nbits;
+    // 3. keys of the index's points (ascending) and of the new points (sorted), merge
+    uint64_t *okeys, *nk, *nk2;
+    uint32_t *ovals, *nv, *nv2;
+    void* rtemp;
+    float *npts, *mpts;
+    int32_t* msid;
+    void* mtg;
+    if (tmp.alloc((void**)&okeys, (size_t)n * 8) || tmp.alloc((void**)&ovals, (size_t)n * 4) ||
+        tmp.alloc((void**)&nk, (size_t)nn * 8) || tmp.alloc((void**)&nk2, (size_t)nn * 8) ||
+        tmp.alloc((void**)&nv, (size_t)nn * 4) || tmp.alloc((void**)&nv2, (size_t)nn * 4) ||
+        tmp.alloc(&rtemp, radix_sort_temp_bytes(nn)) || tmp.alloc((void**)&npts, (size_t)nn * f * 4) ||
+        tmp.alloc((void**)&mpts, (size_t)total * f * 4) || tmp.alloc((void**)&msid, (size_t)total * 4) ||
+        tmp.alloc(&mtg, (size_t)total * 4))
+        return no_memory(tmp, "ghn_insert", "merge");
+    bool alt = false;
+    if ((e = launch_dense_keys(iv.spts, n, f, GHN_F32, mv, okeys, ovals, s)) != hipSuccess ||
+        (e = launch_dense_keys(points, nn, f, dtype, mv, nk, nv, s)) != hipSuccess ||
+        (e = radix_sort_pairs(nk, nv, nk2, nv2, nn, nbits, rtemp, &alt, s)) != hipSuccess ||
+        (e = launch_widen_points(points, nn * f, dtype, npts, s)) != hipSuccess ||
+        (e = launch_merge_points(okeys, iv.spts, iv.sid, n, alt ? nk2 : nk, alt ? nv2 : nv, npts, nn, f, mpts, msid,
+                                 s)) != hipSuccess ||
+        (e = hipMemcpyAsync(mtg, iv.targets, (size_t)n * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync((char*)mtg + (size_t)n * 4, targets, (size_t)nn * 4, hipMemcpyDeviceToDevice, s)) !=
+            hipSuccess)
+        return hip_fail(e, "ghn_insert: merge");
+    // 4. the cell structures of the merged order
+    const Presorted pre = {mpts, msid};
+    const ghn_build_opts bo = {index->want_lookup};
+    DevPool btmp((char*)base + merge_bytes, build_bytes, "build workspace"), keep;
+    return build_impl(mpts, total, f, GHN_F32, mtg, index->info.task, index->info.cell_width, f, index->info.origin,
+                      &bo, s, btmp, keep, nullptr, fresh, &pre);
+}
+
 // Replace the contents of `dst` by those of `src` (which is consumed).
 void adopt(ghn_index* dst, ghn_index* src) {
     for (void* p : dst->allocs) ghn::device_free(p);
@@ -1211,6 +1334,19 @@ ghn_status ghn_insert(ghn_index* index, const void* points, int64_t n_new, int32
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "ghn_insert: pending HIP error");
     hipStream_t s = (hipStream_t)stream;
+    const int32_t dt = index->info.dtype == GHN_BF16 && dtype == GHN_BF16 ? GHN_BF16 : GHN_F32;
+    {
+        ghn_index* merged = nullptr;
+        const ghn_status st = insert_merge(index, points, n_new, dtype, targets, s, &merged);
+        if (st == GHN_OK) {
+            adopt(index, merged);
+            index->info.dtype = dt;
+            log_line("insert n=%lld n_new=%lld: merged into the cell order", (long long)n, (long long)n_new);
+            return GHN_OK;
+        }
+        if (st != GHN_E_UNSUPPORTED) return st;  // the index is left as it was
+    }
+    // a tree index (Morton order), or an enlarged box beyond the merge: rebuild from all points
     DevPool tmp;
     float* pts = nullptr;
     void* tg = nullptr;
@@ -1227,9 +1363,9 @@ ghn_status ghn_insert(ghn_index* index, const void* points, int64_t n_new, int32
     const ghn_status st = ghn_build_ex(pts, total, f, GHN_F32, tg, index->info.task, index->info.cell_width, f,
                                        index->info.origin, &bo, stream, &fresh);
     if (st != GHN_OK) return st;  // the index is left as it was
-    const int32_t dt = index->info.dtype == GHN_BF16 && dtype == GHN_BF16 ? GHN_BF16 : GHN_F32;
     adopt(index, fresh);
     index->info.dtype = dt;
+    log_line("insert n=%lld n_new=%lld: rebuilt from all points", (long long)n, (long long)n_new);
     return GHN_OK;
 }
 

@@ -426,6 +426,61 @@ hipError_t launch_dense_cell_start(const uint64_t* sorted_keys, int64_t n, int64
     return launch_status();
 }
 
+// An insert's merge (Algorithm 1 appends every new point to its cell): the index's
+// points, in cell order with ascending keys `okeys`, and the new points, sorted by key
+// (`nkeys`, ties in row order, `nperm` their rows), into one cell order.  A new point
+// follows the points already in its cell (their row ids are smaller), which is the
+// order a build of all the points gives.  Each element finds its place with a binary
+// search in the other list.
+__global__ __launch_bounds__(BT) void k_merge_points(const uint64_t* __restrict__ okeys, const float* __restrict__ opts,
+                                                     const int32_t* __restrict__ osid, int64_t n,
+                                                     const uint64_t* __restrict__ nkeys,
+                                                     const uint32_t* __restrict__ nperm, const float* __restrict__ npts,
+                                                     int64_t nn, int32_t f, float* __restrict__ mpts,
+                                                     int32_t* __restrict__ msid) {
+    for (int64_t i = blockIdx.x * (int64_t)BT + threadIdx.x; i < n + nn; i += (int64_t)gridDim.x * BT) {
+        int64_t pos;
+        const float* src;
+        int32_t id;
+        if (i < n) {
+            // new points strictly below this key come first
+            const uint64_t key = okeys[i];
+            int64_t lo = 0, hi = nn;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (nkeys[mid] < key) lo = mid + 1;
+                else hi = mid;
+            }
+            pos = i + lo;
+            src = opts + i * f;
+            id = osid[i];
+        } else {
+            // the index's points at or below this key come first
+            const int64_t j = i - n;
+            const uint64_t key = nkeys[j];
+            int64_t lo = 0, hi = n;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (okeys[mid] <= key) lo = mid + 1;
+                else hi = mid;
+            }
+            pos = j + lo;
+            src = npts + (int64_t)nperm[j] * f;
+            id = (int32_t)(n + nperm[j]);
+        }
+        for (int c = 0; c < f; ++c) mpts[pos * f + c] = src[c];
+        msid[pos] = id;
+    }
+}
+
+hipError_t launch_merge_points(const uint64_t* okeys, const float* opts, const int32_t* osid, int64_t n,
+                               const uint64_t* nkeys, const uint32_t* nperm, const float* npts, int64_t nn, int32_t f,
+                               float* mpts, int32_t* msid, hipStream_t s) {
+    hipLaunchKernelGGL(k_merge_points, dim3(grid_for(n + nn, BT)), dim3(BT), 0, s, okeys, opts, osid, n, nkeys, nperm,
+                       npts, nn, f, mpts, msid);
+    return launch_status();
+}
+
 // The index's occupied cells in its cell order: ids and point counts per cell, and for
 // every training point (original row id) the position of its cell.
 __global__ void k_index_cells(const uint32_t* __restrict__ cell_first, const int32_t* __restrict__ coord,

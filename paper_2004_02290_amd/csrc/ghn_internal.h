@@ -310,6 +310,9 @@ hipError_t launch_gather_points(const void* pts, int64_t n, int32_t f, int32_t d
 hipError_t launch_screen_records(const IndexView& iv, uint16_t* rec, float* xn, hipStream_t s);
 hipError_t launch_unsort_points(const float* spts, const int32_t* sid, int64_t n, int32_t f, float* out, hipStream_t s);
 hipError_t launch_widen_points(const void* pts, int64_t count, int32_t dtype, float* out, hipStream_t s);
+hipError_t launch_merge_points(const uint64_t* okeys, const float* opts, const int32_t* osid, int64_t n,
+                               const uint64_t* nkeys, const uint32_t* nperm, const float* npts, int64_t nn, int32_t f,
+                               float* mpts, int32_t* msid, hipStream_t s);
 hipError_t measure_cells(const void* pts, int64_t n, int32_t f, int32_t dtype, float* width, float* origin,
                          int64_t* splits, bool* nonfinite, hipStream_t s);
 hipError_t launch_dense_cell_start(const uint64_t* sorted_keys, int64_t n, int64_t box_cells,

@@ -271,6 +271,42 @@ def test_insert_matches_fresh_build(ghn):
         ix.insert(_dev(all_pts[:5, :3]), _dev(all_tgt[:5]))
 
 
+@pytest.mark.parametrize("lookup", [None, 2, 1])
+def test_insert_merge_paths(ghn, lookup, capfd, monkeypatch):
+    """Dense-table and hash indexes take the new points by a merge into their cell order
+    (Algorithm 1's append; only the new points are sorted), a tree index by a rebuild;
+    either way the index equals a build of all the points: the same cells, the same
+    point order, and the same answers as the oracle."""
+    prob = W.make("clusters4d", n=40_000, m=500)
+    pts, tgt = prob.points, prob.targets
+    # one chunk grows the box below the occupied cells, one lies inside it
+    extra = (pts[:3000] * 1.5 - 0.4).astype(np.float32)
+    all_pts = np.concatenate([pts, extra])
+    all_tgt = np.concatenate([tgt, tgt[:3000] + 1])
+    cut = [0, 25_000, 40_000, all_pts.shape[0]]
+    ix = ghn.Index(_dev(all_pts[:cut[1]]), _dev(all_tgt[:cut[1]]), prob.task, prob.cell_width, lookup=lookup)
+    monkeypatch.setenv("GHN_LOG", "1")
+    capfd.readouterr()
+    for a, b in zip(cut[1:-1], cut[2:]):
+        ix.insert(_dev(all_pts[a:b]), _dev(all_tgt[a:b]))
+    log = capfd.readouterr().err
+    monkeypatch.delenv("GHN_LOG")
+    how = "rebuilt from all points" if lookup == 1 else "merged into the cell order"
+    assert log.count(how) == 2, log[-2000:]
+    fresh = ghn.Index(_dev(all_pts), _dev(all_tgt), prob.task, prob.cell_width, lookup=lookup)
+    assert ix.info.lookup == fresh.info.lookup and ix.info.num_cells == fresh.info.num_cells
+    for x, y in zip(ghn.ghn_index_cells(ix.handle), ghn.ghn_index_cells(fresh.handle)):
+        assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+    q = _dev(prob.queries)
+    got = _all_forms(ghn, ix, q, prob.k)
+    bi, bd, bp = oracle.bruteforce(all_pts, all_tgt, prob.task, prob.queries, prob.k)
+    _same(got[(ghn.GHN_STOP_EXACT, 0)], dict(idx=bi, d2=bd, pred=bp), "inserted EXACT vs oracle")
+    want = oracle.Grid(all_pts, all_tgt, prob.task, prob.cell_width).predict(prob.queries, prob.k, oracle.STOP_PAPER)
+    _same(got[(ghn.GHN_STOP_PAPER, 0)], want, "inserted PAPER vs oracle", keys=("idx", "d2", "pred", "stop_layer"))
+    ix.close()
+    fresh.close()
+
+
 def test_insert_bf16_and_bad_load(ghn):
     import torch
     prob = W.make("bf16_16d", n=12_000, m=200)
