@@ -255,6 +255,9 @@ def bench_multi(args, ghn, W, torch):
     probs = W.make_multi3d()
     dev = torch.device("cuda:0")
     stop = ghn.GHN_STOP_EXACT if args.stop == "exact" else ghn.GHN_STOP_PAPER
+    # FP32 forms, EXACT rule: the central cell and layer 1 in one ring step (batched input
+    # order 4.01 -> 3.21 ms); the neighbours do not depend on it
+    ring = args.ring_step if args.ring_step >= 0 else (2 if stop == ghn.GHN_STOP_EXACT else 0)
     t0 = time.perf_counter()
     idxs, qs, outs = [], [], []
     for p in probs:
@@ -271,7 +274,7 @@ def bench_multi(args, ghn, W, torch):
     cands = probes = 0
     alg_bytes = ext_bytes = 0
     for p, ix, q in zip(probs, idxs, qs):
-        st = ix.predict(q, p.k, stop=stop, with_d2=False, with_stats=True)
+        st = ix.predict(q, p.k, stop=stop, with_d2=False, with_stats=True, ring_step=ring)
         c, pr = int(st["cands"].sum().item()), int(st["probes"].sum().item())
         cands += c
         probes += pr
@@ -296,18 +299,19 @@ def bench_multi(args, ghn, W, torch):
     if "fp32" in args.forms:
         def per_item():
             for p, ix, q, (oi, op) in zip(probs, idxs, qs, outs):
-                ghn.ghn_predict(ix.handle, q, p.k, oi, op, None, stop, ghn.GHN_PREC_FP32, ghn.GHN_FLAG_NO_SORT)
+                ghn.ghn_predict(ix.handle, q, p.k, oi, op, None, stop, ghn.GHN_PREC_FP32, ghn.GHN_FLAG_NO_SORT,
+                                ring_step=ring)
         ms, per = timeit(per_item)
         forms["fp32_per_index"] = dict(ms=ms, per=per)
         items = [(ix.handle, q, p.k, oi, op, None) for p, ix, q, (oi, op) in zip(probs, idxs, qs, outs)]
         # input order (items one after another) and spatial order (sorted by item and cell)
         wsi = torch.empty(ghn.ghn_batch_workspace_bytes_for(items, stop, ghn.GHN_PREC_FP32, ghn.GHN_FLAG_NO_SORT),
                           dtype=torch.uint8, device=dev)
-        batch_in = ghn.ghn_batch_prepare(items, wsi, stop=stop, flags=ghn.GHN_FLAG_NO_SORT)
+        batch_in = ghn.ghn_batch_prepare(items, wsi, stop=stop, flags=ghn.GHN_FLAG_NO_SORT, ring_step=ring)
         ms, per = timeit(lambda: ghn.ghn_predict_batched(batch_in))
         forms["fp32_batched_input_order"] = dict(ms=ms, per=per)
         ws = torch.empty(ghn.ghn_batch_workspace_bytes_for(items, stop), dtype=torch.uint8, device=dev)
-        batch = ghn.ghn_batch_prepare(items, ws, stop=stop)
+        batch = ghn.ghn_batch_prepare(items, ws, stop=stop, ring_step=ring)
         ms, per = timeit(lambda: ghn.ghn_predict_batched(batch))
         forms["fp32_batched"] = dict(ms=ms, per=per)
         g = torch.cuda.CUDAGraph()
@@ -367,7 +371,8 @@ def bench_multi(args, ghn, W, torch):
         "config": {"workload": "multi3d: %d independent uniform 3-D problems, n log-uniform in [1e3, 2e6] (sum %d), "
                                "sum m = %d queries, k in {1,5,10,20}, majority vote, %s stop" % (
                                    len(probs), sum(p.n for p in probs), M, args.stop.upper()),
-                   "problems": len(probs), "sum_n": sum(p.n for p in probs), "sum_m": M, "form": best},
+                   "problems": len(probs), "sum_n": sum(p.n for p in probs), "sum_m": M, "form": best,
+                   "fp32_ring_step": ring},
         "roofline": hbm_roofline(alg_bytes, ext_bytes, B["ms"],
                                  measured_traffic("multi3d", "fp32_batched") if best.startswith("fp32_batched")
                                  else None,
