@@ -269,7 +269,9 @@ __device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
         return (uint32_t)__builtin_amdgcn_ds_swizzle(x, 0x401f);  // bitmask mode: and 0x1f, xor 0x10
     } else {
         static_assert(S == 32, "lane distance must be a power of two below 64");
-        return (uint32_t)__shfl_xor(x, 32, WAVE);
+        // a plain permute (lane ^ 32 is always a lane of the wave): no bounds test, whose
+        // lane-limit value would otherwise be kept live across a whole walk
+        return (uint32_t)__builtin_amdgcn_ds_bpermute((lane_id() ^ 32) << 2, x);
     }
 }
 

@@ -179,8 +179,18 @@ __device__ __forceinline__ void far_dim(const IndexView& ix, const float* querie
 }
 
 __device__ __forceinline__ double wave_max_f64(double x) {
+    // the permute addresses are formed here: shared with the walk's own lane terms, they
+    // were held across the whole walk for this rare path and spilled to scratch per query
+    int lane = lane_id();
+    asm volatile("" : "+v"(lane));
 #pragma unroll
-    for (int m = 1; m < WAVE; m <<= 1) x = fmax(x, __shfl_xor(x, m, WAVE));
+    for (int m = 1; m < WAVE; m <<= 1) {
+        // plain permutes (lane ^ m is always a lane of the wave)
+        const int64_t b = __double_as_longlong(x);
+        const int lo = __builtin_amdgcn_ds_bpermute((lane ^ m) << 2, (int)(uint32_t)b);
+        const int hi = __builtin_amdgcn_ds_bpermute((lane ^ m) << 2, (int)(uint32_t)((uint64_t)b >> 32));
+        x = fmax(x, __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo)));
+    }
     return x;
 }
 
