@@ -88,6 +88,8 @@ def test_clusters4d_full_size(ghn):
     assert np.float32(prob.cell_width) == GOLD["clusters4d/width"]
     ix = ghn.Index(_pts(prob), _dev(prob.targets), prob.task, prob.cell_width)
     forms = {EXACT: [("FP32 input order", dict(prec=FP32, flags=ghn.GHN_FLAG_NO_SORT)),
+                     ("FP32 input order ring 2 (the benchmark's form)",
+                      dict(prec=FP32, flags=ghn.GHN_FLAG_NO_SORT, ring_step=2)),
                      ("FP32 sorted", dict(prec=FP32)),
                      ("FP32 ring grow", dict(prec=FP32, flags=ghn.GHN_FLAG_RING_GROW, ring_step=1)),
                      ("bf16", dict(prec=BF16)),
@@ -170,11 +172,16 @@ def test_multi3d_full_size_batched(ghn):
         items.append((ix.handle, _dev(p.queries), p.k, oi, op, od))
         outs.append((oi, op, od, sl))
     for stop, tag in ((EXACT, "exact"), (PAPER, "paper")):
-        for label, prec, flags in (("FP32 input order", FP32, ghn.GHN_FLAG_NO_SORT), ("FP32 sorted", FP32, 0),
-                                   ("bf16", BF16, 0)):
+        for label, prec, flags, ring in (("FP32 input order", FP32, ghn.GHN_FLAG_NO_SORT, 0),
+                                         ("FP32 input order ring 2 (the benchmark's form)", FP32,
+                                          ghn.GHN_FLAG_NO_SORT, 2),
+                                         ("FP32 sorted", FP32, 0, 0), ("FP32 sorted ring 2", FP32, 0, 2),
+                                         ("bf16", BF16, 0, 0)):
+            if ring and stop == PAPER:
+                continue  # the ring schedule is for the EXACT rule
             ws = torch.empty(ghn.ghn_batch_workspace_bytes_for(items, stop, prec, flags), dtype=torch.uint8,
                              device="cuda")
-            batch = ghn.ghn_batch_prepare(items, ws, stop, flags=flags, prec=prec)
+            batch = ghn.ghn_batch_prepare(items, ws, stop, flags=flags, prec=prec, ring_step=ring)
             ghn.ghn_predict_batched(batch)
             torch.cuda.synchronize()
             ghn.ghn_batch_destroy(batch)

@@ -980,6 +980,7 @@ def test_batched_independent_of_grid_and_order(ghn):
     ("clusters4d", dict(n=60_000, m=1_500), None),                # dense table
     ("skew8d", dict(n=80_000, m=600, seed=5), None),              # cell tree
     ("clusters4d", dict(n=30_000, m=800), HASH),                  # hash lookup
+    ("blobs2d", dict(), None),                                     # full size, the benchmark's ring 2
 ])
 def test_ring_schedule_same_neighbours(ghn, name, kw, lookup):
     """EXACT walks that visit several layers per step (and double the step while the
