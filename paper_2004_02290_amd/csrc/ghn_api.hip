@@ -28,6 +28,7 @@ struct ghn_batch {
     int32_t f;
     int32_t stop;
     bool any_tree;  // some item's index uses the cell tree
+    bool any_dense; // some item's index uses the dense table
     // bf16 screen: one grouped launch over all items' query groups
     int32_t prec;
     int32_t kmax;
@@ -213,7 +214,7 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
     std::vector<BatchItem> h((size_t)n_items);
     int64_t total = 0;
     int32_t f = -1;
-    bool any_tree = false;
+    bool any_tree = false, any_dense = false;
     for (int32_t i = 0; i < n_items; ++i) {
         const ghn_batch_item& it = items[i];
         if (!it.index) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: item %d has no index", i);
@@ -246,6 +247,7 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
         b.m = it.m;
         total += it.m;
         if (it.m > 0 && it.index->view.lookup != LOOKUP_DENSE) any_tree = true;
+        if (it.m > 0 && it.index->view.lookup == LOOKUP_DENSE) any_dense = true;
     }
     // the sort key of every item's queries (item index above kb bits, then the item's
     // Morton code of the central cell, aligned) and its group shift (bf16 groups)
@@ -300,6 +302,7 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
     b->f = f;
     b->stop = o.stop;
     b->any_tree = any_tree;
+    b->any_dense = any_dense;
     b->prec = o.prec;
     b->kmax = kmax;
     b->kb = kb;
@@ -333,7 +336,8 @@ ghn_status ghn_predict_batched(const ghn_batch* batch, void* stream) {
                                                     &order)) != hipSuccess)
         return hip_fail(e, "ghn_predict_batched: query order");
     e = ghn::launch_predict_batched(batch->items_dev, batch->n_items, batch->total, batch->f, batch->stop,
-                                    batch->any_tree, order, batch->blocks, batch->counter_dev, (hipStream_t)stream);
+                                    batch->any_tree, batch->any_dense, order, batch->blocks, batch->counter_dev,
+                                    (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "ghn_predict_batched: launch");
     return GHN_OK;
 }

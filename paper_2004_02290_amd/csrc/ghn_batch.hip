@@ -42,13 +42,24 @@ constexpr int batched_waves_per_eu() {
     return FT < 1 ? 1 : (!TREE ? (FT <= 4 ? 5 : 3) : (FT == 1 ? 7 : (FT == 2 ? 5 : (FT <= 4 ? 4 : 3))));
 }
 
-template <int FT, int STOP, bool TREE>
-__global__ __launch_bounds__(BPT) __attribute__((amdgpu_waves_per_eu(batched_waves_per_eu<FT, TREE>())))
+// Lookups of a batch's items: the dense-table walk only, the tree walk only (the tree
+// and hash indexes), or both.  A one-kind instance holds only that walk's registers:
+// the tree-only one fits the occupancy of the single-index tree kernel (four waves
+// per SIMD at f = 8, where the mixed instance runs three and spills).
+enum BatchKind { DENSE_ONLY = 0, MIXED = 1, TREE_ONLY = 2 };
+template <int FT, int KIND>
+constexpr int batch_kind_waves() {
+    return KIND == TREE_ONLY ? (FT < 1 ? 1 : 4) : batched_waves_per_eu<FT, KIND == MIXED>();
+}
+
+template <int FT, int STOP, int KIND>
+__global__ __launch_bounds__(BPT) __attribute__((amdgpu_waves_per_eu(batch_kind_waves<FT, KIND>())))
 void k_predict_batched(const BatchItem* __restrict__ items, int n_items, int64_t total,
                        const uint32_t* __restrict__ order, uint64_t* counter) {
     __shared__ uint32_t s_begin[BWPB][RUN_CAP];
     __shared__ uint32_t s_pre[BWPB][RUN_CAP];
     __shared__ uint32_t s_key[BWPB][RUN_CAP];
+    constexpr bool TREE = KIND != DENSE_ONLY;
     __shared__ uint64_t s_stack[BWPB][TREE ? TREE_STACK_CAP : 1];
     __shared__ uint64_t s_pend[BWPB][TREE && FT == 8 ? TREE_PEND_CAP : 1];
     const int lane = lane_id();
@@ -71,52 +82,60 @@ void k_predict_batched(const BatchItem* __restrict__ items, int n_items, int64_t
                 const BatchItem& it = items[batch_item_of(items, n_items, pos)];
                 const IndexView& ix = *it.ix;
                 const int64_t qi = pos - it.first;
-                if (!TREE && ix.lookup != LOOKUP_DENSE) continue;  // not launched so (the host checks the items)
-                if (ix.lookup == LOOKUP_DENSE) walk_dense<FT, STOP, false>(ix, it.io, qi, s_begin[wv], s_pre[wv], s_key[wv]);
-                // the tree walk's pending list only where it costs no occupancy: the f = 8
-                // instance already runs at two waves per SIMD; the others hold the dense walk
-                // at three or four, which the extra state would lower
-                else if constexpr (TREE) walk_tree<FT, STOP, FT == 8>(ix, it.io, qi, s_begin[wv], s_pre[wv], s_stack[wv], s_pend[wv]);
+                // (the host launches a one-kind instance only for batches of that kind)
+                if constexpr (KIND == TREE_ONLY) {
+                    if (ix.lookup == LOOKUP_DENSE) continue;
+                    walk_tree<FT, STOP, FT == 8>(ix, it.io, qi, s_begin[wv], s_pre[wv], s_stack[wv], s_pend[wv]);
+                } else if (ix.lookup == LOOKUP_DENSE) {
+                    walk_dense<FT, STOP, false>(ix, it.io, qi, s_begin[wv], s_pre[wv], s_key[wv]);
+                } else if constexpr (KIND == MIXED) {
+                    // the tree walk's pending list only where it costs no occupancy: the f = 8
+                    // instance already runs at few waves per SIMD; the others hold the dense
+                    // walk at three or four, which the extra state would lower
+                    walk_tree<FT, STOP, FT == 8>(ix, it.io, qi, s_begin[wv], s_pre[wv], s_stack[wv], s_pend[wv]);
+                }
             }
         }
     }
 }
 
-template <int FT, bool TREE>
+template <int FT, int KIND>
 void launch_stop(const BatchItem* items, int n_items, int64_t total, const uint32_t* order, uint64_t* counter,
                  int stop, int blocks, hipStream_t s) {
     if (stop == GHN_STOP_PAPER)
-        hipLaunchKernelGGL((k_predict_batched<FT, GHN_STOP_PAPER, TREE>), dim3(blocks), dim3(BPT), 0, s, items, n_items,
+        hipLaunchKernelGGL((k_predict_batched<FT, GHN_STOP_PAPER, KIND>), dim3(blocks), dim3(BPT), 0, s, items, n_items,
                            total, order, counter);
     else
-        hipLaunchKernelGGL((k_predict_batched<FT, GHN_STOP_EXACT, TREE>), dim3(blocks), dim3(BPT), 0, s, items, n_items,
+        hipLaunchKernelGGL((k_predict_batched<FT, GHN_STOP_EXACT, KIND>), dim3(blocks), dim3(BPT), 0, s, items, n_items,
                            total, order, counter);
 }
 
 template <int FT>
 hipError_t launch_ft(const BatchItem* items, int n_items, int64_t total, const uint32_t* order, uint64_t* counter,
-                     int stop, bool any_tree, int blocks, hipStream_t s) {
-    if (any_tree) launch_stop<FT, true>(items, n_items, total, order, counter, stop, blocks, s);
-    else launch_stop<FT, false>(items, n_items, total, order, counter, stop, blocks, s);
+                     int stop, bool any_tree, bool any_dense, int blocks, hipStream_t s) {
+    if (any_tree && any_dense) launch_stop<FT, MIXED>(items, n_items, total, order, counter, stop, blocks, s);
+    else if (any_tree) launch_stop<FT, TREE_ONLY>(items, n_items, total, order, counter, stop, blocks, s);
+    else launch_stop<FT, DENSE_ONLY>(items, n_items, total, order, counter, stop, blocks, s);
     return launch_status();
 }
 
 }  // namespace
 
 hipError_t launch_predict_batched(const BatchItem* items, int n_items, int64_t total, int f, int stop, bool any_tree,
-                                  const uint32_t* order, int blocks_override, uint64_t* counter, hipStream_t s) {
+                                  bool any_dense, const uint32_t* order, int blocks_override, uint64_t* counter,
+                                  hipStream_t s) {
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
     int64_t blocks = (total + BWPB * CHUNK - 1) / (BWPB * CHUNK);
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
     if (blocks_override > 0) blocks = blocks_override;
     switch (f) {
-        case 1: return launch_ft<1>(items, n_items, total, order, counter, stop, any_tree, (int)blocks, s);
-        case 2: return launch_ft<2>(items, n_items, total, order, counter, stop, any_tree, (int)blocks, s);
-        case 3: return launch_ft<3>(items, n_items, total, order, counter, stop, any_tree, (int)blocks, s);
-        case 4: return launch_ft<4>(items, n_items, total, order, counter, stop, any_tree, (int)blocks, s);
-        case 8: return launch_ft<8>(items, n_items, total, order, counter, stop, any_tree, (int)blocks, s);
-        default: return launch_ft<0>(items, n_items, total, order, counter, stop, any_tree, (int)blocks, s);
+        case 1: return launch_ft<1>(items, n_items, total, order, counter, stop, any_tree, any_dense, (int)blocks, s);
+        case 2: return launch_ft<2>(items, n_items, total, order, counter, stop, any_tree, any_dense, (int)blocks, s);
+        case 3: return launch_ft<3>(items, n_items, total, order, counter, stop, any_tree, any_dense, (int)blocks, s);
+        case 4: return launch_ft<4>(items, n_items, total, order, counter, stop, any_tree, any_dense, (int)blocks, s);
+        case 8: return launch_ft<8>(items, n_items, total, order, counter, stop, any_tree, any_dense, (int)blocks, s);
+        default: return launch_ft<0>(items, n_items, total, order, counter, stop, any_tree, any_dense, (int)blocks, s);
     }
 }
 

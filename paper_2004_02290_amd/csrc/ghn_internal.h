@@ -391,7 +391,8 @@ __device__ __forceinline__ int batch_item_of(const BatchItem* items, int n_items
 // order: optional walk order of the global positions (a permutation); counter: 8
 // work counters (one per XCD range); blocks_override > 0 fixes the grid size.
 hipError_t launch_predict_batched(const BatchItem* items, int n_items, int64_t total, int f, int stop, bool any_tree,
-                                  const uint32_t* order, int blocks_override, uint64_t* counter, hipStream_t s);
+                                  bool any_dense, const uint32_t* order, int blocks_override, uint64_t* counter,
+                                  hipStream_t s);
 // The batch's queries sorted by (item, Morton code of the central cell): *order
 // receives the sorted global positions, in `ws` (group_ws_bytes(total) bytes).
 hipError_t batch_query_order(const BatchItem* items, int n_items, int64_t total, int kb, int key_bits, void* ws,

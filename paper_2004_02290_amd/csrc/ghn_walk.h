@@ -537,6 +537,27 @@ __device__ __forceinline__ void score_runs(const IndexView& ix, const float* q, 
     wave_lds_sync();
 }
 
+// A query's set-up is the same on every lane of its wave.  Made wave-uniform after it
+// is computed, its values live in scalar registers for the walk instead of taking
+// vector registers (the walks that set up their own query; the single-index dense
+// kernel reads a block-shared set-up).
+template <int FT>
+__device__ __forceinline__ void uniform_query(Query<FT>& Q) {
+    static_assert(FT > 0, "per-dimension instances only");
+#pragma unroll
+    for (int j = 0; j < FT; ++j) {
+        Q.q[j] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Q.q[j])));
+        const uint64_t b = (uint64_t)__double_as_longlong(Q.v[j]);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+        Q.v[j] = __longlong_as_double((int64_t)(((uint64_t)hi << 32) | lo));
+        Q.c[j] = __builtin_amdgcn_readfirstlane(Q.c[j]);
+    }
+    Q.l0 = __builtin_amdgcn_readfirstlane(Q.l0);
+    Q.lcover = __builtin_amdgcn_readfirstlane(Q.lcover);
+    Q.finite = __builtin_amdgcn_readfirstlane((int)Q.finite) != 0;
+}
+
 // Stop rules, checked after every complete layer l of the walk frame.  In a shifted
 // frame the EXACT bound is that of the frame's layer box, which lies inside the true
 // layer box in every dimension: the bound is smaller (often 0) and the walk stops no

@@ -247,8 +247,12 @@ __device__ __forceinline__ void walk_dense(const IndexView& ix, const QueryIO& i
                                            uint32_t* s_begin, uint32_t* s_pre, uint32_t* s_key,
                                            const Query<FT>* preset = nullptr) {
     Query<FT> Q;
-    if (preset) Q = *preset;
-    else setup_query<FT>(ix, io.queries, qi, FT > 0 ? FT : ix.f, Q);
+    if (preset) {
+        Q = *preset;
+    } else {
+        setup_query<FT>(ix, io.queries, qi, FT > 0 ? FT : ix.f, Q);
+        if constexpr (FT > 0) uniform_query<FT>(Q);
+    }
     if (!Q.finite) {
         write_invalid(ix, io, qi);
         return;

@@ -183,6 +183,7 @@ __device__ __forceinline__ void walk_tree(const IndexView& ix, const QueryIO& io
                                           uint32_t* s_begin, uint32_t* s_pre, uint64_t* stack, uint64_t* pend) {
     Query<FT> Q;
     setup_query<FT>(ix, io.queries, qi, FT > 0 ? FT : ix.f, Q);
+    if constexpr (FT > 0) uniform_query<FT>(Q);
     if (!Q.finite) {
         write_invalid(ix, io, qi);
         return;
