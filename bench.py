@@ -404,7 +404,7 @@ def bench_multi(args, ghn, W, torch):
     print(json.dumps(line), flush=True)
 
 
-def query_parts(prob, qs, ix, ghn, torch, stop, sort32, levels16, reps=3, ring32=0, grow32=0, gs16=0):
+def query_parts(prob, qs, ix, ghn, torch, stop, sort32, levels16, reps=3, ring32=0, grow32=0, gs16=0, tw16=0):
     """Each half of a mixed query set (cluster / uniform background) timed on its own, both forms."""
     out = {}
     k = prob.k
@@ -417,13 +417,13 @@ def query_parts(prob, qs, ix, ghn, torch, stop, sort32, levels16, reps=3, ring32
         oi = torch.empty((mq, k), dtype=torch.int64, device=qs.device)
         op = torch.empty(mq, dtype=torch.int32 if prob.task == 0 else torch.float32, device=qs.device)
         part = {"queries": mq}
-        for form, prec, flags, levels, ring, gs in (
-                ("fp32_plain", ghn.GHN_PREC_FP32, (0 if sort32 else ghn.GHN_FLAG_NO_SORT) | grow32, -1, ring32, 0),
-                ("bf16_grouped", ghn.GHN_PREC_BF16_MFMA, 0, levels16, 0, gs16)):
+        for form, prec, flags, levels, ring, gs, tw in (
+                ("fp32_plain", ghn.GHN_PREC_FP32, (0 if sort32 else ghn.GHN_FLAG_NO_SORT) | grow32, -1, ring32, 0, 0),
+                ("bf16_grouped", ghn.GHN_PREC_BF16_MFMA, 0, levels16, 0, gs16, tw16)):
             nws = ghn.ghn_predict_workspace_bytes(ix.handle, mq, k, stop, prec, flags, levels)
             ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=qs.device)
             st = ix.predict(q, k, stop=stop, prec=prec, flags=flags, with_d2=False, with_stats=True,
-                            group_levels=levels, ring_step=ring, group_size=gs)
+                            group_levels=levels, ring_step=ring, group_size=gs, tile_width=tw)
             torch.cuda.synchronize()
             cands = float(st["cands"].double().mean().item())
             layers = float(st["stop_layer"].double().mean().item())
@@ -432,7 +432,7 @@ def query_parts(prob, qs, ix, ghn, torch, stop, sort32, levels16, reps=3, ring32
             for _ in range(reps + 1):
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 ghn.ghn_predict(ix.handle, q, k, oi, op, None, stop, prec, flags, ws=ws, group_levels=levels,
-                                walk_events=(e0, e1), ring_step=ring, group_size=gs)
+                                walk_events=(e0, e1), ring_step=ring, group_size=gs, tile_width=tw)
                 torch.cuda.synchronize()
                 ms.append(e0.elapsed_time(e1))
             kern = float(np.mean(ms[1:]))
@@ -527,6 +527,7 @@ def main():
     sort32, levels16 = args.sort, args.group_levels
     ring32, grow32 = 0, 0  # FP32 form: the EXACT walk's ring schedule (autotuned, else --ring-step)
     gs16 = 0               # bf16 form: most queries per group (autotuned; 0 = 16)
+    tw16 = 0               # bf16 form: candidates per screened tile (autotuned; 0 = 64)
     if args.autotune == "on" or (args.autotune == "auto" and args.workload in AUTOTUNED and args.cell_width is None
                                     and not args.no_extras):
         # widths around the calibrated one (under PAPER only execution settings are tuned);
@@ -555,12 +556,14 @@ def main():
         if b16 is not None:
             levels16 = int(b16["group_levels"])
             gs16 = int(b16["group_size"])
+            tw16 = int(b16["tile_width"])
         tuned = {"cell_width": width, "tune_ms": tune_ms, "sample_queries": ns, "widths_tried": widths,
                  "fp32_sort": sort32, "fp32_ring_step": ring32, "fp32_ring_grow": bool(grow32),
-                 "bf16_group_levels": levels16, "bf16_group_size": gs16,
+                 "bf16_group_levels": levels16, "bf16_group_size": gs16, "bf16_tile_width": tw16,
                  "trials": [{"w": t["cell_width"], "prec": "fp32" if t["prec"] == ghn.GHN_PREC_FP32 else "bf16",
                              "lookup": t["lookup"], "levels": t["group_levels"], "flags": t["flags"],
-                             "ring_step": t["ring_step"], "group_size": t["group_size"], "ms": t["ms"]}
+                             "ring_step": t["ring_step"], "group_size": t["group_size"],
+                             "tile_width": t["tile_width"], "ms": t["ms"]}
                             for t in trials]}
         print("autotune: width %.6g (calibrated %.6g), %.1f s" % (width, prob.cell_width, tune_ms * 1e-3),
               file=sys.stderr, flush=True)
@@ -599,9 +602,9 @@ def main():
         kern = np.array([wb[i].elapsed_time(we[i]) for i in range(args.steps)])
         return ms, float(kern.mean()), per
 
-    def stats(prec, flags=0, levels=-1, ring=0, gsize=0):
+    def stats(prec, flags=0, levels=-1, ring=0, gsize=0, tw=0):
         st = ix.predict(qs, k, stop=stop, prec=prec, flags=flags, with_d2=False, with_stats=True, group_levels=levels,
-                        ring_step=ring, group_size=gsize)
+                        ring_step=ring, group_size=gsize, tile_width=tw)
         torch.cuda.synchronize()
         out = dict(cands=int(st["cands"].sum().item()), probes=int(st["probes"].sum().item()),
                    layers=float(st["stop_layer"].double().mean().item()),
@@ -638,11 +641,11 @@ def main():
     if "bf16" in args.forms:
         nws = ghn.ghn_predict_workspace_bytes(ix.handle, m, k, stop, ghn.GHN_PREC_BF16_MFMA, 0, levels16)
         ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dev)
-        w = stats(ghn.GHN_PREC_BF16_MFMA, 0, levels16, gsize=gs16)
+        w = stats(ghn.GHN_PREC_BF16_MFMA, 0, levels16, gsize=gs16, tw=tw16)
 
         def step16(evs):
             ghn.ghn_predict(ix.handle, qs, k, out_idx, out_pred, None, stop, ghn.GHN_PREC_BF16_MFMA, 0, ws=ws,
-                            group_levels=levels16, walk_events=evs, group_size=gs16)
+                            group_levels=levels16, walk_events=evs, group_size=gs16, tile_width=tw16)
 
         ms, kern_ms, per = timed(step16)
         flops = 2.0 * f * w["cands"]  # algorithmic: 2 f per screened (query, candidate) pair
@@ -750,7 +753,7 @@ def main():
         line["autotune"] = tuned
     if prob.query_part is not None and not args.no_extras:
         line["query_parts"] = query_parts(prob, qs, ix, ghn, torch, stop, sort32, levels16, ring32=ring32,
-                                          grow32=grow32, gs16=gs16)
+                                          grow32=grow32, gs16=gs16, tw16=tw16)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob)
         line["cpu_oracle_more"] = cpu_more(prob)

@@ -248,6 +248,11 @@ typedef struct {
                                 GHN_STOP_PAPER (and without GHN_FLAG_RING_GROW) */
     int32_t group_size;      /* bf16 screen: most queries per group, 1..16 (0 = 16, a full matrix tile of
                                 query rows; smaller groups leave rows empty but share fewer cells) */
+    int32_t tile_width;      /* bf16 screen: candidates per screened tile, 32 or 64 (0 = 64): two or four
+                                16 x 16 result blocks per admission check.  A narrower tile updates the
+                                thresholds sooner and wastes less at the end of a layer's candidate
+                                list; a wider one spreads the per-tile work over more candidates.  The
+                                neighbours do not depend on it */
 } ghn_predict_opts;
 
 /* Bytes of device workspace ghn_predict needs for these arguments (the bf16
@@ -403,6 +408,7 @@ typedef struct {
     uint32_t flags;        /* GHN_FLAG_* to pass to ghn_predict */
     int32_t ring_step;     /* ghn_predict_opts.ring_step (FP32 screen, GHN_STOP_EXACT) */
     int32_t group_size;    /* ghn_predict_opts.group_size (bf16 screen) */
+    int32_t tile_width;    /* ghn_predict_opts.tile_width (bf16 screen) */
     double ms;             /* time of one predict call over the sample, or -1 if the setting failed */
 } ghn_tune_trial;
 

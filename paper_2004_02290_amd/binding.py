@@ -68,7 +68,7 @@ class ghn_predict_opts(ctypes.Structure):
                 ("out_probes", ctypes.c_void_p), ("order", ctypes.c_void_p),
                 ("group_levels", ctypes.c_int32), ("walk_event_begin", ctypes.c_void_p),
                 ("walk_event_end", ctypes.c_void_p), ("out_rerank", ctypes.c_void_p),
-                ("ring_step", ctypes.c_int32), ("group_size", ctypes.c_int32)]
+                ("ring_step", ctypes.c_int32), ("group_size", ctypes.c_int32), ("tile_width", ctypes.c_int32)]
 
 
 class ghn_batch_item(ctypes.Structure):
@@ -80,7 +80,7 @@ class ghn_batch_item(ctypes.Structure):
 class ghn_tune_trial(ctypes.Structure):
     _fields_ = [("cell_width", ctypes.c_float), ("lookup", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("group_levels", ctypes.c_int32), ("flags", ctypes.c_uint32), ("ring_step", ctypes.c_int32),
-                ("group_size", ctypes.c_int32), ("ms", ctypes.c_double)]
+                ("group_size", ctypes.c_int32), ("tile_width", ctypes.c_int32), ("ms", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -311,11 +311,12 @@ def _event(ev):
 
 
 def _opts(stop, prec, flags, out_stop_layer=None, out_cands=None, out_probes=None, order=None,
-          group_levels=-1, walk_events=None, out_rerank=None, ring_step=0, group_size=0) -> ghn_predict_opts:
+          group_levels=-1, walk_events=None, out_rerank=None, ring_step=0, group_size=0,
+          tile_width=0) -> ghn_predict_opts:
     ev0, ev1 = walk_events if walk_events is not None else (None, None)
     return ghn_predict_opts(int(stop), int(prec), int(flags), _ptr(out_stop_layer), _ptr(out_cands),
                             _ptr(out_probes), _ptr(order), int(group_levels), _event(ev0), _event(ev1),
-                            _ptr(out_rerank), int(ring_step), int(group_size))
+                            _ptr(out_rerank), int(ring_step), int(group_size), int(tile_width))
 
 
 def ghn_predict_workspace_bytes(handle, m: int, k: int, stop=GHN_STOP_EXACT, prec=GHN_PREC_FP32, flags=0,
@@ -330,13 +331,13 @@ def ghn_predict(handle, queries: torch.Tensor, k: int, out_idx: torch.Tensor, ou
                 out_probes: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
                 order: Optional[torch.Tensor] = None, group_levels: int = -1, stream=None,
                 walk_events=None, out_rerank: Optional[torch.Tensor] = None, ring_step: int = 0,
-                group_size: int = 0) -> None:
+                group_size: int = 0, tile_width: int = 0) -> None:
     """ghn_predict into caller-provided outputs (int64 idx m x k, pred m, optional float64 d2 m x k).
 
     walk_events: optional (begin, end) pair of torch.cuda.Event recorded around the walk kernel."""
     m = queries.shape[0]
     o = _opts(stop, prec, flags, out_stop_layer, out_cands, out_probes, order, group_levels, walk_events,
-              out_rerank, ring_step, group_size)
+              out_rerank, ring_step, group_size, tile_width)
     ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
     _check(_lib.ghn_predict(handle, _ptr(queries), m, k, ctypes.byref(o), _ptr(out_idx), _ptr(out_d2),
                             _ptr(out_pred), _ptr(ws), ws_bytes, _stream(stream)))
@@ -393,10 +394,11 @@ def ghn_batch_workspace_bytes_for(items, stop=GHN_STOP_EXACT, prec=GHN_PREC_FP32
 
 
 def ghn_batch_prepare(items, ws: torch.Tensor, stop=GHN_STOP_EXACT, flags=0, stream=None, prec=GHN_PREC_FP32,
-                      group_levels=-1, ring_step=0, group_size=0) -> ctypes.c_void_p:
+                      group_levels=-1, ring_step=0, group_size=0, tile_width=0) -> ctypes.c_void_p:
     """ghn_batch_prepare: items = [(handle, queries, k, out_idx, out_pred, out_d2 or None), ...]."""
     arr = _batch_items(items)
-    o = _opts(stop, prec, flags, group_levels=group_levels, ring_step=ring_step, group_size=group_size)
+    o = _opts(stop, prec, flags, group_levels=group_levels, ring_step=ring_step, group_size=group_size,
+              tile_width=tile_width)
     out = ctypes.c_void_p()
     _check(_lib.ghn_batch_prepare(arr, len(items), ctypes.byref(o), _ptr(ws), ws.numel() * ws.element_size(),
                                   _stream(stream), ctypes.byref(out)))
@@ -495,7 +497,7 @@ class Index:
 
     def predict(self, queries: torch.Tensor, k: int, stop=GHN_STOP_EXACT, prec=GHN_PREC_FP32, flags=0,
                 with_d2: bool = True, with_stats: bool = False, group_levels: int = -1, stream=None,
-                ring_step: int = 0, group_size: int = 0):
+                ring_step: int = 0, group_size: int = 0, tile_width: int = 0):
         """Returns dict(idx, pred[, d2][, stop_layer, cands]) as GPU tensors."""
         dev = queries.device
         m = queries.shape[0]
@@ -513,7 +515,8 @@ class Index:
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev) if nbytes else None
         ghn_predict(self.handle, queries, k, out["idx"], out["pred"], out.get("d2"), stop, prec, flags,
                     out.get("stop_layer"), out.get("cands"), out.get("probes"), ws, None, group_levels, stream,
-                    out_rerank=out.get("rerank"), ring_step=ring_step, group_size=group_size)
+                    out_rerank=out.get("rerank"), ring_step=ring_step, group_size=group_size,
+                    tile_width=tile_width)
         return out
 
     @classmethod

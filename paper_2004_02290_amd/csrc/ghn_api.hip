@@ -36,6 +36,7 @@ struct ghn_batch {
     int32_t key_bits;   // bits of the sort key
     void* group_ws;     // group_ws_bytes(total) bytes of the caller's workspace
     int32_t group_size; // bf16 screen: most queries per group
+    int32_t tile_width; // bf16 screen: candidates per screened tile
     bool sorted;        // FP32 screen: walk the queries in spatial order (sorted by the key)
     int32_t blocks;     // grid size of the FP32 launch (0 = by the query count)
 };
@@ -149,6 +150,8 @@ size_t sort_ws_bytes(int64_t m);  // workspace of the spatial query sort (define
 constexpr size_t BATCH_COUNTER_BYTES = 1024;  // the FP32 batch's 8 work counters, 128 bytes apart
 
 // The ring schedule (ghn_predict_opts.ring_step, GHN_FLAG_RING_GROW) is for the EXACT rule.
+bool tile_width_ok(int32_t tw) { return tw == 0 || tw == 32 || tw == 64; }
+
 bool ring_ok(const ghn_predict_opts& o) {
     if (o.ring_step < 0 || o.ring_step > 64) return false;
     return o.stop != GHN_STOP_PAPER || (o.ring_step <= 1 && !(o.flags & GHN_FLAG_RING_GROW));
@@ -203,6 +206,7 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
     if (o.flags & ~(GHN_FLAG_NO_PRUNE | GHN_FLAG_NO_SORT | GHN_FLAG_MEDIAN | GHN_FLAG_RING_GROW)) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: unknown flags 0x%x", o.flags);
     if (!ring_ok(o)) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: ring_step=%d (0..64, and 0 or 1 without GHN_FLAG_RING_GROW under the PAPER rule)", o.ring_step);
     if (o.group_size < 0 || o.group_size > 16) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: group_size=%d outside [0, 16]", o.group_size);
+    if (!tile_width_ok(o.tile_width)) return fail(GHN_E_INVALID_ARG, "ghn_batch_prepare: tile_width=%d (0, 32 or 64)", o.tile_width);
     const size_t base = ghn_batch_workspace_bytes(n_items);
     ghn_predict_opts oo = o;
     const size_t need = ghn_batch_workspace_bytes_for(items, n_items, &oo);
@@ -310,6 +314,7 @@ ghn_status ghn_batch_prepare(const ghn_batch_item* items, int32_t n_items, const
     b->group_ws = (char*)ws + base;
     b->sorted = sorted;
     b->group_size = o.group_size > 0 ? o.group_size : 16;
+    b->tile_width = o.tile_width > 0 ? o.tile_width : 64;
     b->blocks = 0;
     if (const char* env = std::getenv("GHN_BATCH_BLOCKS")) b->blocks = std::atoi(env) > 0 ? std::atoi(env) : 0;
     ghn::log_line("batch_prepare items=%d queries=%lld f=%d kmax=%d stop=%d prec=%d flags=0x%x sorted=%d", n_items,
@@ -325,7 +330,8 @@ ghn_status ghn_predict_batched(const ghn_batch* batch, void* stream) {
     if (batch->prec == GHN_PREC_BF16_MFMA) {
         const hipError_t e = ghn::run_grouped_batched(batch->items_dev, batch->n_items, batch->total, batch->f,
                                                       batch->kmax, batch->stop, batch->kb, batch->key_bits,
-                                                      batch->group_size, batch->group_ws, (hipStream_t)stream);
+                                                      batch->group_size, batch->tile_width, batch->group_ws,
+                                                      (hipStream_t)stream);
         if (e != hipSuccess) return hip_fail(e, "ghn_predict_batched: grouped launch");
         return GHN_OK;
     }
@@ -374,21 +380,23 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
         const double w0 = std::exp((logvol + std::log(8.0 / (double)n)) / f);
         for (int i = -3; i <= 2; ++i) cand.push_back((float)(w0 * std::ldexp(1.0, i)));
     }
-    struct Setting { int32_t prec, levels; uint32_t flags; int32_t ring, gsize; };
-    std::vector<Setting> settings = {{GHN_PREC_FP32, -1, GHN_FLAG_NO_SORT, 0, 0}, {GHN_PREC_FP32, -1, 0u, 0, 0}};
+    struct Setting { int32_t prec, levels; uint32_t flags; int32_t ring, gsize, tw; };
+    std::vector<Setting> settings = {{GHN_PREC_FP32, -1, GHN_FLAG_NO_SORT, 0, 0, 0}, {GHN_PREC_FP32, -1, 0u, 0, 0, 0}};
+    // bf16 group and tile shapes: 16 queries x 64 candidates, 8 x 64, 16 x 32
+    const int shapes[3][2] = {{16, 64}, {8, 64}, {16, 32}};
     if (stop == GHN_STOP_PAPER) {
-        for (int gs : {16, 8}) settings.push_back({GHN_PREC_BF16_MFMA, 0, 0u, 0, gs});
+        for (const auto& sh : shapes) settings.push_back({GHN_PREC_BF16_MFMA, 0, 0u, 0, sh[0], sh[1]});
     } else {
         // the EXACT walk's ring schedule: 2 layers a step, doubling steps until the buffer is
         // full, or both (input and spatial order)
         for (uint32_t order : {(uint32_t)GHN_FLAG_NO_SORT, 0u}) {
-            settings.push_back({GHN_PREC_FP32, -1, order, 2, 0});
-            settings.push_back({GHN_PREC_FP32, -1, order | GHN_FLAG_RING_GROW, 1, 0});
-            settings.push_back({GHN_PREC_FP32, -1, order | GHN_FLAG_RING_GROW, 2, 0});
+            settings.push_back({GHN_PREC_FP32, -1, order, 2, 0, 0});
+            settings.push_back({GHN_PREC_FP32, -1, order | GHN_FLAG_RING_GROW, 1, 0, 0});
+            settings.push_back({GHN_PREC_FP32, -1, order | GHN_FLAG_RING_GROW, 2, 0, 0});
         }
-        // bf16: groups of 2^lv cells per dimension, of at most 16 or 8 queries
-        for (int gs : {16, 8})
-            for (int lv = 0; lv <= 3; ++lv) settings.push_back({GHN_PREC_BF16_MFMA, lv, 0u, 0, gs});
+        // bf16: groups of 2^lv cells per dimension, in each group and tile shape
+        for (const auto& sh : shapes)
+            for (int lv = 0; lv <= 3; ++lv) settings.push_back({GHN_PREC_BF16_MFMA, lv, 0u, 0, sh[0], sh[1]});
     }
 
     // outputs and a workspace large enough for every setting
@@ -407,13 +415,13 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
         for (float w : cand) {
             ghn_index* ix = nullptr;
             if (ghn_build(points, n, f, dtype, targets, task, &w, 1, nullptr, stream, &ix) != GHN_OK) {
-                if (trials && nt < max_trials) trials[nt] = {w, -1, -1, -1, 0u, 0, 0, -1.0};
+                if (trials && nt < max_trials) trials[nt] = {w, -1, -1, -1, 0u, 0, 0, 0, -1.0};
                 ++nt;
                 continue;
             }
             for (const Setting& st : settings) {
                 ghn_predict_opts o = {stop, st.prec, st.flags, nullptr, nullptr, nullptr, nullptr, st.levels, nullptr, nullptr,
-                                      nullptr, st.ring, st.gsize};
+                                      nullptr, st.ring, st.gsize, st.tw};
                 double ms = -1.0;
                 if (ghn_predict(ix, queries, m, k, &o, oi, nullptr, op, ws, ws_bytes, stream) == GHN_OK &&
                     hipStreamSynchronize(s) == hipSuccess) {
@@ -428,7 +436,7 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
                     }
                     if (best_ms < 1e29f) ms = best_ms;
                 }
-                const ghn_tune_trial tr = {w, ix->info.lookup, st.prec, st.levels, st.flags, st.ring, st.gsize, ms};
+                const ghn_tune_trial tr = {w, ix->info.lookup, st.prec, st.levels, st.flags, st.ring, st.gsize, st.tw, ms};
                 if (trials && nt < max_trials) trials[nt] = tr;
                 ++nt;
                 if (ms >= 0.0 && (!have_best || ms < best->ms)) { *best = tr; have_best = true; }
@@ -442,7 +450,7 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
                 for (const Setting& st : settings) {
                     if (st.prec != GHN_PREC_FP32) continue;
                     ghn_predict_opts o = {stop, st.prec, st.flags, nullptr, nullptr, nullptr, nullptr, st.levels, nullptr, nullptr,
-                                      nullptr, st.ring, st.gsize};
+                                      nullptr, st.ring, st.gsize, st.tw};
                     double ms = -1.0;
                     if (ghn_predict(ix, queries, m, k, &o, oi, nullptr, op, ws, ws_bytes, stream) == GHN_OK &&
                         hipStreamSynchronize(s) == hipSuccess) {
@@ -457,7 +465,7 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
                         }
                         if (best_ms < 1e29f) ms = best_ms;
                     }
-                    const ghn_tune_trial tr = {w, GHN_LOOKUP_HASH, st.prec, st.levels, st.flags, st.ring, st.gsize, ms};
+                    const ghn_tune_trial tr = {w, GHN_LOOKUP_HASH, st.prec, st.levels, st.flags, st.ring, st.gsize, st.tw, ms};
                     if (trials && nt < max_trials) trials[nt] = tr;
                     ++nt;
                     if (ms >= 0.0 && (!have_best || ms < best->ms)) { *best = tr; have_best = true; }
@@ -475,8 +483,8 @@ ghn_status ghn_autotune(const void* points, int64_t n, int32_t f, int32_t dtype,
     if (n_trials) *n_trials = nt;
     if (result == GHN_OK)
         log_line("autotune trials=%d best: width=%g lookup=%d prec=%d group_levels=%d flags=0x%x ring_step=%d "
-                 "group_size=%d ms=%.4f", nt, best->cell_width, best->lookup, best->prec, best->group_levels,
-                 best->flags, best->ring_step, best->group_size, best->ms);
+                 "group_size=%d tile_width=%d ms=%.4f", nt, best->cell_width, best->lookup, best->prec, best->group_levels,
+                 best->flags, best->ring_step, best->group_size, best->tile_width, best->ms);
     return result;
 }
 
@@ -981,6 +989,7 @@ static ghn_status predict_common(const ghn_index* index, const float* queries, i
     if (o.flags & ~(GHN_FLAG_NO_PRUNE | GHN_FLAG_NO_SORT | GHN_FLAG_MEDIAN | GHN_FLAG_RING_GROW)) return fail(GHN_E_INVALID_ARG, "ghn_predict: unknown flags 0x%x", o.flags);
     if (!ring_ok(o)) return fail(GHN_E_INVALID_ARG, "ghn_predict: ring_step=%d (0..64, and 0 or 1 without GHN_FLAG_RING_GROW under the PAPER rule)", o.ring_step);
     if (o.group_size < 0 || o.group_size > 16) return fail(GHN_E_INVALID_ARG, "ghn_predict: group_size=%d outside [0, 16]", o.group_size);
+    if (!tile_width_ok(o.tile_width)) return fail(GHN_E_INVALID_ARG, "ghn_predict: tile_width=%d (0, 32 or 64)", o.tile_width);
     if ((o.flags & GHN_FLAG_MEDIAN) && index->info.task != GHN_REGRESS)
         return fail(GHN_E_INVALID_ARG, "ghn_predict: GHN_FLAG_MEDIAN needs a regression index");
     if (m == 0) return GHN_OK;
@@ -1015,9 +1024,10 @@ static ghn_status predict_common(const ghn_index* index, const float* queries, i
         pa.order = nullptr;
     }
     if (log_enabled())
-        log_line("%s m=%lld k=%d stop=%d prec=%d flags=0x%x ring_step=%d group_levels=%d group_size=%d lookup=%d order=%s",
+        log_line("%s m=%lld k=%d stop=%d prec=%d flags=0x%x ring_step=%d group_levels=%d group_size=%d tile_width=%d "
+                 "lookup=%d order=%s",
                  brute ? "bruteforce" : "predict", (long long)m, k, o.stop, o.prec, o.flags, o.ring_step,
-                 o.group_levels, o.group_size, index->view.lookup,
+                 o.group_levels, o.group_size, o.tile_width, index->view.lookup,
                  o.order ? "given" : (o.prec == GHN_PREC_FP32 && wants_sort(m, o.flags)) ? "sorted" : "input");
     if (o.prec == GHN_PREC_BF16_MFMA) {
         const size_t need = group_ws_bytes(m);
@@ -1027,7 +1037,8 @@ static ghn_status predict_common(const ghn_index* index, const float* queries, i
         const int levels = brute ? 32 : o.stop == GHN_STOP_PAPER ? 0 : (o.group_levels >= 0 ? o.group_levels : (index->info.f >= 12 ? 3 : 1));
         int bits = 0;
         const int gsize = o.group_size > 0 ? o.group_size : 16;
-        e = run_grouped(pa, levels, gsize, ws, s, &bits, (hipEvent_t)o.walk_event_begin, (hipEvent_t)o.walk_event_end,
+        const int tw = o.tile_width > 0 ? o.tile_width : 64;
+        e = run_grouped(pa, levels, gsize, tw, ws, s, &bits, (hipEvent_t)o.walk_event_begin, (hipEvent_t)o.walk_event_end,
                         brute);
         if (e != hipSuccess) return hip_fail(e, "ghn_predict: grouped walk");
         return GHN_OK;

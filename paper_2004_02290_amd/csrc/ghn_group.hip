@@ -231,6 +231,7 @@ struct GroupArgs {
     uint32_t* work;            // next group to take
     const BatchItem* items;    // batch: the items (device), in order of first positions
     int32_t n_items;
+    int32_t tile_w;            // candidates per screened tile: 32 or 64 (2 or 4 column blocks)
 };
 
 template <int FT>
@@ -604,14 +605,16 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
 
         // Screen the points of the run list in LDS (npts points in nrun runs, prefix
         // positions with a sentinel at nrun) and queue the admitted pairs; `last`
-        // flushes the queue at the end (with npts = 0 it only flushes).
+        // flushes the queue at the end (with npts = 0 it only flushes).  A tile holds
+        // tw candidates (lanes below tw), screened as tw / 16 column blocks.
+        const uint32_t tw = (uint32_t)G.tile_w;
         auto score_tiles = [&](uint32_t npts, uint32_t nrun, bool last) {
                 uint32_t seg = 0;
-                for (uint32_t base = 0; base < npts || (last && base == 0); base += WAVE) {
+                for (uint32_t base = 0; base < npts || (last && base == 0); base += tw) {
                     // candidate base + lane: its run (one uniform pass over the runs that
                     // start inside this tile), record position and initial accumulator
                     const uint32_t p = base + lane;
-                    const uint32_t end = base + WAVE;
+                    const uint32_t end = base + tw;
                     uint32_t my = seg;
                     uint32_t s = seg + 1;
                     uint32_t pre_s = (uint32_t)__builtin_amdgcn_readfirstlane((int)S.run_pre[s]);
@@ -621,7 +624,7 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                         pre_s = (uint32_t)__builtin_amdgcn_readfirstlane((int)S.run_pre[s]);
                     }
                     seg = (pre_s == end && s < nrun) ? s : s - 1;
-                    const bool valid = p < npts;
+                    const bool valid = p < npts && (uint32_t)lane < tw;
                     uint32_t pidx = 0;
                     float xinit = __int_as_float(0x7fc00000);  // NaN: never admitted
                     if (valid) {
@@ -632,7 +635,7 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                     const int nvalid = __popcll(ballot(valid));
 #pragma unroll
                     for (int i = 0; i < 4; ++i) if (!done[i]) cands[i] += nvalid;
-                    // Fast path: the 16 x 64 screen of the tile (lane (g, t) holds candidate
+                    // Fast path: the 16 x tw screen of the tile (lane (g, t) holds candidate
                     // 16 cb + t of column block cb); most tiles admit nothing once the
                     // buffers are full.
                     uint64_t any = 0;
@@ -640,6 +643,11 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                     uint32_t pcs[4];
 #pragma unroll
                     for (int cb = 0; cb < 4; ++cb) {
+                        if (cb >= 2 && tw < 64) {
+                            accs[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+                            pcs[cb] = 0;
+                            continue;
+                        }
                         accs[cb] = screen_block<FT, SP>(ix, afr, pidx, xinit, base, npts, cb, g, t, pcs[cb]);
 #pragma unroll
                         for (int i = 0; i < 4; ++i) any |= ballot(accs[cb][i] <= bnd[i]);
@@ -648,6 +656,7 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                         // queue the admitted pairs (query row, point position)
 #pragma unroll
                         for (int cb = 0; cb < 4; ++cb) {
+                            if (cb >= 2 && tw < 64) break;
 #pragma unroll
                             for (int i = 0; i < 4; ++i) {
                                 const uint64_t M = ballot(accs[cb][i] <= bnd[i]);
@@ -661,7 +670,7 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                             }
                         }
                     }
-                    if (qcount >= QFLUSH || (last && qcount > 0 && base + WAVE >= npts)) flush();
+                    if (qcount >= QFLUSH || (last && qcount > 0 && base + tw >= npts)) flush();
                 }
         };
 
@@ -1188,7 +1197,7 @@ size_t group_ws_bytes(int64_t m) {
 }
 
 // Sort + group the queries, then walk the groups.  `ws` holds group_ws_bytes(m).
-hipError_t run_grouped(const PredictArgs& pa, int keep_shift_levels, int gsize, void* ws, hipStream_t s,
+hipError_t run_grouped(const PredictArgs& pa, int keep_shift_levels, int gsize, int tile_w, void* ws, hipStream_t s,
                        int* morton_bits, hipEvent_t ev_begin, hipEvent_t ev_end, bool brute) {
     const IndexView& ix = pa.ix;
     const int64_t m = pa.m;
@@ -1238,6 +1247,7 @@ hipError_t run_grouped(const PredictArgs& pa, int keep_shift_levels, int gsize, 
     ga.work = counters + 1;
     ga.items = nullptr;
     ga.n_items = 0;
+    ga.tile_w = tile_w;
     int64_t blocks = (m + GQ * GWPB - 1) / (GQ * GWPB);
     if (blocks > 2048) blocks = 2048;
     if (ev_begin && (e = hipEventRecord(ev_begin, s)) != hipSuccess) return e;
@@ -1268,7 +1278,7 @@ hipError_t batch_query_order(const BatchItem* items, int n_items, int64_t total,
 }
 
 hipError_t run_grouped_batched(const BatchItem* items, int n_items, int64_t total, int f, int kmax, int stop, int kb,
-                               int key_bits, int gsize, void* ws, hipStream_t s) {
+                               int key_bits, int gsize, int tile_w, void* ws, hipStream_t s) {
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
     const int64_t m = total;
     char* p = (char*)ws;
@@ -1302,6 +1312,7 @@ hipError_t run_grouped_batched(const BatchItem* items, int n_items, int64_t tota
     ga.work = counters + 1;
     ga.items = items;
     ga.n_items = n_items;
+    ga.tile_w = tile_w;
     int64_t blocks = (m + GQ * GWPB - 1) / (GQ * GWPB);
     if (blocks > 2048) blocks = 2048;
     if (blocks < 1) blocks = 1;

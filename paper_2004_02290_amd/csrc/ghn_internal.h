@@ -401,7 +401,7 @@ hipError_t batch_query_order(const BatchItem* items, int n_items, int64_t total,
 // of all its queries by (item, cell) and the grouping; `ws` holds group_ws_bytes(total).
 // kb: key bits below the item index; kmax: largest k.
 hipError_t run_grouped_batched(const BatchItem* items, int n_items, int64_t total, int f, int kmax, int stop, int kb,
-                               int key_bits, int gsize, void* ws, hipStream_t s);
+                               int key_bits, int gsize, int tile_w, void* ws, hipStream_t s);
 
 // Per-dimension range of the finite coordinates of n points (synchronises s).
 hipError_t coord_range(const void* pts, int64_t n, int32_t f, int32_t dtype, float* lo, float* hi, hipStream_t s);
@@ -410,8 +410,8 @@ hipError_t coord_range(const void* pts, int64_t n, int32_t f, int32_t dtype, flo
 size_t group_ws_bytes(int64_t m);
 hipError_t launch_screen_error(const IndexView& ix, const float* qs, int64_t m, uint32_t nsamp, float* out_abs,
                                float* out_rel, hipStream_t s);
-// gsize: most queries per group (1..16)
-hipError_t run_grouped(const PredictArgs& pa, int group_levels, int gsize, void* ws, hipStream_t s, int* morton_bits,
+// gsize: most queries per group (1..16); tile_w: candidates per screened tile (32 or 64)
+hipError_t run_grouped(const PredictArgs& pa, int group_levels, int gsize, int tile_w, void* ws, hipStream_t s, int* morton_bits,
                        hipEvent_t ev_begin, hipEvent_t ev_end, bool brute);
 // Spatial sort key of every query (Morton code of its box-clamped central cell).
 hipError_t launch_query_keys(const float* qs, int64_t m, const IndexView& ix, int keep_bits, uint64_t* keys,

@@ -133,6 +133,7 @@ static void phase_gpu() {
                 ghn_predict_opts q = o;
                 q.stop = stop;
                 q.prec = prec;
+                q.tile_width = lookup == GHN_LOOKUP_TREE ? 32 : 0;  // both screen tile widths
                 CHECK(ghn_predict(jx, dq.as<float>(), m, k, &q, oi.as<int64_t>(), od.as<double>(), op.p, ws.p, wsb,
                                   nullptr) == GHN_OK);
                 if (stop == GHN_STOP_EXACT) CHECK(down<int64_t>(oi, (size_t)m * k) == want);
@@ -163,6 +164,9 @@ static void phase_gpu() {
         q.prec = GHN_PREC_BF16_MFMA;
         CHECK(ghn_predict(ix, dq.as<float>(), m, k, &q, oi.as<int64_t>(), nullptr, op.p, nullptr, 0, nullptr) ==
               GHN_E_WORKSPACE);
+        q.tile_width = 48;
+        CHECK(ghn_predict(ix, dq.as<float>(), m, k, &q, oi.as<int64_t>(), nullptr, op.p, ws.p, wsb, nullptr) ==
+              GHN_E_INVALID_ARG);
     }
 
     // a batch of two items

@@ -148,7 +148,8 @@ def test_bf16_16d_full_size(ghn, width_scale):
     forms = {EXACT: [("FP32 input order", dict(prec=FP32, flags=ghn.GHN_FLAG_NO_SORT)),
                      ("FP32 sorted ring 2 grow", dict(prec=FP32, flags=ghn.GHN_FLAG_RING_GROW, ring_step=2)),
                      ("bf16", dict(prec=BF16)),
-                     ("bf16 levels 2", dict(prec=BF16, group_levels=2))],
+                     ("bf16 levels 2", dict(prec=BF16, group_levels=2)),
+                     ("bf16 levels 1 tiles of 32", dict(prec=BF16, group_levels=1, tile_width=32))],
              PAPER: [("FP32 sorted", dict(prec=FP32)), ("bf16", dict(prec=BF16))]}
     _check_forms(ghn, "bf16_16d", prob, ix, forms, width_scale == 1.0)
     ix.close()

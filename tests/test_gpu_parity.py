@@ -471,17 +471,18 @@ def test_bf16_16d_small(ghn):
 MFMA = 1
 
 
-def _check_mfma(ghn, prob, sample=None, levels=-1, lookup=None, paper=True, seed=0, group_size=0):
+def _check_mfma(ghn, prob, sample=None, levels=-1, lookup=None, paper=True, seed=0, group_size=0, tile_width=0):
     ix = _index(ghn, prob, lookup=lookup)
     got = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_EXACT, prec=MFMA, group_levels=levels,
-               group_size=group_size)
+               group_size=group_size, tile_width=tile_width)
     rows = np.arange(prob.m)
     if sample is not None and sample < prob.m:
         rows = np.sort(np.random.default_rng(seed).choice(prob.m, sample, replace=False))
     bi, bd, bp = oracle.bruteforce(prob.points_f32(), prob.targets, prob.task, prob.queries[rows], prob.k)
     _assert_same({k: v[rows] for k, v in got.items()}, dict(idx=bi, d2=bd, pred=bp), prob.name + " MFMA EXACT")
     if paper:
-        gp = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_PAPER, prec=MFMA, group_size=group_size)
+        gp = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_PAPER, prec=MFMA, group_size=group_size,
+                  tile_width=tile_width)
         want = oracle.Grid(prob.points_f32(), prob.targets, prob.task, prob.cell_width).predict(
             prob.queries[rows], prob.k, oracle.STOP_PAPER)
         _assert_same({k: v[rows] for k, v in gp.items()}, want, prob.name + " MFMA PAPER", check_layers=True)
@@ -498,20 +499,30 @@ def test_mfma_clusters4d_small(ghn):
         _check_mfma(ghn, prob, levels=levels, paper=levels == -1)
 
 
-@pytest.mark.parametrize("group_size", [1, 4, 8])
-def test_mfma_group_sizes(ghn, group_size):
-    """Groups of at most 1, 4 or 8 queries (the tile's other query rows stay empty)."""
+@pytest.mark.parametrize("group_size,tile_width", [(1, 0), (4, 0), (8, 0), (0, 32), (4, 32)])
+def test_mfma_group_sizes(ghn, group_size, tile_width):
+    """Groups of at most 1, 4 or 8 queries (the tile's other query rows stay empty), and
+    tiles of 32 candidates (two column blocks) instead of 64."""
     prob = W.make("clusters4d", n=40_000, m=1_500)
-    _check_mfma(ghn, prob, levels=2, group_size=group_size)
+    _check_mfma(ghn, prob, levels=2, group_size=group_size, tile_width=tile_width)
     probs = _multi(problems=6, n_hi=20_000, m_hi=1_500, seed=61)
     idxs = [_index(ghn, p) for p in probs]
     for stop in (ghn.GHN_STOP_EXACT, ghn.GHN_STOP_PAPER):
-        got = _batch_run_gs(ghn, probs, idxs, stop, group_size)
+        got = _batch_run_gs(ghn, probs, idxs, stop, group_size, tile_width)
         for i, (p, g) in enumerate(zip(probs, got)):
-            _assert_same(g, _oracle_want(p, stop), "bf16 batch group_size=%d item %d" % (group_size, i))
+            _assert_same(g, _oracle_want(p, stop), "bf16 batch group_size=%d tile_width=%d item %d" % (
+                group_size, tile_width, i))
 
 
-def _batch_run_gs(ghn, probs, idxs, stop, group_size):
+@pytest.mark.parametrize("k", [1, 17, 33, 64])
+def test_mfma_tile_width_32_k_values(ghn, k):
+    """32-candidate tiles over every buffer width (one, two and four registers per
+    16-lane row), with ragged tails: n and m are not multiples of the tile."""
+    prob = W.uniform_problem(n=4_999, m=301, f=3, k=k, seed=260 + k, width=0.08)
+    _check_mfma(ghn, prob, tile_width=32)
+
+
+def _batch_run_gs(ghn, probs, idxs, stop, group_size, tile_width=0):
     import torch
     items, outs = [], []
     for p, ix in zip(probs, idxs):
@@ -521,7 +532,7 @@ def _batch_run_gs(ghn, probs, idxs, stop, group_size):
         items.append((ix.handle, _dev(p.queries), p.k, oi, op, od))
         outs.append((oi, op, od))
     ws = torch.empty(ghn.ghn_batch_workspace_bytes_for(items, stop, MFMA), dtype=torch.uint8, device="cuda")
-    batch = ghn.ghn_batch_prepare(items, ws, stop=stop, prec=MFMA, group_size=group_size)
+    batch = ghn.ghn_batch_prepare(items, ws, stop=stop, prec=MFMA, group_size=group_size, tile_width=tile_width)
     ghn.ghn_predict_batched(batch)
     torch.cuda.synchronize()
     ghn.ghn_batch_destroy(batch)
@@ -859,11 +870,12 @@ def test_autotune_exact_and_paper(ghn, tmp_path):
     best = autotune.tune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_EXACT, cache_path=cache)
     assert best["ms"] > 0 and best["cell_width"] > 0
     # widths x (8 FP32 settings: 2 walk orders x 4 ring schedules + bf16 at 4 grouping
-    # levels x 2 group sizes), plus the 8 FP32 settings on the hash lookup for every
-    # width whose build chose the tree (4 dimensions)
+    # levels x 3 group and tile shapes), plus the 8 FP32 settings on the hash lookup for
+    # every width whose build chose the tree (4 dimensions)
     tree_widths = {t["cell_width"] for t in best["trials"] if t["lookup"] == TREE}
-    assert len(best["trials"]) == 6 * 16 + 8 * len(tree_widths)
-    assert {t["group_size"] for t in best["trials"] if t["prec"] == MFMA} == {8, 16}
+    assert len(best["trials"]) == 6 * 20 + 8 * len(tree_widths)
+    assert {(t["group_size"], t["tile_width"]) for t in best["trials"] if t["prec"] == MFMA} == {
+        (16, 64), (8, 64), (16, 32)}
     assert sum(t["lookup"] == HASH for t in best["trials"]) == 8 * len(tree_widths)
     assert {t["ring_step"] for t in best["trials"]} == {0, 1, 2}
     again = autotune.tune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_EXACT, cache_path=cache)
@@ -871,11 +883,12 @@ def test_autotune_exact_and_paper(ghn, tmp_path):
     # the tuned setting still returns the brute-force neighbours
     ix = ghn.Index(pts, tgt, prob.task, best["cell_width"], lookup=best["lookup"])
     got = _run(ghn, ix, prob.queries, prob.k, ghn.GHN_STOP_EXACT, prec=best["prec"], flags=best["flags"],
-               group_levels=best["group_levels"], ring_step=best["ring_step"], group_size=best["group_size"])
+               group_levels=best["group_levels"], ring_step=best["ring_step"], group_size=best["group_size"],
+               tile_width=best["tile_width"])
     bi, bd, bp = oracle.bruteforce(prob.points, prob.targets, prob.task, prob.queries, prob.k)
     _assert_same(got, dict(idx=bi, d2=bd, pred=bp), "autotuned EXACT")
     pb, trials = ghn.ghn_autotune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_PAPER, widths=[prob.cell_width])
-    assert abs(pb["cell_width"] - prob.cell_width) < 1e-9 and len(trials) == 4
+    assert abs(pb["cell_width"] - prob.cell_width) < 1e-9 and len(trials) == 5
     with pytest.raises(ghn.GHNError) as e:
         ghn.ghn_autotune(pts, tgt, prob.task, q, prob.k, ghn.GHN_STOP_PAPER)
     assert e.value.code == -1
