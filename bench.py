@@ -459,6 +459,9 @@ def main():
     ap.add_argument("--ring-step", type=int, default=-1,
                     help="FP32 form, EXACT rule: layers per step of the walk (-1: the autotuned value, else 2, so the "
                          "central cell and layer 1 are walked in one step; the neighbours do not depend on it)")
+    ap.add_argument("--ring-grow", action="store_true",
+                    help="FP32 form, EXACT rule: double the ring step while the buffer is not full (as the "
+                         "autotuner may choose; for profiler runs of an autotuned configuration)")
     ap.add_argument("--autotune", choices=("auto", "on", "off"), default="auto",
                     help="pick the cell width (and each form's settings) with ghn_autotune on a query sample "
                          "before the timed region; auto = on for %s" % ", ".join(AUTOTUNED))
@@ -567,6 +570,8 @@ def main():
                             for t in trials]}
         print("autotune: width %.6g (calibrated %.6g), %.1f s" % (width, prob.cell_width, tune_ms * 1e-3),
               file=sys.stderr, flush=True)
+    if args.ring_grow:
+        grow32 = ghn.GHN_FLAG_RING_GROW
     if args.ring_step >= 0:
         ring32 = args.ring_step
     elif tuned is None and stop == ghn.GHN_STOP_EXACT:
@@ -689,7 +694,7 @@ def main():
         forms["fp32_persistent"] = dict(
             qps=m / (ms * 1e-3), ms_per_step=ms, kernel_ms=kern_ms, per=per, work=w,
             roofline=hbm_roofline(alg_bytes, walk_bytes_extended(m, f, k, w["cands"], w["probes"]), kern_ms,
-                                  None, "k_predict_batched"),
+                                  measured_traffic(args.workload, "fp32_batched"), "k_predict_batched"),
             alg={"bytes_per_step": alg_bytes, "timed": "counter reset (+ query sort) + persistent kernel",
                  "spatial_order": bool(sort32)})
     if "brute" in args.forms:
