@@ -340,6 +340,41 @@ __device__ __forceinline__ floatx4 screen_block(const IndexView& ix, const bf16x
     return acc;
 }
 
+// Screen of the first NB column blocks of a tile, with every block's record loads
+// issued before the first matrix instruction, so that NB loads per lane are in flight
+// at once.  The loads are not guarded: a lane without a candidate has position 0 (a
+// record of the index) and a NaN initial accumulator, so its column is never admitted
+// whatever the loaded values are.
+template <int FT, int SP, int NB>
+__device__ __forceinline__ void screen_tile(const IndexView& ix, const bf16x8* afr, uint32_t pidx, float xinit, int g,
+                                            int t, floatx4* acc, uint32_t* pc) {
+    using SC = Screen<SP>;
+    bf16x8 ld[NB][SC::NCH];
+    float xi[NB];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+        pc[cb] = (uint32_t)__shfl((int)pidx, 16 * cb + t, WAVE);
+        xi[cb] = __shfl(xinit, 16 * cb + t, WAVE);
+#pragma unroll
+        for (int c = 0; c < SC::NCH; ++c)
+            ld[cb][c] = *(const bf16x8*)(ix.srec + (size_t)pc[cb] * (2 * SP) + 8 * SC::chunk(c, g));
+    }
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+        acc[cb] = floatx4{xi[cb], xi[cb], xi[cb], xi[cb]};
+#pragma unroll
+        for (int kb = 0; kb < SC::NKB; ++kb) {
+            const int src = SC::b_src(kb, g);
+            bf16x8 bb = ld[cb][(SC::NCH > 1 && src > 0) ? SC::NCH - 1 : 0];
+            if (src < 0) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bb[e] = (__bf16)0.0f;
+            }
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[kb], bb, acc[cb], 0, 0, 0);
+        }
+    }
+}
+
 // BATCH: the groups come from many indexes (a batch); each group belongs to one item,
 // found from its first query's global position, and is walked with that item's index,
 // queries, k and outputs.  KR covers the largest k of the batch.
@@ -641,16 +676,18 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                     uint64_t any = 0;
                     floatx4 accs[4];
                     uint32_t pcs[4];
+                    if (tw == 64) {
+                        screen_tile<FT, SP, 4>(ix, afr, pidx, xinit, g, t, accs, pcs);
 #pragma unroll
-                    for (int cb = 0; cb < 4; ++cb) {
-                        if (cb >= 2 && tw < 64) {
-                            accs[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
-                            pcs[cb] = 0;
-                            continue;
-                        }
-                        accs[cb] = screen_block<FT, SP>(ix, afr, pidx, xinit, base, npts, cb, g, t, pcs[cb]);
+                        for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) any |= ballot(accs[cb][i] <= bnd[i]);
+                            for (int i = 0; i < 4; ++i) any |= ballot(accs[cb][i] <= bnd[i]);
+                    } else {
+                        screen_tile<FT, SP, 2>(ix, afr, pidx, xinit, g, t, accs, pcs);
+#pragma unroll
+                        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) any |= ballot(accs[cb][i] <= bnd[i]);
                     }
                     if (any) {
                         // queue the admitted pairs (query row, point position)
