@@ -58,8 +58,13 @@ def source_hash(kernel: str) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, form: str):
-    """HBM bytes per launch from the committed rocprofv3 counter runs, if the kernel is unchanged."""
+def measured_traffic(workload: str, form: str, run=None, calibrated_width=None):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if the kernel is unchanged
+    and the counters were taken in this run's configuration.
+
+    `run` holds this run's settings (cell_width, and ring_step, ring_grow, sort for the FP32 walk
+    or group_levels for the bf16 screen); an entry's recorded `config` must agree with every
+    setting it records (a recorded cell width of None stands for `calibrated_width`)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -70,7 +75,29 @@ def measured_traffic(workload: str, form: str):
         return None
     if entry.get("source_sha256_16") != source_hash(entry["kernel"]):
         return None
+    cfg = entry.get("config")
+    if cfg is not None and run is not None:
+        for key, want in cfg.items():
+            if key not in run:
+                continue
+            if key == "cell_width":
+                w = calibrated_width if want is None else want
+                if w is None or abs(float(run[key]) - float(w)) > 1e-6 * abs(float(w)):
+                    return None
+            elif run[key] != want:
+                return None
     return entry.get("bytes_per_launch")
+
+
+def traffic_config(args, form: str) -> dict:
+    """Settings of a profiler run of `form` (bench.py arguments), recorded with its counters."""
+    cfg = {"cell_width": args.cell_width}
+    if form.startswith("fp32"):
+        cfg.update(ring_step=args.ring_step if args.ring_step >= 0 else 2, ring_grow=bool(args.ring_grow),
+                   sort=bool(args.sort))
+    else:
+        cfg.update(group_levels=args.group_levels, group_size=args.group_size or 16, tile_width=args.tile_width or 64)
+    return cfg
 
 
 # Algorithmic bytes of the gather/probe walk per query: 4f per candidate point gathered, 16 per
@@ -102,7 +129,7 @@ def hbm_roofline(alg_bytes, ext_bytes, kern_ms, traffic, kernel):
     return r
 
 
-def write_traffic(pmc_dir: str, workloads, out_file: str = TRAFFIC_FILE) -> dict:
+def write_traffic(pmc_dir: str, workloads, out_file: str = TRAFFIC_FILE, args=None) -> dict:
     """Turn rocprofv3 --pmc runs into HBM bytes per launch (profiles/traffic.json).
 
     Expects <pmc_dir>/<tag>/pmc_counter_collection.csv for the tags fetch_copy,
@@ -139,6 +166,8 @@ def write_traffic(pmc_dir: str, workloads, out_file: str = TRAFFIC_FILE) -> dict
                 "kernel": kname, "dispatches": len(fv), "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
                 "bytes_per_launch": fk * 1024.0 * fetch_scale + wk * 1024.0 * write_scale,
                 "source_sha256_16": source_hash(kname)}
+            if args is not None and w != "multi3d":
+                out["%s/%s" % (w, form)]["config"] = traffic_config(args, form)
     with open(out_file, "w") as fh:
         json.dump(out, fh, indent=1, sort_keys=True)
     print(json.dumps(out, indent=1, sort_keys=True))
@@ -456,6 +485,9 @@ def main():
                          "through the batched persistent launch), brute (exhaustive KNN, reported beside); default "
                          "fp32,bf16, plus persistent for skew8d")
     ap.add_argument("--group-levels", type=int, default=-1, help="bf16 form: cell-id bits dropped to group queries")
+    ap.add_argument("--group-size", type=int, default=0, help="bf16 form: most queries per group (0 = 16)")
+    ap.add_argument("--tile-width", type=int, default=0, help="bf16 form: candidates per screened tile, 32 or 64 "
+                                                               "(0 = 64)")
     ap.add_argument("--ring-step", type=int, default=-1,
                     help="FP32 form, EXACT rule: layers per step of the walk (-1: the autotuned value, else 2, so the "
                          "central cell and layer 1 are walked in one step; the neighbours do not depend on it)")
@@ -484,7 +516,7 @@ def main():
     if args.forms is None:
         args.forms = "fp32,bf16" + (",persistent" if args.workload == "skew8d" else "")
     if args.write_traffic:
-        write_traffic(args.write_traffic, args.workload.split(","))
+        write_traffic(args.write_traffic, args.workload.split(","), args=args)
         return
     if args.gpus != 1:
         print("bench.py: this benchmark measures one GPU only; run with --gpus 1", file=sys.stderr)
@@ -529,8 +561,8 @@ def main():
     tuned = None
     sort32, levels16 = args.sort, args.group_levels
     ring32, grow32 = 0, 0  # FP32 form: the EXACT walk's ring schedule (autotuned, else --ring-step)
-    gs16 = 0               # bf16 form: most queries per group (autotuned; 0 = 16)
-    tw16 = 0               # bf16 form: candidates per screened tile (autotuned; 0 = 64)
+    gs16 = args.group_size  # bf16 form: most queries per group (autotuned; 0 = 16)
+    tw16 = args.tile_width  # bf16 form: candidates per screened tile (autotuned; 0 = 64)
     if args.autotune == "on" or (args.autotune == "auto" and args.workload in AUTOTUNED and args.cell_width is None
                                     and not args.no_extras):
         # widths around the calibrated one (under PAPER only execution settings are tuned);
@@ -617,6 +649,9 @@ def main():
         del st
         return out
 
+    # this run's settings, matched against those the committed counter runs were taken with
+    run32 = {"cell_width": width, "ring_step": ring32, "ring_grow": bool(grow32), "sort": bool(sort32)}
+    run16 = {"cell_width": width, "group_levels": levels16, "group_size": gs16 or 16, "tile_width": tw16 or 64}
     forms = {}
     if "fp32" in args.forms:
         # per-query walk; with --sort a step = spatial order (Morton sort) + walk, events
@@ -640,7 +675,7 @@ def main():
         forms["fp32_plain"] = dict(
             qps=m / (ms * 1e-3), ms_per_step=ms, kernel_ms=kern_ms, per=per, work=w,
             roofline=hbm_roofline(alg_bytes, walk_bytes_extended(m, f, k, w["cands"], w["probes"]), kern_ms,
-                                  measured_traffic(args.workload, "fp32"),
+                                  measured_traffic(args.workload, "fp32", run32, prob.cell_width),
                                   "k_predict_%s" % ("tree" if ix.info.lookup == 1 else "dense")),
             alg={"bytes_per_step": alg_bytes})
     if "bf16" in args.forms:
@@ -658,7 +693,7 @@ def main():
         forms["bf16_grouped"] = dict(
             qps=m / (ms * 1e-3), ms_per_step=ms, kernel_ms=kern_ms, per=per, work=w,
             roofline={"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                      "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": measured_traffic(args.workload, "bf16"),
+                      "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": measured_traffic(args.workload, "bf16", run16, prob.cell_width),
                       "kernel": "k_predict_group"},
             alg={"flops_per_step": flops, "issued_mfma_flops_per_step": 2.0 * (-(-3 * f // 32) * 32) * w["cands"]})
         # the screen's distance error against FP64, on a query sample against points spread over the index
@@ -694,7 +729,8 @@ def main():
         forms["fp32_persistent"] = dict(
             qps=m / (ms * 1e-3), ms_per_step=ms, kernel_ms=kern_ms, per=per, work=w,
             roofline=hbm_roofline(alg_bytes, walk_bytes_extended(m, f, k, w["cands"], w["probes"]), kern_ms,
-                                  measured_traffic(args.workload, "fp32_batched"), "k_predict_batched"),
+                                  measured_traffic(args.workload, "fp32_batched", run32, prob.cell_width),
+                                  "k_predict_batched"),
             alg={"bytes_per_step": alg_bytes, "timed": "counter reset (+ query sort) + persistent kernel",
                  "spatial_order": bool(sort32)})
     if "brute" in args.forms:
