@@ -38,6 +38,7 @@
 // in registers of its row (entry e = 16 j + t in register j of lane t), so the
 // four rows insert in parallel with row-local DPP shifts.
 #include <cstring>
+#include <type_traits>
 
 #include "ghn_walk.h"
 
@@ -340,28 +341,32 @@ __device__ __forceinline__ floatx4 screen_block(const IndexView& ix, const bf16x
     return acc;
 }
 
-// Screen of the first NB column blocks of a tile, with every block's record loads
-// issued before the first matrix instruction, so that NB loads per lane are in flight
-// at once.  The loads are not guarded: a lane without a candidate has position 0 (a
-// record of the index) and a NaN initial accumulator, so its column is never admitted
-// whatever the loaded values are.
-template <int FT, int SP, int NB>
-__device__ __forceinline__ void screen_tile(const IndexView& ix, const bf16x8* afr, uint32_t pidx, float xinit, int g,
-                                            int t, floatx4* acc, uint32_t* pc) {
+// Screen of the first NB column blocks of a tile, in two halves for a software-pipelined
+// walk: the record loads (issued, not waited for), then the matrix instructions, which
+// start each column's accumulator at its candidate's initial value.  The loads are not
+// guarded: a lane without a candidate has position 0 (a record of the index) and a NaN
+// initial value, so its column is never admitted whatever the loaded values are.
+template <int SP, int NB>
+__device__ __forceinline__ void tile_load(const IndexView& ix, uint32_t pidx, int g, int t,
+                                          bf16x8 (&ld)[NB][Screen<SP>::NCH]) {
     using SC = Screen<SP>;
-    bf16x8 ld[NB][SC::NCH];
-    float xi[NB];
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) {
-        pc[cb] = (uint32_t)__shfl((int)pidx, 16 * cb + t, WAVE);
-        xi[cb] = __shfl(xinit, 16 * cb + t, WAVE);
+        const uint32_t pc = (uint32_t)__shfl((int)pidx, 16 * cb + t, WAVE);
 #pragma unroll
         for (int c = 0; c < SC::NCH; ++c)
-            ld[cb][c] = *(const bf16x8*)(ix.srec + (size_t)pc[cb] * (2 * SP) + 8 * SC::chunk(c, g));
+            ld[cb][c] = *(const bf16x8*)(ix.srec + (size_t)pc * (2 * SP) + 8 * SC::chunk(c, g));
     }
+}
+
+template <int SP, int NB>
+__device__ __forceinline__ void tile_mfma(const bf16x8* afr, const bf16x8 (&ld)[NB][Screen<SP>::NCH], float xinit,
+                                          int g, int t, floatx4 (&acc)[NB]) {
+    using SC = Screen<SP>;
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) {
-        acc[cb] = floatx4{xi[cb], xi[cb], xi[cb], xi[cb]};
+        const float xi = __shfl(xinit, 16 * cb + t, WAVE);
+        acc[cb] = floatx4{xi, xi, xi, xi};
 #pragma unroll
         for (int kb = 0; kb < SC::NKB; ++kb) {
             const int src = SC::b_src(kb, g);
@@ -552,7 +557,7 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
         // flushed before a layer's stop test, so the buffer after layer l and whether
         // layer l changed it do not depend on when pairs are inserted.
         int qcount = 0;
-        auto flush = [&]() {
+        auto flush = [&]() __attribute__((always_inline)) {
             wave_lds_sync();
             for (int qb = 0; qb < qcount; qb += WAVE) {
                 const int e = qb + lane;
@@ -644,12 +649,23 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
         // tw candidates (lanes below tw), screened as tw / 16 column blocks.
         const uint32_t tw = (uint32_t)G.tile_w;
         auto score_tiles = [&](uint32_t npts, uint32_t nrun, bool last) {
+            if (npts == 0 && !last) return;
+            // With records of 16 or more dimensions the tiles are software-pipelined: the
+            // record loads of the next tile are issued before the current tile is screened,
+            // so they are in flight while it is (bf16_16d 78.5 -> 70.2 ms).  With 8 the
+            // registers this holds cost more than the overlap gains (skew8d 950 -> 983 ms), and
+            // a tile's loads are issued once the previous tile is done.
+            constexpr bool PIPE = SP >= 16;
+            auto run_tiles = [&](auto nbc) __attribute__((always_inline)) {
+                constexpr int NB = decltype(nbc)::value;
+                constexpr uint32_t TW = 16u * NB;
                 uint32_t seg = 0;
-                for (uint32_t base = 0; base < npts || (last && base == 0); base += tw) {
-                    // candidate base + lane: its run (one uniform pass over the runs that
-                    // start inside this tile), record position and initial accumulator
-                    const uint32_t p = base + lane;
-                    const uint32_t end = base + tw;
+                // set-up of the tile at b: candidate b + lane's run (one uniform pass over
+                // the runs that start inside the tile), its record position (0 for a lane
+                // without a candidate) and its |x'|^2 (a load still in flight)
+                auto setup = [&](uint32_t b, uint32_t& pidx, float& xn, bool& valid) __attribute__((always_inline)) {
+                    const uint32_t p = b + lane;
+                    const uint32_t end = b + TW;
                     uint32_t my = seg;
                     uint32_t s = seg + 1;
                     uint32_t pre_s = (uint32_t)__builtin_amdgcn_readfirstlane((int)S.run_pre[s]);
@@ -659,47 +675,50 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                         pre_s = (uint32_t)__builtin_amdgcn_readfirstlane((int)S.run_pre[s]);
                     }
                     seg = (pre_s == end && s < nrun) ? s : s - 1;
-                    const bool valid = p < npts && (uint32_t)lane < tw;
-                    uint32_t pidx = 0;
-                    float xinit = __int_as_float(0x7fc00000);  // NaN: never admitted
-                    if (valid) {
-                        pidx = S.run_begin[my] + (p - S.run_pre[my]);
-                        const float xn = ix.sxn[pidx];
-                        xinit = __builtin_fmaf(-SCREEN_REL, xn, xn) - SCREEN_ABS;
-                    }
+                    valid = p < npts && (uint32_t)lane < TW;
+                    const uint32_t at = S.run_begin[my] + (p - S.run_pre[my]);
+                    pidx = valid ? at : 0u;
+                    xn = ix.sxn[pidx];
                     const int nvalid = __popcll(ballot(valid));
 #pragma unroll
                     for (int i = 0; i < 4; ++i) if (!done[i]) cands[i] += nvalid;
-                    // Fast path: the 16 x tw screen of the tile (lane (g, t) holds candidate
-                    // 16 cb + t of column block cb); most tiles admit nothing once the
-                    // buffers are full.
-                    uint64_t any = 0;
-                    floatx4 accs[4];
-                    uint32_t pcs[4];
-                    if (tw == 64) {
-                        screen_tile<FT, SP, 4>(ix, afr, pidx, xinit, g, t, accs, pcs);
-#pragma unroll
-                        for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) any |= ballot(accs[cb][i] <= bnd[i]);
-                    } else {
-                        screen_tile<FT, SP, 2>(ix, afr, pidx, xinit, g, t, accs, pcs);
-#pragma unroll
-                        for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) any |= ballot(accs[cb][i] <= bnd[i]);
+                };
+                bf16x8 ld[NB][Screen<SP>::NCH], ldn[NB][Screen<SP>::NCH];
+                uint32_t pidx, pidxn = 0;
+                float xn, xnn = 0.0f;
+                bool valid, validn = false;
+                setup(0u, pidx, xn, valid);
+                tile_load<SP, NB>(ix, pidx, g, t, ld);
+                for (uint32_t base = 0;; base += TW) {
+                    const bool more = base + TW < npts;
+                    if (PIPE && more) {
+                        setup(base + TW, pidxn, xnn, validn);
+                        tile_load<SP, NB>(ix, pidxn, g, t, ldn);
                     }
+                    // Fast path: the 16 x TW screen of the tile (lane (g, t) holds candidate
+                    // 16 cb + t of column block cb); most tiles admit nothing once the
+                    // buffers are full.  A lane without a candidate starts at NaN, which
+                    // is never admitted.
+                    const float xinit = valid ? __builtin_fmaf(-SCREEN_REL, xn, xn) - SCREEN_ABS
+                                              : __int_as_float(0x7fc00000);
+                    floatx4 accs[NB];
+                    tile_mfma<SP, NB>(afr, ld, xinit, g, t, accs);
+                    uint64_t any = 0;
+#pragma unroll
+                    for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) any |= ballot(accs[cb][i] <= bnd[i]);
                     if (any) {
                         // queue the admitted pairs (query row, point position)
 #pragma unroll
-                        for (int cb = 0; cb < 4; ++cb) {
-                            if (cb >= 2 && tw < 64) break;
+                        for (int cb = 0; cb < NB; ++cb) {
+                            const uint32_t pc = (uint32_t)__shfl((int)pidx, 16 * cb + t, WAVE);
 #pragma unroll
                             for (int i = 0; i < 4; ++i) {
                                 const uint64_t M = ballot(accs[cb][i] <= bnd[i]);
                                 if ((M >> lane) & 1) {
                                     const int pos = qcount + __popcll(M & __lanemask_lt());
-                                    S.qp[pos] = pcs[cb];
+                                    S.qp[pos] = pc;
                                     S.qr[pos] = (uint8_t)(4 * g + i);
                                 }
                                 qcount += __popcll(M);
@@ -707,8 +726,32 @@ __global__ __launch_bounds__(GT, 2) void k_predict_group(GroupArgs G) {
                             }
                         }
                     }
-                    if (qcount >= QFLUSH || (last && qcount > 0 && base + tw >= npts)) flush();
+                    if (qcount >= QFLUSH || (last && qcount > 0 && !more)) {
+                        flush();
+                        // the next tile's loads are issued again after the flush, so that
+                        // they do not hold registers through it (flushes are rare)
+                        if (PIPE && more) {
+                            xnn = ix.sxn[pidxn];
+                            tile_load<SP, NB>(ix, pidxn, g, t, ldn);
+                        }
+                    }
+                    if (!more) break;
+                    if constexpr (PIPE) {
+#pragma unroll
+                        for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+                            for (int c = 0; c < Screen<SP>::NCH; ++c) ld[cb][c] = ldn[cb][c];
+                        pidx = pidxn;
+                        xn = xnn;
+                        valid = validn;
+                    } else {
+                        setup(base + TW, pidx, xn, valid);
+                        tile_load<SP, NB>(ix, pidx, g, t, ld);
+                    }
                 }
+            };
+            if (tw == 64) run_tiles(std::integral_constant<int, 4>{});
+            else run_tiles(std::integral_constant<int, 2>{});
         };
 
         if (G.brute) {
